@@ -1,0 +1,128 @@
+"""Plug-in denoisers D_tau and their divergence, FP64 (test infrastructure).
+
+Sec. 4.3 (eqs. rGAMP, r_input, D_in): the denoiser sees r = x + sqrt(tau_r) psi
+in the preconditioned space and returns x^{t+1} = D(r); its divergence
+D'(r) = (1/N) sum_i dD_i/dr_i gives tau_x^{t+1} = tau_r D'(r).
+eq. MC_SURE: D'(r) ~ (1/(N eps)) b^T (D(r + eps b) - D(r)) with one probe.
+
+Denoisers (the paper uses BM3D; the Haar and patch-based plug-ins are this
+build's, the paper treats D as a black box):
+  * haar_soft: orthonormal 2D Haar pyramid with J levels, soft threshold
+    eta(w) = sign(w) max(|w| - lam, 0) on the detail coefficients,
+    lam = alpha * sqrt(tau_r); the coarsest approximation is kept.
+    Exact divergence = (#approximation coeffs + #{detail: |w| > lam}) / N.
+  * nlm: non-local means (patch distance averaged over a (2pr+1)^2 patch,
+    (2sr+1)^2 search window, weight exp(-max(d2 - 2 sigma^2, 0)/(hfac sigma)^2),
+    sigma = sqrt(tau_r), half-sample symmetric borders), from the C core.
+
+Parity: haar_soft pinned (orthonormality, exact divergence by brute force);
+nlm pinned only by special cases (constant images are fixed points; sigma->0
+is the identity; symmetry under image transposition) -- against the paper it
+is unpinned, the paper's BM3D being a different denoiser.
+"""
+import math
+
+import numpy as np
+
+from . import _lib
+from .probe import rademacher
+
+HAAR = 0
+NLM = 1
+CNN = 2
+
+SQ2 = math.sqrt(2.0)
+
+
+def haar_levels(I):
+    return max(int(round(math.log2(I))) - 2, 1)
+
+
+def haar_fwd(x, J):
+    """Mallat-ordered orthonormal 2D Haar coefficients of a square image."""
+    c = np.array(x, dtype=np.float64, copy=True)
+    n = c.shape[0]
+    for _ in range(J):
+        a = c[:n, :n]
+        lo = (a[:, 0::2] + a[:, 1::2]) / SQ2
+        hi = (a[:, 0::2] - a[:, 1::2]) / SQ2
+        rows = np.concatenate([lo, hi], axis=1)
+        top = (rows[0::2, :] + rows[1::2, :]) / SQ2
+        bot = (rows[0::2, :] - rows[1::2, :]) / SQ2
+        c[:n, :n] = np.concatenate([top, bot], axis=0)
+        n //= 2
+    return c
+
+
+def haar_inv(c, J):
+    x = np.array(c, dtype=np.float64, copy=True)
+    n = x.shape[0] >> (J - 1)
+    for _ in range(J):
+        a = x[:n, :n]
+        h = n // 2
+        top, bot = a[:h, :], a[h:, :]
+        rows = np.empty_like(a)
+        rows[0::2, :] = (top + bot) / SQ2
+        rows[1::2, :] = (top - bot) / SQ2
+        lo, hi = rows[:, :h], rows[:, h:]
+        out = np.empty_like(a)
+        out[:, 0::2] = (lo + hi) / SQ2
+        out[:, 1::2] = (lo - hi) / SQ2
+        x[:n, :n] = out
+        n *= 2
+    return x
+
+
+def haar_soft(r, tau_r, alpha=1.5, J=None):
+    r = np.asarray(r, dtype=np.float64)
+    I = r.shape[0]
+    J = J or haar_levels(I)
+    lam = alpha * math.sqrt(tau_r)
+    c = haar_fwd(r, J)
+    k = I >> J
+    detail = np.ones_like(c, dtype=bool)
+    detail[:k, :k] = False
+    c[detail] = np.sign(c[detail]) * np.maximum(np.abs(c[detail]) - lam, 0.0)
+    return haar_inv(c, J)
+
+
+def haar_soft_exact_div(r, tau_r, alpha=1.5, J=None):
+    r = np.asarray(r, dtype=np.float64)
+    I = r.shape[0]
+    J = J or haar_levels(I)
+    lam = alpha * math.sqrt(tau_r)
+    c = haar_fwd(r, J)
+    k = I >> J
+    detail = np.ones_like(c, dtype=bool)
+    detail[:k, :k] = False
+    return (k * k + np.count_nonzero(np.abs(c[detail]) > lam)) / float(I * I)
+
+
+def nlm(r, tau_r, pr=2, sr=10, hfac=0.4):
+    r = np.ascontiguousarray(r, dtype=np.float64)
+    I = r.shape[0]
+    out = np.empty_like(r)
+    _lib.lib().oracle_nlm(I, _lib.dptr(r), math.sqrt(max(tau_r, 0.0)), pr, sr, hfac,
+                          _lib.dptr(out))
+    return out
+
+
+def apply(kind, r, tau_r, params):
+    if kind == HAAR:
+        return haar_soft(r, tau_r, **params)
+    if kind == NLM:
+        return nlm(r, tau_r, **params)
+    if kind == CNN:
+        from . import cnn
+        return cnn.denoise(r, params["net"])
+    raise ValueError("unknown denoiser kind")
+
+
+def mc_divergence(kind, r, tau_r, params, x_out, seed, t, eps_rel=1e-3):
+    """eq. MC_SURE with K = 1 Rademacher probe; eps = eps_rel * max|r|."""
+    r = np.asarray(r, dtype=np.float64)
+    N = r.size
+    b = rademacher(seed, t, N).reshape(r.shape)
+    eps = max(eps_rel * float(np.max(np.abs(r))), 1e-12)
+    x_pert = apply(kind, r + eps * b, tau_r, params)
+    return float(np.sum(b * (x_pert - x_out)) / (N * eps)), eps
