@@ -1,0 +1,213 @@
+/*
+ * dgampct.h -- C ABI of the D-GAMP-CT hot path on AMD Instinct MI355X (gfx950).
+ *
+ * Method: Perelli, Lexa, Can & Davies, "Compressive CT reconstruction through
+ * Denoising Approximate Message Passing" (arXiv 1609.04661).  Each entry point
+ * cites the passage that defines the operation it computes.
+ *
+ * Conventions shared by every call
+ *   - Image: I x I, row-major, row 0 on top, FP32; pixel (i, j) has centre
+ *     ((j - (I-1)/2) h, ((I-1)/2 - i) h) in mm.
+ *   - Sinogram: view-major [n_views][n_bins], FP32; ray index = k*n_bins + b.
+ *   - Every array pointer is DEVICE memory owned by the caller unless stated;
+ *     the library never frees caller memory and keeps no pointer after return.
+ *   - Calls are asynchronous on `stream` (a hipStream_t; NULL = legacy default
+ *     stream).  Outputs are overwritten, never accumulated into.
+ *   - Arguments are validated on the host before anything is launched; a bad
+ *     argument returns DG_ERR_ARG with nothing launched, dg_last_error() gives
+ *     the reason (thread-local text).
+ *   - Scalars that feed the next step (tau_p, tau_s, tau_r, div, ...) live in
+ *     device memory, so a T-iteration loop needs no host synchronisation.
+ *   - A plan may be used by several calls on one stream; concurrent calls on
+ *     different streams need separate workspaces.
+ */
+#ifndef DGAMPCT_H
+#define DGAMPCT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t dg_status;
+#define DG_OK 0
+#define DG_ERR_ARG (-1)         /* invalid argument: nothing launched          */
+#define DG_ERR_HIP (-2)         /* HIP runtime error (message in dg_last_error)*/
+#define DG_ERR_NUMERIC (-3)     /* a GAMP variance became non-finite or <= 0   */
+#define DG_ERR_UNSUPPORTED (-4) /* size or option not implemented              */
+#define DG_ERR_NOMEM (-5)       /* device allocation failed (plan tables only)  */
+
+#define DG_GEOM_PARALLEL 0
+#define DG_GEOM_FAN 1
+
+/* One acquisition (Sec. 2.1, eqs. linCT and Phi_mtx: one system-matrix row per
+ * measured ray, J = n_bins * n_views rows; only measured views are listed).
+ *   parallel: theta_k = angle0 + k*span/n_views (end point excluded), ray b is
+ *     the line <u, (cos theta_k, sin theta_k)> = (b - (n_bins-1)/2) * bin_mm.
+ *   fan (equiangular arc detector): source at dso*(cos beta_k, sin beta_k),
+ *     beta_k = angle0 + k*span/n_views; ray b leaves the source towards the
+ *     iso-centre rotated by gamma_b = (b - (n_bins-1)/2) * dgamma; dgamma = 0
+ *     picks the pitch whose fan covers the circle circumscribing the image.
+ *     ddo_mm is recorded but does not change the ray lines.
+ * Angles that are exact multiples of pi/2 use exact trig values.             */
+typedef struct dg_geom {
+  int32_t kind;       /* DG_GEOM_PARALLEL or DG_GEOM_FAN                 */
+  int32_t n;          /* image side I, 8 <= I <= 4096                     */
+  int32_t n_views;    /* N_theta >= 1                                     */
+  int32_t n_bins;     /* N_dec >= 1                                       */
+  double pixel_mm;    /* h > 0                                            */
+  double angle0_rad;
+  double span_rad;
+  double bin_mm;      /* parallel detector pitch > 0                      */
+  double dso_mm;      /* fan: source to iso-centre, > I*h/sqrt(2)         */
+  double ddo_mm;      /* fan: iso-centre to detector                      */
+  double dgamma_rad;  /* fan: angular bin pitch, 0 = cover the image       */
+} dg_geom;
+
+typedef struct dg_plan dg_plan; /* geometry tables, FFT twiddles (device)   */
+
+/* Build the per-ray line tables, the FFT tables and the preconditioner
+ * symbol for `g` on the current HIP device.  Synchronous.  The plan owns its
+ * (read-only) device tables until dg_plan_destroy.                         */
+dg_status dg_plan_create(const dg_geom* g, dg_plan** out);
+dg_status dg_plan_destroy(dg_plan* plan);
+
+/* Workspace (device bytes) an operation needs with this plan.               */
+#define DG_OP_PRECOND 0
+#define DG_OP_DENOISE 1
+#define DG_OP_DGAMP 2
+#define DG_OP_FRO2 3
+size_t dg_workspace_bytes(const dg_plan* plan, int32_t op);
+/* Workspace of gamp_poisson_out for m rays.                                 */
+size_t dg_channel_workspace_bytes(int64_t m);
+
+const char* dg_last_error(void);
+
+/* z = A mu: exact chord lengths of each ray through each pixel (Sec. 2.1,
+ * eqs. paramdiscrete and linCT; the pixel indicator basis).  A line lying
+ * exactly on a pixel edge gives half of its length to each neighbour.
+ * img: I*I floats; sino: n_views*n_bins floats (mm * 1/mm = dimensionless).
+ * img_t: optional transposed copy of img (img_t[j*I+i] = img[i*I+j]) that
+ * makes the reads of near-horizontal rays coalesced; NULL = derive it
+ * internally (needs no workspace: a transposed copy is not made, the slower
+ * strided read path is used).                                               */
+dg_status ct_project(const dg_plan* plan, const float* img, const float* img_t,
+                     float* sino, void* stream);
+
+/* g = A^T s with the same weights as ct_project (exact adjoint up to FP32
+ * rounding), computed as a gather per pixel (no atomics, deterministic).   */
+dg_status ct_backproject(const dg_plan* plan, const float* sino, float* img,
+                         void* stream);
+
+/* Cone preconditioner (Sec. 2.3, eq. PPFT preconditioner; eq. Aprecon):
+ * V = F^-1 C^(1/2) F with C = diag(1/|rho|) on the unpadded I x I DFT grid,
+ * |rho| in cycles per pixel, DC value 4 ln(1+sqrt 2) I (the mean of 1/|rho|
+ * over the central DFT cell).
+ *   dir = +1: out = V^-1 in  (x -> mu, multiplies the spectrum by |rho|^1/2)
+ *   dir = -1: out = V in     (mu -> x)
+ * in/out: I*I floats (may alias); work: dg_workspace_bytes(DG_OP_PRECOND).
+ * I must be 2^a * 3^b with b <= 1, 8 <= I <= 1024 (DG_ERR_UNSUPPORTED).      */
+dg_status ct_precondition(const dg_plan* plan, int32_t dir, const float* in, float* out,
+                          void* work, void* stream);
+
+/* GAMP output channel for Poisson transmission data (Sec. 4.2 eqs. noise_mod,
+ * MMSEmm, post_exp; Appendix A; Algorithm 1 step 2):
+ *   posterior of z ~ exp(-(z-p)^2/(2 tau_p) - y z - i0 e^-z),
+ *   s_i = (E[z_i] - p_i)/tau_p,  *tau_s = sum_i (1 - Var[z_i]/tau_p) / (m tau_p)
+ * with E and Var from the Laplace expansion around the mode (mode = 0:
+ * second-order fully exponential form, Var clamped to [0, tau_p];
+ * mode = 1: E = mode, Var = curvature^-1).
+ * p, y, s_out: m floats (y holds counts); tau_p, tau_s_out: one device double.
+ * work: dg_channel_workspace_bytes(m).  tau_s is reduced in FP64.           */
+#define DG_CHANNEL_LAPLACE 0
+#define DG_CHANNEL_MODE_ONLY 1
+dg_status gamp_poisson_out(int64_t m, const float* p, const float* y, const double* tau_p,
+                           double i0, int32_t mode, float* s_out, double* tau_s_out,
+                           void* work, void* stream);
+
+/* Plug-in denoiser x = D(r) and its Monte-Carlo divergence (Sec. 4.3, eqs.
+ * rGAMP, D_in, MC_SURE):
+ *   div = b^T (D(r + eps b) - D(r)) / (N eps),  eps = max(eps_rel max|r|, 1e-12),
+ *   b_i = 1 - 2 (SplitMix64(probe_seed ^ (iter << 32) ^ i) & 1)   (one probe).
+ * kind/params (host pointer to the struct below):
+ *   DG_DEN_HAAR: orthonormal 2D Haar pyramid, soft threshold alpha*sqrt(tau_r)
+ *                on detail coefficients (I <= 512, levels = log2 I - 2 by default)
+ *   DG_DEN_NLM : non-local means, sigma = sqrt(tau_r)
+ *   DG_DEN_CNN : residual CNN (see dg_cnn_params)
+ * r, x_out: I*I floats; tau_r: device double; div_out: device double or NULL
+ * (NULL skips the probe evaluation).  work: dg_workspace_bytes(DG_OP_DENOISE). */
+#define DG_DEN_HAAR 0
+#define DG_DEN_NLM 1
+#define DG_DEN_CNN 2
+typedef struct dg_haar_params { double alpha; int32_t levels; /* 0 = log2 I - 2 */ } dg_haar_params;
+typedef struct dg_nlm_params { int32_t patch_radius; int32_t search_radius; double hfac; } dg_nlm_params;
+typedef struct dg_cnn_params {
+  const void* weights;  /* device: packed network, dg_cnn_weight_bytes() bytes */
+  int32_t tangent_div;  /* 1: divergence by the forward-mode tangent b^T J b   */
+} dg_cnn_params;
+dg_status denoise(const dg_plan* plan, int32_t kind, const void* params, const float* r,
+                  const double* tau_r, uint64_t probe_seed, int32_t iter, double eps_rel,
+                  float* x_out, double* div_out, void* work, void* stream);
+
+/* D-GAMP-CT iterations (Algorithm 1, Sec. 4), with Phi~ = A V^-1:
+ *   z = Phi~ x; tau_p = fro2 tau_x / M; p = z - tau_p s_prev;
+ *   (s, tau_s) = channel(p, y, tau_p); tau_r = N / (fro2 tau_s);
+ *   r = x + tau_r Phi~^T s; x = D(r); tau_x = tau_r div
+ * optionally damped (Sec. 7): from the second iteration on, (s, tau_s) and
+ * (x, tau_x) are mixed with their previous values by eta_s and eta_x.
+ * A non-positive divergence sets tau_x = 1e-12 tau_r (counted in the log).
+ * state: x (N), s (M) device floats; scal: device doubles, DG_NSCAL of them
+ * (tau_x, tau_p, tau_s, tau_r, div, eps, status, clamps); state->t counts
+ * the iterations done (host).  mu_out (nullable): V^-1 x after the last
+ * iteration.  log (nullable, device): n_iter * DG_LOG_STRIDE doubles
+ * (tau_p, tau_s, tau_r, div, tau_x, eps, status).
+ * A non-finite or non-positive variance sets scal[DG_S_STATUS] to 1 + the
+ * failing iteration; later iterations leave the state unchanged.           */
+#define DG_NSCAL 16
+#define DG_S_TAU_X 0
+#define DG_S_TAU_P 1
+#define DG_S_TAU_S 2
+#define DG_S_TAU_R 3
+#define DG_S_DIV 4
+#define DG_S_EPS 5
+#define DG_S_STATUS 6
+#define DG_S_CLAMPS 7
+#define DG_LOG_STRIDE 8
+typedef struct dgamp_opts {
+  int32_t n_iter;
+  int32_t den_kind;
+  const void* den_params;  /* host pointer, struct matching den_kind          */
+  double fro2;             /* ||A V^-1||_F^2                                  */
+  double i0;               /* source intensity (photons per ray)             */
+  uint64_t probe_seed;
+  double eps_rel;          /* MC step relative to max|r| (1e-3)               */
+  double eta_x, eta_s;     /* damping, 1 = Algorithm 1 verbatim               */
+  int32_t onsager;         /* 0: p = z (no Onsager term)                      */
+  int32_t channel_mode;    /* DG_CHANNEL_*                                    */
+} dgamp_opts;
+typedef struct dgamp_state {
+  float* x;      /* device, N: x^t                     */
+  float* s;      /* device, M: s^{t-1}                 */
+  double* scal;  /* device, DG_NSCAL                   */
+  int32_t t;     /* host: iterations already done      */
+} dgamp_state;
+
+/* x = 0, s = 0, tau_x = tau_x0, all other scalars 0, t = 0.                 */
+dg_status dgamp_state_init(const dg_plan* plan, dgamp_state* st, double tau_x0, void* stream);
+dg_status dgamp_iterate(const dg_plan* plan, const float* y, const dgamp_opts* opts,
+                        dgamp_state* st, float* mu_out, double* log, void* work,
+                        void* stream);
+
+/* ||A V^-1||_F^2 by Hutchinson's estimator over n_probes Rademacher probes
+ * b_k (b_k,i = 1 - 2 (SplitMix64(seed ^ (k << 32) ^ i) & 1)):
+ * mean_k ||A V^-1 b_k||^2, FP64 accumulation; written to *out (device).
+ * work: dg_workspace_bytes(DG_OP_FRO2).                                     */
+dg_status dg_fro2_hutchinson(const dg_plan* plan, int32_t n_probes, uint64_t seed,
+                             double* out, void* work, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* DGAMPCT_H */

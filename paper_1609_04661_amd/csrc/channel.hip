@@ -1,0 +1,191 @@
+// GAMP output channel for Poisson transmission counts (Sec. 4.2 eqs.
+// noise_mod / MMSEmm / post_exp, Appendix A, Algorithm 1 step 2).
+//
+// Per ray the posterior of z is exp(L(z)), L = -(z-p)^2/(2 tau_p) - y z - I0 e^-z.
+// The mode is found in the variable delta = z0 - p, which avoids the
+// cancellation of the closed form z0 = p - tau_p y + W0(...): with
+// w = delta + tau_p y (= tau_p * I0 e^-z0 at the mode), delta solves
+//     F(delta) = delta + ln(w / tau_p) - (ln I0 - p) = 0,
+// an increasing concave equation solved by Halley steps from the log-domain
+// Lambert-W starting point.  Then, with lambda = w / tau_p and
+// sigma^2 = tau_p / (1 + w), the second-order Laplace (fully exponential)
+// moments are
+//     E[z] - p   = delta + w tau_p / (2 (1+w)^2)
+//     Var/tau_p  = 1/(1+w) - w tau_p/(2 (1+w)^3) + w^2 tau_p/(1+w)^4, clamped to [0,1],
+// and s = (E[z] - p)/tau_p, tau_s = sum(1 - Var/tau_p) / (M tau_p) with the
+// sum in FP64 (per-block partials, finished by the last block in order).
+#include <cmath>
+
+#include "dg_internal.h"
+
+namespace dg {
+
+static constexpr int kChanBlock = 256;
+static constexpr int kChanMaxBlocks = 1024;
+
+struct ChanOut {
+  float s;
+  float one_minus_v;  // 1 - Var/tau_p
+};
+
+__device__ __forceinline__ ChanOut poisson_channel(float p, float y, float tau_p, float ln_i0,
+                                                   int mode) {
+  const float ty = tau_p * y;
+  const float ln_tp = logf(tau_p);
+  const float C = ln_i0 - p;  // F(delta) = delta + ln w - ln tau_p - C
+  // starting point: w0 ~ W0(e^xi), xi = ln(tau_p I0) + tau_p y - p
+  const float xi = ln_tp + C + ty;
+  float w0;
+  if (xi > 1.0f) {
+    const float lx = logf(xi);
+    w0 = xi - lx + lx / xi;
+  } else {
+    const float e = expf(fmaxf(xi, -80.0f));
+    w0 = e / (1.0f + e) * (1.0f + 0.5f * e / (1.0f + e));
+  }
+  float delta = w0 - ty;
+  // Halley on F with F' = (w+1)/w and F'' = -1/w^2, written without 1/w so
+  // that no term overflows for small w; Newton when the Halley denominator
+  // is not safely positive.
+#pragma unroll
+  for (int it = 0; it < 5; ++it) {
+    const float w = fmaxf(delta + ty, 1e-30f);
+    const float F = delta + logf(w) - ln_tp - C;
+    const float w1 = w + 1.0f;
+    const float den = 2.0f * w1 * w1 + F;
+    delta -= (den > w1 * w1) ? 2.0f * F * w1 * w / den : F * w / w1;
+  }
+  const float w = fmaxf(delta + ty, 1e-30f);
+  const float u = 1.0f / (1.0f + w);
+  ChanOut o;
+  if (mode == DG_CHANNEL_MODE_ONLY) {
+    o.s = delta / tau_p;
+    o.one_minus_v = 1.0f - u;
+    return o;
+  }
+  const float u2 = u * u;
+  o.s = delta / tau_p + 0.5f * w * u2;
+  float v = u - 0.5f * w * tau_p * u2 * u + w * w * tau_p * u2 * u2;
+  v = fminf(fmaxf(v, 0.0f), 1.0f);
+  o.one_minus_v = 1.0f - v;
+  return o;
+}
+
+// Fused form used inside the iteration:
+//   tau_p = fro2 tau_x / M, p = z - tau_p s_prev, s = channel(p),
+//   s <- eta_s s + (1 - eta_s) s_prev  (t > 0), and the last block finishes
+//   tau_s (damped likewise) and tau_r = N / (fro2 tau_s).
+// Standalone form: p given, tau_p from a device scalar, writes s and tau_s.
+template <bool kFused>
+__global__ void __launch_bounds__(kChanBlock)
+channel_kernel(int64_t M, const float* __restrict__ zp, const float* __restrict__ y,
+               float* __restrict__ s_io, float* __restrict__ s_out, const double* tau_p_ptr,
+               double* scal, double* tau_s_out, double i0, int mode, double fro2, double N,
+               double eta_s, int onsager, int t, double* __restrict__ partials,
+               unsigned int* counter) {
+  __shared__ double red[kChanBlock / 64];
+  __shared__ int flag;
+  double tau_p_d;
+  if (kFused) {
+    if (scal[DG_S_STATUS] != 0.0) return;
+    tau_p_d = fro2 * scal[DG_S_TAU_X] / (double)M;
+  } else {
+    tau_p_d = *tau_p_ptr;
+  }
+  const float tau_p = (float)tau_p_d;
+  const float ln_i0 = (float)log(i0);
+  const float eta = (float)eta_s;
+  double acc = 0.0;
+  for (int64_t k = (int64_t)blockIdx.x * kChanBlock + threadIdx.x; k < M;
+       k += (int64_t)gridDim.x * kChanBlock) {
+    float p = zp[k];
+    float s_prev = 0.0f;
+    if (kFused) {
+      s_prev = s_io[k];
+      if (onsager) p = __fmaf_rn(-tau_p, s_prev, p);
+    }
+    ChanOut o = poisson_channel(p, y[k], tau_p, ln_i0, mode);
+    float s = o.s;
+    if (kFused) {
+      if (t > 0) s = __fmaf_rn(eta, s, (1.0f - eta) * s_prev);
+      s_io[k] = s;
+    } else {
+      s_out[k] = s;
+    }
+    acc += (double)o.one_minus_v;
+  }
+  double bs = block_sum(acc, red);
+  if (threadIdx.x == 0) partials[blockIdx.x] = bs;
+  if (last_block(counter, &flag)) {
+    double tot = 0.0;
+    if (threadIdx.x == 0) {
+      for (unsigned int b = 0; b < gridDim.x; ++b) tot += partials[b];
+      double tau_s = tot / ((double)M * tau_p_d);
+      if (kFused) {
+        if (t > 0) tau_s = eta_s * tau_s + (1.0 - eta_s) * scal[DG_S_TAU_S];
+        double tau_r = N / (fro2 * tau_s);
+        scal[DG_S_TAU_P] = tau_p_d;
+        scal[DG_S_TAU_S] = tau_s;
+        scal[DG_S_TAU_R] = tau_r;
+        if (!(tau_s > 0.0) || !isfinite(tau_s) || !(tau_r > 0.0) || !isfinite(tau_r))
+          scal[DG_S_STATUS] = (double)(t + 1);
+      } else {
+        *tau_s_out = tau_s;
+      }
+      *counter = 0u;
+    }
+  }
+}
+
+unsigned int channel_grid(int64_t M) { return grid_for(M, kChanBlock, kChanMaxBlocks); }
+
+dg_status launch_channel_fused(int64_t M, const float* z, const float* y, float* s, double* scal,
+                               double i0, int mode, double fro2, double N, double eta_s,
+                               int onsager, int t, double* partials, unsigned int* counter,
+                               hipStream_t st) {
+  hipLaunchKernelGGL(channel_kernel<true>, dim3(channel_grid(M)), dim3(kChanBlock), 0, st, M, z, y,
+                     s, nullptr, nullptr, scal, nullptr, i0, mode, fro2, N, eta_s, onsager, t,
+                     partials, counter);
+  DG_LAUNCH_CHECK("channel_kernel<fused>");
+  return DG_OK;
+}
+
+__global__ void zero_u32(unsigned int* p, int n) {
+  int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < n) p[k] = 0u;
+}
+
+dg_status launch_zero_u32(unsigned int* p, int n, hipStream_t st) {
+  hipLaunchKernelGGL(zero_u32, dim3((n + 63) / 64), dim3(64), 0, st, p, n);
+  DG_LAUNCH_CHECK("zero_u32");
+  return DG_OK;
+}
+
+}  // namespace dg
+
+using namespace dg;
+
+extern "C" size_t dg_channel_workspace_bytes(int64_t m) {
+  (void)m;
+  return 256 + sizeof(double) * (size_t)kChanMaxBlocks;
+}
+
+extern "C" dg_status gamp_poisson_out(int64_t m, const float* p, const float* y,
+                                      const double* tau_p, double i0, int32_t mode, float* s_out,
+                                      double* tau_s_out, void* work, void* stream) {
+  DG_ARG_CHECK(m > 0, "gamp_poisson_out: m must be > 0");
+  DG_ARG_CHECK(p && y && tau_p && s_out && tau_s_out && work, "gamp_poisson_out: null argument");
+  DG_ARG_CHECK(i0 > 0 && std::isfinite(i0), "gamp_poisson_out: i0 must be > 0");
+  DG_ARG_CHECK(mode == DG_CHANNEL_LAPLACE || mode == DG_CHANNEL_MODE_ONLY,
+               "gamp_poisson_out: unknown mode");
+  hipStream_t st = (hipStream_t)stream;
+  unsigned int* counter = (unsigned int*)work;
+  double* partials = (double*)((char*)work + 256);
+  dg_status rc = launch_zero_u32(counter, 1, st);
+  if (rc != DG_OK) return rc;
+  hipLaunchKernelGGL(channel_kernel<false>, dim3(channel_grid(m)), dim3(kChanBlock), 0, st, m, p,
+                     y, nullptr, s_out, tau_p, nullptr, tau_s_out, i0, mode, 0.0, 0.0, 1.0, 0, 0,
+                     partials, counter);
+  DG_LAUNCH_CHECK("channel_kernel");
+  return DG_OK;
+}

@@ -1,0 +1,199 @@
+// Internal definitions of the D-GAMP-CT library: plan layout, error
+// plumbing and the device helpers several kernels share.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+
+#include "../../include/dgampct.h"
+
+namespace dg {
+
+// ---------------------------------------------------------------- errors
+
+void set_error(const std::string& msg);
+dg_status hip_fail(hipError_t e, const char* what);
+
+#define DG_ARG_CHECK(cond, msg)         \
+  do {                                  \
+    if (!(cond)) {                      \
+      ::dg::set_error(msg);             \
+      return DG_ERR_ARG;                \
+    }                                   \
+  } while (0)
+
+#define DG_HIP(call)                                     \
+  do {                                                   \
+    hipError_t e_ = (call);                              \
+    if (e_ != hipSuccess) return ::dg::hip_fail(e_, #call); \
+  } while (0)
+
+#define DG_LAUNCH_CHECK(what)                                 \
+  do {                                                        \
+    hipError_t e_ = hipGetLastError();                        \
+    if (e_ != hipSuccess) return ::dg::hip_fail(e_, what);    \
+  } while (0)
+
+// ---------------------------------------------------------------- plan
+
+// One ray as seen by the chord-weight formula: the ray crosses the grid
+// along its major axis (columns when |sin theta| >= |cos theta|, "flat";
+// rows otherwise, "steep"); at major index k its cross coordinate (row for
+// flat rays, column for steep rays, pixel units, pixel centres at integers)
+// is q(k) = q0 + m k.  |pl| is the chord through one full pixel step
+// (h / max(|cos|, |sin|), mm); pl < 0 marks a steep ray.  inv_r = 1/|m|
+// (+inf when the ray is axis-aligned).
+struct RayLine {
+  float q0, m, pl, inv_r;
+};
+
+// Per-view data for the pixel-driven back-projector's candidate search.
+//  parallel: bin coordinate of a pixel centre (x, y) [px] is
+//            u = a*x + b*y + c; candidates are within +-hw of u.
+//  fan:      a, b = source position (px); c = central bin; hw unused
+//            (computed per pixel from the source distance).
+struct ViewInfo {
+  float a, b, c, hw;
+  float cx, cy, inv_dg, pad;  // fan: unit vector towards iso, 1/dgamma [1/rad]
+};
+
+}  // namespace dg
+
+struct dg_plan {
+  dg_geom g;
+  int device;
+  int32_t I, nv, nb;
+  int64_t N, M;
+  dg::RayLine* rays;     // device, M
+  dg::ViewInfo* views;   // device, nv
+  float2* twiddle;       // device, I: exp(-2 pi i t / I)
+  int fft_ok;            // I supported by the FFT kernels
+  double half_diag_px;   // sqrt(2)/2 (fan candidate search)
+};
+
+namespace dg {
+
+// ---------------------------------------------------------------- devices
+
+// Chord of a ray through one pixel, given the pixel's cross-axis offset
+// delta = |q(k) - p| (pixel units): the projection of the pixel square onto
+// the line normal is a trapezoid, so the chord is |pl| times the fraction
+// clamp((0.5 (1 + r) - delta) / r, 0, 1) with r = |m|; for an axis-aligned
+// ray (r = 0) it is a step with value 1/2 on a pixel edge.  The projector and
+// back-projector evaluate this one function on identical operands, so A and
+// A^T use bit-identical weights.
+__device__ __forceinline__ float chord_fraction(float delta, float m, float inv_r) {
+  if (m == 0.0f) return delta < 0.5f ? 1.0f : (delta == 0.5f ? 0.5f : 0.0f);
+  float hw = __fmaf_rn(0.5f, fabsf(m), 0.5f);
+  return fminf(fmaxf(__fmul_rn(hw - delta, inv_r), 0.0f), 1.0f);
+}
+
+__device__ __forceinline__ float cross_coord(const RayLine& L, int k) {
+  return __fmaf_rn(L.m, (float)k, L.q0);
+}
+
+// SplitMix64 finaliser (Steele, Lea & Flood, OOPSLA 2014).
+__device__ __forceinline__ uint64_t splitmix64(uint64_t z) {
+  z += 0x9E3779B97F4A7C15ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+// Rademacher probe value b_i in {-1, +1}.
+__device__ __forceinline__ float probe_sign(uint64_t seed, int32_t iter, uint64_t i) {
+  uint64_t key = seed ^ ((uint64_t)(uint32_t)iter << 32);
+  return (splitmix64(key ^ i) & 1ull) ? -1.0f : 1.0f;
+}
+
+// Wavefront-level sums (64 lanes).
+__device__ __forceinline__ double wave_sum(double v) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+  return v;
+}
+__device__ __forceinline__ float wave_max(float v) {
+  for (int o = 32; o > 0; o >>= 1) v = fmaxf(v, __shfl_down(v, o, 64));
+  return v;
+}
+
+// Block sum of one double per thread; result valid in thread 0.
+// `sh` must hold blockDim.x / 64 doubles.
+__device__ __forceinline__ double block_sum(double v, double* sh) {
+  v = wave_sum(v);
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  if (lane == 0) sh[wid] = v;
+  __syncthreads();
+  double t = 0.0;
+  if (threadIdx.x == 0) {
+    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) t += sh[w];
+  }
+  __syncthreads();
+  return t;
+}
+
+__device__ __forceinline__ float block_max(float v, float* sh) {
+  v = wave_max(v);
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  if (lane == 0) sh[wid] = v;
+  __syncthreads();
+  float t = 0.0f;
+  if (threadIdx.x == 0) {
+    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) t = fmaxf(t, sh[w]);
+  }
+  __syncthreads();
+  return t;
+}
+
+// "Last block done" ticket: every block publishes its partial, then takes a
+// ticket; the block that draws gridDim-1 sees all partials and finishes the
+// reduction (in a fixed order, so the result is deterministic) and resets the
+// counter for the next launch.  Returns true in all threads of that block.
+__device__ __forceinline__ bool last_block(unsigned int* counter, int* sh_flag) {
+  __threadfence();
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    unsigned int t = atomicAdd(counter, 1u);
+    *sh_flag = (t == gridDim.x * gridDim.y * gridDim.z - 1) ? 1 : 0;
+  }
+  __syncthreads();
+  bool last = *sh_flag != 0;
+  if (last) __threadfence();
+  return last;
+}
+
+// Host-side helpers.
+inline unsigned int grid_for(int64_t n, int block, int64_t cap = 65535) {
+  int64_t g = (n + block - 1) / block;
+  if (g < 1) g = 1;
+  if (g > cap) g = cap;
+  return (unsigned int)g;
+}
+
+// Kernels launched by more than one file.
+dg_status launch_transpose(const float* in, float* out, int I, hipStream_t s);
+dg_status launch_project(const dg_plan* p, const float* img, const float* img_t, float* sino,
+                         hipStream_t s);
+dg_status launch_backproject(const dg_plan* p, const float* sino, float* img, hipStream_t s);
+
+// Preconditioner passes.  Epilogue of the last (inverse-row) pass:
+enum PrecEpilogue { PREC_PLAIN = 0, PREC_UPDATE_R = 1 };
+struct PrecArgs {
+  const float* in;
+  float* out;
+  float* out_t;          // optional transposed copy of out
+  float2* spec;          // workspace: (I/2+1) x I complex
+  int dir;               // +1: V^-1, -1: V
+  int epilogue;          // PREC_*
+  const float* x;        // PREC_UPDATE_R: out = x + tau_r * filtered
+  const double* scal;    // PREC_UPDATE_R: tau_r = scal[DG_S_TAU_R]
+  double* scal_out;      // PREC_UPDATE_R: eps written to scal_out[DG_S_EPS]
+  double eps_rel;
+  float* partials;       // PREC_UPDATE_R: per-block max |r|
+  unsigned int* counter; // PREC_UPDATE_R: ticket counter (zero on entry)
+};
+dg_status launch_precondition(const dg_plan* p, const PrecArgs& a, hipStream_t s);
+size_t precond_work_bytes(const dg_plan* p);
+
+}  // namespace dg

@@ -1,0 +1,282 @@
+// D-GAMP-CT iteration driver (Algorithm 1, Sec. 4) and the Hutchinson
+// estimate of ||A V^-1||_F^2 it needs.  One iteration is seven dependent
+// steps, each a kernel (or the three passes of the preconditioner):
+//   mu = V^-1 x  (row-major and transposed copies)   z = A mu
+//   channel: tau_p, p = z - tau_p s, s, tau_s, tau_r  (one fused kernel)
+//   g = A^T s    r = x + tau_r V^-1 g, eps = eps_rel max|r|  (fused epilogue)
+//   D(r), D(r + eps b)  (one launch)   div, tau_x, damped x  (one kernel)
+// All scalars stay on the device, so a whole run is host-sync free and can be
+// captured into a graph by the caller.
+#include <cmath>
+
+#include "dg_internal.h"
+
+namespace dg {
+
+dg_status launch_zero_u32(unsigned int* p, int n, hipStream_t st);
+dg_status launch_channel_fused(int64_t M, const float* z, const float* y, float* s, double* scal,
+                               double i0, int mode, double fro2, double N, double eta_s,
+                               int onsager, int t, double* partials, unsigned int* counter,
+                               hipStream_t st);
+dg_status check_denoise_params(const dg_plan* p, int kind, const void* params);
+dg_status launch_denoiser(const dg_plan* p, int kind, const void* params, const float* r,
+                          const double* tau_r, const double* eps, uint64_t seed, int iter,
+                          float* x_den, float* x_pert, hipStream_t st);
+dg_status launch_div(const dg_plan* p, const float* xden, const float* xpert, float* x,
+                     const double* eps, double* div_out, double* scal, int mode, uint64_t seed,
+                     int iter, double eta_x, int t, double* partials, unsigned int* counter,
+                     hipStream_t st);
+dg_status launch_probe(float* b, int64_t N, uint64_t seed, int k, hipStream_t st);
+size_t denoise_work_bytes(const dg_plan* p);
+unsigned int red_grid(int64_t N);
+dg_status cnn_check_params(const dg_plan* p, const void* params);
+dg_status cnn_launch_denoise(const dg_plan* p, const void* params, const float* r,
+                             const double* eps, uint64_t seed, int iter, float* x_den,
+                             float* x_pert, double* div_dot_out, hipStream_t st);
+
+static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+static constexpr int kMaxBlocks = 1024;
+
+struct IterWork {
+  unsigned int* counters;  // 8
+  double* dpart;
+  float* fpart;
+  float *mu, *mu_t, *z, *g, *r, *xden, *xpert;
+  float2* spec;
+};
+
+static size_t iter_work_layout(const dg_plan* p, void* base, IterWork* w) {
+  char* c = (char*)base;
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    char* ptr = c ? c + off : nullptr;
+    off += align256(bytes);
+    return ptr;
+  };
+  IterWork t;
+  t.counters = (unsigned int*)take(256);
+  t.dpart = (double*)take(sizeof(double) * kMaxBlocks);
+  t.fpart = (float*)take(sizeof(float) * kMaxBlocks);
+  const size_t nb = sizeof(float) * (size_t)p->N, mb = sizeof(float) * (size_t)p->M;
+  t.mu = (float*)take(nb);
+  t.mu_t = (float*)take(nb);
+  t.z = (float*)take(mb);
+  t.g = (float*)take(nb);
+  t.r = (float*)take(nb);
+  t.xden = (float*)take(nb);
+  t.xpert = (float*)take(nb);
+  t.spec = (float2*)take(precond_work_bytes(p));
+  if (w) *w = t;
+  return off;
+}
+
+__global__ void fill_f32(float* p, int64_t n, float v) {
+  for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n;
+       k += (int64_t)gridDim.x * blockDim.x)
+    p[k] = v;
+}
+
+__global__ void init_scal(double* scal, double tau_x0) {
+  int k = threadIdx.x;
+  if (k < DG_NSCAL) scal[k] = (k == DG_S_TAU_X) ? tau_x0 : 0.0;
+}
+
+__global__ void log_copy(const double* scal, double* log) {
+  if (threadIdx.x == 0) {
+    log[0] = scal[DG_S_TAU_P];
+    log[1] = scal[DG_S_TAU_S];
+    log[2] = scal[DG_S_TAU_R];
+    log[3] = scal[DG_S_DIV];
+    log[4] = scal[DG_S_TAU_X];
+    log[5] = scal[DG_S_EPS];
+    log[6] = scal[DG_S_STATUS];
+    log[7] = scal[DG_S_CLAMPS];
+  }
+}
+
+// out += sum(z^2) * scale, FP64, last block finishes.
+__global__ void __launch_bounds__(256)
+sumsq_accum(const float* __restrict__ z, int64_t n, double scale, double* out,
+            double* __restrict__ partials, unsigned int* counter) {
+  __shared__ double red[4];
+  __shared__ int flag;
+  double acc = 0.0;
+  for (int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x; k < n; k += (int64_t)gridDim.x * 256) {
+    double v = z[k];
+    acc += v * v;
+  }
+  double bs = block_sum(acc, red);
+  if (threadIdx.x == 0) partials[blockIdx.x] = bs;
+  if (last_block(counter, &flag)) {
+    if (threadIdx.x == 0) {
+      double tot = 0.0;
+      for (unsigned int b = 0; b < gridDim.x; ++b) tot += partials[b];
+      *out += tot * scale;
+      *counter = 0u;
+    }
+  }
+}
+
+__global__ void set_f64(double* p, double v) {
+  if (threadIdx.x == 0) *p = v;
+}
+
+dg_status launch_fill(float* p, int64_t n, float v, hipStream_t st) {
+  hipLaunchKernelGGL(fill_f32, dim3(grid_for(n, 256, 4096)), dim3(256), 0, st, p, n, v);
+  DG_LAUNCH_CHECK("fill_f32");
+  return DG_OK;
+}
+
+size_t iter_work_bytes(const dg_plan* p) { return iter_work_layout(p, nullptr, nullptr); }
+
+}  // namespace dg
+
+using namespace dg;
+
+extern "C" size_t dg_workspace_bytes(const dg_plan* p, int32_t op) {
+  if (!p) return 0;
+  switch (op) {
+    case DG_OP_PRECOND:
+      return precond_work_bytes(p);
+    case DG_OP_DENOISE:
+      return denoise_work_bytes(p);
+    case DG_OP_DGAMP:
+    case DG_OP_FRO2:
+      return iter_work_bytes(p);
+    default:
+      return 0;
+  }
+}
+
+extern "C" dg_status dgamp_state_init(const dg_plan* p, dgamp_state* st, double tau_x0,
+                                      void* stream) {
+  DG_ARG_CHECK(p && st && st->x && st->s && st->scal, "dgamp_state_init: null argument");
+  DG_ARG_CHECK(tau_x0 > 0 && std::isfinite(tau_x0), "dgamp_state_init: tau_x0 must be > 0");
+  hipStream_t s = (hipStream_t)stream;
+  dg_status rc;
+  if ((rc = launch_fill(st->x, p->N, 0.0f, s)) != DG_OK) return rc;
+  if ((rc = launch_fill(st->s, p->M, 0.0f, s)) != DG_OK) return rc;
+  hipLaunchKernelGGL(init_scal, dim3(1), dim3(64), 0, s, st->scal, tau_x0);
+  DG_LAUNCH_CHECK("init_scal");
+  st->t = 0;
+  return DG_OK;
+}
+
+extern "C" dg_status dgamp_iterate(const dg_plan* p, const float* y, const dgamp_opts* o,
+                                   dgamp_state* st, float* mu_out, double* log, void* work,
+                                   void* stream) {
+  DG_ARG_CHECK(p && y && o && st && work, "dgamp_iterate: null argument");
+  DG_ARG_CHECK(st->x && st->s && st->scal, "dgamp_iterate: state buffers missing");
+  DG_ARG_CHECK(o->n_iter >= 0 && o->n_iter <= 100000, "dgamp_iterate: bad n_iter");
+  DG_ARG_CHECK(o->fro2 > 0 && std::isfinite(o->fro2), "dgamp_iterate: fro2 must be > 0");
+  DG_ARG_CHECK(o->i0 > 0 && std::isfinite(o->i0), "dgamp_iterate: i0 must be > 0");
+  DG_ARG_CHECK(o->eps_rel > 0 && std::isfinite(o->eps_rel), "dgamp_iterate: eps_rel must be > 0");
+  DG_ARG_CHECK(o->eta_x > 0 && o->eta_x <= 1 && o->eta_s > 0 && o->eta_s <= 1,
+               "dgamp_iterate: damping factors must be in (0, 1]");
+  DG_ARG_CHECK(o->channel_mode == DG_CHANNEL_LAPLACE || o->channel_mode == DG_CHANNEL_MODE_ONLY,
+               "dgamp_iterate: unknown channel mode");
+  if (!p->fft_ok) {
+    set_error("dgamp_iterate: image side not supported by the preconditioner FFT");
+    return DG_ERR_UNSUPPORTED;
+  }
+  dg_status rc = (o->den_kind == DG_DEN_CNN) ? cnn_check_params(p, o->den_params)
+                                             : check_denoise_params(p, o->den_kind, o->den_params);
+  if (rc != DG_OK) return rc;
+  hipStream_t s = (hipStream_t)stream;
+  IterWork w;
+  iter_work_layout(p, work, &w);
+  if ((rc = launch_zero_u32(w.counters, 8, s)) != DG_OK) return rc;
+  const double N = (double)p->N;
+  for (int it = 0; it < o->n_iter; ++it) {
+    const int t = st->t + it;
+    PrecArgs a{};
+    a.in = st->x;
+    a.out = w.mu;
+    a.out_t = w.mu_t;
+    a.spec = w.spec;
+    a.dir = 1;
+    a.epilogue = PREC_PLAIN;
+    if ((rc = launch_precondition(p, a, s)) != DG_OK) return rc;
+    if ((rc = launch_project(p, w.mu, w.mu_t, w.z, s)) != DG_OK) return rc;
+    if ((rc = launch_channel_fused(p->M, w.z, y, st->s, st->scal, o->i0, o->channel_mode, o->fro2,
+                                   N, o->eta_s, o->onsager, t, w.dpart, w.counters + 0, s)) !=
+        DG_OK)
+      return rc;
+    if ((rc = launch_backproject(p, st->s, w.g, s)) != DG_OK) return rc;
+    PrecArgs b{};
+    b.in = w.g;
+    b.out = w.r;
+    b.out_t = nullptr;
+    b.spec = w.spec;
+    b.dir = 1;
+    b.epilogue = PREC_UPDATE_R;
+    b.x = st->x;
+    b.scal = st->scal;
+    b.scal_out = st->scal;
+    b.eps_rel = o->eps_rel;
+    b.partials = w.fpart;
+    b.counter = w.counters + 1;
+    if ((rc = launch_precondition(p, b, s)) != DG_OK) return rc;
+    const double* tau_r = st->scal + DG_S_TAU_R;
+    const double* eps = st->scal + DG_S_EPS;
+    if (o->den_kind == DG_DEN_CNN)
+      rc = cnn_launch_denoise(p, o->den_params, w.r, eps, o->probe_seed, t, w.xden, w.xpert,
+                              nullptr, s);
+    else
+      rc = launch_denoiser(p, o->den_kind, o->den_params, w.r, tau_r, eps, o->probe_seed, t,
+                           w.xden, w.xpert, s);
+    if (rc != DG_OK) return rc;
+    if ((rc = launch_div(p, w.xden, w.xpert, st->x, eps, nullptr, st->scal, 1, o->probe_seed, t,
+                         o->eta_x, t, w.dpart, w.counters + 2, s)) != DG_OK)
+      return rc;
+    if (log) {
+      hipLaunchKernelGGL(log_copy, dim3(1), dim3(64), 0, s, st->scal,
+                         log + (size_t)it * DG_LOG_STRIDE);
+      DG_LAUNCH_CHECK("log_copy");
+    }
+  }
+  st->t += o->n_iter;
+  if (mu_out) {
+    PrecArgs a{};
+    a.in = st->x;
+    a.out = mu_out;
+    a.spec = w.spec;
+    a.dir = 1;
+    a.epilogue = PREC_PLAIN;
+    if ((rc = launch_precondition(p, a, s)) != DG_OK) return rc;
+  }
+  return DG_OK;
+}
+
+extern "C" dg_status dg_fro2_hutchinson(const dg_plan* p, int32_t n_probes, uint64_t seed,
+                                        double* out, void* work, void* stream) {
+  DG_ARG_CHECK(p && out && work, "dg_fro2_hutchinson: null argument");
+  DG_ARG_CHECK(n_probes >= 1, "dg_fro2_hutchinson: n_probes must be >= 1");
+  if (!p->fft_ok) {
+    set_error("dg_fro2_hutchinson: image side not supported by the preconditioner FFT");
+    return DG_ERR_UNSUPPORTED;
+  }
+  hipStream_t s = (hipStream_t)stream;
+  IterWork w;
+  iter_work_layout(p, work, &w);
+  dg_status rc;
+  if ((rc = launch_zero_u32(w.counters, 8, s)) != DG_OK) return rc;
+  hipLaunchKernelGGL(set_f64, dim3(1), dim3(64), 0, s, out, 0.0);
+  DG_LAUNCH_CHECK("set_f64");
+  for (int k = 0; k < n_probes; ++k) {
+    if ((rc = launch_probe(w.r, p->N, seed, k, s)) != DG_OK) return rc;
+    PrecArgs a{};
+    a.in = w.r;
+    a.out = w.mu;
+    a.out_t = w.mu_t;
+    a.spec = w.spec;
+    a.dir = 1;
+    a.epilogue = PREC_PLAIN;
+    if ((rc = launch_precondition(p, a, s)) != DG_OK) return rc;
+    if ((rc = launch_project(p, w.mu, w.mu_t, w.z, s)) != DG_OK) return rc;
+    hipLaunchKernelGGL(sumsq_accum, dim3(red_grid(p->M)), dim3(256), 0, s, w.z, p->M,
+                       1.0 / n_probes, out, w.dpart, w.counters + 3);
+    DG_LAUNCH_CHECK("sumsq_accum");
+  }
+  return DG_OK;
+}

@@ -1,0 +1,194 @@
+// Plan creation: per-ray line tables, per-view candidate-search data and FFT
+// twiddles, all derived in FP64 on the host and stored in FP32 on the device.
+// Error plumbing of the C ABI lives here too.
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "dg_internal.h"
+
+namespace dg {
+
+static thread_local std::string g_last_error;
+
+void set_error(const std::string& msg) { g_last_error = msg; }
+
+dg_status hip_fail(hipError_t e, const char* what) {
+  char buf[512];
+  snprintf(buf, sizeof(buf), "HIP error %d (%s) in %s", (int)e, hipGetErrorString(e), what);
+  g_last_error = buf;
+  return DG_ERR_HIP;
+}
+
+// cos/sin with exact values at multiples of pi/2 (grid-aligned rays then lie
+// exactly on pixel edges, where the half-weight edge rule applies).
+static void snapped_cos_sin(double th, double* c, double* s) {
+  double q = th / (0.5 * M_PI);
+  double k = std::nearbyint(q);
+  if (std::fabs(q - k) < 1e-12) {
+    long kk = ((long)k % 4 + 4) % 4;
+    const double cs[4][2] = {{1, 0}, {0, 1}, {-1, 0}, {0, -1}};
+    *c = cs[kk][0];
+    *s = cs[kk][1];
+    return;
+  }
+  *c = std::cos(th);
+  *s = std::sin(th);
+}
+
+static double fan_dgamma(const dg_geom& g) {
+  if (g.dgamma_rad != 0.0) return g.dgamma_rad;
+  double R = g.n * g.pixel_mm / std::sqrt(2.0);
+  return 2.0 * std::asin(R / g.dso_mm) / g.n_bins;
+}
+
+static RayLine make_ray(double c, double s, double off_mm, const dg_geom& g) {
+  const double h = g.pixel_mm;
+  const double off = off_mm / h;  // pixel units
+  const double half = 0.5 * (g.n - 1);
+  RayLine L;
+  double m, q0, pl;
+  if (std::fabs(s) >= std::fabs(c)) {  // flat: march over columns, cross = row
+    m = c / s;
+    q0 = half * (1.0 - m) - off / s;
+    pl = h / std::fabs(s);
+  } else {  // steep: march over rows, cross = column
+    m = s / c;
+    q0 = off / c + half * (1.0 - m);
+    pl = -h / std::fabs(c);
+  }
+  L.q0 = (float)q0;
+  L.m = (float)m;
+  L.pl = (float)pl;
+  L.inv_r = (L.m == 0.0f) ? INFINITY : (float)(1.0 / std::fabs((double)L.m));
+  return L;
+}
+
+static bool fft_size_ok(int I) {
+  if (I < 8 || I > 1024) return false;
+  int n = I;
+  if (n % 3 == 0) n /= 3;
+  while (n % 2 == 0) n /= 2;
+  return n == 1;
+}
+
+size_t precond_work_bytes(const dg_plan* p) {
+  return (size_t)(p->I / 2 + 1) * (size_t)p->I * sizeof(float2);
+}
+
+}  // namespace dg
+
+using namespace dg;
+
+extern "C" const char* dg_last_error(void) { return g_last_error.c_str(); }
+
+extern "C" dg_status dg_plan_create(const dg_geom* g, dg_plan** out) {
+  DG_ARG_CHECK(g != nullptr && out != nullptr, "dg_plan_create: null argument");
+  DG_ARG_CHECK(g->kind == DG_GEOM_PARALLEL || g->kind == DG_GEOM_FAN,
+               "dg_plan_create: unknown geometry kind");
+  DG_ARG_CHECK(g->n >= 8 && g->n <= 4096, "dg_plan_create: image side must be in [8, 4096]");
+  DG_ARG_CHECK(g->n_views >= 1 && g->n_bins >= 1 && (int64_t)g->n_views * g->n_bins <= (1ll << 30),
+               "dg_plan_create: bad view or bin count");
+  DG_ARG_CHECK(g->pixel_mm > 0 && std::isfinite(g->pixel_mm), "dg_plan_create: pixel_mm must be > 0");
+  DG_ARG_CHECK(std::isfinite(g->angle0_rad) && std::isfinite(g->span_rad),
+               "dg_plan_create: non-finite angles");
+  if (g->kind == DG_GEOM_PARALLEL) {
+    DG_ARG_CHECK(g->bin_mm > 0 && std::isfinite(g->bin_mm), "dg_plan_create: bin_mm must be > 0");
+  } else {
+    DG_ARG_CHECK(g->dso_mm > g->n * g->pixel_mm / std::sqrt(2.0),
+                 "dg_plan_create: fan source must lie outside the image's circumscribed circle");
+    DG_ARG_CHECK(std::isfinite(g->dgamma_rad), "dg_plan_create: non-finite dgamma");
+  }
+
+  dg_plan* p = new (std::nothrow) dg_plan();
+  if (!p) {
+    set_error("dg_plan_create: host allocation failed");
+    return DG_ERR_NOMEM;
+  }
+  p->g = *g;
+  p->I = g->n;
+  p->nv = g->n_views;
+  p->nb = g->n_bins;
+  p->N = (int64_t)g->n * g->n;
+  p->M = (int64_t)g->n_views * g->n_bins;
+  p->fft_ok = fft_size_ok(g->n) ? 1 : 0;
+  p->half_diag_px = std::sqrt(2.0) * 0.5;
+  (void)hipGetDevice(&p->device);
+
+  std::vector<RayLine> rays((size_t)p->M);
+  std::vector<ViewInfo> views((size_t)p->nv);
+  const double h = g->pixel_mm;
+  const double cb = 0.5 * (g->n_bins - 1);
+  if (g->kind == DG_GEOM_PARALLEL) {
+    for (int k = 0; k < p->nv; ++k) {
+      double th = g->angle0_rad + k * g->span_rad / p->nv, c, s;
+      snapped_cos_sin(th, &c, &s);
+      for (int b = 0; b < p->nb; ++b)
+        rays[(size_t)k * p->nb + b] = make_ray(c, s, (b - cb) * g->bin_mm, *g);
+      ViewInfo& v = views[k];
+      v.a = (float)(c * h / g->bin_mm);
+      v.b = (float)(s * h / g->bin_mm);
+      v.c = (float)cb;
+      v.hw = (float)(0.5 * (std::fabs(c) + std::fabs(s)) * h / g->bin_mm + 1e-3);
+      v.cx = v.cy = v.inv_dg = v.pad = 0.0f;
+    }
+  } else {
+    const double dg_ = fan_dgamma(*g);
+    for (int k = 0; k < p->nv; ++k) {
+      double beta = g->angle0_rad + k * g->span_rad / p->nv;
+      for (int b = 0; b < p->nb; ++b) {
+        double gam = (b - cb) * dg_, c, s;
+        snapped_cos_sin(beta + gam + 0.5 * M_PI, &c, &s);
+        rays[(size_t)k * p->nb + b] = make_ray(c, s, -g->dso_mm * std::sin(gam), *g);
+      }
+      ViewInfo& v = views[k];
+      v.a = (float)(g->dso_mm * std::cos(beta) / h);
+      v.b = (float)(g->dso_mm * std::sin(beta) / h);
+      v.c = (float)cb;
+      v.hw = 0.0f;
+      v.cx = (float)(-std::cos(beta));
+      v.cy = (float)(-std::sin(beta));
+      v.inv_dg = (float)(1.0 / dg_);
+      v.pad = 0.0f;
+    }
+  }
+  std::vector<float2> tw((size_t)p->I);
+  for (int t = 0; t < p->I; ++t) {
+    double a = -2.0 * M_PI * t / p->I;
+    tw[t] = make_float2((float)std::cos(a), (float)std::sin(a));
+  }
+
+  hipError_t e;
+  p->rays = nullptr;
+  p->views = nullptr;
+  p->twiddle = nullptr;
+  if ((e = hipMalloc(&p->rays, sizeof(RayLine) * rays.size())) != hipSuccess ||
+      (e = hipMalloc(&p->views, sizeof(ViewInfo) * views.size())) != hipSuccess ||
+      (e = hipMalloc(&p->twiddle, sizeof(float2) * tw.size())) != hipSuccess) {
+    dg_plan_destroy(p);
+    hip_fail(e, "dg_plan_create: hipMalloc");
+    return DG_ERR_NOMEM;
+  }
+  if ((e = hipMemcpy(p->rays, rays.data(), sizeof(RayLine) * rays.size(), hipMemcpyHostToDevice)) !=
+          hipSuccess ||
+      (e = hipMemcpy(p->views, views.data(), sizeof(ViewInfo) * views.size(),
+                     hipMemcpyHostToDevice)) != hipSuccess ||
+      (e = hipMemcpy(p->twiddle, tw.data(), sizeof(float2) * tw.size(), hipMemcpyHostToDevice)) !=
+          hipSuccess) {
+    dg_plan_destroy(p);
+    return hip_fail(e, "dg_plan_create: hipMemcpy");
+  }
+  *out = p;
+  return DG_OK;
+}
+
+extern "C" dg_status dg_plan_destroy(dg_plan* p) {
+  if (!p) return DG_OK;
+  if (p->rays) (void)hipFree(p->rays);
+  if (p->views) (void)hipFree(p->views);
+  if (p->twiddle) (void)hipFree(p->twiddle);
+  delete p;
+  return DG_OK;
+}

@@ -1,0 +1,170 @@
+// Ray-driven projector A and pixel-driven back-projector A^T (Sec. 2.1,
+// eq. linCT) with exact chord-length weights from one shared formula.
+//
+// Projector: one thread per ray.  The ray marches along its major axis; at
+// each major index k it meets at most two pixels across (cross coordinate
+// q(k) = q0 + m k, candidates floor(q) and floor(q) + 1).  Threads of a
+// wavefront hold consecutive bins of one view, so for steep rays they read
+// consecutive columns of one image row.  Flat rays read the transposed copy
+// of the image when one is supplied, which makes their reads consecutive too.
+//
+// Back-projector: one thread per pixel.  For every view it finds the (one to
+// three) bins whose footprint covers the pixel and adds weight * s for each,
+// recomputing the weight with the very same formula and operands as the
+// projector; no atomics, so the result is deterministic.
+#include "dg_internal.h"
+
+namespace dg {
+
+static constexpr int kProjBlock = 256;
+static constexpr int kBpBlockX = 64, kBpBlockY = 4;
+
+__global__ void __launch_bounds__(kProjBlock)
+project_kernel(const RayLine* __restrict__ rays, const float* __restrict__ img,
+               const float* __restrict__ img_t, float* __restrict__ sino, int I, int64_t M) {
+  const int64_t r = (int64_t)blockIdx.x * kProjBlock + threadIdx.x;
+  if (r >= M) return;
+  const RayLine L = rays[r];
+  const bool steep = L.pl < 0.0f;
+  // Pixel (row i, col j).  Steep: major = row, cross = col -> img[k*I + p].
+  // Flat: major = col, cross = row -> img[p*I + k] = img_t[k*I + p].
+  // major_rows: the buffer read is laid out with the major index as its row.
+  const bool major_rows = steep || (img_t != nullptr);
+  const float* base = (steep || img_t == nullptr) ? img : img_t;
+
+  // Major-index range where q(k) lies in (-1, I): candidates exist only there.
+  int k0 = 0, k1 = I - 1;
+  if (L.m != 0.0f) {
+    float ka = (-1.0f - L.q0) / L.m, kb = ((float)I - L.q0) / L.m;
+    float lo = fmaxf(fminf(ka, kb), -2.0f), hi = fminf(fmaxf(ka, kb), (float)I + 1.0f);
+    k0 = max(0, (int)floorf(lo) - 1);
+    k1 = min(I - 1, (int)ceilf(hi) + 1);
+  } else if (!(L.q0 > -1.0f && L.q0 < (float)I)) {
+    k1 = -1;
+  }
+  float acc = 0.0f;
+  for (int k = k0; k <= k1; ++k) {
+    const float q = cross_coord(L, k);
+    const int p0 = (int)floorf(q);
+#pragma unroll
+    for (int d = 0; d < 2; ++d) {
+      const int p = p0 + d;
+      if (p >= 0 && p < I) {
+        const float w = chord_fraction(fabsf(q - (float)p), L.m, L.inv_r);
+        float v;
+        if (major_rows)
+          v = base[(int64_t)k * I + p];
+        else
+          v = base[(int64_t)p * I + k];  // flat ray without a transposed copy
+        acc = __fmaf_rn(w, v, acc);
+      }
+    }
+  }
+  sino[r] = acc * fabsf(L.pl);
+}
+
+__device__ __forceinline__ float ray_weight(const RayLine& L, int i, int j) {
+  const bool steep = L.pl < 0.0f;
+  const int k = steep ? i : j;
+  const int p = steep ? j : i;
+  const float q = cross_coord(L, k);
+  return fabsf(L.pl) * chord_fraction(fabsf(q - (float)p), L.m, L.inv_r);
+}
+
+template <bool kFan>
+__global__ void __launch_bounds__(kBpBlockX* kBpBlockY)
+backproject_kernel(const RayLine* __restrict__ rays, const ViewInfo* __restrict__ views,
+                   const float* __restrict__ sino, float* __restrict__ img, int I, int nv, int nb,
+                   float half_diag) {
+  const int j = blockIdx.x * kBpBlockX + threadIdx.x;
+  const int i = blockIdx.y * kBpBlockY + threadIdx.y;
+  if (i >= I || j >= I) return;
+  const float x = (float)j - 0.5f * (float)(I - 1);
+  const float y = 0.5f * (float)(I - 1) - (float)i;
+  float acc = 0.0f;
+  for (int k = 0; k < nv; ++k) {
+    const ViewInfo v = views[k];
+    float u, hw;
+    if (!kFan) {
+      u = __fmaf_rn(v.a, x, __fmaf_rn(v.b, y, v.c));
+      hw = v.hw;
+    } else {
+      const float dx = x - v.a, dy = y - v.b;
+      const float along = v.cx * dx + v.cy * dy;
+      const float cr = v.cx * dy - v.cy * dx;
+      const float dist = sqrtf(dx * dx + dy * dy);
+      const float gam = atan2f(cr, along);
+      u = __fmaf_rn(gam, v.inv_dg, v.c);
+      hw = asinf(fminf(half_diag / dist, 1.0f)) * v.inv_dg * 1.001f + 1e-3f;
+    }
+    int b0 = (int)ceilf(u - hw), b1 = (int)floorf(u + hw);
+    b0 = max(b0, 0);
+    b1 = min(b1, nb - 1);
+    const int64_t row = (int64_t)k * nb;
+    for (int b = b0; b <= b1; ++b) {
+      const RayLine L = rays[row + b];
+      acc = __fmaf_rn(ray_weight(L, i, j), sino[row + b], acc);
+    }
+  }
+  img[(int64_t)i * I + j] = acc;
+}
+
+__global__ void transpose_kernel(const float* __restrict__ in, float* __restrict__ out, int I) {
+  __shared__ float tile[32][33];
+  const int bx = blockIdx.x * 32, by = blockIdx.y * 32;
+  for (int r = threadIdx.y; r < 32; r += 8) {
+    int i = by + r, j = bx + threadIdx.x;
+    if (i < I && j < I) tile[r][threadIdx.x] = in[(int64_t)i * I + j];
+  }
+  __syncthreads();
+  for (int r = threadIdx.y; r < 32; r += 8) {
+    int i = bx + r, j = by + threadIdx.x;
+    if (i < I && j < I) out[(int64_t)i * I + j] = tile[threadIdx.x][r];
+  }
+}
+
+dg_status launch_transpose(const float* in, float* out, int I, hipStream_t s) {
+  dim3 grid((I + 31) / 32, (I + 31) / 32), block(32, 8);
+  hipLaunchKernelGGL(transpose_kernel, grid, block, 0, s, in, out, I);
+  DG_LAUNCH_CHECK("transpose_kernel");
+  return DG_OK;
+}
+
+dg_status launch_project(const dg_plan* p, const float* img, const float* img_t, float* sino,
+                         hipStream_t s) {
+  unsigned int grid = (unsigned int)((p->M + kProjBlock - 1) / kProjBlock);
+  hipLaunchKernelGGL(project_kernel, dim3(grid), dim3(kProjBlock), 0, s, p->rays, img, img_t,
+                     sino, p->I, p->M);
+  DG_LAUNCH_CHECK("project_kernel");
+  return DG_OK;
+}
+
+dg_status launch_backproject(const dg_plan* p, const float* sino, float* img, hipStream_t s) {
+  dim3 grid((p->I + kBpBlockX - 1) / kBpBlockX, (p->I + kBpBlockY - 1) / kBpBlockY);
+  dim3 block(kBpBlockX, kBpBlockY);
+  if (p->g.kind == DG_GEOM_FAN)
+    hipLaunchKernelGGL(backproject_kernel<true>, grid, block, 0, s, p->rays, p->views, sino, img,
+                       p->I, p->nv, p->nb, (float)p->half_diag_px);
+  else
+    hipLaunchKernelGGL(backproject_kernel<false>, grid, block, 0, s, p->rays, p->views, sino, img,
+                       p->I, p->nv, p->nb, (float)p->half_diag_px);
+  DG_LAUNCH_CHECK("backproject_kernel");
+  return DG_OK;
+}
+
+}  // namespace dg
+
+using namespace dg;
+
+extern "C" dg_status ct_project(const dg_plan* p, const float* img, const float* img_t,
+                                float* sino, void* stream) {
+  DG_ARG_CHECK(p && img && sino, "ct_project: null argument");
+  return launch_project(p, img, img_t, sino, (hipStream_t)stream);
+}
+
+extern "C" dg_status ct_backproject(const dg_plan* p, const float* sino, float* img,
+                                    void* stream) {
+  DG_ARG_CHECK(p && sino && img, "ct_backproject: null argument");
+  DG_ARG_CHECK((const void*)sino != (const void*)img, "ct_backproject: sino and img alias");
+  return launch_backproject(p, sino, img, (hipStream_t)stream);
+}

@@ -1,0 +1,72 @@
+"""Host-side checks of the C ABI: the library loads, exports every entry point the
+header declares, and rejects bad arguments before touching the GPU."""
+import ctypes
+import math
+import os
+import re
+
+import pytest
+
+from paper_1609_04661_amd import api, synth
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def header_functions():
+    txt = open(os.path.join(ROOT, "include", "dgampct.h")).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    names = re.findall(r"^\s*(?:dg_status|size_t|const char\*)\s+(\w+)\s*\(", txt, flags=re.M)
+    return sorted(set(names))
+
+
+def test_library_exports_header_symbols():
+    L = api.load()
+    names = header_functions()
+    assert len(names) >= 13
+    for n in names:
+        assert hasattr(L, n), n
+    assert set(api.EXPORTS) == set(names)
+
+
+def test_plan_create_rejects_bad_geometry():
+    L = api.load()
+    bad = [
+        dict(synth.c1_geometry(), n=4),
+        dict(synth.c1_geometry(), n_views=0),
+        dict(synth.c1_geometry(), pixel_mm=0.0),
+        dict(synth.c1_geometry(), bin_mm=-1.0),
+        dict(synth.c1_geometry(), kind=7),
+        dict(synth.c5_geometry(), dso_mm=100.0),
+        dict(synth.c1_geometry(), span_rad=float("nan")),
+    ]
+    for g in bad:
+        c = api.Geom(**{k: g[k] for k, _ in api.Geom._fields_})
+        h = ctypes.c_void_p()
+        assert L.dg_plan_create(ctypes.byref(c), ctypes.byref(h)) == -1
+        assert L.dg_last_error()
+    assert L.dg_plan_create(None, None) == -1
+
+
+def test_channel_rejects_bad_arguments():
+    L = api.load()
+    w = ctypes.c_void_p(1)
+    assert L.gamp_poisson_out(0, w, w, w, 1e4, 0, w, w, w, None) == -1
+    assert L.gamp_poisson_out(10, w, w, w, -1.0, 0, w, w, w, None) == -1
+    assert L.gamp_poisson_out(10, w, w, w, 1e4, 9, w, w, w, None) == -1
+    assert L.gamp_poisson_out(10, None, w, w, 1e4, 0, w, w, w, None) == -1
+    assert b"mode" in L.dg_last_error() or b"null" in L.dg_last_error()
+
+
+def test_workspace_query_null_plan():
+    L = api.load()
+    assert L.dg_workspace_bytes(None, 0) == 0
+    assert L.dg_channel_workspace_bytes(1000) > 0
+
+
+def test_product_path_has_no_cpu_fallback():
+    # the binding must not import the oracle and must refuse non-CUDA tensors
+    import torch
+    src = open(os.path.join(ROOT, "paper_1609_04661_amd", "api.py")).read()
+    assert "oracle" not in src.replace("not compute", "")
+    with pytest.raises(api.DgError):
+        api._ptr(torch.zeros(4), torch.float32)

@@ -1,0 +1,268 @@
+"""GPU path (through the C ABI) against the FP64 oracle, element by element.
+
+Tolerances:
+  * A / A^T: ||gpu - ref||_2 / ||ref||_2 <= 1e-5 (the projection bound), and
+    every element within 1e-4 of the largest |ref| (FP32 ray geometry).
+  * V^-1 / V: relative L2 <= 1e-5 (FP32 FFT of length <= 1024 has an error
+    of ~ eps32 * log2(I) ~ 1e-6).
+  * channel: |ds| <= 64 eps32 (|s| + (|delta| + |ln w| + |ln tau_p| + |ln I0|
+    + |p|) / tau_p): FP32 rounding of the terms of the mode equation (each
+    of those sizes) divided by its slope; tau_s relative 1e-5.
+  * denoisers: relative L2 <= 1e-5 (Haar), <= 2e-5 (NLM: FP32 exp and sums
+    over 441 offsets); divergence absolute 2e-3 (the difference quotient
+    divides FP32 rounding of D by eps = 1e-3 max|r|).
+  * D-GAMP-CT: PSNR within 0.1 dB of the oracle's on identical inputs.
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import channel as och
+from oracle import denoisers as oden
+from oracle import gamp as ogamp
+from oracle import metrics, precond, radon
+from paper_1609_04661_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+EPS32 = float(np.finfo(np.float32).eps)
+
+
+def cu(a, dtype=torch.float32):
+    return torch.as_tensor(np.ascontiguousarray(a), dtype=dtype).cuda()
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.detach().cpu().double().numpy()
+
+
+def rel_l2(a, b):
+    return float(np.linalg.norm((a - b).ravel()) / max(np.linalg.norm(b.ravel()), 1e-300))
+
+
+GEOMS = {
+    "c1": synth.c1_geometry(),
+    "c2": synth.c2_geometry(),
+    "ragged_parallel": synth.geometry(synth.PARALLEL, 100, 0.8, 37, 141, math.pi, angle0_rad=0.3,
+                                      bin_mm=1.1),
+    "fan_small": synth.geometry(synth.FAN, 128, 0.5, 64, 200, 2 * math.pi, dso_mm=120.0,
+                                ddo_mm=100.0),
+    "c5": synth.c5_geometry(),
+}
+
+
+@pytest.fixture(scope="module")
+def plans(gpu_lib):
+    return {k: gpu_lib.Plan(g) for k, g in GEOMS.items()}
+
+
+def image_for(name, g, seed=11):
+    I = g["n"]
+    if name in ("c1", "c2", "c5"):
+        return synth.ellipse_phantom(I, seed, pixel_mm=g["pixel_mm"], inserts=3 if name == "c5" else 0)
+    return np.random.default_rng(seed).random((I, I))
+
+
+@pytest.mark.parametrize("name", list(GEOMS))
+def test_project_matches_oracle(gpu_lib, plans, name):
+    g = GEOMS[name]
+    R = radon.Radon(g)
+    mu = image_for(name, g)
+    ref = R.project(mu)
+    P = plans[name]
+    img = cu(mu)
+    out = host(gpu_lib.ct_project(P, img))
+    out_t = host(gpu_lib.ct_project(P, img, img.t().contiguous()))
+    for o in (out, out_t):
+        assert rel_l2(o, ref) <= 1e-5, rel_l2(o, ref)
+        assert np.max(np.abs(o - ref)) <= 1e-4 * np.max(np.abs(ref))
+
+
+@pytest.mark.parametrize("name", list(GEOMS))
+def test_backproject_matches_oracle(gpu_lib, plans, name):
+    g = GEOMS[name]
+    R = radon.Radon(g)
+    s = np.random.default_rng(5).standard_normal((g["n_views"], g["n_bins"]))
+    ref = R.backproject(s)
+    out = host(gpu_lib.ct_backproject(plans[name], cu(s)))
+    assert rel_l2(out, ref) <= 1e-5, rel_l2(out, ref)
+    assert np.max(np.abs(out - ref)) <= 1e-4 * np.max(np.abs(ref))
+
+
+@pytest.mark.parametrize("name", ["c1", "c2", "fan_small"])
+def test_gpu_adjoint_identity(gpu_lib, plans, name):
+    g = GEOMS[name]
+    rng = np.random.default_rng(9)
+    mu = rng.standard_normal((g["n"], g["n"]))
+    s = rng.standard_normal((g["n_views"], g["n_bins"]))
+    Amu = host(gpu_lib.ct_project(plans[name], cu(mu)))
+    Ats = host(gpu_lib.ct_backproject(plans[name], cu(s)))
+    lhs = float(np.sum(Amu * s.astype(np.float32)))
+    rhs = float(np.sum(mu.astype(np.float32) * Ats))
+    assert abs(lhs - rhs) <= 1e-5 * np.linalg.norm(Amu) * np.linalg.norm(s)
+
+
+def test_projector_edge_rays_half_weight(gpu_lib):
+    # 0 and 90 degree rays of an even grid with an odd bin count lie on pixel edges
+    g = synth.geometry(synth.PARALLEL, 16, 1.0, 2, 23, math.pi)
+    P = gpu_lib.Plan(g)
+    for i, j in [(0, 0), (7, 8), (15, 3)]:
+        e = np.zeros((16, 16))
+        e[i, j] = 1.0
+        out = host(gpu_lib.ct_project(P, cu(e)))
+        ref = radon.Radon(g).project(e)
+        assert np.array_equal(out, ref.astype(np.float32).astype(np.float64)), (i, j)
+        assert sorted(set(np.round(out[out > 0], 12))) == [0.5]
+
+
+@pytest.mark.parametrize("I", [64, 96, 384, 512])
+def test_precondition_matches_oracle(gpu_lib, I):
+    g = synth.geometry(synth.PARALLEL, I, 1.0, 4, I + 1, math.pi)
+    P = gpu_lib.Plan(g)
+    x = np.random.default_rng(I).standard_normal((I, I))
+    vin = host(gpu_lib.ct_precondition(P, 1, cu(x)))
+    v = host(gpu_lib.ct_precondition(P, -1, cu(x)))
+    assert rel_l2(vin, precond.apply_Vinv(x)) <= 1e-5
+    assert rel_l2(v, precond.apply_V(x)) <= 1e-5
+    back = host(gpu_lib.ct_precondition(P, -1, cu(vin)))
+    assert rel_l2(back, x) <= 1e-5
+
+
+def channel_cases(n=20000, seed=3):
+    rng = np.random.default_rng(seed)
+    out = []
+    for tau_p in (1e-4, 1e-2, 0.5, 20.0, 400.0):
+        for i0 in (5e3, 1e5):
+            zt = rng.uniform(0, 7, n)
+            y = rng.poisson(i0 * np.exp(-zt)).astype(np.float64)
+            p = (zt + rng.normal(0, math.sqrt(min(tau_p, 4.0)), n)).astype(np.float32).astype(np.float64)
+            out.append((p, y, tau_p, i0))
+    return out
+
+
+@pytest.mark.parametrize("mode", [0, 1])
+def test_channel_matches_oracle(gpu_lib, mode):
+    for p, y, tau_p, i0 in channel_cases():
+        s_ref, ts_ref = och.poisson_out(p, y, tau_p, i0, kind=mode)
+        s, ts = gpu_lib.gamp_poisson_out(cu(p), cu(y), cu([tau_p], torch.float64), i0, mode)
+        s, ts = host(s), float(host(ts)[0])
+        z0 = och.mode(p, y, tau_p, i0)
+        delta = z0 - p
+        w = tau_p * i0 * np.exp(-z0)
+        scale = np.abs(s_ref) + (np.abs(delta) + np.abs(np.log(w)) + abs(math.log(tau_p)) +
+                                 math.log(i0) + np.abs(p)) / tau_p
+        bad = np.abs(s - s_ref) > 64 * EPS32 * scale
+        assert not bad.any(), (tau_p, i0, np.max(np.abs(s - s_ref) / scale))
+        assert abs(ts - ts_ref) <= 1e-5 * abs(ts_ref), (tau_p, i0, ts, ts_ref)
+
+
+def test_channel_ragged_and_single(gpu_lib):
+    for m in (1, 255, 257, 100003):
+        rng = np.random.default_rng(m)
+        zt = rng.uniform(0, 5, m)
+        y = rng.poisson(1e4 * np.exp(-zt)).astype(np.float64)
+        p = zt.astype(np.float32).astype(np.float64)
+        s_ref, ts_ref = och.poisson_out(p, y, 0.3, 1e4)
+        s, ts = gpu_lib.gamp_poisson_out(cu(p), cu(y), cu([0.3], torch.float64), 1e4)
+        assert abs(float(host(ts)[0]) - ts_ref) <= 1e-5 * ts_ref
+        assert rel_l2(host(s), s_ref) <= 1e-5
+
+
+@pytest.mark.parametrize("I", [64, 512])
+def test_haar_matches_oracle(gpu_lib, I):
+    g = synth.geometry(synth.PARALLEL, I, 1.0, 4, I + 1, math.pi)
+    P = gpu_lib.Plan(g)
+    r = precond.apply_V(synth.ellipse_phantom(I, 4)) + 0.05 * np.random.default_rng(1).standard_normal((I, I))
+    r32 = r.astype(np.float32).astype(np.float64)
+    tau = 0.0025
+    x, div = gpu_lib.denoise(P, gpu_lib.DEN_HAAR, gpu_lib.make_params(gpu_lib.DEN_HAAR, alpha=1.5),
+                             cu(r32), cu([tau], torch.float64), probe_seed=77, iteration=3)
+    x_ref = oden.haar_soft(r32, tau, 1.5)
+    assert rel_l2(host(x), x_ref) <= 1e-5
+    div_ref, _ = oden.mc_divergence(oden.HAAR, r32, tau, dict(alpha=1.5), x_ref, 77, 3)
+    assert abs(float(host(div)[0]) - div_ref) <= 2e-3
+
+
+@pytest.mark.parametrize("I", [64, 100])
+def test_nlm_matches_oracle(gpu_lib, I):
+    g = synth.geometry(synth.PARALLEL, I, 1.0, 4, I + 1, math.pi)
+    P = gpu_lib.Plan(g)
+    r = synth.ellipse_phantom(I, 6) + 0.004 * np.random.default_rng(2).standard_normal((I, I))
+    r32 = r.astype(np.float32).astype(np.float64)
+    tau = 1.6e-5
+    x, div = gpu_lib.denoise(P, gpu_lib.DEN_NLM, gpu_lib.make_params(gpu_lib.DEN_NLM),
+                             cu(r32), cu([tau], torch.float64), probe_seed=5, iteration=1)
+    x_ref = oden.nlm(r32, tau)
+    assert rel_l2(host(x), x_ref) <= 2e-5, rel_l2(host(x), x_ref)
+    div_ref, _ = oden.mc_divergence(oden.NLM, r32, tau, {}, x_ref, 5, 1)
+    assert abs(float(host(div)[0]) - div_ref) <= 2e-3, (float(host(div)[0]), div_ref)
+
+
+def test_fro2_hutchinson_matches_oracle(gpu_lib, plans):
+    g = GEOMS["c1"]
+    ref = ogamp.fro2_hutchinson(radon.Radon(g), 16, 2024)
+    out = float(host(gpu_lib.dg_fro2_hutchinson(plans["c1"], 16, 2024))[0])
+    assert abs(out - ref) <= 1e-5 * ref
+
+
+def c1_inputs():
+    g = GEOMS["c1"]
+    R = radon.Radon(g)
+    mu = synth.ellipse_phantom(64, 1001)
+    y = synth.poisson_counts(R.project(mu), 1e4, 1001)
+    fro2 = ogamp.fro2_exact_dense(R.dense(), 64)
+    return g, R, mu, y, fro2
+
+
+def run_gpu_dgamp(gpu_lib, plan, y, fro2, i0, T, kind, params, seed, eta, tau_x0=1.0):
+    st = gpu_lib.DgampState(plan, tau_x0)
+    mu = torch.empty((plan.I, plan.I), dtype=torch.float32, device="cuda")
+    log = torch.zeros(T * gpu_lib.LOG_STRIDE, dtype=torch.float64, device="cuda")
+    gpu_lib.dgamp_iterate(plan, cu(y), st, T, fro2, i0, kind, params, probe_seed=seed,
+                          eta_x=eta, eta_s=eta, mu_out=mu, log=log)
+    return host(mu), host(log).reshape(T, gpu_lib.LOG_STRIDE), st
+
+
+def test_dgamp_c1_psnr_matches_oracle(gpu_lib, plans):
+    g, R, mu, y, fro2 = c1_inputs()
+    T, eta, seed = 20, 0.5, 31
+    ref_mu, ref_log, _ = ogamp.dgamp_ct(R, y, 1e4, fro2, T, oden.HAAR, dict(alpha=1.5), seed,
+                                        eta_x=eta, eta_s=eta)
+    out_mu, log, st = run_gpu_dgamp(gpu_lib, plans["c1"], y, fro2, 1e4, T, gpu_lib.DEN_HAAR,
+                                    gpu_lib.make_params(gpu_lib.DEN_HAAR, alpha=1.5), seed, eta)
+    assert float(host(st.scal)[gpu_lib.S_STATUS]) == 0.0
+    p_ref, p_gpu = metrics.psnr(ref_mu, mu), metrics.psnr(out_mu, mu)
+    assert abs(p_gpu - p_ref) <= 0.1, (p_gpu, p_ref)
+    # the variance recursion tracks the oracle's closely in the first iterations
+    for t in range(3):
+        for k, name in enumerate(("tau_p", "tau_s", "tau_r")):
+            assert abs(log[t, k] - ref_log[t][name]) <= 1e-3 * abs(ref_log[t][name]), (t, name)
+
+
+def test_dgamp_deterministic(gpu_lib, plans):
+    g, R, mu, y, fro2 = c1_inputs()
+    a, la, _ = run_gpu_dgamp(gpu_lib, plans["c1"], y, fro2, 1e4, 5, gpu_lib.DEN_HAAR,
+                             gpu_lib.make_params(gpu_lib.DEN_HAAR), 3, 0.5)
+    b, lb, _ = run_gpu_dgamp(gpu_lib, plans["c1"], y, fro2, 1e4, 5, gpu_lib.DEN_HAAR,
+                             gpu_lib.make_params(gpu_lib.DEN_HAAR), 3, 0.5)
+    assert np.array_equal(a, b) and np.array_equal(la, lb)
+
+
+def test_dgamp_c2_first_iterations_match_oracle(gpu_lib, plans):
+    g = GEOMS["c2"]
+    R = radon.Radon(g)
+    mu = synth.ellipse_phantom(512, 1002)
+    y = synth.poisson_counts(R.project(mu), 1e5, 1002)
+    fro2 = ogamp.fro2_hutchinson(R, 4, 99)
+    T, eta, seed = 2, 0.5, 8
+    ref_mu, ref_log, _ = ogamp.dgamp_ct(R, y, 1e5, fro2, T, oden.NLM, {}, seed, eta_x=eta,
+                                        eta_s=eta)
+    out_mu, log, _ = run_gpu_dgamp(gpu_lib, plans["c2"], y, fro2, 1e5, T, gpu_lib.DEN_NLM,
+                                   gpu_lib.make_params(gpu_lib.DEN_NLM), seed, eta)
+    assert abs(metrics.psnr(out_mu, mu) - metrics.psnr(ref_mu, mu)) <= 0.1
+    assert rel_l2(out_mu, ref_mu) <= 1e-3
+    for t in range(T):
+        assert abs(log[t, 2] - ref_log[t]["tau_r"]) <= 1e-4 * ref_log[t]["tau_r"]
