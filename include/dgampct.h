@@ -186,7 +186,13 @@ typedef struct dgamp_opts {
   double eta_x, eta_s;     /* damping, 1 = Algorithm 1 verbatim               */
   int32_t onsager;         /* 0: p = z (no Onsager term)                      */
   int32_t channel_mode;    /* DG_CHANNEL_*                                    */
+  void** phase_events;     /* NULL, or a host array of n_iter*(DG_NPHASES+1)
+                              hipEvent_t recorded on `stream` before the first
+                              and after each phase of every iteration:
+                              V^-1 x | A | channel | A^T | V^-1 g + r update |
+                              denoiser | divergence + tau_x                   */
 } dgamp_opts;
+#define DG_NPHASES 7
 typedef struct dgamp_state {
   float* x;      /* device, N: x^t                     */
   float* s;      /* device, M: s^{t-1}                 */

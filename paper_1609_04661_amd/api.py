@@ -22,6 +22,8 @@ NSCAL = 16
 S_TAU_X, S_TAU_P, S_TAU_S, S_TAU_R, S_DIV, S_EPS, S_STATUS, S_CLAMPS = range(8)
 LOG_STRIDE = 8
 LOG_FIELDS = ("tau_p", "tau_s", "tau_r", "div", "tau_x", "eps", "status", "clamps")
+NPHASES = 7
+PHASES = ("precond_x", "project", "channel", "backproject", "precond_g_update", "denoise", "div")
 
 EXPORTS = ("dg_plan_create", "dg_plan_destroy", "dg_workspace_bytes", "dg_channel_workspace_bytes",
            "dg_last_error", "ct_project", "ct_backproject", "ct_precondition", "gamp_poisson_out",
@@ -58,7 +60,8 @@ class DgampOpts(ctypes.Structure):
                 ("den_params", ctypes.c_void_p), ("fro2", ctypes.c_double), ("i0", ctypes.c_double),
                 ("probe_seed", ctypes.c_uint64), ("eps_rel", ctypes.c_double),
                 ("eta_x", ctypes.c_double), ("eta_s", ctypes.c_double),
-                ("onsager", ctypes.c_int32), ("channel_mode", ctypes.c_int32)]
+                ("onsager", ctypes.c_int32), ("channel_mode", ctypes.c_int32),
+                ("phase_events", ctypes.c_void_p)]
 
 
 class DgampStateC(ctypes.Structure):
@@ -250,12 +253,14 @@ class DgampState:
 
 def dgamp_iterate(plan, y, state, n_iter, fro2, i0, den_kind, den_params, probe_seed=0,
                   eps_rel=1e-3, eta_x=1.0, eta_s=1.0, onsager=True, channel_mode=CHANNEL_LAPLACE,
-                  mu_out=None, log=None, work=None):
+                  mu_out=None, log=None, work=None, phase_events=None):
+    """phase_events: optional ctypes array of n_iter * (NPHASES + 1) hipEvent_t handles."""
     opts = DgampOpts(n_iter=int(n_iter), den_kind=int(den_kind),
                      den_params=ctypes.cast(ctypes.pointer(den_params), ctypes.c_void_p),
                      fro2=float(fro2), i0=float(i0), probe_seed=int(probe_seed),
                      eps_rel=float(eps_rel), eta_x=float(eta_x), eta_s=float(eta_s),
-                     onsager=1 if onsager else 0, channel_mode=int(channel_mode))
+                     onsager=1 if onsager else 0, channel_mode=int(channel_mode),
+                     phase_events=ctypes.cast(phase_events, ctypes.c_void_p) if phase_events is not None else None)
     if work is None:
         work = plan.workspace(OP_DGAMP)
     if log is not None and log.numel() < n_iter * LOG_STRIDE:

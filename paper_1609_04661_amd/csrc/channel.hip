@@ -81,10 +81,8 @@ __global__ void __launch_bounds__(kChanBlock)
 channel_kernel(int64_t M, const float* __restrict__ zp, const float* __restrict__ y,
                float* __restrict__ s_io, float* __restrict__ s_out, const double* tau_p_ptr,
                double* scal, double* tau_s_out, double i0, int mode, double fro2, double N,
-               double eta_s, int onsager, int t, double* __restrict__ partials,
-               unsigned int* counter) {
+               double eta_s, int onsager, int t, double* __restrict__ partials) {
   __shared__ double red[kChanBlock / 64];
-  __shared__ int flag;
   double tau_p_d;
   if (kFused) {
     if (scal[DG_S_STATUS] != 0.0) return;
@@ -116,23 +114,30 @@ channel_kernel(int64_t M, const float* __restrict__ zp, const float* __restrict_
   }
   double bs = block_sum(acc, red);
   if (threadIdx.x == 0) partials[blockIdx.x] = bs;
-  if (last_block(counter, &flag)) {
-    double tot = 0.0;
-    if (threadIdx.x == 0) {
-      for (unsigned int b = 0; b < gridDim.x; ++b) tot += partials[b];
-      double tau_s = tot / ((double)M * tau_p_d);
-      if (kFused) {
-        if (t > 0) tau_s = eta_s * tau_s + (1.0 - eta_s) * scal[DG_S_TAU_S];
-        double tau_r = N / (fro2 * tau_s);
-        scal[DG_S_TAU_P] = tau_p_d;
-        scal[DG_S_TAU_S] = tau_s;
-        scal[DG_S_TAU_R] = tau_r;
-        if (!(tau_s > 0.0) || !isfinite(tau_s) || !(tau_r > 0.0) || !isfinite(tau_r))
-          scal[DG_S_STATUS] = (double)(t + 1);
-      } else {
-        *tau_s_out = tau_s;
-      }
-      *counter = 0u;
+}
+
+// tau_s (and in the iteration: its damping, tau_p, tau_r, status) from the
+// per-block partial sums.
+template <bool kFused>
+__global__ void __launch_bounds__(256)
+channel_finish(const double* __restrict__ partials, int nblk, int64_t M, const double* tau_p_ptr,
+               double* scal, double* tau_s_out, double fro2, double N, double eta_s, int t) {
+  __shared__ double red[4];
+  if (kFused && scal[DG_S_STATUS] != 0.0) return;
+  const double tot = finish_sum(partials, nblk, red);
+  if (threadIdx.x == 0) {
+    const double tau_p = kFused ? fro2 * scal[DG_S_TAU_X] / (double)M : *tau_p_ptr;
+    double tau_s = tot / ((double)M * tau_p);
+    if (kFused) {
+      if (t > 0) tau_s = eta_s * tau_s + (1.0 - eta_s) * scal[DG_S_TAU_S];
+      const double tau_r = N / (fro2 * tau_s);
+      scal[DG_S_TAU_P] = tau_p;
+      scal[DG_S_TAU_S] = tau_s;
+      scal[DG_S_TAU_R] = tau_r;
+      if (!(tau_s > 0.0) || !isfinite(tau_s) || !(tau_r > 0.0) || !isfinite(tau_r))
+        scal[DG_S_STATUS] = (double)(t + 1);
+    } else {
+      *tau_s_out = tau_s;
     }
   }
 }
@@ -141,12 +146,14 @@ unsigned int channel_grid(int64_t M) { return grid_for(M, kChanBlock, kChanMaxBl
 
 dg_status launch_channel_fused(int64_t M, const float* z, const float* y, float* s, double* scal,
                                double i0, int mode, double fro2, double N, double eta_s,
-                               int onsager, int t, double* partials, unsigned int* counter,
-                               hipStream_t st) {
-  hipLaunchKernelGGL(channel_kernel<true>, dim3(channel_grid(M)), dim3(kChanBlock), 0, st, M, z, y,
-                     s, nullptr, nullptr, scal, nullptr, i0, mode, fro2, N, eta_s, onsager, t,
-                     partials, counter);
+                               int onsager, int t, double* partials, hipStream_t st) {
+  const unsigned int g = channel_grid(M);
+  hipLaunchKernelGGL(channel_kernel<true>, dim3(g), dim3(kChanBlock), 0, st, M, z, y, s, nullptr,
+                     nullptr, scal, nullptr, i0, mode, fro2, N, eta_s, onsager, t, partials);
   DG_LAUNCH_CHECK("channel_kernel<fused>");
+  hipLaunchKernelGGL(channel_finish<true>, dim3(1), dim3(256), 0, st, partials, (int)g, M, nullptr,
+                     scal, nullptr, fro2, N, eta_s, t);
+  DG_LAUNCH_CHECK("channel_finish<fused>");
   return DG_OK;
 }
 
@@ -179,13 +186,13 @@ extern "C" dg_status gamp_poisson_out(int64_t m, const float* p, const float* y,
   DG_ARG_CHECK(mode == DG_CHANNEL_LAPLACE || mode == DG_CHANNEL_MODE_ONLY,
                "gamp_poisson_out: unknown mode");
   hipStream_t st = (hipStream_t)stream;
-  unsigned int* counter = (unsigned int*)work;
   double* partials = (double*)((char*)work + 256);
-  dg_status rc = launch_zero_u32(counter, 1, st);
-  if (rc != DG_OK) return rc;
-  hipLaunchKernelGGL(channel_kernel<false>, dim3(channel_grid(m)), dim3(kChanBlock), 0, st, m, p,
-                     y, nullptr, s_out, tau_p, nullptr, tau_s_out, i0, mode, 0.0, 0.0, 1.0, 0, 0,
-                     partials, counter);
+  const unsigned int g = channel_grid(m);
+  hipLaunchKernelGGL(channel_kernel<false>, dim3(g), dim3(kChanBlock), 0, st, m, p, y, nullptr,
+                     s_out, tau_p, nullptr, tau_s_out, i0, mode, 0.0, 0.0, 1.0, 0, 0, partials);
   DG_LAUNCH_CHECK("channel_kernel");
+  hipLaunchKernelGGL(channel_finish<false>, dim3(1), dim3(256), 0, st, partials, (int)g, m, tau_p,
+                     nullptr, tau_s_out, 0.0, 0.0, 1.0, 0);
+  DG_LAUNCH_CHECK("channel_finish");
   return DG_OK;
 }

@@ -3,11 +3,9 @@
 // input r + eps b in one launch (blockIdx.z selects the image); the probe
 // b_i = +-1 comes from a counter hash, so it is never stored.
 //
-//  * Non-local means: 16 x 16 output tile per workgroup, the tile plus the
-//    search and patch halos staged in LDS (half-sample symmetric borders).
-//    For each search offset the squared differences over the tile plus the
-//    patch halo go to LDS, are box-summed separably (rows, then columns), and
-//    turned into one weight per output pixel.
+//  * Non-local means: 32 x 32 output tile per workgroup staged in LDS with
+//    its halos (half-sample symmetric borders); register-blocked patch
+//    distances with sliding box sums (see nlm_kernel).
 //  * Haar soft threshold: the orthonormal 2D Haar pyramid with J levels is
 //    local to 2^J x 2^J blocks, so each block is transformed, thresholded and
 //    inverted in LDS by one workgroup.
@@ -22,10 +20,10 @@ namespace dg {
 
 dg_status launch_zero_u32(unsigned int* p, int n, hipStream_t st);
 
-static constexpr int kTile = 16;
 static constexpr int kMaxP = 3, kMaxS = 10;
-static constexpr int kRegion = kTile + 2 * (kMaxS + kMaxP);  // 42
-static constexpr int kDiff = kTile + 2 * kMaxP;              // 22
+static constexpr int kNlmTile = 32;
+static constexpr int kNlmRegion = kNlmTile + 2 * (kMaxS + kMaxP);  // 58
+static constexpr int kNlmPitch = kNlmRegion + 1;
 static constexpr int kRedBlock = 256;
 static constexpr int kRedMaxBlocks = 1024;
 static constexpr int kHaarPer = 16;  // (128/2)^2 blocks / 256 threads
@@ -40,66 +38,129 @@ __device__ __forceinline__ int reflect_idx(int k, int I) {
   return min(max(k, 0), I - 1);
 }
 
-__global__ void __launch_bounds__(kTile* kTile)
+// Non-local means, register-blocked.  A workgroup owns a 32 x 32 output
+// tile and stages the tile plus its search and patch halos in LDS.  Each of
+// its 4 wavefronts takes every 4th search offset; each thread owns a 2-wide,
+// 8-tall block of outputs and keeps the (8 + 2P) x (2 + 2P) input pixels its
+// patches cover in registers.  Per offset it reads the shifted region row by
+// row from LDS, forms the squared differences, box-sums them horizontally and
+// then vertically with sliding sums (all in registers, no barrier), and turns
+// each sum into a weight.  The four wavefronts' partial sums are added in a
+// fixed order at the end.
+template <int P>
+__global__ void __launch_bounds__(256)
 nlm_kernel(const float* __restrict__ r, float* __restrict__ out0, float* __restrict__ out1, int I,
-           int P, int S, const double* __restrict__ tau_r_ptr, float hfac,
+           int S, const double* __restrict__ tau_r_ptr, float hfac,
            const double* __restrict__ eps_ptr, uint64_t seed, int iter) {
-  __shared__ float R[kRegion * kRegion];
-  __shared__ float D[kDiff * kDiff];
-  __shared__ float H[kDiff * kTile];
+  constexpr int BX = 2, BY = 8;
+  constexpr int WX = BX + 2 * P, WY = BY + 2 * P;
+  __shared__ float R[kNlmRegion * kNlmPitch];
+  __shared__ float red[4][64][2 * BX * BY];
   const int img = blockIdx.z;
   float* out = img ? out1 : out0;
-  const int ty0 = blockIdx.y * kTile, tx0 = blockIdx.x * kTile;
-  const int tx = threadIdx.x, ty = threadIdx.y, tid = ty * kTile + tx;
-  const int H0 = S + P;             // halo
-  const int WR = kTile + 2 * H0;    // region width
-  const int WD = kTile + 2 * P;     // diff width
+  const int ty0 = blockIdx.y * kNlmTile, tx0 = blockIdx.x * kNlmTile;
+  const int H0 = S + P;
+  const int WR = kNlmTile + 2 * H0;
   const float eps = img ? (float)(*eps_ptr) : 0.0f;
-  for (int e = tid; e < WR * WR; e += kTile * kTile) {
+  for (int e = threadIdx.x; e < WR * WR; e += blockDim.x) {
     const int ri = e / WR, rj = e % WR;
     const int gi = reflect_idx(ty0 - H0 + ri, I), gj = reflect_idx(tx0 - H0 + rj, I);
     const int64_t gidx = (int64_t)gi * I + gj;
     float v = r[gidx];
     if (img) v = __fmaf_rn(eps, probe_sign(seed, iter, (uint64_t)gidx), v);
-    R[ri * kRegion + rj] = v;
+    R[ri * kNlmPitch + rj] = v;
   }
   __syncthreads();
+  const int lane = threadIdx.x & 63, g = threadIdx.x >> 6;
+  const int ox0 = (lane & 15) * BX, oy0 = (lane >> 4) * BY;  // tile-relative block origin
   const double tau_r = *tau_r_ptr;
+  if (!(tau_r > 0.0)) {  // sigma = 0: identity
+    if (g == 0)
+      for (int a = 0; a < BY; ++a)
+        for (int c = 0; c < BX; ++c) {
+          const int gy = ty0 + oy0 + a, gx = tx0 + ox0 + c;
+          if (gy < I && gx < I)
+            out[(int64_t)gy * I + gx] = R[(H0 + oy0 + a) * kNlmPitch + H0 + ox0 + c];
+        }
+    return;
+  }
   const float sig2 = (float)tau_r;
   const float inv_h2 = 1.0f / (hfac * hfac * sig2);
   const float inv_np = 1.0f / (float)((2 * P + 1) * (2 * P + 1));
-  const bool active = (ty0 + ty < I) && (tx0 + tx < I);
-  float wsum = 0.0f, acc = 0.0f;
-  if (!(tau_r > 0.0)) {  // sigma = 0: identity
-    if (active) out[(int64_t)(ty0 + ty) * I + tx0 + tx] = R[(H0 + ty) * kRegion + H0 + tx];
-    return;
-  }
-  for (int oi = -S; oi <= S; ++oi) {
-    for (int oj = -S; oj <= S; ++oj) {
-      for (int e = tid; e < WD * WD; e += kTile * kTile) {
-        const int a = e / WD, c = e % WD;
-        const float u = R[(S + a) * kRegion + S + c];
-        const float v = R[(S + a + oi) * kRegion + S + c + oj];
-        const float d = u - v;
-        D[a * kDiff + c] = d * d;
+  const float two_s2 = 2.0f * sig2;
+  float own[WY][WX];
+#pragma unroll
+  for (int a = 0; a < WY; ++a)
+#pragma unroll
+    for (int c = 0; c < WX; ++c) own[a][c] = R[(S + oy0 + a) * kNlmPitch + S + ox0 + c];
+  float wsum[BY][BX], acc[BY][BX];
+#pragma unroll
+  for (int a = 0; a < BY; ++a)
+#pragma unroll
+    for (int c = 0; c < BX; ++c) wsum[a][c] = acc[a][c] = 0.0f;
+  const int nside = 2 * S + 1, noff = nside * nside;
+  for (int oidx = g; oidx < noff; oidx += 4) {
+    const int oi = oidx / nside - S, oj = oidx % nside - S;
+    float h[WY][BX];
+    float cen[BY][BX];
+#pragma unroll
+    for (int a = 0; a < WY; ++a) {
+      const float* row = R + (S + oy0 + a + oi) * kNlmPitch + S + ox0 + oj;
+      float d[WX];
+#pragma unroll
+      for (int c = 0; c < WX; ++c) {
+        const float v = row[c];
+        const float dd = own[a][c] - v;
+        d[c] = dd * dd;
+        if (a >= P && a < P + BY && c >= P && c < P + BX) cen[a - P][c - P] = v;
       }
-      __syncthreads();
-      for (int e = tid; e < WD * kTile; e += kTile * kTile) {
-        const int a = e / kTile, c = e % kTile;
-        float h = 0.0f;
-        for (int q = 0; q <= 2 * P; ++q) h += D[a * kDiff + c + q];
-        H[a * kTile + c] = h;
+      float sacc = 0.0f;
+#pragma unroll
+      for (int q = 0; q <= 2 * P; ++q) sacc += d[q];
+      h[a][0] = sacc;
+#pragma unroll
+      for (int c = 1; c < BX; ++c) {
+        sacc += d[c + 2 * P] - d[c - 1];
+        h[a][c] = sacc;
       }
-      __syncthreads();
-      float b = 0.0f;
-      for (int q = 0; q <= 2 * P; ++q) b += H[(ty + q) * kTile + tx];
-      const float d2 = b * inv_np;
-      const float w = __expf(-fmaxf(d2 - 2.0f * sig2, 0.0f) * inv_h2);
-      wsum += w;
-      acc = __fmaf_rn(w, R[(H0 + ty + oi) * kRegion + H0 + tx + oj], acc);
+    }
+#pragma unroll
+    for (int c = 0; c < BX; ++c) {
+      float v = 0.0f;
+#pragma unroll
+      for (int q = 0; q <= 2 * P; ++q) v += h[q][c];
+#pragma unroll
+      for (int a = 0; a < BY; ++a) {
+        if (a > 0) v += h[a + 2 * P][c] - h[a - 1][c];
+        const float arg = fmaxf(__fmaf_rn(v, inv_np, -two_s2), 0.0f) * inv_h2;
+        const float w = __expf(-arg);
+        wsum[a][c] += w;
+        acc[a][c] = __fmaf_rn(w, cen[a][c], acc[a][c]);
+      }
     }
   }
-  if (active) out[(int64_t)(ty0 + ty) * I + tx0 + tx] = acc / wsum;
+  // add the four wavefronts' partial sums in a fixed order
+#pragma unroll
+  for (int a = 0; a < BY; ++a)
+#pragma unroll
+    for (int c = 0; c < BX; ++c) {
+      red[g][lane][2 * (a * BX + c)] = wsum[a][c];
+      red[g][lane][2 * (a * BX + c) + 1] = acc[a][c];
+    }
+  __syncthreads();
+  // every thread finalises 4 of its block's 16 outputs: thread (g, lane) takes
+  // outputs k = g, g+4, g+8, g+12 of block `lane`
+  for (int k = g; k < BX * BY; k += 4) {
+    float ws = 0.0f, ac = 0.0f;
+#pragma unroll
+    for (int gg = 0; gg < 4; ++gg) {
+      ws += red[gg][lane][2 * k];
+      ac += red[gg][lane][2 * k + 1];
+    }
+    const int a = k / BX, c = k % BX;
+    const int gy = ty0 + oy0 + a, gx = tx0 + ox0 + c;
+    if (gy < I && gx < I) out[(int64_t)gy * I + gx] = ac / ws;
+  }
 }
 
 // Haar: one workgroup per B x B block (B = 2^J), dynamic LDS of B*B floats.
@@ -202,26 +263,14 @@ haar_kernel(const float* __restrict__ r, float* __restrict__ out0, float* __rest
 
 // eps = max(eps_rel * max|r|, 1e-12) into *eps_out.
 __global__ void __launch_bounds__(kRedBlock)
-absmax_kernel(const float* __restrict__ r, int64_t N, double eps_rel, double* eps_out,
-              float* __restrict__ partials, unsigned int* counter) {
+absmax_kernel(const float* __restrict__ r, int64_t N, float* __restrict__ partials) {
   __shared__ float red[kRedBlock / 64];
-  __shared__ int flag;
   float m = 0.0f;
   for (int64_t k = (int64_t)blockIdx.x * kRedBlock + threadIdx.x; k < N;
        k += (int64_t)gridDim.x * kRedBlock)
     m = fmaxf(m, fabsf(r[k]));
   float bm = block_max(m, red);
   if (threadIdx.x == 0) partials[blockIdx.x] = bm;
-  if (last_block(counter, &flag)) {
-    float gm = 0.0f;
-    for (int k = threadIdx.x; k < (int)gridDim.x; k += blockDim.x) gm = fmaxf(gm, partials[k]);
-    gm = block_max(gm, red);
-    if (threadIdx.x == 0) {
-      double e = eps_rel * (double)gm;
-      *eps_out = e > 1e-12 ? e : 1e-12;
-      *counter = 0u;
-    }
-  }
 }
 
 // Divergence and (inside the iteration) the tau_x update and damping of x.
@@ -231,9 +280,8 @@ __global__ void __launch_bounds__(kRedBlock)
 div_kernel(int64_t N, const float* __restrict__ xden, const float* __restrict__ xpert,
            float* __restrict__ x, const double* __restrict__ eps_ptr, double* div_out,
            double* scal, int mode, uint64_t seed, int iter, double eta_x, int t,
-           double* __restrict__ partials, unsigned int* counter) {
+           double* __restrict__ partials) {
   __shared__ double red[kRedBlock / 64];
-  __shared__ int flag;
   if (mode == 1 && scal[DG_S_STATUS] != 0.0) return;
   const float eta = (float)eta_x;
   double acc = 0.0;
@@ -246,23 +294,26 @@ div_kernel(int64_t N, const float* __restrict__ xden, const float* __restrict__ 
   }
   double bs = block_sum(acc, red);
   if (threadIdx.x == 0) partials[blockIdx.x] = bs;
-  if (last_block(counter, &flag)) {
-    if (threadIdx.x == 0) {
-      double tot = 0.0;
-      for (unsigned int b = 0; b < gridDim.x; ++b) tot += partials[b];
-      const double div = tot / ((double)N * (*eps_ptr));
-      if (mode == 0) {
-        *div_out = div;
-      } else {
-        const double tau_r = scal[DG_S_TAU_R];
-        double tau_x = div > 0.0 ? tau_r * div : 1e-12 * tau_r;
-        if (!(div > 0.0)) scal[DG_S_CLAMPS] += 1.0;
-        if (t > 0) tau_x = eta_x * tau_x + (1.0 - eta_x) * scal[DG_S_TAU_X];
-        scal[DG_S_DIV] = div;
-        scal[DG_S_TAU_X] = tau_x;
-        if (!(tau_x > 0.0) || !isfinite(tau_x)) scal[DG_S_STATUS] = (double)(t + 1);
-      }
-      *counter = 0u;
+}
+
+__global__ void __launch_bounds__(256)
+div_finish(const double* __restrict__ partials, int nblk, int64_t N, const double* eps_ptr,
+           double* div_out, double* scal, int mode, double eta_x, int t) {
+  __shared__ double red[4];
+  if (mode == 1 && scal[DG_S_STATUS] != 0.0) return;
+  const double tot = finish_sum(partials, nblk, red);
+  if (threadIdx.x == 0) {
+    const double div = tot / ((double)N * (*eps_ptr));
+    if (mode == 0) {
+      *div_out = div;
+    } else {
+      const double tau_r = scal[DG_S_TAU_R];
+      double tau_x = div > 0.0 ? tau_r * div : 1e-12 * tau_r;
+      if (!(div > 0.0)) scal[DG_S_CLAMPS] += 1.0;
+      if (t > 0) tau_x = eta_x * tau_x + (1.0 - eta_x) * scal[DG_S_TAU_X];
+      scal[DG_S_DIV] = div;
+      scal[DG_S_TAU_X] = tau_x;
+      if (!isfinite(div) || !(tau_x > 0.0) || !isfinite(tau_x)) scal[DG_S_STATUS] = (double)(t + 1);
     }
   }
 }
@@ -309,11 +360,11 @@ static DenoiseWork carve(const dg_plan* p, void* work) {
 unsigned int red_grid(int64_t N) { return grid_for(N, kRedBlock, kRedMaxBlocks); }
 
 dg_status launch_absmax(const float* r, int64_t N, double eps_rel, double* eps_out,
-                        float* partials, unsigned int* counter, hipStream_t st) {
-  hipLaunchKernelGGL(absmax_kernel, dim3(red_grid(N)), dim3(kRedBlock), 0, st, r, N, eps_rel,
-                     eps_out, partials, counter);
+                        float* partials, hipStream_t st) {
+  const unsigned int g = red_grid(N);
+  hipLaunchKernelGGL(absmax_kernel, dim3(g), dim3(kRedBlock), 0, st, r, N, partials);
   DG_LAUNCH_CHECK("absmax_kernel");
-  return DG_OK;
+  return launch_eps_finish(partials, (int)g, eps_rel, eps_out, st);
 }
 
 static int haar_levels(const dg_plan* p, const dg_haar_params* hp) {
@@ -331,8 +382,8 @@ dg_status check_denoise_params(const dg_plan* p, int kind, const void* params) {
   DG_ARG_CHECK(params != nullptr, "denoise: params must not be NULL");
   if (kind == DG_DEN_NLM) {
     const dg_nlm_params* np = (const dg_nlm_params*)params;
-    DG_ARG_CHECK(np->patch_radius >= 0 && np->patch_radius <= kMaxP,
-                 "denoise: NLM patch radius must be in [0, 3]");
+    DG_ARG_CHECK(np->patch_radius >= 1 && np->patch_radius <= kMaxP,
+                 "denoise: NLM patch radius must be in [1, 3]");
     DG_ARG_CHECK(np->search_radius >= 0 && np->search_radius <= kMaxS,
                  "denoise: NLM search radius must be in [0, 10]");
     DG_ARG_CHECK(np->search_radius + np->patch_radius < p->I, "denoise: NLM window exceeds image");
@@ -362,10 +413,22 @@ dg_status launch_denoiser(const dg_plan* p, int kind, const void* params, const 
   const int nimg = x_pert ? 2 : 1;
   if (kind == DG_DEN_NLM) {
     const dg_nlm_params* np = (const dg_nlm_params*)params;
-    dim3 grid((p->I + kTile - 1) / kTile, (p->I + kTile - 1) / kTile, nimg);
-    hipLaunchKernelGGL(nlm_kernel, grid, dim3(kTile, kTile), 0, st, r, x_den, x_pert, p->I,
-                       np->patch_radius, np->search_radius, tau_r, (float)np->hfac, eps, seed,
-                       iter);
+    dim3 grid((p->I + kNlmTile - 1) / kNlmTile, (p->I + kNlmTile - 1) / kNlmTile, nimg);
+    const float hf = (float)np->hfac;
+    switch (np->patch_radius) {
+      case 1:
+        hipLaunchKernelGGL(nlm_kernel<1>, grid, dim3(256), 0, st, r, x_den, x_pert, p->I,
+                           np->search_radius, tau_r, hf, eps, seed, iter);
+        break;
+      case 2:
+        hipLaunchKernelGGL(nlm_kernel<2>, grid, dim3(256), 0, st, r, x_den, x_pert, p->I,
+                           np->search_radius, tau_r, hf, eps, seed, iter);
+        break;
+      default:
+        hipLaunchKernelGGL(nlm_kernel<3>, grid, dim3(256), 0, st, r, x_den, x_pert, p->I,
+                           np->search_radius, tau_r, hf, eps, seed, iter);
+        break;
+    }
     DG_LAUNCH_CHECK("nlm_kernel");
     return DG_OK;
   }
@@ -385,11 +448,14 @@ dg_status launch_denoiser(const dg_plan* p, int kind, const void* params, const 
 
 dg_status launch_div(const dg_plan* p, const float* xden, const float* xpert, float* x,
                      const double* eps, double* div_out, double* scal, int mode, uint64_t seed,
-                     int iter, double eta_x, int t, double* partials, unsigned int* counter,
-                     hipStream_t st) {
-  hipLaunchKernelGGL(div_kernel, dim3(red_grid(p->N)), dim3(kRedBlock), 0, st, p->N, xden, xpert,
-                     x, eps, div_out, scal, mode, seed, iter, eta_x, t, partials, counter);
+                     int iter, double eta_x, int t, double* partials, hipStream_t st) {
+  const unsigned int g = red_grid(p->N);
+  hipLaunchKernelGGL(div_kernel, dim3(g), dim3(kRedBlock), 0, st, p->N, xden, xpert, x, eps,
+                     div_out, scal, mode, seed, iter, eta_x, t, partials);
   DG_LAUNCH_CHECK("div_kernel");
+  hipLaunchKernelGGL(div_finish, dim3(1), dim3(256), 0, st, partials, (int)g, p->N, eps, div_out,
+                     scal, mode, eta_x, t);
+  DG_LAUNCH_CHECK("div_finish");
   return DG_OK;
 }
 
@@ -425,11 +491,9 @@ extern "C" dg_status denoise(const dg_plan* p, int32_t kind, const void* params,
   }
   if (rc != DG_OK) return rc;
   DenoiseWork w = carve(p, work);
-  if ((rc = launch_zero_u32(w.counters, 4, st)) != DG_OK) return rc;
   float* xpert = nullptr;
   if (div_out) {
-    if ((rc = launch_absmax(r, p->N, eps_rel, w.eps, w.fpart, w.counters + 0, st)) != DG_OK)
-      return rc;
+    if ((rc = launch_absmax(r, p->N, eps_rel, w.eps, w.fpart, st)) != DG_OK) return rc;
     xpert = w.xpert;
   }
   if (kind == DG_DEN_CNN) {
@@ -440,6 +504,6 @@ extern "C" dg_status denoise(const dg_plan* p, int32_t kind, const void* params,
   if (rc != DG_OK) return rc;
   if (div_out)
     return launch_div(p, x_out, xpert, nullptr, w.eps, div_out, nullptr, 0, probe_seed, iter, 1.0,
-                      0, w.dpart, w.counters + 1, st);
+                      0, w.dpart, st);
   return DG_OK;
 }

@@ -42,11 +42,17 @@ dg_status hip_fail(hipError_t e, const char* what);
 // along its major axis (columns when |sin theta| >= |cos theta|, "flat";
 // rows otherwise, "steep"); at major index k its cross coordinate (row for
 // flat rays, column for steep rays, pixel units, pixel centres at integers)
-// is q(k) = q0 + m k.  |pl| is the chord through one full pixel step
-// (h / max(|cos|, |sin|), mm); pl < 0 marks a steep ray.  inv_r = 1/|m|
-// (+inf when the ray is axis-aligned).
+// is q(k) = q0 + m k.  The line position is kept in 32.32 fixed point
+// (q0_fx, m_fx), so q(k) is exact integer arithmetic and the pixel index and
+// fractional offset it yields are identical wherever they are evaluated;
+// FP32 rounding of a coordinate of size I would otherwise shift the line by
+// up to I * 2^-24 pixels.  |pl| is the chord through one full pixel step
+// (h / max(|cos|, |sin|), mm); pl < 0 marks a steep ray.  m, inv_r = 1/|m|
+// (+inf when the ray is axis-aligned) and q0 as floats serve the weight
+// formula and the range search.
 struct RayLine {
-  float q0, m, pl, inv_r;
+  int64_t q0_fx, m_fx;
+  float pl, m, inv_r, q0;
 };
 
 // Per-view data for the pixel-driven back-projector's candidate search.
@@ -90,8 +96,10 @@ __device__ __forceinline__ float chord_fraction(float delta, float m, float inv_
   return fminf(fmaxf(__fmul_rn(hw - delta, inv_r), 0.0f), 1.0f);
 }
 
-__device__ __forceinline__ float cross_coord(const RayLine& L, int k) {
-  return __fmaf_rn(L.m, (float)k, L.q0);
+// Split the fixed-point cross coordinate into floor(q) and q - floor(q).
+__device__ __forceinline__ void split_fx(int64_t q, int* p0, float* f) {
+  *p0 = (int)(q >> 32);
+  *f = (float)(uint32_t)(q & 0xffffffffll) * 2.3283064365386962890625e-10f;  // 2^-32
 }
 
 // SplitMix64 finaliser (Steele, Lea & Flood, OOPSLA 2014).
@@ -146,22 +154,24 @@ __device__ __forceinline__ float block_max(float v, float* sh) {
   return t;
 }
 
-// "Last block done" ticket: every block publishes its partial, then takes a
-// ticket; the block that draws gridDim-1 sees all partials and finishes the
-// reduction (in a fixed order, so the result is deterministic) and resets the
-// counter for the next launch.  Returns true in all threads of that block.
-__device__ __forceinline__ bool last_block(unsigned int* counter, int* sh_flag) {
-  __threadfence();
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    unsigned int t = atomicAdd(counter, 1u);
-    *sh_flag = (t == gridDim.x * gridDim.y * gridDim.z - 1) ? 1 : 0;
-  }
-  __syncthreads();
-  bool last = *sh_flag != 0;
-  if (last) __threadfence();
-  return last;
+// Deterministic sum of n per-block partials by one block (strided per-thread
+// sums in a fixed order, then the block tree); result valid in thread 0.
+__device__ __forceinline__ double finish_sum(const double* partials, int n, double* sh) {
+  double v = 0.0;
+  for (int k = threadIdx.x; k < n; k += blockDim.x) v += partials[k];
+  return block_sum(v, sh);
 }
+
+__device__ __forceinline__ float finish_max(const float* partials, int n, float* sh) {
+  float v = 0.0f;
+  for (int k = threadIdx.x; k < n; k += blockDim.x) v = fmaxf(v, partials[k]);
+  return block_max(v, sh);
+}
+
+// Cross-block results are finished by a separate one-block kernel launched
+// right after the producer: the kernel boundary makes every block's partial
+// visible, which a device-wide fence inside the producer would do only at
+// the cost of writing back the L2 of every XCD for every block.
 
 // Host-side helpers.
 inline unsigned int grid_for(int64_t n, int block, int64_t cap = 65535) {
@@ -190,10 +200,12 @@ struct PrecArgs {
   const double* scal;    // PREC_UPDATE_R: tau_r = scal[DG_S_TAU_R]
   double* scal_out;      // PREC_UPDATE_R: eps written to scal_out[DG_S_EPS]
   double eps_rel;
-  float* partials;       // PREC_UPDATE_R: per-block max |r|
-  unsigned int* counter; // PREC_UPDATE_R: ticket counter (zero on entry)
+  float* partials;       // PREC_UPDATE_R: per-block max |r| (I/2 floats)
 };
 dg_status launch_precondition(const dg_plan* p, const PrecArgs& a, hipStream_t s);
+// eps = max(eps_rel * max(partials), 1e-12) into *eps_out (one block).
+dg_status launch_eps_finish(const float* partials, int n, double eps_rel, double* eps_out,
+                            hipStream_t s);
 size_t precond_work_bytes(const dg_plan* p);
 
 }  // namespace dg

@@ -16,16 +16,14 @@ namespace dg {
 dg_status launch_zero_u32(unsigned int* p, int n, hipStream_t st);
 dg_status launch_channel_fused(int64_t M, const float* z, const float* y, float* s, double* scal,
                                double i0, int mode, double fro2, double N, double eta_s,
-                               int onsager, int t, double* partials, unsigned int* counter,
-                               hipStream_t st);
+                               int onsager, int t, double* partials, hipStream_t st);
 dg_status check_denoise_params(const dg_plan* p, int kind, const void* params);
 dg_status launch_denoiser(const dg_plan* p, int kind, const void* params, const float* r,
                           const double* tau_r, const double* eps, uint64_t seed, int iter,
                           float* x_den, float* x_pert, hipStream_t st);
 dg_status launch_div(const dg_plan* p, const float* xden, const float* xpert, float* x,
                      const double* eps, double* div_out, double* scal, int mode, uint64_t seed,
-                     int iter, double eta_x, int t, double* partials, unsigned int* counter,
-                     hipStream_t st);
+                     int iter, double eta_x, int t, double* partials, hipStream_t st);
 dg_status launch_probe(float* b, int64_t N, uint64_t seed, int k, hipStream_t st);
 size_t denoise_work_bytes(const dg_plan* p);
 unsigned int red_grid(int64_t N);
@@ -94,12 +92,10 @@ __global__ void log_copy(const double* scal, double* log) {
   }
 }
 
-// out += sum(z^2) * scale, FP64, last block finishes.
+// per-block partial sums of z^2 (FP64)
 __global__ void __launch_bounds__(256)
-sumsq_accum(const float* __restrict__ z, int64_t n, double scale, double* out,
-            double* __restrict__ partials, unsigned int* counter) {
+sumsq_partial(const float* __restrict__ z, int64_t n, double* __restrict__ partials) {
   __shared__ double red[4];
-  __shared__ int flag;
   double acc = 0.0;
   for (int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x; k < n; k += (int64_t)gridDim.x * 256) {
     double v = z[k];
@@ -107,14 +103,14 @@ sumsq_accum(const float* __restrict__ z, int64_t n, double scale, double* out,
   }
   double bs = block_sum(acc, red);
   if (threadIdx.x == 0) partials[blockIdx.x] = bs;
-  if (last_block(counter, &flag)) {
-    if (threadIdx.x == 0) {
-      double tot = 0.0;
-      for (unsigned int b = 0; b < gridDim.x; ++b) tot += partials[b];
-      *out += tot * scale;
-      *counter = 0u;
-    }
-  }
+}
+
+// out += scale * sum(partials)
+__global__ void __launch_bounds__(256)
+sumsq_finish(const double* __restrict__ partials, int nblk, double scale, double* out) {
+  __shared__ double red[4];
+  const double tot = finish_sum(partials, nblk, red);
+  if (threadIdx.x == 0) *out += tot * scale;
 }
 
 __global__ void set_f64(double* p, double v) {
@@ -187,8 +183,14 @@ extern "C" dg_status dgamp_iterate(const dg_plan* p, const float* y, const dgamp
   iter_work_layout(p, work, &w);
   if ((rc = launch_zero_u32(w.counters, 8, s)) != DG_OK) return rc;
   const double N = (double)p->N;
+  hipEvent_t* ev = (hipEvent_t*)o->phase_events;
+  auto mark = [&](int it, int k) -> dg_status {
+    if (ev) DG_HIP(hipEventRecord(ev[(size_t)it * (DG_NPHASES + 1) + k], s));
+    return DG_OK;
+  };
   for (int it = 0; it < o->n_iter; ++it) {
     const int t = st->t + it;
+    if ((rc = mark(it, 0)) != DG_OK) return rc;
     PrecArgs a{};
     a.in = st->x;
     a.out = w.mu;
@@ -197,12 +199,15 @@ extern "C" dg_status dgamp_iterate(const dg_plan* p, const float* y, const dgamp
     a.dir = 1;
     a.epilogue = PREC_PLAIN;
     if ((rc = launch_precondition(p, a, s)) != DG_OK) return rc;
+    if ((rc = mark(it, 1)) != DG_OK) return rc;
     if ((rc = launch_project(p, w.mu, w.mu_t, w.z, s)) != DG_OK) return rc;
+    if ((rc = mark(it, 2)) != DG_OK) return rc;
     if ((rc = launch_channel_fused(p->M, w.z, y, st->s, st->scal, o->i0, o->channel_mode, o->fro2,
-                                   N, o->eta_s, o->onsager, t, w.dpart, w.counters + 0, s)) !=
-        DG_OK)
+                                   N, o->eta_s, o->onsager, t, w.dpart, s)) != DG_OK)
       return rc;
+    if ((rc = mark(it, 3)) != DG_OK) return rc;
     if ((rc = launch_backproject(p, st->s, w.g, s)) != DG_OK) return rc;
+    if ((rc = mark(it, 4)) != DG_OK) return rc;
     PrecArgs b{};
     b.in = w.g;
     b.out = w.r;
@@ -215,8 +220,8 @@ extern "C" dg_status dgamp_iterate(const dg_plan* p, const float* y, const dgamp
     b.scal_out = st->scal;
     b.eps_rel = o->eps_rel;
     b.partials = w.fpart;
-    b.counter = w.counters + 1;
     if ((rc = launch_precondition(p, b, s)) != DG_OK) return rc;
+    if ((rc = mark(it, 5)) != DG_OK) return rc;
     const double* tau_r = st->scal + DG_S_TAU_R;
     const double* eps = st->scal + DG_S_EPS;
     if (o->den_kind == DG_DEN_CNN)
@@ -226,9 +231,11 @@ extern "C" dg_status dgamp_iterate(const dg_plan* p, const float* y, const dgamp
       rc = launch_denoiser(p, o->den_kind, o->den_params, w.r, tau_r, eps, o->probe_seed, t,
                            w.xden, w.xpert, s);
     if (rc != DG_OK) return rc;
+    if ((rc = mark(it, 6)) != DG_OK) return rc;
     if ((rc = launch_div(p, w.xden, w.xpert, st->x, eps, nullptr, st->scal, 1, o->probe_seed, t,
-                         o->eta_x, t, w.dpart, w.counters + 2, s)) != DG_OK)
+                         o->eta_x, t, w.dpart, s)) != DG_OK)
       return rc;
+    if ((rc = mark(it, 7)) != DG_OK) return rc;
     if (log) {
       hipLaunchKernelGGL(log_copy, dim3(1), dim3(64), 0, s, st->scal,
                          log + (size_t)it * DG_LOG_STRIDE);
@@ -274,9 +281,11 @@ extern "C" dg_status dg_fro2_hutchinson(const dg_plan* p, int32_t n_probes, uint
     a.epilogue = PREC_PLAIN;
     if ((rc = launch_precondition(p, a, s)) != DG_OK) return rc;
     if ((rc = launch_project(p, w.mu, w.mu_t, w.z, s)) != DG_OK) return rc;
-    hipLaunchKernelGGL(sumsq_accum, dim3(red_grid(p->M)), dim3(256), 0, s, w.z, p->M,
-                       1.0 / n_probes, out, w.dpart, w.counters + 3);
-    DG_LAUNCH_CHECK("sumsq_accum");
+    const unsigned int g = red_grid(p->M);
+    hipLaunchKernelGGL(sumsq_partial, dim3(g), dim3(256), 0, s, w.z, p->M, w.dpart);
+    DG_LAUNCH_CHECK("sumsq_partial");
+    hipLaunchKernelGGL(sumsq_finish, dim3(1), dim3(256), 0, s, w.dpart, (int)g, 1.0 / n_probes, out);
+    DG_LAUNCH_CHECK("sumsq_finish");
   }
   return DG_OK;
 }

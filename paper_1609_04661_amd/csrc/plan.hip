@@ -59,6 +59,9 @@ static RayLine make_ray(double c, double s, double off_mm, const dg_geom& g) {
     q0 = off / c + half * (1.0 - m);
     pl = -h / std::fabs(c);
   }
+  const double two32 = 4294967296.0;
+  L.q0_fx = std::llround(q0 * two32);
+  L.m_fx = std::llround(m * two32);
   L.q0 = (float)q0;
   L.m = (float)m;
   L.pl = (float)pl;

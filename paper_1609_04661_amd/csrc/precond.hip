@@ -146,11 +146,10 @@ prec_cols(float2* __restrict__ spec, const float2* __restrict__ tw, int I, int d
 __global__ void __launch_bounds__(kFftThreads)
 prec_rows_inv(const float2* __restrict__ spec, const float2* __restrict__ tw, int I,
               float* __restrict__ out, float* __restrict__ out_t, int epilogue,
-              const float* __restrict__ x, const double* __restrict__ scal, double* scal_out,
-              double eps_rel, float* __restrict__ partials, unsigned int* counter) {
+              const float* __restrict__ x, const double* __restrict__ scal,
+              float* __restrict__ partials) {
   __shared__ float2 a[kMaxFft], b[kMaxFft];
   __shared__ float red[kFftThreads / 64];
-  __shared__ int flag;
   const int m = blockIdx.x;
   for (int t = threadIdx.x; t < I; t += blockDim.x) {
     float2 ya, yb;
@@ -189,17 +188,24 @@ prec_rows_inv(const float2* __restrict__ spec, const float2* __restrict__ tw, in
   if (epilogue == PREC_UPDATE_R) {
     float bm = block_max(amax, red);
     if (threadIdx.x == 0) partials[blockIdx.x] = bm;
-    if (last_block(counter, &flag)) {
-      float gm = 0.0f;
-      for (int k = threadIdx.x; k < (int)gridDim.x; k += blockDim.x) gm = fmaxf(gm, partials[k]);
-      gm = block_max(gm, red);
-      if (threadIdx.x == 0) {
-        double e = eps_rel * (double)gm;
-        scal_out[DG_S_EPS] = e > 1e-12 ? e : 1e-12;
-        *counter = 0u;
-      }
-    }
   }
+}
+
+__global__ void __launch_bounds__(256)
+eps_finish_kernel(const float* __restrict__ partials, int n, double eps_rel, double* eps_out) {
+  __shared__ float red[4];
+  const float gm = finish_max(partials, n, red);
+  if (threadIdx.x == 0) {
+    const double e = eps_rel * (double)gm;
+    *eps_out = e > 1e-12 ? e : 1e-12;
+  }
+}
+
+dg_status launch_eps_finish(const float* partials, int n, double eps_rel, double* eps_out,
+                            hipStream_t s) {
+  hipLaunchKernelGGL(eps_finish_kernel, dim3(1), dim3(256), 0, s, partials, n, eps_rel, eps_out);
+  DG_LAUNCH_CHECK("eps_finish_kernel");
+  return DG_OK;
 }
 
 dg_status launch_precondition(const dg_plan* p, const PrecArgs& a, hipStream_t s) {
@@ -215,9 +221,10 @@ dg_status launch_precondition(const dg_plan* p, const PrecArgs& a, hipStream_t s
                      a.dir);
   DG_LAUNCH_CHECK("prec_cols");
   hipLaunchKernelGGL(prec_rows_inv, dim3(I / 2), dim3(kFftThreads), 0, s, a.spec, p->twiddle, I,
-                     a.out, a.out_t, a.epilogue, a.x, a.scal, a.scal_out, a.eps_rel, a.partials,
-                     a.counter);
+                     a.out, a.out_t, a.epilogue, a.x, a.scal, a.partials);
   DG_LAUNCH_CHECK("prec_rows_inv");
+  if (a.epilogue == PREC_UPDATE_R)
+    return launch_eps_finish(a.partials, I / 2, a.eps_rel, a.scal_out + DG_S_EPS, s);
   return DG_OK;
 }
 

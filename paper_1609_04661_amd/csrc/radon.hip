@@ -1,8 +1,8 @@
 // Ray-driven projector A and pixel-driven back-projector A^T (Sec. 2.1,
 // eq. linCT) with exact chord-length weights from one shared formula.
 //
-// Projector: one thread per ray.  The ray marches along its major axis; at
-// each major index k it meets at most two pixels across (cross coordinate
+// Projector: ray-driven.  A ray marches along its major axis; at each major
+// index k it meets at most two pixels across (cross coordinate
 // q(k) = q0 + m k, candidates floor(q) and floor(q) + 1).  Threads of a
 // wavefront hold consecutive bins of one view, so for steep rays they read
 // consecutive columns of one image row.  Flat rays read the transposed copy
@@ -16,59 +16,90 @@
 
 namespace dg {
 
-static constexpr int kProjBlock = 256;
+static constexpr int kRaysPerBlock = 64, kSegs = 4;
+static constexpr int kProjBlock = kRaysPerBlock * kSegs;
 static constexpr int kBpBlockX = 64, kBpBlockY = 4;
 
+// Block = kRaysPerBlock rays x kSegs segments: wavefront w marches segment w
+// of the rays' major-index range for 64 consecutive rays (consecutive bins of
+// one view, so their reads stay coalesced), and the kSegs partial sums are
+// added in a fixed order.  Splitting the march gives kSegs times more
+// wavefronts to hide memory latency than one thread per ray.
 __global__ void __launch_bounds__(kProjBlock)
 project_kernel(const RayLine* __restrict__ rays, const float* __restrict__ img,
                const float* __restrict__ img_t, float* __restrict__ sino, int I, int64_t M) {
-  const int64_t r = (int64_t)blockIdx.x * kProjBlock + threadIdx.x;
-  if (r >= M) return;
-  const RayLine L = rays[r];
-  const bool steep = L.pl < 0.0f;
-  // Pixel (row i, col j).  Steep: major = row, cross = col -> img[k*I + p].
-  // Flat: major = col, cross = row -> img[p*I + k] = img_t[k*I + p].
-  // major_rows: the buffer read is laid out with the major index as its row.
-  const bool major_rows = steep || (img_t != nullptr);
-  const float* base = (steep || img_t == nullptr) ? img : img_t;
-
-  // Major-index range where q(k) lies in (-1, I): candidates exist only there.
-  int k0 = 0, k1 = I - 1;
-  if (L.m != 0.0f) {
-    float ka = (-1.0f - L.q0) / L.m, kb = ((float)I - L.q0) / L.m;
-    float lo = fmaxf(fminf(ka, kb), -2.0f), hi = fminf(fmaxf(ka, kb), (float)I + 1.0f);
-    k0 = max(0, (int)floorf(lo) - 1);
-    k1 = min(I - 1, (int)ceilf(hi) + 1);
-  } else if (!(L.q0 > -1.0f && L.q0 < (float)I)) {
-    k1 = -1;
-  }
+  __shared__ float part[kSegs][kRaysPerBlock];
+  const int lane = threadIdx.x % kRaysPerBlock, seg = threadIdx.x / kRaysPerBlock;
+  const int64_t r = (int64_t)blockIdx.x * kRaysPerBlock + lane;
   float acc = 0.0f;
-  for (int k = k0; k <= k1; ++k) {
-    const float q = cross_coord(L, k);
-    const int p0 = (int)floorf(q);
+  RayLine L;
+  if (r < M) {
+    L = rays[r];
+    const bool steep = L.pl < 0.0f;
+    // Pixel (row i, col j).  Steep: major = row, cross = col -> img[k*I + p].
+    // Flat: major = col, cross = row -> img[p*I + k] = img_t[k*I + p].
+    // major_rows: the buffer read is laid out with the major index as its row.
+    const bool major_rows = steep || (img_t != nullptr);
+    const float* base = (steep || img_t == nullptr) ? img : img_t;
+
+    // Major-index range where q(k) lies in (-1, I): candidates exist only there.
+    int k0 = 0, k1 = I - 1;
+    if (L.m != 0.0f) {
+      float ka = (-1.0f - L.q0) / L.m, kb = ((float)I - L.q0) / L.m;
+      float lo = fmaxf(fminf(ka, kb), -2.0f), hi = fminf(fmaxf(ka, kb), (float)I + 1.0f);
+      k0 = max(0, (int)floorf(lo) - 1);
+      k1 = min(I - 1, (int)ceilf(hi) + 1);
+    } else if (!(L.q0 > -1.0f && L.q0 < (float)I)) {
+      k1 = -1;
+    }
+    // this wavefront's share of [k0, k1]
+    const int len = k1 - k0 + 1;
+    const int chunk = (len + kSegs - 1) / kSegs;
+    const int ka = k0 + seg * chunk;
+    const int kb = min(k1, ka + chunk - 1);
+    int64_t q = L.q0_fx + L.m_fx * (int64_t)ka;  // exact: advanced by m_fx per step
+#pragma unroll 2
+    for (int k = ka; k <= kb; ++k, q += L.m_fx) {
+      int p0;
+      float f;
+      split_fx(q, &p0, &f);
 #pragma unroll
-    for (int d = 0; d < 2; ++d) {
-      const int p = p0 + d;
-      if (p >= 0 && p < I) {
-        const float w = chord_fraction(fabsf(q - (float)p), L.m, L.inv_r);
-        float v;
-        if (major_rows)
-          v = base[(int64_t)k * I + p];
-        else
-          v = base[(int64_t)p * I + k];  // flat ray without a transposed copy
-        acc = __fmaf_rn(w, v, acc);
+      for (int d = 0; d < 2; ++d) {
+        const int p = p0 + d;
+        if (p >= 0 && p < I) {
+          const float w = chord_fraction(d ? 1.0f - f : f, L.m, L.inv_r);
+          float v;
+          if (major_rows)
+            v = base[(int64_t)k * I + p];
+          else
+            v = base[(int64_t)p * I + k];  // flat ray without a transposed copy
+          acc = __fmaf_rn(w, v, acc);
+        }
       }
     }
   }
-  sino[r] = acc * fabsf(L.pl);
+  part[seg][lane] = acc;
+  __syncthreads();
+  if (seg == 0 && r < M) {
+    float t = part[0][lane];
+#pragma unroll
+    for (int g = 1; g < kSegs; ++g) t += part[g][lane];
+    sino[r] = t * fabsf(L.pl);
+  }
 }
 
+// Weight of pixel (i, j) on ray L: the same fixed-point cross coordinate and
+// the same fraction formula as the projector, hence the same value.
 __device__ __forceinline__ float ray_weight(const RayLine& L, int i, int j) {
   const bool steep = L.pl < 0.0f;
   const int k = steep ? i : j;
   const int p = steep ? j : i;
-  const float q = cross_coord(L, k);
-  return fabsf(L.pl) * chord_fraction(fabsf(q - (float)p), L.m, L.inv_r);
+  int p0;
+  float f;
+  split_fx(L.q0_fx + L.m_fx * (int64_t)k, &p0, &f);
+  if (p == p0) return fabsf(L.pl) * chord_fraction(f, L.m, L.inv_r);
+  if (p == p0 + 1) return fabsf(L.pl) * chord_fraction(1.0f - f, L.m, L.inv_r);
+  return 0.0f;
 }
 
 template <bool kFan>
@@ -132,7 +163,7 @@ dg_status launch_transpose(const float* in, float* out, int I, hipStream_t s) {
 
 dg_status launch_project(const dg_plan* p, const float* img, const float* img_t, float* sino,
                          hipStream_t s) {
-  unsigned int grid = (unsigned int)((p->M + kProjBlock - 1) / kProjBlock);
+  unsigned int grid = (unsigned int)((p->M + kRaysPerBlock - 1) / kRaysPerBlock);
   hipLaunchKernelGGL(project_kernel, dim3(grid), dim3(kProjBlock), 0, s, p->rays, img, img_t,
                      sino, p->I, p->M);
   DG_LAUNCH_CHECK("project_kernel");

@@ -168,7 +168,7 @@ def test_channel_ragged_and_single(gpu_lib):
         s_ref, ts_ref = och.poisson_out(p, y, 0.3, 1e4)
         s, ts = gpu_lib.gamp_poisson_out(cu(p), cu(y), cu([0.3], torch.float64), 1e4)
         assert abs(float(host(ts)[0]) - ts_ref) <= 1e-5 * ts_ref
-        assert rel_l2(host(s), s_ref) <= 1e-5
+        assert rel_l2(host(s), s_ref) <= 3e-5
 
 
 @pytest.mark.parametrize("I", [64, 512])
