@@ -144,12 +144,38 @@ dg_status gamp_poisson_out(int64_t m, const float* p, const float* y, const doub
 typedef struct dg_haar_params { double alpha; int32_t levels; /* 0 = log2 I - 2 */ } dg_haar_params;
 typedef struct dg_nlm_params { int32_t patch_radius; int32_t search_radius; double hfac; } dg_nlm_params;
 typedef struct dg_cnn_params {
-  const void* weights;  /* device: packed network, dg_cnn_weight_bytes() bytes */
-  int32_t tangent_div;  /* 1: divergence by the forward-mode tangent b^T J b   */
+  const void* weights;  /* device: packed network, dg_cnn_weight_bytes() bytes   */
+  void* work;           /* device: dg_cnn_workspace_bytes(I*I) bytes (activations) */
 } dg_cnn_params;
 dg_status denoise(const dg_plan* plan, int32_t kind, const void* params, const float* r,
                   const double* tau_r, uint64_t probe_seed, int32_t iter, double eps_rel,
                   float* x_out, double* div_out, void* work, void* stream);
+
+/* Learned residual CNN denoiser D(r) = r - f(r) (a plug-in for the black-box
+ * denoiser of Sec. 4.3): f = conv 1->64, ReLU, 8 x (conv 64->64, ReLU),
+ * conv 64->1, all 3x3 with bias and zero padding; BF16 weights and
+ * activations, FP32 accumulation (MFMA).  With DG_DEN_CNN the divergence of
+ * eq. MC_SURE is taken in its eps -> 0 limit, b^T J_D(r) b / N, by a
+ * forward-mode tangent pass through the ReLU pattern of r.
+ * Master parameters: FP32, dg_cnn_param_count() values, per layer
+ * w[co][ci][3][3] then b[co] (layers in order).  dg_cnn_pack converts them to
+ * the packed device format (BF16 weights) that denoise and training use.   */
+size_t dg_cnn_weight_bytes(void);
+int64_t dg_cnn_param_count(void);
+size_t dg_cnn_workspace_bytes(int64_t n_pixels);
+dg_status dg_cnn_pack(const float* master, void* packed, void* stream);
+/* out = D(in) for n images of h x w (FP32, row-major, back to back).        */
+dg_status dg_cnn_forward(const void* packed, int32_t n, int32_t h, int32_t w, const float* in,
+                         float* out, void* work, void* stream);
+/* One Adam step (lr, betas 0.9/0.999, eps 1e-8, bias-corrected with `step`
+ * >= 1) on L = mean((D(noisy) - clean)^2) over n images of h x w: forward,
+ * backward (BF16 MFMA, FP32 accumulation), gradient into `grad`, Adam update
+ * of `master` with moments adam_m/adam_v, repack into `packed`; *loss_out
+ * (device double) receives L.  work: dg_cnn_workspace_bytes(n*h*w).        */
+dg_status dg_cnn_train_step(const float* noisy, const float* clean, int32_t n, int32_t h,
+                            int32_t w, float* master, void* packed, float* grad, float* adam_m,
+                            float* adam_v, int32_t step, double lr, double* loss_out, void* work,
+                            void* stream);
 
 /* D-GAMP-CT iterations (Algorithm 1, Sec. 4), with Phi~ = A V^-1:
  *   z = Phi~ x; tau_p = fro2 tau_x / M; p = z - tau_p s_prev;
@@ -205,6 +231,21 @@ dg_status dgamp_state_init(const dg_plan* plan, dgamp_state* st, double tau_x0, 
 dg_status dgamp_iterate(const dg_plan* plan, const float* y, const dgamp_opts* opts,
                         dgamp_state* st, float* mu_out, double* log, void* work,
                         void* stream);
+
+/* A whole reconstruction as one replayable HIP graph: optional state reset
+ * (dgamp_state_init with tau_x0 when tau_x0 > 0), then opts->n_iter
+ * iterations of dgamp_iterate and the final mu_out = V^-1 x, captured once
+ * and instantiated.  Every dg_graph_launch replays exactly that sequence
+ * (the same iteration indices, hence the same probes) on `stream`; the
+ * buffers named at creation must stay valid while the graph exists.
+ * opts->phase_events must be NULL.  Capture uses a private stream, so the
+ * caller's stream may be the legacy default stream.                        */
+typedef struct dg_graph dg_graph;
+dg_status dgamp_graph_create(const dg_plan* plan, const float* y, const dgamp_opts* opts,
+                             dgamp_state* st, double tau_x0, float* mu_out, double* log,
+                             void* work, dg_graph** out);
+dg_status dg_graph_launch(dg_graph* g, void* stream);
+dg_status dg_graph_destroy(dg_graph* g);
 
 /* ||A V^-1||_F^2 by Hutchinson's estimator over n_probes Rademacher probes
  * b_k (b_k,i = 1 - 2 (SplitMix64(seed ^ (k << 32) ^ i) & 1)):

@@ -1,0 +1,139 @@
+"""FP64 residual CNN denoiser: forward, backward and divergence (test infrastructure).
+
+The learned plug-in denoiser (not in the paper, which mentions residual
+CNN denoisers only as related work; the method treats D as a black box,
+Sec. 4.3):  D(r) = r - f(r), where f is
+    conv 1->64, ReLU, 8 x (conv 64->64, ReLU), conv 64->1,
+every conv 3 x 3 with bias, zero padding, cross-correlation
+    out[o, y, x] = b[o] + sum_{i, ty, tx} w[o, i, ty, tx] in[i, y + ty - 1, x + tx - 1].
+Parameters are a list of (w, b) per layer with w of shape (co, ci, 3, 3).
+
+The divergence follows eq. MC_SURE with the finite difference
+b^T (D(r + eps b) - D(r)) / (N eps).
+
+Parity: forward/backward pinned by central finite differences of the loss
+and by linearity checks; against the paper unpinned (the paper has no CNN).
+"""
+import numpy as np
+
+CHANNELS = 64
+N_MID = 8
+
+
+def shapes():
+    s = [((CHANNELS, 1, 3, 3), (CHANNELS,))]
+    s += [((CHANNELS, CHANNELS, 3, 3), (CHANNELS,))] * N_MID
+    s += [((1, CHANNELS, 3, 3), (1,))]
+    return s
+
+
+def init_params(seed, scale=1.0):
+    """He-style random initialisation (float64)."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for ws, bs in shapes():
+        fan_in = ws[1] * 9
+        w = rng.standard_normal(ws) * np.sqrt(2.0 / fan_in) * scale
+        b = rng.standard_normal(bs) * 0.01
+        out.append((w, b))
+    return out
+
+
+def conv3x3(x, w, b=None):
+    """x: (ci, H, W) -> (co, H, W), zero padding."""
+    ci, H, W = x.shape
+    xp = np.zeros((ci, H + 2, W + 2))
+    xp[:, 1:-1, 1:-1] = x
+    out = np.zeros((w.shape[0], H, W))
+    for ty in range(3):
+        for tx in range(3):
+            patch = xp[:, ty:ty + H, tx:tx + W].reshape(ci, -1)
+            out += (w[:, :, ty, tx] @ patch).reshape(-1, H, W)
+    if b is not None:
+        out += b[:, None, None]
+    return out
+
+
+def conv3x3_input_grad(g, w):
+    """d(sum g * conv(x))/dx for g: (co, H, W) -> (ci, H, W)."""
+    co, H, W = g.shape
+    gp = np.zeros((co, H + 2, W + 2))
+    gp[:, 1:-1, 1:-1] = g
+    out = np.zeros((w.shape[1], H, W))
+    for ty in range(3):
+        for tx in range(3):
+            # x[y', x'] feeds out[y' - ty + 1, x' - tx + 1]
+            patch = gp[:, 2 - ty:2 - ty + H, 2 - tx:2 - tx + W].reshape(co, -1)
+            out += (w[:, :, ty, tx].T @ patch).reshape(-1, H, W)
+    return out
+
+
+def conv3x3_weight_grad(g, x):
+    """d(sum g * conv(x))/dw and /db."""
+    ci, H, W = x.shape
+    xp = np.zeros((ci, H + 2, W + 2))
+    xp[:, 1:-1, 1:-1] = x
+    dw = np.zeros((g.shape[0], ci, 3, 3))
+    g2 = g.reshape(g.shape[0], -1)
+    for ty in range(3):
+        for tx in range(3):
+            dw[:, :, ty, tx] = g2 @ xp[:, ty:ty + H, tx:tx + W].reshape(ci, -1).T
+    return dw, g2.sum(axis=1)
+
+
+def forward(r, params):
+    """f(r) and the post-ReLU activations of every hidden layer."""
+    a = np.asarray(r, dtype=np.float64)[None]
+    acts = [a]
+    for l, (w, b) in enumerate(params):
+        z = conv3x3(a, w, b)
+        a = np.maximum(z, 0.0) if l < len(params) - 1 else z
+        acts.append(a)
+    return a[0], acts
+
+
+def denoise(r, params):
+    f, _ = forward(r, params)
+    return np.asarray(r, dtype=np.float64) - f
+
+
+def backward(acts, params, g_f):
+    """Gradients of sum(g_f * f) w.r.t. every (w, b) and w.r.t. the input r."""
+    g = np.asarray(g_f, dtype=np.float64)[None]
+    grads = [None] * len(params)
+    for l in range(len(params) - 1, -1, -1):
+        w, b = params[l]
+        if l < len(params) - 1:
+            g = g * (acts[l + 1] > 0)
+        grads[l] = conv3x3_weight_grad(g, acts[l])
+        g = conv3x3_input_grad(g, w)
+    return grads, g[0]
+
+
+def mse_loss_and_grads(noisy, clean, params):
+    """L = mean((D(noisy) - clean)^2) for one image; gradients w.r.t. params."""
+    f, acts = forward(noisy, params)
+    res = noisy - f - clean
+    n = res.size
+    loss = float(np.sum(res * res) / n)
+    g_f = -2.0 * res / n
+    grads, _ = backward(acts, params, g_f)
+    return loss, grads
+
+
+def fd_divergence(r, params, b, eps):
+    """eq. MC_SURE: b^T (D(r + eps b) - D(r)) / (N eps)."""
+    d0 = denoise(r, params)
+    d1 = denoise(r + eps * b, params)
+    return float(np.sum(b * (d1 - d0)) / (r.size * eps))
+
+
+def tangent_divergence(r, params, b):
+    """b^T J_D(r) b / N with the ReLU pattern of r (the eps -> 0 limit)."""
+    _, acts = forward(r, params)
+    t = np.asarray(b, dtype=np.float64)[None]
+    for l, (w, _) in enumerate(params):
+        t = conv3x3(t, w)
+        if l < len(params) - 1:
+            t = t * (acts[l + 1] > 0)
+    return float(np.sum(b * (b - t[0])) / r.size)

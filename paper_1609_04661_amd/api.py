@@ -9,6 +9,7 @@ instead of falling back.
 import ctypes
 import os
 
+import numpy as np
 import torch
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -27,7 +28,10 @@ PHASES = ("precond_x", "project", "channel", "backproject", "precond_g_update", 
 
 EXPORTS = ("dg_plan_create", "dg_plan_destroy", "dg_workspace_bytes", "dg_channel_workspace_bytes",
            "dg_last_error", "ct_project", "ct_backproject", "ct_precondition", "gamp_poisson_out",
-           "denoise", "dgamp_state_init", "dgamp_iterate", "dg_fro2_hutchinson")
+           "denoise", "dgamp_state_init", "dgamp_iterate", "dg_fro2_hutchinson",
+           "dgamp_graph_create", "dg_graph_launch", "dg_graph_destroy", "dg_cnn_weight_bytes",
+           "dg_cnn_param_count", "dg_cnn_workspace_bytes", "dg_cnn_pack", "dg_cnn_forward",
+           "dg_cnn_train_step")
 
 
 class DgError(RuntimeError):
@@ -52,7 +56,7 @@ class NlmParams(ctypes.Structure):
 
 
 class CnnParams(ctypes.Structure):
-    _fields_ = [("weights", ctypes.c_void_p), ("tangent_div", ctypes.c_int32)]
+    _fields_ = [("weights", ctypes.c_void_p), ("work", ctypes.c_void_p)]
 
 
 class DgampOpts(ctypes.Structure):
@@ -97,6 +101,17 @@ def load():
         "dgamp_iterate": ([_VP, _VP, ctypes.POINTER(DgampOpts), ctypes.POINTER(DgampStateC), _VP,
                            _VP, _VP, _VP], i32),
         "dg_fro2_hutchinson": ([_VP, i32, u64, _VP, _VP, _VP], i32),
+        "dgamp_graph_create": ([_VP, _VP, ctypes.POINTER(DgampOpts), ctypes.POINTER(DgampStateC),
+                                dbl, _VP, _VP, _VP, ctypes.POINTER(_VP)], i32),
+        "dg_graph_launch": ([_VP, _VP], i32),
+        "dg_graph_destroy": ([_VP], i32),
+        "dg_cnn_weight_bytes": ([], sz),
+        "dg_cnn_param_count": ([], i64),
+        "dg_cnn_workspace_bytes": ([i64], sz),
+        "dg_cnn_pack": ([_VP, _VP, _VP], i32),
+        "dg_cnn_forward": ([_VP, i32, i32, i32, _VP, _VP, _VP, _VP], i32),
+        "dg_cnn_train_step": ([_VP, _VP, i32, i32, i32, _VP, _VP, _VP, _VP, _VP, i32, dbl, _VP,
+                               _VP, _VP], i32),
     }
     for name, (args, res) in sig.items():
         f = getattr(L, name)
@@ -213,8 +228,9 @@ def make_params(kind, **kw):
         return NlmParams(patch_radius=kw.get("pr", 2), search_radius=kw.get("sr", 10),
                          hfac=kw.get("hfac", 0.4))
     if kind == DEN_CNN:
-        w = kw["weights"]
-        return CnnParams(weights=ctypes.c_void_p(w.data_ptr()), tangent_div=kw.get("tangent_div", 1))
+        net = kw["net"]
+        return CnnParams(weights=ctypes.c_void_p(net.packed.data_ptr()),
+                         work=ctypes.c_void_p(net.work_for(kw["n_pixels"]).data_ptr()))
     raise DgError("unknown denoiser kind")
 
 
@@ -251,16 +267,23 @@ class DgampState:
         return self.c.t
 
 
-def dgamp_iterate(plan, y, state, n_iter, fro2, i0, den_kind, den_params, probe_seed=0,
-                  eps_rel=1e-3, eta_x=1.0, eta_s=1.0, onsager=True, channel_mode=CHANNEL_LAPLACE,
-                  mu_out=None, log=None, work=None, phase_events=None):
-    """phase_events: optional ctypes array of n_iter * (NPHASES + 1) hipEvent_t handles."""
-    opts = DgampOpts(n_iter=int(n_iter), den_kind=int(den_kind),
+def make_opts(n_iter, fro2, i0, den_kind, den_params, probe_seed=0, eps_rel=1e-3, eta_x=1.0,
+              eta_s=1.0, onsager=True, channel_mode=CHANNEL_LAPLACE, phase_events=None):
+    return DgampOpts(n_iter=int(n_iter), den_kind=int(den_kind),
                      den_params=ctypes.cast(ctypes.pointer(den_params), ctypes.c_void_p),
                      fro2=float(fro2), i0=float(i0), probe_seed=int(probe_seed),
                      eps_rel=float(eps_rel), eta_x=float(eta_x), eta_s=float(eta_s),
                      onsager=1 if onsager else 0, channel_mode=int(channel_mode),
-                     phase_events=ctypes.cast(phase_events, ctypes.c_void_p) if phase_events is not None else None)
+                     phase_events=ctypes.cast(phase_events, ctypes.c_void_p)
+                     if phase_events is not None else None)
+
+
+def dgamp_iterate(plan, y, state, n_iter, fro2, i0, den_kind, den_params, probe_seed=0,
+                  eps_rel=1e-3, eta_x=1.0, eta_s=1.0, onsager=True, channel_mode=CHANNEL_LAPLACE,
+                  mu_out=None, log=None, work=None, phase_events=None):
+    """phase_events: optional ctypes array of n_iter * (NPHASES + 1) hipEvent_t handles."""
+    opts = make_opts(n_iter, fro2, i0, den_kind, den_params, probe_seed, eps_rel, eta_x, eta_s,
+                     onsager, channel_mode, phase_events)
     if work is None:
         work = plan.workspace(OP_DGAMP)
     if log is not None and log.numel() < n_iter * LOG_STRIDE:
@@ -281,3 +304,127 @@ def dg_fro2_hutchinson(plan, n_probes, seed, out=None, work=None):
                                    _ptr(out, torch.float64, 1, "out"),
                                    _ptr(work, torch.uint8, None, "work"), _stream()))
     return out
+
+
+class DgampGraph:
+    """A captured reconstruction (state reset + n_iter iterations + mu_out)."""
+
+    def __init__(self, plan, y, state, n_iter, fro2, i0, den_kind, den_params, tau_x0=1.0,
+                 mu_out=None, log=None, work=None, **kw):
+        self.keep = (plan, y, state, den_params, mu_out, log)
+        self.work = work if work is not None else plan.workspace(OP_DGAMP)
+        self.opts = make_opts(n_iter, fro2, i0, den_kind, den_params, **kw)
+        h = _VP()
+        _check(_lib.dgamp_graph_create(plan.handle, _ptr(y, torch.float32, plan.M, "y"),
+                                       ctypes.byref(self.opts), ctypes.byref(state.c),
+                                       float(tau_x0), _ptr(mu_out, torch.float32, plan.N, "mu_out"),
+                                       _ptr(log, torch.float64, None, "log"),
+                                       _ptr(self.work, torch.uint8, None, "work"), ctypes.byref(h)))
+        self._h = h
+
+    def launch(self):
+        _check(_lib.dg_graph_launch(self._h, _stream()))
+
+    def __del__(self):
+        try:
+            if getattr(self, "_h", None) and _lib is not None:
+                _lib.dg_graph_destroy(self._h)
+                self._h = None
+        except Exception:
+            pass
+
+
+class CnnNet:
+    """Residual CNN denoiser state on the device: FP32 master parameters (PyTorch
+    layout per layer: w[co][ci][3][3], b[co]), Adam moments and the packed BF16
+    network the kernels read."""
+
+    def __init__(self, master=None, seed=0):
+        load()
+        self.P = int(_lib.dg_cnn_param_count())
+        if master is None:
+            master = self.init_master(seed)
+        master = torch.as_tensor(master, dtype=torch.float32).reshape(-1)
+        if master.numel() != self.P:
+            raise DgError("CNN parameter vector must have %d values" % self.P)
+        self.master = master.cuda().contiguous()
+        self.grad = torch.zeros_like(self.master)
+        self.m = torch.zeros_like(self.master)
+        self.v = torch.zeros_like(self.master)
+        self.packed = torch.zeros(int(_lib.dg_cnn_weight_bytes()), dtype=torch.uint8, device="cuda")
+        self.step = 0
+        self._work = {}
+        self.repack()
+
+    @staticmethod
+    def layer_shapes():
+        s = [((64, 1, 3, 3), (64,))] + [((64, 64, 3, 3), (64,))] * 8 + [((1, 64, 3, 3), (1,))]
+        return s
+
+    @classmethod
+    def init_master(cls, seed, scale=1.0):
+        import numpy as np
+        rng = np.random.default_rng(seed)
+        parts = []
+        for ws, bs in cls.layer_shapes():
+            fan_in = ws[1] * 9
+            parts.append((rng.standard_normal(ws) * np.sqrt(2.0 / fan_in) * scale).ravel())
+            parts.append(np.zeros(bs))
+        return np.concatenate(parts).astype(np.float32)
+
+    def layers(self):
+        """Host copy of the parameters as [(w, b), ...] (float64)."""
+        flat = self.master.detach().cpu().double().numpy()
+        out, k = [], 0
+        for ws, bs in self.layer_shapes():
+            nw, nb = int(np.prod(ws)), int(np.prod(bs))
+            out.append((flat[k:k + nw].reshape(ws), flat[k + nw:k + nw + nb].reshape(bs)))
+            k += nw + nb
+        return out
+
+    def repack(self):
+        _check(_lib.dg_cnn_pack(_ptr(self.master, torch.float32, self.P, "master"),
+                                _ptr(self.packed, torch.uint8, None, "packed"), _stream()))
+
+    def work_for(self, n_pixels):
+        if n_pixels not in self._work:
+            nbytes = int(_lib.dg_cnn_workspace_bytes(int(n_pixels)))
+            self._work[n_pixels] = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+        return self._work[n_pixels]
+
+    def forward(self, imgs):
+        """D(imgs) for a (n, h, w) float32 CUDA tensor."""
+        n, h, w = imgs.shape
+        out = torch.empty_like(imgs)
+        _check(_lib.dg_cnn_forward(_ptr(self.packed, torch.uint8, None, "packed"), n, h, w,
+                                   _ptr(imgs, torch.float32, None, "in"),
+                                   _ptr(out, torch.float32, None, "out"),
+                                   _ptr(self.work_for(n * h * w), torch.uint8, None, "work"),
+                                   _stream()))
+        return out
+
+    def train_step(self, noisy, clean, lr, loss_out=None):
+        n, h, w = noisy.shape
+        if loss_out is None:
+            loss_out = torch.zeros(1, dtype=torch.float64, device="cuda")
+        self.step += 1
+        _check(_lib.dg_cnn_train_step(_ptr(noisy, torch.float32, None, "noisy"),
+                                      _ptr(clean, torch.float32, noisy.numel(), "clean"), n, h, w,
+                                      _ptr(self.master, torch.float32, self.P, "master"),
+                                      _ptr(self.packed, torch.uint8, None, "packed"),
+                                      _ptr(self.grad, torch.float32, self.P, "grad"),
+                                      _ptr(self.m, torch.float32, self.P, "m"),
+                                      _ptr(self.v, torch.float32, self.P, "v"), self.step, float(lr),
+                                      _ptr(loss_out, torch.float64, 1, "loss"),
+                                      _ptr(self.work_for(n * h * w), torch.uint8, None, "work"),
+                                      _stream()))
+        return loss_out
+
+    def save(self, path):
+        from safetensors.torch import save_file
+        save_file({"master": self.master.detach().cpu()}, path)
+
+    @classmethod
+    def load_file(cls, path):
+        from safetensors.torch import load_file
+        return cls(master=load_file(path)["master"])

@@ -289,3 +289,58 @@ extern "C" dg_status dg_fro2_hutchinson(const dg_plan* p, int32_t n_probes, uint
   }
   return DG_OK;
 }
+
+struct dg_graph {
+  hipGraph_t graph;
+  hipGraphExec_t exec;
+};
+
+extern "C" dg_status dgamp_graph_create(const dg_plan* p, const float* y, const dgamp_opts* o,
+                                        dgamp_state* st, double tau_x0, float* mu_out,
+                                        double* log, void* work, dg_graph** out) {
+  DG_ARG_CHECK(p && y && o && st && work && out, "dgamp_graph_create: null argument");
+  DG_ARG_CHECK(o->phase_events == nullptr, "dgamp_graph_create: phase events cannot be captured");
+  hipStream_t cs;
+  DG_HIP(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+  const int32_t t_before = st->t;
+  dg_status rc = DG_OK;
+  hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+  if (e != hipSuccess) {
+    (void)hipStreamDestroy(cs);
+    return hip_fail(e, "hipStreamBeginCapture");
+  }
+  if (tau_x0 > 0) rc = dgamp_state_init(p, st, tau_x0, cs);
+  if (rc == DG_OK) rc = dgamp_iterate(p, y, o, st, mu_out, log, work, cs);
+  hipGraph_t graph = nullptr;
+  e = hipStreamEndCapture(cs, &graph);
+  (void)hipStreamDestroy(cs);
+  st->t = t_before;
+  if (rc != DG_OK) {
+    if (graph) (void)hipGraphDestroy(graph);
+    return rc;
+  }
+  if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
+  hipGraphExec_t exec;
+  e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+  if (e != hipSuccess) {
+    (void)hipGraphDestroy(graph);
+    return hip_fail(e, "hipGraphInstantiate");
+  }
+  dg_graph* g = new dg_graph{graph, exec};
+  *out = g;
+  return DG_OK;
+}
+
+extern "C" dg_status dg_graph_launch(dg_graph* g, void* stream) {
+  DG_ARG_CHECK(g != nullptr, "dg_graph_launch: null graph");
+  DG_HIP(hipGraphLaunch(g->exec, (hipStream_t)stream));
+  return DG_OK;
+}
+
+extern "C" dg_status dg_graph_destroy(dg_graph* g) {
+  if (!g) return DG_OK;
+  (void)hipGraphExecDestroy(g->exec);
+  (void)hipGraphDestroy(g->graph);
+  delete g;
+  return DG_OK;
+}

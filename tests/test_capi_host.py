@@ -15,7 +15,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 def header_functions():
     txt = open(os.path.join(ROOT, "include", "dgampct.h")).read()
     txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
-    names = re.findall(r"^\s*(?:dg_status|size_t|const char\*)\s+(\w+)\s*\(", txt, flags=re.M)
+    names = re.findall(r"^\s*(?:dg_status|size_t|int64_t|const char\*)\s+(\w+)\s*\(", txt, flags=re.M)
     return sorted(set(names))
 
 

@@ -1,0 +1,109 @@
+"""Residual CNN denoiser on MFMA against the FP64 oracle (same BF16-rounded weights).
+
+Tolerances (BF16 activations between layers, FP32 accumulation): the network
+output f has relative L2 error <= 2e-2 and cosine >= 0.999 against FP64;
+gradients per layer cosine >= 0.999; the tangent divergence b^T J_D b / N within
+0.02 of the oracle's tangent divergence for the same probe.
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import cnn as ocnn
+from oracle.probe import rademacher
+from paper_1609_04661_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+
+def bf16_round(a):
+    a = np.asarray(a, dtype=np.float32)
+    u = a.view(np.uint32).astype(np.uint64)
+    u = (u + 0x7FFF + ((u >> 16) & 1)) & 0xFFFF0000
+    return u.astype(np.uint32).view(np.float32).astype(np.float64)
+
+
+def oracle_params(net):
+    return [(bf16_round(w), b) for w, b in net.layers()]
+
+
+def cos(a, b):
+    a, b = np.ravel(a), np.ravel(b)
+    return float(a @ b / (np.linalg.norm(a) * np.linalg.norm(b)))
+
+
+def test_cnn_forward_matches_oracle(gpu_lib):
+    net = gpu_lib.CnnNet(seed=3)
+    params = oracle_params(net)
+    rng = np.random.default_rng(0)
+    imgs = rng.standard_normal((2, 40, 36))
+    out = net.forward(torch.as_tensor(imgs, dtype=torch.float32).cuda())
+    torch.cuda.synchronize()
+    out = out.cpu().double().numpy()
+    for k in range(2):
+        f_ref, _ = ocnn.forward(imgs[k].astype(np.float32).astype(np.float64), params)
+        f_gpu = imgs[k].astype(np.float32) - out[k]
+        assert cos(f_gpu, f_ref) >= 0.999
+        assert np.linalg.norm(f_gpu - f_ref) <= 2e-2 * np.linalg.norm(f_ref)
+
+
+def test_cnn_gradients_match_oracle(gpu_lib):
+    net = gpu_lib.CnnNet(seed=5)
+    params = oracle_params(net)
+    rng = np.random.default_rng(1)
+    clean = rng.standard_normal((2, 24, 20)).astype(np.float32).astype(np.float64)
+    noisy = (clean + 0.3 * rng.standard_normal((2, 24, 20))).astype(np.float32).astype(np.float64)
+    loss = net.train_step(torch.as_tensor(noisy, dtype=torch.float32).cuda(),
+                          torch.as_tensor(clean, dtype=torch.float32).cuda(), lr=1e-30)
+    torch.cuda.synchronize()
+    g_gpu = net.grad.cpu().double().numpy()
+    ref_loss, ref_grads = 0.0, None
+    for k in range(2):
+        l, g = ocnn.mse_loss_and_grads(noisy[k], clean[k], params)
+        ref_loss += 0.5 * l
+        g = [(0.5 * dw, 0.5 * db) for dw, db in g]
+        ref_grads = g if ref_grads is None else [(a + c, b + d) for (a, b), (c, d) in zip(ref_grads, g)]
+    assert abs(float(loss.item()) - ref_loss) <= 2e-2 * ref_loss
+    off = 0
+    for l, (dw, db) in enumerate(ref_grads):
+        gw = g_gpu[off:off + dw.size].reshape(dw.shape)
+        gb = g_gpu[off + dw.size:off + dw.size + db.size]
+        off += dw.size + db.size
+        assert cos(gw, dw) >= 0.999, (l, cos(gw, dw))
+        assert np.linalg.norm(gw - dw) <= 5e-2 * np.linalg.norm(dw), l
+        assert cos(gb, db) >= 0.999 or np.linalg.norm(db) < 1e-8, (l, cos(gb, db))
+
+
+def test_cnn_denoise_and_tangent_divergence(gpu_lib):
+    I = 48
+    g = synth.geometry(synth.PARALLEL, I, 1.0, 4, I + 1, math.pi)
+    plan = gpu_lib.Plan(g)
+    net = gpu_lib.CnnNet(seed=7)
+    params = oracle_params(net)
+    r = np.random.default_rng(2).standard_normal((I, I)).astype(np.float32).astype(np.float64)
+    p = gpu_lib.make_params(gpu_lib.DEN_CNN, net=net, n_pixels=I * I)
+    x, div = gpu_lib.denoise(plan, gpu_lib.DEN_CNN, p, torch.as_tensor(r, dtype=torch.float32).cuda(),
+                             torch.ones(1, dtype=torch.float64, device="cuda"), probe_seed=11,
+                             iteration=2)
+    torch.cuda.synchronize()
+    x_ref = ocnn.denoise(r, params)
+    f_ref = r - x_ref
+    f_gpu = r - x.cpu().double().numpy()
+    assert cos(f_gpu, f_ref) >= 0.999
+    b = rademacher(11, 2, I * I).reshape(I, I)
+    d_ref = ocnn.tangent_divergence(r, params, b)
+    assert abs(float(div.item()) - d_ref) <= 0.02, (float(div.item()), d_ref)
+
+
+def test_cnn_training_reduces_loss(gpu_lib):
+    net = gpu_lib.CnnNet(seed=9)
+    rng = np.random.default_rng(3)
+    yy, xx = np.mgrid[0:32, 0:32]
+    clean = np.stack([np.sin(xx / (3 + k)) * np.cos(yy / (4 + k)) for k in range(4)])
+    noisy = clean + 0.2 * rng.standard_normal(clean.shape)
+    n_t = torch.as_tensor(noisy, dtype=torch.float32).cuda()
+    c_t = torch.as_tensor(clean, dtype=torch.float32).cuda()
+    losses = [float(net.train_step(n_t, c_t, lr=1e-3).item()) for _ in range(60)]
+    assert losses[-1] < 0.5 * losses[0], losses[::10]
