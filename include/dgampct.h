@@ -254,6 +254,68 @@ dg_status dg_graph_destroy(dg_graph* g);
 dg_status dg_fro2_hutchinson(const dg_plan* plan, int32_t n_probes, uint64_t seed,
                              double* out, void* work, void* stream);
 
+/* ------------------------------------------------------------------ batch
+ * Many independent slices in one set of launches (not in the paper, whose
+ * method reconstructs one slice at a time; every slice runs exactly the
+ * iteration of Algorithm 1 that dgamp_iterate runs, with its own scalars).
+ * Slices may differ in image side and view count; each phase of an
+ * iteration (V^-1, A, channel, A^T, V^-1 + r update, denoiser, divergence)
+ * is one launch over the blocks of every slice.  Small slices that would
+ * leave most compute units idle on their own fill the chip together.
+ *
+ * Layout: the batch's images and sinograms are packed back to back; slice k
+ * owns x[img_off[k] .. img_off[k+1]) (row-major I_k x I_k) and
+ * y, s[sino_off[k] .. sino_off[k+1]) (view-major), and scal[k*DG_NSCAL ..].
+ * All buffers are device memory owned by the caller.                        */
+typedef struct dg_batch dg_batch;
+
+/* Build one plan per geometry (n in 1..4096, every image side supported by
+ * the preconditioner FFT, else DG_ERR_UNSUPPORTED).                         */
+dg_status dg_batch_create(const dg_geom* geoms, int32_t n, dg_batch** out);
+dg_status dg_batch_destroy(dg_batch* b);
+/* Host arrays of n+1 entries: element offsets of every slice's image and
+ * sinogram (the last entry is the total).                                   */
+dg_status dg_batch_layout(const dg_batch* b, int64_t* img_off, int64_t* sino_off);
+/* Bytes of the work buffer dg_batch_bind takes (256-byte aligned device).  */
+size_t dg_batch_workspace_bytes(const dg_batch* b);
+/* Bind the batch to its buffers and build the per-slice argument tables
+ * (device uploads; call outside any stream capture).  y: counts; i0, fro2:
+ * host arrays of n (source intensity and ||A V^-1||_F^2 per slice); x, s,
+ * scal: the state (as dgamp_state, packed); mu_out: NULL, or where
+ * mu = V^-1 x lands when an iteration call asks for it.  den_kind is
+ * DG_DEN_NLM (dg_nlm_params) or DG_DEN_CNN (dg_cnn_params; all slices of
+ * one side, its work buffer sized for dg_cnn_workspace_bytes(totN));
+ * DG_DEN_HAAR is DG_ERR_UNSUPPORTED here.  den_params is copied.           */
+dg_status dg_batch_bind(dg_batch* b, const float* y, const double* i0, const double* fro2,
+                        float* x, float* s, double* scal, float* mu_out, int32_t den_kind,
+                        const void* den_params, double eps_rel, void* work);
+/* Every slice's state as dgamp_state_init sets it.                          */
+dg_status dg_batch_state_init(dg_batch* b, double tau_x0, void* stream);
+/* n_iter iterations t0 .. t0+n_iter-1 of every slice, then mu_out when
+ * write_mu != 0.  Arguments as the fields of dgamp_opts.  Slice k's result
+ * equals that of dgamp_iterate on its own plan with the same arguments.     */
+dg_status dgamp_batch_iterate(dg_batch* b, int32_t n_iter, int32_t t0, uint64_t probe_seed,
+                              double eta_x, double eta_s, int32_t onsager,
+                              int32_t channel_mode, int32_t write_mu, void* stream);
+/* dg_batch_state_init + dgamp_batch_iterate(t0 = 0, write_mu when mu_out
+ * was bound) captured as one graph, replayed by dg_graph_launch.            */
+dg_status dg_batch_graph_create(dg_batch* b, double tau_x0, int32_t n_iter,
+                                uint64_t probe_seed, double eta_x, double eta_s,
+                                int32_t onsager, int32_t channel_mode, dg_graph** out);
+
+/* ------------------------------------------------------------------ autotune
+ * The forward projector marches every ray in 2, 4 or 8 segments per block
+ * (variants 0, 1, 2); all variants give bit-identical sinograms.  These
+ * calls time each variant `reps` times on the given data (synchronising the
+ * stream) and keep the fastest for later calls on the plan or batch.  The
+ * batch tuner overwrites the batch's z work buffer only; the plan tuner
+ * writes `sino` (img_t may be NULL).                                        */
+dg_status dg_batch_autotune(dg_batch* b, int32_t reps, void* stream);
+int32_t dg_batch_projector_variant(const dg_batch* b);
+dg_status dg_plan_autotune(dg_plan* plan, const float* img, const float* img_t, float* sino,
+                           int32_t reps, void* stream);
+int32_t dg_plan_projector_variant(const dg_plan* plan);
+
 #ifdef __cplusplus
 }
 #endif

@@ -31,7 +31,10 @@ EXPORTS = ("dg_plan_create", "dg_plan_destroy", "dg_workspace_bytes", "dg_channe
            "denoise", "dgamp_state_init", "dgamp_iterate", "dg_fro2_hutchinson",
            "dgamp_graph_create", "dg_graph_launch", "dg_graph_destroy", "dg_cnn_weight_bytes",
            "dg_cnn_param_count", "dg_cnn_workspace_bytes", "dg_cnn_pack", "dg_cnn_forward",
-           "dg_cnn_train_step")
+           "dg_cnn_train_step", "dg_batch_create", "dg_batch_destroy", "dg_batch_layout",
+           "dg_batch_workspace_bytes", "dg_batch_bind", "dg_batch_state_init",
+           "dgamp_batch_iterate", "dg_batch_graph_create", "dg_batch_autotune",
+           "dg_batch_projector_variant", "dg_plan_autotune", "dg_plan_projector_variant")
 
 
 class DgError(RuntimeError):
@@ -112,7 +115,24 @@ def load():
         "dg_cnn_forward": ([_VP, i32, i32, i32, _VP, _VP, _VP, _VP], i32),
         "dg_cnn_train_step": ([_VP, _VP, i32, i32, i32, _VP, _VP, _VP, _VP, _VP, i32, dbl, _VP,
                                _VP, _VP], i32),
+        "dg_batch_create": ([ctypes.POINTER(Geom), i32, ctypes.POINTER(_VP)], i32),
+        "dg_batch_destroy": ([_VP], i32),
+        "dg_batch_layout": ([_VP, ctypes.POINTER(i64), ctypes.POINTER(i64)], i32),
+        "dg_batch_workspace_bytes": ([_VP], sz),
+        "dg_batch_bind": ([_VP, _VP, ctypes.POINTER(dbl), ctypes.POINTER(dbl), _VP, _VP, _VP, _VP,
+                           i32, _VP, dbl, _VP], i32),
+        "dg_batch_state_init": ([_VP, dbl, _VP], i32),
+        "dgamp_batch_iterate": ([_VP, i32, i32, u64, dbl, dbl, i32, i32, i32, _VP], i32),
+        "dg_batch_graph_create": ([_VP, dbl, i32, u64, dbl, dbl, i32, i32, ctypes.POINTER(_VP)],
+                                  i32),
+        "dg_batch_autotune": ([_VP, i32, _VP], i32),
+        "dg_batch_projector_variant": ([_VP], i32),
+        "dg_plan_autotune": ([_VP, _VP, _VP, _VP, i32, _VP], i32),
+        "dg_plan_projector_variant": ([_VP], i32),
     }
+    missing = set(EXPORTS) - set(sig)
+    if missing:
+        raise DgError("no ctypes signature for %s" % sorted(missing))
     for name, (args, res) in sig.items():
         f = getattr(L, name)
         f.argtypes = args
@@ -167,6 +187,20 @@ class Plan:
     def workspace(self, op):
         n = int(_lib.dg_workspace_bytes(self._h, op))
         return torch.empty(max(n, 256), dtype=torch.uint8, device="cuda")
+
+    def autotune(self, img, img_t=None, sino=None, reps=10):
+        """Time the projector variants on `img` and keep the fastest."""
+        if sino is None:
+            sino = torch.empty(self.shape_sino, dtype=torch.float32, device="cuda")
+        _check(_lib.dg_plan_autotune(self._h, _ptr(img, torch.float32, self.N, "img"),
+                                     _ptr(img_t, torch.float32, self.N, "img_t"),
+                                     _ptr(sino, torch.float32, self.M, "sino"), int(reps),
+                                     _stream()))
+        return int(_lib.dg_plan_projector_variant(self._h))
+
+    @property
+    def projector_variant(self):
+        return int(_lib.dg_plan_projector_variant(self._h))
 
     def __del__(self):
         try:
@@ -332,6 +366,97 @@ class DgampGraph:
                 self._h = None
         except Exception:
             pass
+
+
+class Batch:
+    """Many slices (list of geometry dicts, image sides and view counts may
+    differ) reconstructed together: images, sinograms and scalar blocks are
+    packed back to back (``img_off``/``sino_off``); ``image(k)``/``sino(k)``
+    give views of slice k."""
+
+    def __init__(self, geoms):
+        L = load()
+        self.geoms = [dict(g) for g in geoms]
+        n = len(self.geoms)
+        arr = (Geom * n)(*[Geom(**{k: g[k] for k, _ in Geom._fields_}) for g in self.geoms])
+        h = _VP()
+        _check(L.dg_batch_create(arr, n, ctypes.byref(h)))
+        self._h = h
+        self.n = n
+        io = (ctypes.c_int64 * (n + 1))()
+        so = (ctypes.c_int64 * (n + 1))()
+        _check(L.dg_batch_layout(h, io, so))
+        self.img_off = [int(v) for v in io]
+        self.sino_off = [int(v) for v in so]
+        self.sides = [int(g["n"]) for g in self.geoms]
+        self.sino_shapes = [(int(g["n_views"]), int(g["n_bins"])) for g in self.geoms]
+        self.totN, self.totM = self.img_off[-1], self.sino_off[-1]
+        self.x = torch.zeros(self.totN, dtype=torch.float32, device="cuda")
+        self.s = torch.zeros(self.totM, dtype=torch.float32, device="cuda")
+        self.scal = torch.zeros(n * NSCAL, dtype=torch.float64, device="cuda")
+        self.work = torch.empty(max(int(L.dg_batch_workspace_bytes(h)), 256), dtype=torch.uint8,
+                                device="cuda")
+        self.keep = None
+
+    def image(self, t, k):
+        return t[self.img_off[k]:self.img_off[k + 1]].view(self.sides[k], self.sides[k])
+
+    def sino(self, t, k):
+        return t[self.sino_off[k]:self.sino_off[k + 1]].view(*self.sino_shapes[k])
+
+    def bind(self, y, i0, fro2, den_kind, den_params, mu_out=None, eps_rel=1e-3):
+        """y: packed counts (totM); i0, fro2: one float per slice."""
+        n = self.n
+        i0a = (ctypes.c_double * n)(*[float(v) for v in i0])
+        fra = (ctypes.c_double * n)(*[float(v) for v in fro2])
+        _check(_lib.dg_batch_bind(self._h, _ptr(y, torch.float32, self.totM, "y"), i0a, fra,
+                                  _ptr(self.x, torch.float32), _ptr(self.s, torch.float32),
+                                  _ptr(self.scal, torch.float64),
+                                  _ptr(mu_out, torch.float32, self.totN, "mu_out"), int(den_kind),
+                                  ctypes.cast(ctypes.pointer(den_params), ctypes.c_void_p),
+                                  float(eps_rel), _ptr(self.work, torch.uint8)))
+        self.keep = (y, den_params, mu_out)
+
+    def state_init(self, tau_x0=1.0):
+        _check(_lib.dg_batch_state_init(self._h, float(tau_x0), _stream()))
+
+    def iterate(self, n_iter, t0=0, probe_seed=0, eta_x=1.0, eta_s=1.0, onsager=True,
+                channel_mode=CHANNEL_LAPLACE, write_mu=False):
+        _check(_lib.dgamp_batch_iterate(self._h, int(n_iter), int(t0), int(probe_seed),
+                                        float(eta_x), float(eta_s), 1 if onsager else 0,
+                                        int(channel_mode), 1 if write_mu else 0, _stream()))
+
+    def autotune(self, reps=10):
+        _check(_lib.dg_batch_autotune(self._h, int(reps), _stream()))
+        return int(_lib.dg_batch_projector_variant(self._h))
+
+    @property
+    def projector_variant(self):
+        return int(_lib.dg_batch_projector_variant(self._h))
+
+    def graph(self, n_iter, tau_x0=1.0, probe_seed=0, eta_x=1.0, eta_s=1.0, onsager=True,
+              channel_mode=CHANNEL_LAPLACE):
+        return BatchGraph(self, n_iter, tau_x0, probe_seed, eta_x, eta_s, onsager, channel_mode)
+
+    def __del__(self):
+        try:
+            if getattr(self, "_h", None) and _lib is not None:
+                _lib.dg_batch_destroy(self._h)
+                self._h = None
+        except Exception:
+            pass
+
+
+class BatchGraph(DgampGraph):
+    """A captured batched reconstruction (state reset + n_iter iterations + mu_out)."""
+
+    def __init__(self, batch, n_iter, tau_x0, probe_seed, eta_x, eta_s, onsager, channel_mode):
+        self.keep = batch
+        h = _VP()
+        _check(_lib.dg_batch_graph_create(batch._h, float(tau_x0), int(n_iter), int(probe_seed),
+                                          float(eta_x), float(eta_s), 1 if onsager else 0,
+                                          int(channel_mode), ctypes.byref(h)))
+        self._h = h
 
 
 class CnnNet:

@@ -77,69 +77,87 @@ __device__ __forceinline__ ChanOut poisson_channel(float p, float y, float tau_p
 //   tau_s (damped likewise) and tau_r = N / (fro2 tau_s).
 // Standalone form: p given, tau_p from a device scalar, writes s and tau_s.
 template <bool kFused>
-__global__ void __launch_bounds__(kChanBlock)
-channel_kernel(int64_t M, const float* __restrict__ zp, const float* __restrict__ y,
-               float* __restrict__ s_io, float* __restrict__ s_out, const double* tau_p_ptr,
-               double* scal, double* tau_s_out, double i0, int mode, double fro2, double N,
-               double eta_s, int onsager, int t, double* __restrict__ partials) {
-  __shared__ double red[kChanBlock / 64];
+__device__ void channel_body(const ChanArgs& A, int blk, int mode, double eta_s, int onsager,
+                             int t, double* red) {
   double tau_p_d;
   if (kFused) {
-    if (scal[DG_S_STATUS] != 0.0) return;
-    tau_p_d = fro2 * scal[DG_S_TAU_X] / (double)M;
+    if (A.scal[DG_S_STATUS] != 0.0) return;
+    tau_p_d = A.fro2 * A.scal[DG_S_TAU_X] / (double)A.M;
   } else {
-    tau_p_d = *tau_p_ptr;
+    tau_p_d = *A.tau_p_ptr;
   }
   const float tau_p = (float)tau_p_d;
-  const float ln_i0 = (float)log(i0);
+  const float ln_i0 = (float)log(A.i0);
   const float eta = (float)eta_s;
   double acc = 0.0;
-  for (int64_t k = (int64_t)blockIdx.x * kChanBlock + threadIdx.x; k < M;
-       k += (int64_t)gridDim.x * kChanBlock) {
-    float p = zp[k];
+  for (int64_t k = (int64_t)blk * kChanBlock + threadIdx.x; k < A.M;
+       k += (int64_t)A.nblk * kChanBlock) {
+    float p = A.zp[k];
     float s_prev = 0.0f;
     if (kFused) {
-      s_prev = s_io[k];
+      s_prev = A.s_io[k];
       if (onsager) p = __fmaf_rn(-tau_p, s_prev, p);
     }
-    ChanOut o = poisson_channel(p, y[k], tau_p, ln_i0, mode);
+    ChanOut o = poisson_channel(p, A.y[k], tau_p, ln_i0, mode);
     float s = o.s;
     if (kFused) {
       if (t > 0) s = __fmaf_rn(eta, s, (1.0f - eta) * s_prev);
-      s_io[k] = s;
+      A.s_io[k] = s;
     } else {
-      s_out[k] = s;
+      A.s_out[k] = s;
     }
     acc += (double)o.one_minus_v;
   }
   double bs = block_sum(acc, red);
-  if (threadIdx.x == 0) partials[blockIdx.x] = bs;
+  if (threadIdx.x == 0) A.partials[blk] = bs;
 }
 
 // tau_s (and in the iteration: its damping, tau_p, tau_r, status) from the
 // per-block partial sums.
 template <bool kFused>
-__global__ void __launch_bounds__(256)
-channel_finish(const double* __restrict__ partials, int nblk, int64_t M, const double* tau_p_ptr,
-               double* scal, double* tau_s_out, double fro2, double N, double eta_s, int t) {
-  __shared__ double red[4];
-  if (kFused && scal[DG_S_STATUS] != 0.0) return;
-  const double tot = finish_sum(partials, nblk, red);
+__device__ void channel_finish_body(const ChanArgs& A, double eta_s, int t, double* red) {
+  if (kFused && A.scal[DG_S_STATUS] != 0.0) return;
+  const double tot = finish_sum(A.partials, A.nblk, red);
   if (threadIdx.x == 0) {
-    const double tau_p = kFused ? fro2 * scal[DG_S_TAU_X] / (double)M : *tau_p_ptr;
-    double tau_s = tot / ((double)M * tau_p);
+    const double tau_p = kFused ? A.fro2 * A.scal[DG_S_TAU_X] / (double)A.M : *A.tau_p_ptr;
+    double tau_s = tot / ((double)A.M * tau_p);
     if (kFused) {
+      double* scal = A.scal;
       if (t > 0) tau_s = eta_s * tau_s + (1.0 - eta_s) * scal[DG_S_TAU_S];
-      const double tau_r = N / (fro2 * tau_s);
+      const double tau_r = A.N / (A.fro2 * tau_s);
       scal[DG_S_TAU_P] = tau_p;
       scal[DG_S_TAU_S] = tau_s;
       scal[DG_S_TAU_R] = tau_r;
       if (!(tau_s > 0.0) || !isfinite(tau_s) || !(tau_r > 0.0) || !isfinite(tau_r))
         scal[DG_S_STATUS] = (double)(t + 1);
     } else {
-      *tau_s_out = tau_s;
+      *A.tau_s_out = tau_s;
     }
   }
+}
+
+template <bool kFused>
+__global__ void __launch_bounds__(kChanBlock)
+channel_kernel(ChanArgs A, int mode, double eta_s, int onsager, int t) {
+  __shared__ double red[kChanBlock / 64];
+  channel_body<kFused>(A, blockIdx.x, mode, eta_s, onsager, t, red);
+}
+__global__ void __launch_bounds__(kChanBlock)
+channel_batch(const ChanArgs* __restrict__ T, const int* __restrict__ prefix, int n, int mode,
+              double eta_s, int onsager, int t) {
+  __shared__ double red[kChanBlock / 64];
+  const int s = slice_of(prefix, n, blockIdx.x);
+  channel_body<true>(T[s], blockIdx.x - prefix[s], mode, eta_s, onsager, t, red);
+}
+template <bool kFused>
+__global__ void __launch_bounds__(256) channel_finish(ChanArgs A, double eta_s, int t) {
+  __shared__ double red[4];
+  channel_finish_body<kFused>(A, eta_s, t, red);
+}
+__global__ void __launch_bounds__(256)
+channel_finish_batch(const ChanArgs* __restrict__ T, double eta_s, int t) {
+  __shared__ double red[4];
+  channel_finish_body<true>(T[blockIdx.x], eta_s, t, red);
 }
 
 unsigned int channel_grid(int64_t M) { return grid_for(M, kChanBlock, kChanMaxBlocks); }
@@ -148,12 +166,22 @@ dg_status launch_channel_fused(int64_t M, const float* z, const float* y, float*
                                double i0, int mode, double fro2, double N, double eta_s,
                                int onsager, int t, double* partials, hipStream_t st) {
   const unsigned int g = channel_grid(M);
-  hipLaunchKernelGGL(channel_kernel<true>, dim3(g), dim3(kChanBlock), 0, st, M, z, y, s, nullptr,
-                     nullptr, scal, nullptr, i0, mode, fro2, N, eta_s, onsager, t, partials);
+  ChanArgs A{M, z, y, s, nullptr, nullptr, scal, nullptr, i0, fro2, N, partials, (int)g};
+  hipLaunchKernelGGL(channel_kernel<true>, dim3(g), dim3(kChanBlock), 0, st, A, mode, eta_s,
+                     onsager, t);
   DG_LAUNCH_CHECK("channel_kernel<fused>");
-  hipLaunchKernelGGL(channel_finish<true>, dim3(1), dim3(256), 0, st, partials, (int)g, M, nullptr,
-                     scal, nullptr, fro2, N, eta_s, t);
+  hipLaunchKernelGGL(channel_finish<true>, dim3(1), dim3(256), 0, st, A, eta_s, t);
   DG_LAUNCH_CHECK("channel_finish<fused>");
+  return DG_OK;
+}
+
+dg_status launch_channel_batch(const ChanArgs* T, const int* prefix, int n, int total, int mode,
+                               double eta_s, int onsager, int t, hipStream_t st) {
+  hipLaunchKernelGGL(channel_batch, dim3(total), dim3(kChanBlock), 0, st, T, prefix, n, mode, eta_s,
+                     onsager, t);
+  DG_LAUNCH_CHECK("channel_batch");
+  hipLaunchKernelGGL(channel_finish_batch, dim3(n), dim3(256), 0, st, T, eta_s, t);
+  DG_LAUNCH_CHECK("channel_finish_batch");
   return DG_OK;
 }
 
@@ -188,11 +216,10 @@ extern "C" dg_status gamp_poisson_out(int64_t m, const float* p, const float* y,
   hipStream_t st = (hipStream_t)stream;
   double* partials = (double*)((char*)work + 256);
   const unsigned int g = channel_grid(m);
-  hipLaunchKernelGGL(channel_kernel<false>, dim3(g), dim3(kChanBlock), 0, st, m, p, y, nullptr,
-                     s_out, tau_p, nullptr, tau_s_out, i0, mode, 0.0, 0.0, 1.0, 0, 0, partials);
+  ChanArgs A{m, p, y, nullptr, s_out, tau_p, nullptr, tau_s_out, i0, 0.0, 0.0, partials, (int)g};
+  hipLaunchKernelGGL(channel_kernel<false>, dim3(g), dim3(kChanBlock), 0, st, A, mode, 1.0, 0, 0);
   DG_LAUNCH_CHECK("channel_kernel");
-  hipLaunchKernelGGL(channel_finish<false>, dim3(1), dim3(256), 0, st, partials, (int)g, m, tau_p,
-                     nullptr, tau_s_out, 0.0, 0.0, 1.0, 0);
+  hipLaunchKernelGGL(channel_finish<false>, dim3(1), dim3(256), 0, st, A, 1.0, 0);
   DG_LAUNCH_CHECK("channel_finish");
   return DG_OK;
 }

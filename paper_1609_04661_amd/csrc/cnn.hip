@@ -246,8 +246,8 @@ __global__ void __launch_bounds__(256)
 cnn_out_kernel(const bf16* __restrict__ act, const void* __restrict__ packed,
                const float* __restrict__ r, const float* __restrict__ xden,
                const float* __restrict__ clean, float* __restrict__ out, int n, int H, int W,
-               int mode, const double* __restrict__ eps_ptr, uint64_t seed, int iter,
-               double* __restrict__ loss_partials, double inv_count) {
+               int mode, const double* __restrict__ eps_ptr, int eps_stride, uint64_t seed,
+               int iter, double* __restrict__ loss_partials, double inv_count) {
   __shared__ double red[4];
   const int64_t pix = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t npix = (int64_t)n * H * W;
@@ -274,7 +274,7 @@ cnn_out_kernel(const bf16* __restrict__ act, const void* __restrict__ packed,
       out[pix] = r[pix] - f;
     } else if (mode == 1) {
       const float b = probe_sign(seed, iter, (uint64_t)rem);
-      out[pix] = __fmaf_rn((float)(*eps_ptr), b - f, xden[pix]);
+      out[pix] = __fmaf_rn((float)eps_ptr[(int64_t)img * eps_stride], b - f, xden[pix]);
     } else {
       const float res = r[pix] - f - clean[pix];
       lsum = (double)res * (double)res;
@@ -580,33 +580,34 @@ static dg_status cnn_forward(const void* packed, const float* r, float* out, int
   if (out) {
     hipLaunchKernelGGL(cnn_out_kernel, dim3(g256(npix)), dim3(256), 0, st, w.act[8], packed, r,
                        (const float*)nullptr, (const float*)nullptr, out, n, H, W, 0,
-                       (const double*)nullptr, (uint64_t)0, 0, (double*)nullptr, 0.0);
+                       (const double*)nullptr, 0, (uint64_t)0, 0, (double*)nullptr, 0.0);
     DG_LAUNCH_CHECK("cnn_out_kernel");
   }
   return DG_OK;
 }
 
-// Tangent pass with the primal ReLU pattern: x_pert = x_den + eps (b - J_f b).
+// Tangent pass with the primal ReLU pattern: x_pert = x_den + eps (b - J_f b),
+// for n images (eps of image k at eps[k * eps_stride]).
 static dg_status cnn_tangent(const void* packed, const float* xden, float* xpert,
-                             const double* eps, uint64_t seed, int iter, int H, int W, CnnWork& w,
-                             hipStream_t st) {
+                             const double* eps, int eps_stride, uint64_t seed, int iter, int n,
+                             int H, int W, CnnWork& w, hipStream_t st) {
   const Packed P = unpack(packed);
-  const int64_t npix = (int64_t)H * W;
+  const int64_t npix = (int64_t)n * H * W;
   hipLaunchKernelGGL(cnn_in_kernel, dim3(g256(npix)), dim3(256), 0, st, (const float*)nullptr,
-                     packed, w.act[0], w.tan[0], 1, H, W, 1, seed, iter, 1);
+                     packed, w.act[0], w.tan[0], n, H, W, 1, seed, iter, 1);
   DG_LAUNCH_CHECK("cnn_in_kernel<tangent>");
-  const int tiles = ((H + kTile - 1) / kTile) * ((W + kTile - 1) / kTile);
+  const int tiles = n * ((H + kTile - 1) / kTile) * ((W + kTile - 1) / kTile);
   int cur = 0;
   for (int l = 0; l < kMid; ++l) {
     hipLaunchKernelGGL(cnn_mid_kernel, dim3(tiles), dim3(256), 0, st, w.tan[cur],
                        P.wm + (size_t)l * 9 * 64 * 64, (const float*)nullptr, w.act[l + 1],
-                       w.tan[cur ^ 1], 1, H, W, 1);
+                       w.tan[cur ^ 1], n, H, W, 1);
     DG_LAUNCH_CHECK("cnn_mid_kernel<tangent>");
     cur ^= 1;
   }
   hipLaunchKernelGGL(cnn_out_kernel, dim3(g256(npix)), dim3(256), 0, st, w.tan[cur], packed,
-                     (const float*)nullptr, xden, (const float*)nullptr, xpert, 1, H, W, 1, eps,
-                     seed, iter, (double*)nullptr, 0.0);
+                     (const float*)nullptr, xden, (const float*)nullptr, xpert, n, H, W, 1, eps,
+                     eps_stride, seed, iter, (double*)nullptr, 0.0);
   DG_LAUNCH_CHECK("cnn_out_kernel<tangent>");
   return DG_OK;
 }
@@ -629,7 +630,20 @@ dg_status cnn_launch_denoise(const dg_plan* p, const void* params, const float* 
   cnn_work_layout((int64_t)p->N, cp->work, &w);
   dg_status rc = cnn_forward(cp->weights, r, x_den, 1, p->I, p->I, w, st);
   if (rc != DG_OK || !x_pert) return rc;
-  return cnn_tangent(cp->weights, x_den, x_pert, eps, seed, iter, p->I, p->I, w, st);
+  return cnn_tangent(cp->weights, x_den, x_pert, eps, 0, seed, iter, 1, p->I, p->I, w, st);
+}
+
+// n slices of one image size, stored back to back (r, x_den, x_pert); the
+// work buffer of `params` must hold dg_cnn_workspace_bytes(n * I * I).
+dg_status cnn_launch_denoise_batch(const void* params, const float* r, const double* scal_eps,
+                                   int eps_stride, uint64_t seed, int iter, float* x_den,
+                                   float* x_pert, int n, int I, hipStream_t st) {
+  const dg_cnn_params* cp = (const dg_cnn_params*)params;
+  CnnWork w;
+  cnn_work_layout((int64_t)n * I * I, cp->work, &w);
+  dg_status rc = cnn_forward(cp->weights, r, x_den, n, I, I, w, st);
+  if (rc != DG_OK) return rc;
+  return cnn_tangent(cp->weights, x_den, x_pert, scal_eps, eps_stride, seed, iter, n, I, I, w, st);
 }
 
 }  // namespace dg
@@ -676,7 +690,7 @@ extern "C" dg_status dg_cnn_train_step(const float* noisy, const float* clean, i
   const unsigned int gb = g256(npix);
   DG_ARG_CHECK(gb <= 65536, "dg_cnn_train_step: batch too large");
   hipLaunchKernelGGL(cnn_out_kernel, dim3(gb), dim3(256), 0, st, cw.act[8], packed, noisy,
-                     (const float*)nullptr, clean, cw.f, n, h, w, 2, (const double*)nullptr,
+                     (const float*)nullptr, clean, cw.f, n, h, w, 2, (const double*)nullptr, 0,
                      (uint64_t)0, 0, cw.dpart, 1.0 / (double)npix);
   DG_LAUNCH_CHECK("cnn_out_kernel<train>");
   hipLaunchKernelGGL(cnn_loss_finish, dim3(1), dim3(256), 0, st, cw.dpart, (int)gb,

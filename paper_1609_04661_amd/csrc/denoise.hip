@@ -47,21 +47,21 @@ __device__ __forceinline__ int reflect_idx(int k, int I) {
 // then vertically with sliding sums (all in registers, no barrier), and turns
 // each sum into a weight.  The four wavefronts' partial sums are added in a
 // fixed order at the end.
+static constexpr int kNlmBX = 2, kNlmBY = 8;
 template <int P>
-__global__ void __launch_bounds__(256)
-nlm_kernel(const float* __restrict__ r, float* __restrict__ out0, float* __restrict__ out1, int I,
-           int S, const double* __restrict__ tau_r_ptr, float hfac,
-           const double* __restrict__ eps_ptr, uint64_t seed, int iter) {
-  constexpr int BX = 2, BY = 8;
+__device__ void nlm_body(const NlmArgs& Ar, int bx, int by, int img, uint64_t seed, int iter,
+                         float* R, float (*red)[64][2 * kNlmBX * kNlmBY]) {
+  constexpr int BX = kNlmBX, BY = kNlmBY;
   constexpr int WX = BX + 2 * P, WY = BY + 2 * P;
-  __shared__ float R[kNlmRegion * kNlmPitch];
-  __shared__ float red[4][64][2 * BX * BY];
-  const int img = blockIdx.z;
-  float* out = img ? out1 : out0;
-  const int ty0 = blockIdx.y * kNlmTile, tx0 = blockIdx.x * kNlmTile;
+  const float* __restrict__ r = Ar.r;
+  const int I = Ar.I, S = Ar.S;
+  const double* __restrict__ tau_r_ptr = Ar.tau_r;
+  const float hfac = Ar.hfac;
+  float* out = img ? Ar.out1 : Ar.out0;
+  const int ty0 = by * kNlmTile, tx0 = bx * kNlmTile;
   const int H0 = S + P;
   const int WR = kNlmTile + 2 * H0;
-  const float eps = img ? (float)(*eps_ptr) : 0.0f;
+  const float eps = img ? (float)(*Ar.eps) : 0.0f;
   for (int e = threadIdx.x; e < WR * WR; e += blockDim.x) {
     const int ri = e / WR, rj = e % WR;
     const int gi = reflect_idx(ty0 - H0 + ri, I), gj = reflect_idx(tx0 - H0 + rj, I);
@@ -161,6 +161,25 @@ nlm_kernel(const float* __restrict__ r, float* __restrict__ out0, float* __restr
     const int gy = ty0 + oy0 + a, gx = tx0 + ox0 + c;
     if (gy < I && gx < I) out[(int64_t)gy * I + gx] = ac / ws;
   }
+}
+
+template <int P>
+__global__ void __launch_bounds__(256) nlm_kernel(NlmArgs A, uint64_t seed, int iter) {
+  __shared__ float R[kNlmRegion * kNlmPitch];
+  __shared__ float red[4][64][2 * kNlmBX * kNlmBY];
+  nlm_body<P>(A, blockIdx.x, blockIdx.y, blockIdx.z, seed, iter, R, red);
+}
+template <int P>
+__global__ void __launch_bounds__(256)
+nlm_batch(const NlmArgs* __restrict__ T, const int* __restrict__ prefix, int n, uint64_t seed,
+          int iter) {
+  __shared__ float R[kNlmRegion * kNlmPitch];
+  __shared__ float red[4][64][2 * kNlmBX * kNlmBY];
+  const int s = slice_of(prefix, n, blockIdx.x);
+  const NlmArgs A = T[s];
+  const int local = blockIdx.x - prefix[s];
+  const int g = (A.I + kNlmTile - 1) / kNlmTile;
+  nlm_body<P>(A, local % g, (local / g) % g, local / (g * g), seed, iter, R, red);
 }
 
 // Haar: one workgroup per B x B block (B = 2^J), dynamic LDS of B*B floats.
@@ -276,37 +295,31 @@ absmax_kernel(const float* __restrict__ r, int64_t N, float* __restrict__ partia
 // Divergence and (inside the iteration) the tau_x update and damping of x.
 //   mode 0: *div_out = div                                  (standalone)
 //   mode 1: scal[DIV] = div, scal[TAU_X] updated, x updated (iteration)
-__global__ void __launch_bounds__(kRedBlock)
-div_kernel(int64_t N, const float* __restrict__ xden, const float* __restrict__ xpert,
-           float* __restrict__ x, const double* __restrict__ eps_ptr, double* div_out,
-           double* scal, int mode, uint64_t seed, int iter, double eta_x, int t,
-           double* __restrict__ partials) {
-  __shared__ double red[kRedBlock / 64];
-  if (mode == 1 && scal[DG_S_STATUS] != 0.0) return;
+__device__ void div_body(const DivArgs& A, int blk, int mode, uint64_t seed, int iter,
+                         double eta_x, int t, double* red) {
+  if (mode == 1 && A.scal[DG_S_STATUS] != 0.0) return;
   const float eta = (float)eta_x;
   double acc = 0.0;
-  for (int64_t k = (int64_t)blockIdx.x * kRedBlock + threadIdx.x; k < N;
-       k += (int64_t)gridDim.x * kRedBlock) {
-    const float d0 = xden[k];
+  for (int64_t k = (int64_t)blk * kRedBlock + threadIdx.x; k < A.N;
+       k += (int64_t)A.nblk * kRedBlock) {
+    const float d0 = A.xden[k];
     const float b = probe_sign(seed, iter, (uint64_t)k);
-    acc += (double)(b * (xpert[k] - d0));
-    if (mode == 1) x[k] = (t > 0) ? __fmaf_rn(eta, d0, (1.0f - eta) * x[k]) : d0;
+    acc += (double)(b * (A.xpert[k] - d0));
+    if (mode == 1) A.x[k] = (t > 0) ? __fmaf_rn(eta, d0, (1.0f - eta) * A.x[k]) : d0;
   }
   double bs = block_sum(acc, red);
-  if (threadIdx.x == 0) partials[blockIdx.x] = bs;
+  if (threadIdx.x == 0) A.partials[blk] = bs;
 }
 
-__global__ void __launch_bounds__(256)
-div_finish(const double* __restrict__ partials, int nblk, int64_t N, const double* eps_ptr,
-           double* div_out, double* scal, int mode, double eta_x, int t) {
-  __shared__ double red[4];
-  if (mode == 1 && scal[DG_S_STATUS] != 0.0) return;
-  const double tot = finish_sum(partials, nblk, red);
+__device__ void div_finish_body(const DivArgs& A, int mode, double eta_x, int t, double* red) {
+  if (mode == 1 && A.scal[DG_S_STATUS] != 0.0) return;
+  const double tot = finish_sum(A.partials, A.nblk, red);
   if (threadIdx.x == 0) {
-    const double div = tot / ((double)N * (*eps_ptr));
+    const double div = tot / ((double)A.N * (*A.eps));
     if (mode == 0) {
-      *div_out = div;
+      *A.div_out = div;
     } else {
+      double* scal = A.scal;
       const double tau_r = scal[DG_S_TAU_R];
       double tau_x = div > 0.0 ? tau_r * div : 1e-12 * tau_r;
       if (!(div > 0.0)) scal[DG_S_CLAMPS] += 1.0;
@@ -316,6 +329,28 @@ div_finish(const double* __restrict__ partials, int nblk, int64_t N, const doubl
       if (!isfinite(div) || !(tau_x > 0.0) || !isfinite(tau_x)) scal[DG_S_STATUS] = (double)(t + 1);
     }
   }
+}
+
+__global__ void __launch_bounds__(kRedBlock)
+div_kernel(DivArgs A, int mode, uint64_t seed, int iter, double eta_x, int t) {
+  __shared__ double red[kRedBlock / 64];
+  div_body(A, blockIdx.x, mode, seed, iter, eta_x, t, red);
+}
+__global__ void __launch_bounds__(kRedBlock)
+div_batch(const DivArgs* __restrict__ T, const int* __restrict__ prefix, int n, uint64_t seed,
+          int iter, double eta_x, int t) {
+  __shared__ double red[kRedBlock / 64];
+  const int s = slice_of(prefix, n, blockIdx.x);
+  div_body(T[s], blockIdx.x - prefix[s], 1, seed, iter, eta_x, t, red);
+}
+__global__ void __launch_bounds__(256) div_finish(DivArgs A, int mode, double eta_x, int t) {
+  __shared__ double red[4];
+  div_finish_body(A, mode, eta_x, t, red);
+}
+__global__ void __launch_bounds__(256)
+div_finish_batch(const DivArgs* __restrict__ T, double eta_x, int t) {
+  __shared__ double red[4];
+  div_finish_body(T[blockIdx.x], 1, eta_x, t, red);
 }
 
 // b_k for Hutchinson's estimator (probe counter k), as floats.
@@ -414,19 +449,16 @@ dg_status launch_denoiser(const dg_plan* p, int kind, const void* params, const 
   if (kind == DG_DEN_NLM) {
     const dg_nlm_params* np = (const dg_nlm_params*)params;
     dim3 grid((p->I + kNlmTile - 1) / kNlmTile, (p->I + kNlmTile - 1) / kNlmTile, nimg);
-    const float hf = (float)np->hfac;
+    NlmArgs A{r, x_den, x_pert, p->I, np->search_radius, tau_r, eps, (float)np->hfac};
     switch (np->patch_radius) {
       case 1:
-        hipLaunchKernelGGL(nlm_kernel<1>, grid, dim3(256), 0, st, r, x_den, x_pert, p->I,
-                           np->search_radius, tau_r, hf, eps, seed, iter);
+        hipLaunchKernelGGL(nlm_kernel<1>, grid, dim3(256), 0, st, A, seed, iter);
         break;
       case 2:
-        hipLaunchKernelGGL(nlm_kernel<2>, grid, dim3(256), 0, st, r, x_den, x_pert, p->I,
-                           np->search_radius, tau_r, hf, eps, seed, iter);
+        hipLaunchKernelGGL(nlm_kernel<2>, grid, dim3(256), 0, st, A, seed, iter);
         break;
       default:
-        hipLaunchKernelGGL(nlm_kernel<3>, grid, dim3(256), 0, st, r, x_den, x_pert, p->I,
-                           np->search_radius, tau_r, hf, eps, seed, iter);
+        hipLaunchKernelGGL(nlm_kernel<3>, grid, dim3(256), 0, st, A, seed, iter);
         break;
     }
     DG_LAUNCH_CHECK("nlm_kernel");
@@ -450,12 +482,43 @@ dg_status launch_div(const dg_plan* p, const float* xden, const float* xpert, fl
                      const double* eps, double* div_out, double* scal, int mode, uint64_t seed,
                      int iter, double eta_x, int t, double* partials, hipStream_t st) {
   const unsigned int g = red_grid(p->N);
-  hipLaunchKernelGGL(div_kernel, dim3(g), dim3(kRedBlock), 0, st, p->N, xden, xpert, x, eps,
-                     div_out, scal, mode, seed, iter, eta_x, t, partials);
+  DivArgs A{p->N, xden, xpert, x, eps, div_out, scal, partials, (int)g};
+  hipLaunchKernelGGL(div_kernel, dim3(g), dim3(kRedBlock), 0, st, A, mode, seed, iter, eta_x, t);
   DG_LAUNCH_CHECK("div_kernel");
-  hipLaunchKernelGGL(div_finish, dim3(1), dim3(256), 0, st, partials, (int)g, p->N, eps, div_out,
-                     scal, mode, eta_x, t);
+  hipLaunchKernelGGL(div_finish, dim3(1), dim3(256), 0, st, A, mode, eta_x, t);
   DG_LAUNCH_CHECK("div_finish");
+  return DG_OK;
+}
+
+unsigned int nlm_blocks(int I) {
+  const int g = (I + kNlmTile - 1) / kNlmTile;
+  return (unsigned int)(g * g * 2);
+}
+
+dg_status launch_nlm_batch(int P, const NlmArgs* T, const int* prefix, int n, int total,
+                           uint64_t seed, int iter, hipStream_t st) {
+  switch (P) {
+    case 1:
+      hipLaunchKernelGGL(nlm_batch<1>, dim3(total), dim3(256), 0, st, T, prefix, n, seed, iter);
+      break;
+    case 2:
+      hipLaunchKernelGGL(nlm_batch<2>, dim3(total), dim3(256), 0, st, T, prefix, n, seed, iter);
+      break;
+    default:
+      hipLaunchKernelGGL(nlm_batch<3>, dim3(total), dim3(256), 0, st, T, prefix, n, seed, iter);
+      break;
+  }
+  DG_LAUNCH_CHECK("nlm_batch");
+  return DG_OK;
+}
+
+dg_status launch_div_batch(const DivArgs* T, const int* prefix, int n, int total, uint64_t seed,
+                           int iter, double eta_x, int t, hipStream_t st) {
+  hipLaunchKernelGGL(div_batch, dim3(total), dim3(kRedBlock), 0, st, T, prefix, n, seed, iter,
+                     eta_x, t);
+  DG_LAUNCH_CHECK("div_batch");
+  hipLaunchKernelGGL(div_finish_batch, dim3(n), dim3(256), 0, st, T, eta_x, t);
+  DG_LAUNCH_CHECK("div_finish_batch");
   return DG_OK;
 }
 

@@ -67,6 +67,11 @@ struct ViewInfo {
 
 }  // namespace dg
 
+struct dg_graph {
+  hipGraph_t graph;
+  hipGraphExec_t exec;
+};
+
 struct dg_plan {
   dg_geom g;
   int device;
@@ -77,6 +82,7 @@ struct dg_plan {
   float2* twiddle;       // device, I: exp(-2 pi i t / I)
   int fft_ok;            // I supported by the FFT kernels
   double half_diag_px;   // sqrt(2)/2 (fan candidate search)
+  int proj_variant;      // index into kProjSegVariants (autotuned; default 1)
 };
 
 namespace dg {
@@ -173,6 +179,18 @@ __device__ __forceinline__ float finish_max(const float* partials, int n, float*
 // visible, which a device-wide fence inside the producer would do only at
 // the cost of writing back the L2 of every XCD for every block.
 
+// Batched launches: one grid covers many slices.  prefix[s] is the first
+// block of slice s (prefix[0] = 0, prefix[n] = total blocks); a block finds its
+// slice by binary search (uniform per block, so it runs on scalar registers).
+__device__ __forceinline__ int slice_of(const int* __restrict__ prefix, int n, int b) {
+  int lo = 0, hi = n;
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (prefix[mid] <= b) lo = mid; else hi = mid;
+  }
+  return lo;
+}
+
 // Host-side helpers.
 inline unsigned int grid_for(int64_t n, int block, int64_t cap = 65535) {
   int64_t g = (n + block - 1) / block;
@@ -181,11 +199,101 @@ inline unsigned int grid_for(int64_t n, int block, int64_t cap = 65535) {
   return (unsigned int)g;
 }
 
+// Projector / back-projector argument blocks.
+struct ProjArgs {
+  const RayLine* rays;
+  const float* img;
+  const float* img_t;
+  float* sino;
+  int I;
+  int64_t M;
+};
+struct BpArgs {
+  const RayLine* rays;
+  const ViewInfo* views;
+  const float* sino;
+  float* img;
+  int I, nv, nb, fan;
+  float half_diag;
+};
+// Output channel argument block (per slice).  Standalone: zp = p, s_out,
+// tau_p_ptr, tau_s_out.  Fused: zp = z, s_io = s (in: s_prev, out: s), scal.
+struct ChanArgs {
+  int64_t M;
+  const float* zp;
+  const float* y;
+  float* s_io;
+  float* s_out;
+  const double* tau_p_ptr;
+  double* scal;
+  double* tau_s_out;
+  double i0, fro2, N;
+  double* partials;
+  int nblk;  // blocks of the channel launch for this slice
+};
+
+// Non-local-means argument block (per slice): image 0 = r, image 1 = r + eps b.
+struct NlmArgs {
+  const float* r;
+  float* out0;
+  float* out1;
+  int I, S;
+  const double* tau_r;
+  const double* eps;
+  float hfac;
+};
+// Divergence argument block (per slice).
+struct DivArgs {
+  int64_t N;
+  const float* xden;
+  const float* xpert;
+  float* x;
+  const double* eps;
+  double* div_out;
+  double* scal;
+  double* partials;
+  int nblk;
+};
+
+// projector variants (march segments per ray) the autotuner chooses from
+static constexpr int kProjSegVariants[3] = {2, 4, 8};
+static constexpr int kRaysPerBlock = 64;
+
 // Kernels launched by more than one file.
 dg_status launch_transpose(const float* in, float* out, int I, hipStream_t s);
 dg_status launch_project(const dg_plan* p, const float* img, const float* img_t, float* sino,
                          hipStream_t s);
 dg_status launch_backproject(const dg_plan* p, const float* sino, float* img, hipStream_t s);
+
+// Per-launch argument blocks of the preconditioner passes (one per slice in
+// batched launches).
+struct RowsFwdArgs {
+  const float* in;
+  float2* spec;
+  const float2* tw;
+  int I;
+};
+struct ColsArgs {
+  float2* spec;
+  const float2* tw;
+  int I, dir;
+};
+struct RowsInvArgs {
+  const float2* spec;
+  const float2* tw;
+  int I, epilogue;
+  float* out;
+  float* out_t;
+  const float* x;
+  const double* scal;
+  float* partials;
+};
+struct EpsArgs {
+  const float* partials;
+  int n;
+  double eps_rel;
+  double* eps_out;
+};
 
 // Preconditioner passes.  Epilogue of the last (inverse-row) pass:
 enum PrecEpilogue { PREC_PLAIN = 0, PREC_UPDATE_R = 1 };

@@ -290,11 +290,6 @@ extern "C" dg_status dg_fro2_hutchinson(const dg_plan* p, int32_t n_probes, uint
   return DG_OK;
 }
 
-struct dg_graph {
-  hipGraph_t graph;
-  hipGraphExec_t exec;
-};
-
 extern "C" dg_status dgamp_graph_create(const dg_plan* p, const float* y, const dgamp_opts* o,
                                         dgamp_state* st, double tau_x0, float* mu_out,
                                         double* log, void* work, dg_graph** out) {

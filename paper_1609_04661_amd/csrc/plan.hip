@@ -118,6 +118,7 @@ extern "C" dg_status dg_plan_create(const dg_geom* g, dg_plan** out) {
   p->M = (int64_t)g->n_views * g->n_bins;
   p->fft_ok = fft_size_ok(g->n) ? 1 : 0;
   p->half_diag_px = std::sqrt(2.0) * 0.5;
+  p->proj_variant = 1;
   (void)hipGetDevice(&p->device);
 
   std::vector<RayLine> rays((size_t)p->M);

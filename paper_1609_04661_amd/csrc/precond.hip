@@ -98,113 +98,165 @@ __device__ void lds_fft(float2* buf0, float2* buf1, int L, const float2* __restr
 // Forward row pass: rows 2m, 2m+1 packed as one complex row; the two real
 // spectra are separated by conjugate symmetry and stored column-major as
 // spec[k][row], k = 0..I/2.
-__global__ void __launch_bounds__(kFftThreads)
-prec_rows_fwd(const float* __restrict__ in, float2* __restrict__ spec,
-              const float2* __restrict__ tw, int I) {
-  __shared__ float2 a[kMaxFft], b[kMaxFft];
-  const int m = blockIdx.x;
-  const float* r0 = in + (int64_t)(2 * m) * I;
+__device__ void rows_fwd_body(const RowsFwdArgs& A, int m, float2* a, float2* b) {
+  const int I = A.I;
+  const float* r0 = A.in + (int64_t)(2 * m) * I;
   const float* r1 = r0 + I;
   for (int t = threadIdx.x; t < I; t += blockDim.x) a[t] = make_float2(r0[t], r1[t]);
   __syncthreads();
-  lds_fft(a, b, I, tw, false);
+  lds_fft(a, b, I, A.tw, false);
   for (int k = threadIdx.x; k <= I / 2; k += blockDim.x) {
     float2 Z = a[k], Zc = a[(I - k) % I];
     Zc.y = -Zc.y;
     float2 Xa = make_float2(0.5f * (Z.x + Zc.x), 0.5f * (Z.y + Zc.y));
     float2 d = make_float2(0.5f * (Z.x - Zc.x), 0.5f * (Z.y - Zc.y));
     float2 Xb = make_float2(d.y, -d.x);  // d / i
-    float2* col = spec + (int64_t)k * I;
+    float2* col = A.spec + (int64_t)k * I;
     col[2 * m] = Xa;
     col[2 * m + 1] = Xb;
   }
 }
 
 // Column pass with the symbol multiply.
-__global__ void __launch_bounds__(kFftThreads)
-prec_cols(float2* __restrict__ spec, const float2* __restrict__ tw, int I, int dir) {
-  __shared__ float2 a[kMaxFft], b[kMaxFft];
-  const int kx = blockIdx.x;  // 0..I/2
-  float2* col = spec + (int64_t)kx * I;
+__device__ void cols_body(const ColsArgs& A, int kx, float2* a, float2* b) {
+  const int I = A.I;
+  float2* col = A.spec + (int64_t)kx * I;
   for (int t = threadIdx.x; t < I; t += blockDim.x) a[t] = col[t];
   __syncthreads();
-  lds_fft(a, b, I, tw, false);
+  lds_fft(a, b, I, A.tw, false);
   const float dc = 3.52549435174692f * (float)I;  // 4 ln(1 + sqrt 2) I
   for (int t = threadIdx.x; t < I; t += blockDim.x) {
     const int ky = (t <= I / 2) ? t : t - I;
     const float k2 = (float)(kx * kx + ky * ky);
     float c = (k2 > 0.0f) ? (float)I / sqrtf(k2) : dc;  // 1/|rho|
-    float h = (dir > 0) ? rsqrtf(c) : sqrtf(c);
+    float h = (A.dir > 0) ? rsqrtf(c) : sqrtf(c);
     a[t] = make_float2(a[t].x * h, a[t].y * h);
   }
   __syncthreads();
-  lds_fft(a, b, I, tw, true);
+  lds_fft(a, b, I, A.tw, true);
   for (int t = threadIdx.x; t < I; t += blockDim.x) col[t] = a[t];
 }
 
 // Inverse row pass (two real rows per complex FFT) with epilogue.
-__global__ void __launch_bounds__(kFftThreads)
-prec_rows_inv(const float2* __restrict__ spec, const float2* __restrict__ tw, int I,
-              float* __restrict__ out, float* __restrict__ out_t, int epilogue,
-              const float* __restrict__ x, const double* __restrict__ scal,
-              float* __restrict__ partials) {
-  __shared__ float2 a[kMaxFft], b[kMaxFft];
-  __shared__ float red[kFftThreads / 64];
-  const int m = blockIdx.x;
+__device__ void rows_inv_body(const RowsInvArgs& A, int m, float2* a, float2* b, float* red) {
+  const int I = A.I;
   for (int t = threadIdx.x; t < I; t += blockDim.x) {
     float2 ya, yb;
     if (t <= I / 2) {
-      ya = spec[(int64_t)t * I + 2 * m];
-      yb = spec[(int64_t)t * I + 2 * m + 1];
+      ya = A.spec[(int64_t)t * I + 2 * m];
+      yb = A.spec[(int64_t)t * I + 2 * m + 1];
     } else {
-      ya = spec[(int64_t)(I - t) * I + 2 * m];
-      yb = spec[(int64_t)(I - t) * I + 2 * m + 1];
+      ya = A.spec[(int64_t)(I - t) * I + 2 * m];
+      yb = A.spec[(int64_t)(I - t) * I + 2 * m + 1];
       ya.y = -ya.y;
       yb.y = -yb.y;
     }
     a[t] = make_float2(ya.x - yb.y, ya.y + yb.x);  // ya + i yb
   }
   __syncthreads();
-  lds_fft(a, b, I, tw, true);
+  lds_fft(a, b, I, A.tw, true);
   const float scale = 1.0f / ((float)I * (float)I);
-  float tau_r = 0.0f;
-  if (epilogue == PREC_UPDATE_R) tau_r = (float)scal[DG_S_TAU_R];
+  const bool upd = A.epilogue == PREC_UPDATE_R;
+  const float tau_r = upd ? (float)A.scal[DG_S_TAU_R] : 0.0f;
   float amax = 0.0f;
   for (int t = threadIdx.x; t < I; t += blockDim.x) {
     float v0 = a[t].x * scale, v1 = a[t].y * scale;
     const int64_t i0 = (int64_t)(2 * m) * I + t, i1 = i0 + I;
-    if (epilogue == PREC_UPDATE_R) {
-      v0 = __fmaf_rn(tau_r, v0, x[i0]);
-      v1 = __fmaf_rn(tau_r, v1, x[i1]);
+    if (upd) {
+      v0 = __fmaf_rn(tau_r, v0, A.x[i0]);
+      v1 = __fmaf_rn(tau_r, v1, A.x[i1]);
       amax = fmaxf(amax, fmaxf(fabsf(v0), fabsf(v1)));
     }
-    out[i0] = v0;
-    out[i1] = v1;
-    if (out_t) {
-      out_t[(int64_t)t * I + 2 * m] = v0;
-      out_t[(int64_t)t * I + 2 * m + 1] = v1;
+    A.out[i0] = v0;
+    A.out[i1] = v1;
+    if (A.out_t) {
+      A.out_t[(int64_t)t * I + 2 * m] = v0;
+      A.out_t[(int64_t)t * I + 2 * m + 1] = v1;
     }
   }
-  if (epilogue == PREC_UPDATE_R) {
+  if (upd) {
     float bm = block_max(amax, red);
-    if (threadIdx.x == 0) partials[blockIdx.x] = bm;
+    if (threadIdx.x == 0) A.partials[m] = bm;
   }
 }
 
-__global__ void __launch_bounds__(256)
-eps_finish_kernel(const float* __restrict__ partials, int n, double eps_rel, double* eps_out) {
-  __shared__ float red[4];
-  const float gm = finish_max(partials, n, red);
+__device__ void eps_body(const EpsArgs& A, float* red) {
+  const float gm = finish_max(A.partials, A.n, red);
   if (threadIdx.x == 0) {
-    const double e = eps_rel * (double)gm;
-    *eps_out = e > 1e-12 ? e : 1e-12;
+    const double e = A.eps_rel * (double)gm;
+    *A.eps_out = e > 1e-12 ? e : 1e-12;
   }
+}
+
+__global__ void __launch_bounds__(kFftThreads) prec_rows_fwd(RowsFwdArgs A) {
+  __shared__ float2 a[kMaxFft], b[kMaxFft];
+  rows_fwd_body(A, blockIdx.x, a, b);
+}
+__global__ void __launch_bounds__(kFftThreads)
+prec_rows_fwd_batch(const RowsFwdArgs* __restrict__ T, const int* __restrict__ prefix, int n) {
+  __shared__ float2 a[kMaxFft], b[kMaxFft];
+  const int s = slice_of(prefix, n, blockIdx.x);
+  rows_fwd_body(T[s], blockIdx.x - prefix[s], a, b);
+}
+__global__ void __launch_bounds__(kFftThreads) prec_cols(ColsArgs A) {
+  __shared__ float2 a[kMaxFft], b[kMaxFft];
+  cols_body(A, blockIdx.x, a, b);
+}
+__global__ void __launch_bounds__(kFftThreads)
+prec_cols_batch(const ColsArgs* __restrict__ T, const int* __restrict__ prefix, int n) {
+  __shared__ float2 a[kMaxFft], b[kMaxFft];
+  const int s = slice_of(prefix, n, blockIdx.x);
+  cols_body(T[s], blockIdx.x - prefix[s], a, b);
+}
+__global__ void __launch_bounds__(kFftThreads) prec_rows_inv(RowsInvArgs A) {
+  __shared__ float2 a[kMaxFft], b[kMaxFft];
+  __shared__ float red[kFftThreads / 64];
+  rows_inv_body(A, blockIdx.x, a, b, red);
+}
+__global__ void __launch_bounds__(kFftThreads)
+prec_rows_inv_batch(const RowsInvArgs* __restrict__ T, const int* __restrict__ prefix, int n) {
+  __shared__ float2 a[kMaxFft], b[kMaxFft];
+  __shared__ float red[kFftThreads / 64];
+  const int s = slice_of(prefix, n, blockIdx.x);
+  rows_inv_body(T[s], blockIdx.x - prefix[s], a, b, red);
+}
+__global__ void __launch_bounds__(256) eps_finish_kernel(EpsArgs A) {
+  __shared__ float red[4];
+  eps_body(A, red);
+}
+__global__ void __launch_bounds__(256) eps_finish_batch(const EpsArgs* __restrict__ T) {
+  __shared__ float red[4];
+  eps_body(T[blockIdx.x], red);
 }
 
 dg_status launch_eps_finish(const float* partials, int n, double eps_rel, double* eps_out,
                             hipStream_t s) {
-  hipLaunchKernelGGL(eps_finish_kernel, dim3(1), dim3(256), 0, s, partials, n, eps_rel, eps_out);
+  EpsArgs A{partials, n, eps_rel, eps_out};
+  hipLaunchKernelGGL(eps_finish_kernel, dim3(1), dim3(256), 0, s, A);
   DG_LAUNCH_CHECK("eps_finish_kernel");
+  return DG_OK;
+}
+
+dg_status launch_prec_batch(int pass, const void* table, const int* prefix, int n, int total,
+                            hipStream_t s) {
+  switch (pass) {
+    case 0:
+      hipLaunchKernelGGL(prec_rows_fwd_batch, dim3(total), dim3(kFftThreads), 0, s,
+                         (const RowsFwdArgs*)table, prefix, n);
+      break;
+    case 1:
+      hipLaunchKernelGGL(prec_cols_batch, dim3(total), dim3(kFftThreads), 0, s,
+                         (const ColsArgs*)table, prefix, n);
+      break;
+    case 2:
+      hipLaunchKernelGGL(prec_rows_inv_batch, dim3(total), dim3(kFftThreads), 0, s,
+                         (const RowsInvArgs*)table, prefix, n);
+      break;
+    default:
+      hipLaunchKernelGGL(eps_finish_batch, dim3(n), dim3(256), 0, s, (const EpsArgs*)table);
+      break;
+  }
+  DG_LAUNCH_CHECK("prec batch");
   return DG_OK;
 }
 
@@ -214,14 +266,14 @@ dg_status launch_precondition(const dg_plan* p, const PrecArgs& a, hipStream_t s
     return DG_ERR_UNSUPPORTED;
   }
   const int I = p->I;
-  hipLaunchKernelGGL(prec_rows_fwd, dim3(I / 2), dim3(kFftThreads), 0, s, a.in, a.spec,
-                     p->twiddle, I);
+  RowsFwdArgs f{a.in, a.spec, p->twiddle, I};
+  hipLaunchKernelGGL(prec_rows_fwd, dim3(I / 2), dim3(kFftThreads), 0, s, f);
   DG_LAUNCH_CHECK("prec_rows_fwd");
-  hipLaunchKernelGGL(prec_cols, dim3(I / 2 + 1), dim3(kFftThreads), 0, s, a.spec, p->twiddle, I,
-                     a.dir);
+  ColsArgs c{a.spec, p->twiddle, I, a.dir};
+  hipLaunchKernelGGL(prec_cols, dim3(I / 2 + 1), dim3(kFftThreads), 0, s, c);
   DG_LAUNCH_CHECK("prec_cols");
-  hipLaunchKernelGGL(prec_rows_inv, dim3(I / 2), dim3(kFftThreads), 0, s, a.spec, p->twiddle, I,
-                     a.out, a.out_t, a.epilogue, a.x, a.scal, a.partials);
+  RowsInvArgs r{a.spec, p->twiddle, I, a.epilogue, a.out, a.out_t, a.x, a.scal, a.partials};
+  hipLaunchKernelGGL(prec_rows_inv, dim3(I / 2), dim3(kFftThreads), 0, s, r);
   DG_LAUNCH_CHECK("prec_rows_inv");
   if (a.epilogue == PREC_UPDATE_R)
     return launch_eps_finish(a.partials, I / 2, a.eps_rel, a.scal_out + DG_S_EPS, s);

@@ -16,31 +16,28 @@
 
 namespace dg {
 
-static constexpr int kRaysPerBlock = 64, kSegs = 4;
-static constexpr int kProjBlock = kRaysPerBlock * kSegs;
 static constexpr int kBpBlockX = 64, kBpBlockY = 4;
 
-// Block = kRaysPerBlock rays x kSegs segments: wavefront w marches segment w
+// Block = kRaysPerBlock rays x SEGS segments: wavefront w marches segment w
 // of the rays' major-index range for 64 consecutive rays (consecutive bins of
-// one view, so their reads stay coalesced), and the kSegs partial sums are
-// added in a fixed order.  Splitting the march gives kSegs times more
+// one view, so their reads stay coalesced), and the SEGS partial sums are
+// added in a fixed order.  Splitting the march gives SEGS times more
 // wavefronts to hide memory latency than one thread per ray.
-__global__ void __launch_bounds__(kProjBlock)
-project_kernel(const RayLine* __restrict__ rays, const float* __restrict__ img,
-               const float* __restrict__ img_t, float* __restrict__ sino, int I, int64_t M) {
-  __shared__ float part[kSegs][kRaysPerBlock];
+template <int SEGS>
+__device__ void project_body(const ProjArgs& A, int blk, float (*part)[kRaysPerBlock]) {
   const int lane = threadIdx.x % kRaysPerBlock, seg = threadIdx.x / kRaysPerBlock;
-  const int64_t r = (int64_t)blockIdx.x * kRaysPerBlock + lane;
+  const int64_t r = (int64_t)blk * kRaysPerBlock + lane;
+  const int I = A.I;
   float acc = 0.0f;
   RayLine L;
-  if (r < M) {
-    L = rays[r];
+  if (r < A.M) {
+    L = A.rays[r];
     const bool steep = L.pl < 0.0f;
     // Pixel (row i, col j).  Steep: major = row, cross = col -> img[k*I + p].
     // Flat: major = col, cross = row -> img[p*I + k] = img_t[k*I + p].
     // major_rows: the buffer read is laid out with the major index as its row.
-    const bool major_rows = steep || (img_t != nullptr);
-    const float* base = (steep || img_t == nullptr) ? img : img_t;
+    const bool major_rows = steep || (A.img_t != nullptr);
+    const float* base = (steep || A.img_t == nullptr) ? A.img : A.img_t;
 
     // Major-index range where q(k) lies in (-1, I): candidates exist only there.
     int k0 = 0, k1 = I - 1;
@@ -54,7 +51,7 @@ project_kernel(const RayLine* __restrict__ rays, const float* __restrict__ img,
     }
     // this wavefront's share of [k0, k1]
     const int len = k1 - k0 + 1;
-    const int chunk = (len + kSegs - 1) / kSegs;
+    const int chunk = (len + SEGS - 1) / SEGS;
     const int ka = k0 + seg * chunk;
     const int kb = min(k1, ka + chunk - 1);
     int64_t q = L.q0_fx + L.m_fx * (int64_t)ka;  // exact: advanced by m_fx per step
@@ -80,12 +77,25 @@ project_kernel(const RayLine* __restrict__ rays, const float* __restrict__ img,
   }
   part[seg][lane] = acc;
   __syncthreads();
-  if (seg == 0 && r < M) {
+  if (seg == 0 && r < A.M) {
     float t = part[0][lane];
 #pragma unroll
-    for (int g = 1; g < kSegs; ++g) t += part[g][lane];
-    sino[r] = t * fabsf(L.pl);
+    for (int g = 1; g < SEGS; ++g) t += part[g][lane];
+    A.sino[r] = t * fabsf(L.pl);
   }
+}
+
+template <int SEGS>
+__global__ void __launch_bounds__(kRaysPerBlock * SEGS) project_kernel(ProjArgs A) {
+  __shared__ float part[SEGS][kRaysPerBlock];
+  project_body<SEGS>(A, blockIdx.x, part);
+}
+template <int SEGS>
+__global__ void __launch_bounds__(kRaysPerBlock * SEGS)
+project_batch(const ProjArgs* __restrict__ T, const int* __restrict__ prefix, int n) {
+  __shared__ float part[SEGS][kRaysPerBlock];
+  const int s = slice_of(prefix, n, blockIdx.x);
+  project_body<SEGS>(T[s], blockIdx.x - prefix[s], part);
 }
 
 // Weight of pixel (i, j) on ray L: the same fixed-point cross coordinate and
@@ -102,21 +112,19 @@ __device__ __forceinline__ float ray_weight(const RayLine& L, int i, int j) {
   return 0.0f;
 }
 
-template <bool kFan>
-__global__ void __launch_bounds__(kBpBlockX* kBpBlockY)
-backproject_kernel(const RayLine* __restrict__ rays, const ViewInfo* __restrict__ views,
-                   const float* __restrict__ sino, float* __restrict__ img, int I, int nv, int nb,
-                   float half_diag) {
-  const int j = blockIdx.x * kBpBlockX + threadIdx.x;
-  const int i = blockIdx.y * kBpBlockY + threadIdx.y;
+// bx, by: block coordinates of a (kBpBlockX x kBpBlockY) pixel block.
+__device__ void backproject_body(const BpArgs& A, int bx, int by) {
+  const int I = A.I;
+  const int j = bx * kBpBlockX + threadIdx.x;
+  const int i = by * kBpBlockY + threadIdx.y;
   if (i >= I || j >= I) return;
   const float x = (float)j - 0.5f * (float)(I - 1);
   const float y = 0.5f * (float)(I - 1) - (float)i;
   float acc = 0.0f;
-  for (int k = 0; k < nv; ++k) {
-    const ViewInfo v = views[k];
+  for (int k = 0; k < A.nv; ++k) {
+    const ViewInfo v = A.views[k];
     float u, hw;
-    if (!kFan) {
+    if (!A.fan) {
       u = __fmaf_rn(v.a, x, __fmaf_rn(v.b, y, v.c));
       hw = v.hw;
     } else {
@@ -126,18 +134,30 @@ backproject_kernel(const RayLine* __restrict__ rays, const ViewInfo* __restrict_
       const float dist = sqrtf(dx * dx + dy * dy);
       const float gam = atan2f(cr, along);
       u = __fmaf_rn(gam, v.inv_dg, v.c);
-      hw = asinf(fminf(half_diag / dist, 1.0f)) * v.inv_dg * 1.001f + 1e-3f;
+      hw = asinf(fminf(A.half_diag / dist, 1.0f)) * v.inv_dg * 1.001f + 1e-3f;
     }
     int b0 = (int)ceilf(u - hw), b1 = (int)floorf(u + hw);
     b0 = max(b0, 0);
-    b1 = min(b1, nb - 1);
-    const int64_t row = (int64_t)k * nb;
+    b1 = min(b1, A.nb - 1);
+    const int64_t row = (int64_t)k * A.nb;
     for (int b = b0; b <= b1; ++b) {
-      const RayLine L = rays[row + b];
-      acc = __fmaf_rn(ray_weight(L, i, j), sino[row + b], acc);
+      const RayLine L = A.rays[row + b];
+      acc = __fmaf_rn(ray_weight(L, i, j), A.sino[row + b], acc);
     }
   }
-  img[(int64_t)i * I + j] = acc;
+  A.img[(int64_t)i * I + j] = acc;
+}
+
+__global__ void __launch_bounds__(kBpBlockX* kBpBlockY) backproject_kernel(BpArgs A) {
+  backproject_body(A, blockIdx.x, blockIdx.y);
+}
+__global__ void __launch_bounds__(kBpBlockX* kBpBlockY)
+backproject_batch(const BpArgs* __restrict__ T, const int* __restrict__ prefix, int n) {
+  const int s = slice_of(prefix, n, blockIdx.x);
+  const BpArgs A = T[s];
+  const int local = blockIdx.x - prefix[s];
+  const int gx = (A.I + kBpBlockX - 1) / kBpBlockX;
+  backproject_body(A, local % gx, local / gx);
 }
 
 __global__ void transpose_kernel(const float* __restrict__ in, float* __restrict__ out, int I) {
@@ -161,24 +181,64 @@ dg_status launch_transpose(const float* in, float* out, int I, hipStream_t s) {
   return DG_OK;
 }
 
-dg_status launch_project(const dg_plan* p, const float* img, const float* img_t, float* sino,
-                         hipStream_t s) {
-  unsigned int grid = (unsigned int)((p->M + kRaysPerBlock - 1) / kRaysPerBlock);
-  hipLaunchKernelGGL(project_kernel, dim3(grid), dim3(kProjBlock), 0, s, p->rays, img, img_t,
-                     sino, p->I, p->M);
+unsigned int project_blocks(int64_t M) { return (unsigned int)((M + kRaysPerBlock - 1) / kRaysPerBlock); }
+unsigned int backproject_blocks(int I) {
+  return (unsigned int)(((I + kBpBlockX - 1) / kBpBlockX) * ((I + kBpBlockY - 1) / kBpBlockY));
+}
+
+dg_status launch_project_variant(int variant, const ProjArgs& A, hipStream_t s) {
+  const dim3 grid(project_blocks(A.M));
+  switch (variant) {
+    case 0:
+      hipLaunchKernelGGL(project_kernel<2>, grid, dim3(kRaysPerBlock * 2), 0, s, A);
+      break;
+    case 2:
+      hipLaunchKernelGGL(project_kernel<8>, grid, dim3(kRaysPerBlock * 8), 0, s, A);
+      break;
+    default:
+      hipLaunchKernelGGL(project_kernel<4>, grid, dim3(kRaysPerBlock * 4), 0, s, A);
+      break;
+  }
   DG_LAUNCH_CHECK("project_kernel");
   return DG_OK;
+}
+
+dg_status launch_project_batch(int variant, const ProjArgs* T, const int* prefix, int n, int total,
+                               hipStream_t s) {
+  switch (variant) {
+    case 0:
+      hipLaunchKernelGGL(project_batch<2>, dim3(total), dim3(kRaysPerBlock * 2), 0, s, T, prefix, n);
+      break;
+    case 2:
+      hipLaunchKernelGGL(project_batch<8>, dim3(total), dim3(kRaysPerBlock * 8), 0, s, T, prefix, n);
+      break;
+    default:
+      hipLaunchKernelGGL(project_batch<4>, dim3(total), dim3(kRaysPerBlock * 4), 0, s, T, prefix, n);
+      break;
+  }
+  DG_LAUNCH_CHECK("project_batch");
+  return DG_OK;
+}
+
+dg_status launch_backproject_batch(const BpArgs* T, const int* prefix, int n, int total,
+                                   hipStream_t s) {
+  hipLaunchKernelGGL(backproject_batch, dim3(total), dim3(kBpBlockX, kBpBlockY), 0, s, T, prefix, n);
+  DG_LAUNCH_CHECK("backproject_batch");
+  return DG_OK;
+}
+
+dg_status launch_project(const dg_plan* p, const float* img, const float* img_t, float* sino,
+                         hipStream_t s) {
+  ProjArgs A{p->rays, img, img_t, sino, p->I, p->M};
+  return launch_project_variant(p->proj_variant, A, s);
 }
 
 dg_status launch_backproject(const dg_plan* p, const float* sino, float* img, hipStream_t s) {
   dim3 grid((p->I + kBpBlockX - 1) / kBpBlockX, (p->I + kBpBlockY - 1) / kBpBlockY);
   dim3 block(kBpBlockX, kBpBlockY);
-  if (p->g.kind == DG_GEOM_FAN)
-    hipLaunchKernelGGL(backproject_kernel<true>, grid, block, 0, s, p->rays, p->views, sino, img,
-                       p->I, p->nv, p->nb, (float)p->half_diag_px);
-  else
-    hipLaunchKernelGGL(backproject_kernel<false>, grid, block, 0, s, p->rays, p->views, sino, img,
-                       p->I, p->nv, p->nb, (float)p->half_diag_px);
+  BpArgs A{p->rays, p->views, sino, img, p->I, p->nv, p->nb, p->g.kind == DG_GEOM_FAN ? 1 : 0,
+           (float)p->half_diag_px};
+  hipLaunchKernelGGL(backproject_kernel, grid, block, 0, s, A);
   DG_LAUNCH_CHECK("backproject_kernel");
   return DG_OK;
 }

@@ -15,7 +15,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 def header_functions():
     txt = open(os.path.join(ROOT, "include", "dgampct.h")).read()
     txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
-    names = re.findall(r"^\s*(?:dg_status|size_t|int64_t|const char\*)\s+(\w+)\s*\(", txt, flags=re.M)
+    names = re.findall(r"^\s*(?:dg_status|size_t|int64_t|int32_t|const char\*)\s+(\w+)\s*\(", txt, flags=re.M)
     return sorted(set(names))
 
 
@@ -70,3 +70,22 @@ def test_product_path_has_no_cpu_fallback():
     assert "oracle" not in src.replace("not compute", "")
     with pytest.raises(api.DgError):
         api._ptr(torch.zeros(4), torch.float32)
+
+
+def test_batch_entry_points_reject_bad_arguments():
+    """Argument checks run before any device call."""
+    L = api.load()
+    g = api.Geom(**{k: synth.c1_geometry()[k] for k, _ in api.Geom._fields_})
+    h = ctypes.c_void_p()
+    assert L.dg_batch_create(ctypes.byref(g), 0, ctypes.byref(h)) == -1
+    assert L.dg_batch_create(None, 1, ctypes.byref(h)) == -1
+    a = (ctypes.c_double * 1)(1.0)
+    assert L.dg_batch_bind(None, None, a, a, None, None, None, None, 1, None, 1e-3, None) == -1
+    assert L.dg_batch_state_init(None, 1.0, None) == -1
+    assert L.dgamp_batch_iterate(None, 1, 0, 0, 1.0, 1.0, 1, 0, 0, None) == -1
+    assert L.dg_batch_autotune(None, 1, None) == -1
+    assert L.dg_batch_workspace_bytes(None) == 0
+    assert L.dg_batch_projector_variant(None) == -1
+    assert L.dg_plan_projector_variant(None) == -1
+    assert L.dg_plan_autotune(None, None, None, None, 1, None) == -1
+    assert L.dg_last_error()

@@ -1,0 +1,213 @@
+"""Batched multi-slice D-GAMP-CT and the projector autotuner, through the C ABI.
+
+A batch runs every phase of an iteration as one launch over the blocks of
+all slices; each block reads its slice's arguments and reduces into that
+slice's own partials with the block count a single-slice launch uses, so
+slice k of a batch must reproduce the single-slice run bit for bit (and so
+inherit its parity with the oracle, which one slice re-checks directly).
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import denoisers as oden
+from oracle import gamp as ogamp
+from oracle import radon
+from paper_1609_04661_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+# uneven batch: sides 64/96/128, parallel and fan, different view counts
+SLICES = [
+    (synth.c1_geometry(), 1e4),
+    (synth.geometry(synth.PARALLEL, 96, 0.9, 37, 141, math.pi, angle0_rad=0.3, bin_mm=1.1), 3e4),
+    (synth.geometry(synth.FAN, 128, 0.5, 64, 200, 2 * math.pi, dso_mm=120.0, ddo_mm=100.0), 5e4),
+    (synth.geometry(synth.PARALLEL, 64, 1.0, 12, 91, math.pi), 2e4),
+]
+N_ITER, ETA, SEED = 4, 0.5, 17
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.detach().cpu().double().numpy()
+
+
+def slice_inputs(api, geoms_i0, seed0=500):
+    """Per slice: phantom, Poisson counts of its exact projection (oracle
+    projector, FP64), fro2 from the GPU Hutchinson estimator."""
+    out = []
+    for k, (g, i0) in enumerate(geoms_i0):
+        R = radon.Radon(g)
+        mu = synth.ellipse_phantom(g["n"], seed0 + k, pixel_mm=g["pixel_mm"])
+        y = synth.poisson_counts(R.project(mu), i0, seed0 + k)
+        P = api.Plan(g)
+        fro2 = float(api.dg_fro2_hutchinson(P, 8, 99 + k).item())
+        out.append(dict(g=g, i0=i0, R=R, mu=mu, y=y, plan=P, fro2=fro2))
+    return out
+
+
+def single_run(api, d, den_kind, params, n_iter=N_ITER, seed=SEED, eta=ETA):
+    P = d["plan"]
+    y = torch.as_tensor(d["y"], dtype=torch.float32).cuda().contiguous()
+    st = api.DgampState(P, 1.0)
+    mu_out = torch.empty((P.I, P.I), dtype=torch.float32, device="cuda")
+    api.dgamp_iterate(P, y, st, n_iter, d["fro2"], d["i0"], den_kind, params, probe_seed=seed,
+                      eta_x=eta, eta_s=eta, mu_out=mu_out)
+    return host(st.x), host(st.s), host(st.scal), host(mu_out)
+
+
+def make_batch(api, data):
+    B = api.Batch([d["g"] for d in data])
+    y = torch.cat([torch.as_tensor(d["y"], dtype=torch.float32).reshape(-1) for d in data]).cuda()
+    return B, y.contiguous()
+
+
+@pytest.fixture(scope="module")
+def data(gpu_lib):
+    return slice_inputs(gpu_lib, SLICES)
+
+
+def check_slices_equal(api, B, data, mu_out, singles):
+    for k, d in enumerate(data):
+        x, s, scal, mu = singles[k]
+        bx = host(B.image(B.x, k))
+        bs = host(B.sino(B.s, k))
+        bscal = host(B.scal[k * api.NSCAL:(k + 1) * api.NSCAL])
+        bmu = host(B.image(mu_out, k))
+        assert np.array_equal(bx, x), (k, np.abs(bx - x).max())
+        assert np.array_equal(bs, s), (k, np.abs(bs - s).max())
+        assert np.array_equal(bscal[:8], scal[:8]), (k, bscal[:8], scal[:8])
+        assert np.array_equal(bmu, mu), (k, np.abs(bmu - mu).max())
+
+
+def test_batch_layout(gpu_lib, data):
+    B, _ = make_batch(gpu_lib, data)
+    assert B.img_off[0] == 0 and B.sino_off[0] == 0
+    for k, d in enumerate(data):
+        assert B.img_off[k + 1] - B.img_off[k] == d["g"]["n"] ** 2
+        assert B.sino_off[k + 1] - B.sino_off[k] == d["g"]["n_views"] * d["g"]["n_bins"]
+
+
+def test_batch_nlm_equals_single_slices(gpu_lib, data):
+    api = gpu_lib
+    params = api.make_params(api.DEN_NLM)
+    singles = [single_run(api, d, api.DEN_NLM, params) for d in data]
+    B, y = make_batch(api, data)
+    mu_out = torch.empty(B.totN, dtype=torch.float32, device="cuda")
+    B.bind(y, [d["i0"] for d in data], [d["fro2"] for d in data], api.DEN_NLM, params, mu_out)
+    B.state_init(1.0)
+    B.iterate(N_ITER, probe_seed=SEED, eta_x=ETA, eta_s=ETA, write_mu=True)
+    check_slices_equal(api, B, data, mu_out, singles)
+    # split into two calls (t0 carries the iteration index of the probes)
+    B.state_init(1.0)
+    B.iterate(1, probe_seed=SEED, eta_x=ETA, eta_s=ETA)
+    B.iterate(N_ITER - 1, t0=1, probe_seed=SEED, eta_x=ETA, eta_s=ETA, write_mu=True)
+    check_slices_equal(api, B, data, mu_out, singles)
+
+
+def test_batch_slice_matches_oracle(gpu_lib, data):
+    """Slice 0 (64 x 64, 30 parallel views) of the batch against the FP64
+    oracle's D-GAMP-CT with the same inputs: first iterations' tau_r within
+    1e-4 relative, mu within 1e-3 relative L2."""
+    api = gpu_lib
+    T = 2
+    params = api.make_params(api.DEN_NLM)
+    B, y = make_batch(api, data)
+    mu_out = torch.empty(B.totN, dtype=torch.float32, device="cuda")
+    B.bind(y, [d["i0"] for d in data], [d["fro2"] for d in data], api.DEN_NLM, params, mu_out)
+    B.state_init(1.0)
+    B.iterate(T, probe_seed=SEED, eta_x=ETA, eta_s=ETA, write_mu=True)
+    d = data[0]
+    ref_mu, ref_log, _ = ogamp.dgamp_ct(d["R"], d["y"], d["i0"], d["fro2"], T, oden.NLM, {}, SEED,
+                                        eta_x=ETA, eta_s=ETA)
+    got = host(B.image(mu_out, 0))
+    err = np.linalg.norm(got - ref_mu) / np.linalg.norm(ref_mu)
+    assert err <= 1e-3, err
+    tau_r = float(host(B.scal[api.S_TAU_R:api.S_TAU_R + 1])[0])
+    assert abs(tau_r - ref_log[T - 1]["tau_r"]) <= 1e-4 * ref_log[T - 1]["tau_r"]
+
+
+def test_batch_graph_replays_equal_eager(gpu_lib, data):
+    api = gpu_lib
+    params = api.make_params(api.DEN_NLM)
+    B, y = make_batch(api, data)
+    mu_out = torch.empty(B.totN, dtype=torch.float32, device="cuda")
+    B.bind(y, [d["i0"] for d in data], [d["fro2"] for d in data], api.DEN_NLM, params, mu_out)
+    B.state_init(1.0)
+    B.iterate(N_ITER, probe_seed=SEED, eta_x=ETA, eta_s=ETA, write_mu=True)
+    eager = (host(B.x), host(B.s), host(B.scal), host(mu_out))
+    G = B.graph(N_ITER, tau_x0=1.0, probe_seed=SEED, eta_x=ETA, eta_s=ETA)
+    for rep in range(3):
+        B.x.fill_(7.0)  # eager work between replays; the graph resets the state itself
+        mu_out.zero_()
+        torch.cuda.synchronize()
+        G.launch()
+        got = (host(B.x), host(B.s), host(B.scal), host(mu_out))
+        for a, b in zip(got, eager):
+            assert np.array_equal(a, b), rep
+
+
+def test_batch_cnn_equals_single_slices(gpu_lib):
+    api = gpu_lib
+    geoms = [(synth.c1_geometry(), 1e4),
+             (synth.geometry(synth.PARALLEL, 64, 1.0, 20, 91, math.pi / 2), 2e4),
+             (synth.geometry(synth.FAN, 64, 1.0, 48, 110, 2 * math.pi, dso_mm=90.0,
+                             ddo_mm=60.0), 3e4)]
+    data = slice_inputs(api, geoms, seed0=700)
+    net = api.CnnNet(master=api.CnnNet.init_master(5, scale=0.5))
+    singles = []
+    for d in data:
+        p1 = api.make_params(api.DEN_CNN, net=net, n_pixels=d["plan"].N)
+        singles.append(single_run(api, d, api.DEN_CNN, p1, n_iter=3))
+    B, y = make_batch(api, data)
+    pb = api.make_params(api.DEN_CNN, net=net, n_pixels=B.totN)
+    mu_out = torch.empty(B.totN, dtype=torch.float32, device="cuda")
+    B.bind(y, [d["i0"] for d in data], [d["fro2"] for d in data], api.DEN_CNN, pb, mu_out)
+    B.state_init(1.0)
+    B.iterate(3, probe_seed=SEED, eta_x=ETA, eta_s=ETA, write_mu=True)
+    check_slices_equal(api, B, data, mu_out, singles)
+
+
+def test_batch_rejects_haar_and_mixed_cnn(gpu_lib, data):
+    api = gpu_lib
+    B, y = make_batch(api, data)
+    i0 = [d["i0"] for d in data]
+    fro2 = [d["fro2"] for d in data]
+    with pytest.raises(api.DgError, match="status -4"):
+        B.bind(y, i0, fro2, api.DEN_HAAR, api.make_params(api.DEN_HAAR))
+    net = api.CnnNet(seed=1)
+    with pytest.raises(api.DgError, match="status -4"):
+        B.bind(y, i0, fro2, api.DEN_CNN, api.make_params(api.DEN_CNN, net=net, n_pixels=B.totN))
+    with pytest.raises(api.DgError, match="status -1"):
+        B.bind(y, [0.0] + i0[1:], fro2, api.DEN_NLM, api.make_params(api.DEN_NLM))
+    with pytest.raises(api.DgError, match="status -1"):
+        B.iterate(1)  # never bound successfully
+
+
+def test_plan_autotune_keeps_projection_bit_identical(gpu_lib):
+    api = gpu_lib
+    g = synth.c2_geometry()
+    P = api.Plan(g)
+    mu = torch.as_tensor(synth.ellipse_phantom(512, 3), dtype=torch.float32).cuda()
+    mu_t = mu.t().contiguous()
+    before = host(api.ct_project(P, mu, mu_t))
+    v = P.autotune(mu, mu_t, reps=5)
+    assert v in (0, 1, 2) and P.projector_variant == v
+    after = host(api.ct_project(P, mu, mu_t))
+    assert np.array_equal(before, after)
+
+
+def test_batch_autotune_keeps_results(gpu_lib, data):
+    api = gpu_lib
+    params = api.make_params(api.DEN_NLM)
+    singles = [single_run(api, d, api.DEN_NLM, params) for d in data]
+    B, y = make_batch(api, data)
+    mu_out = torch.empty(B.totN, dtype=torch.float32, device="cuda")
+    B.bind(y, [d["i0"] for d in data], [d["fro2"] for d in data], api.DEN_NLM, params, mu_out)
+    v = B.autotune(reps=3)
+    assert v in (0, 1, 2)
+    B.state_init(1.0)
+    B.iterate(N_ITER, probe_seed=SEED, eta_x=ETA, eta_s=ETA, write_mu=True)
+    check_slices_equal(api, B, data, mu_out, singles)
