@@ -34,7 +34,8 @@ EXPORTS = ("dg_plan_create", "dg_plan_destroy", "dg_workspace_bytes", "dg_channe
            "dg_cnn_train_step", "dg_batch_create", "dg_batch_destroy", "dg_batch_layout",
            "dg_batch_workspace_bytes", "dg_batch_bind", "dg_batch_state_init",
            "dgamp_batch_iterate", "dg_batch_graph_create", "dg_batch_autotune",
-           "dg_batch_projector_variant", "dg_plan_autotune", "dg_plan_projector_variant")
+           "dg_batch_projector_variant", "dg_plan_autotune", "dg_plan_projector_variant",
+           "dg_batch_set_projector_variant", "dg_plan_set_projector_variant")
 
 
 class DgError(RuntimeError):
@@ -129,6 +130,8 @@ def load():
         "dg_batch_projector_variant": ([_VP], i32),
         "dg_plan_autotune": ([_VP, _VP, _VP, _VP, i32, _VP], i32),
         "dg_plan_projector_variant": ([_VP], i32),
+        "dg_batch_set_projector_variant": ([_VP, i32], i32),
+        "dg_plan_set_projector_variant": ([_VP, i32], i32),
     }
     missing = set(EXPORTS) - set(sig)
     if missing:
@@ -201,6 +204,10 @@ class Plan:
     @property
     def projector_variant(self):
         return int(_lib.dg_plan_projector_variant(self._h))
+
+    @projector_variant.setter
+    def projector_variant(self, v):
+        _check(_lib.dg_plan_set_projector_variant(self._h, int(v)))
 
     def __del__(self):
         try:
@@ -433,6 +440,10 @@ class Batch:
     @property
     def projector_variant(self):
         return int(_lib.dg_batch_projector_variant(self._h))
+
+    @projector_variant.setter
+    def projector_variant(self, v):
+        _check(_lib.dg_batch_set_projector_variant(self._h, int(v)))
 
     def graph(self, n_iter, tau_x0=1.0, probe_seed=0, eta_x=1.0, eta_s=1.0, onsager=True,
               channel_mode=CHANNEL_LAPLACE):

@@ -474,6 +474,13 @@ extern "C" dg_status dg_batch_autotune(dg_batch* b, int32_t reps, void* stream) 
 
 extern "C" int32_t dg_batch_projector_variant(const dg_batch* b) { return b ? b->proj_variant : -1; }
 
+extern "C" dg_status dg_batch_set_projector_variant(dg_batch* b, int32_t variant) {
+  DG_ARG_CHECK(b && variant >= 0 && variant < 3, "dg_batch_set_projector_variant: bad argument");
+  b->proj_variant = variant;
+  for (dg_plan* p : b->plans) p->proj_variant = variant;
+  return DG_OK;
+}
+
 extern "C" dg_status dg_plan_autotune(dg_plan* p, const float* img, const float* img_t,
                                       float* sino, int32_t reps, void* stream) {
   DG_ARG_CHECK(p && img && sino && reps >= 1, "dg_plan_autotune: null argument");
@@ -506,3 +513,9 @@ extern "C" dg_status dg_plan_autotune(dg_plan* p, const float* img, const float*
 }
 
 extern "C" int32_t dg_plan_projector_variant(const dg_plan* p) { return p ? p->proj_variant : -1; }
+
+extern "C" dg_status dg_plan_set_projector_variant(dg_plan* p, int32_t variant) {
+  DG_ARG_CHECK(p && variant >= 0 && variant < 3, "dg_plan_set_projector_variant: bad argument");
+  p->proj_variant = variant;
+  return DG_OK;
+}
