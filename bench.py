@@ -1,18 +1,29 @@
 """Benchmark: D-GAMP-CT iterations per second on one MI355X.
 
-Workload (the configuration the headline metric is quoted on): 512 x 512
-image (1 mm pixels), parallel beam, 64 views over 180 degrees, 729 bins,
-Poisson counts at I0 = 1e5, patch-based (non-local means) denoiser with a
-one-probe Monte-Carlo divergence.  Inputs are synthetic (seeded ellipse +
-texture phantom, counts drawn from the library's own projection) and are
-resident in HBM before timing starts.
+Headline workload: 512 x 512 image (1 mm pixels), parallel beam, 64 views
+over 180 degrees, 729 bins, Poisson counts at I0 = 1e5, patch-based
+(non-local means) denoiser with a one-probe Monte-Carlo divergence.  Inputs
+are synthetic (seeded ellipse + texture phantom, counts drawn from the
+library's own projection) and are resident in HBM before timing starts.
 
 One step = one full D-GAMP-CT iteration (V^-1 x, A, Poisson channel, A^T,
-V^-1 g + r update, denoiser on r and r + eps b, divergence + tau_x).
-The timed region runs `--steps` iterations from a fresh state through the C
-ABI, bracketed by torch.cuda.synchronize(); HIP events recorded by the
-library between the phases of every timed iteration give the per-phase
-durations used for the roofline fields.
+V^-1 g + r update, denoiser on r and r + eps b, divergence + tau_x).  The
+timed region runs `--steps` iterations from a fresh state through the C ABI,
+bracketed by torch.cuda.synchronize(); HIP events that the library records
+between the phases of every timed iteration (on the stream the kernels run
+on) give the per-phase durations used for the roofline fields.  The same
+iterations replayed from a HIP graph are timed beside it.
+
+Further figures on the same line (each its own untimed-setup, timed-run pair):
+  * learned_vs_plain: the residual CNN denoiser against NLM on the headline
+    workload, PSNR after every iteration, time to reach the plain run's
+    final PSNR;
+  * batch_uneven: 64 independent slices (sides 256/384/512, 32/64/128 views,
+    I0 log-uniform in [5e3, 1e5]) in one batch, 30 iterations, autotuned
+    projector, HIP graph;
+  * fan_lowdose: 16 fan-beam slices of 1024 x 1024 (0.5 mm) at I0 = 5e3,
+    50 iterations of the batched learned-denoiser path in a HIP graph (and
+    the NLM path beside it).
 
 Prints one JSON line.  With `--gpus N`, N > 1 exits with a message: this
 build runs on one GPU.
@@ -21,7 +32,9 @@ import argparse
 import ctypes
 import json
 import math
+import multiprocessing as mp
 import os
+import statistics
 import sys
 import time
 
@@ -32,10 +45,19 @@ if ROOT not in sys.path:
 METRIC = "D-GAMP-CT iters/s & A+Aᵀ GB/s at 512², 64 views; learned vs plain at equal PSNR"
 HBM_PEAK_GBS = 8000.0
 FP32_VECTOR_TFLOPS = 157.3
+BF16_MFMA_TFLOPS = 2500.0
+WEIGHTS = os.path.join(ROOT, "paper_1609_04661_amd", "weights", "cnn_c2_x_space.safetensors")
 
-# configured recursion for this workload (damping of means and variances)
+# configured recursion for these workloads (damping of means and variances)
 CFG = dict(i0=1e5, seed=1002, probe_seed=7, eta=0.15, tau_x0=1.0, fro2_probes=16,
            nlm=dict(pr=2, sr=10, hfac=0.4))
+# HBM bytes per launch of nlm_kernel<2> at this workload, from two rocprofv3
+# counter passes (FETCH_SIZE, WRITE_SIZE) scaled by a 256 MiB copy kernel
+# (profiles/dgamp_c2_512x512_64views_hbm_traffic.md).  Set to None whenever
+# that kernel changes until the counters are taken again.
+NLM_TRAFFIC_BYTES = 5.234e6
+C3 = dict(seed=1003, slices=64, iters=30)
+C5 = dict(seed=1005, slices=16, iters=50)
 
 
 def nlm_flops_per_pixel(pr, sr):
@@ -46,6 +68,12 @@ def nlm_flops_per_pixel(pr, sr):
     weight sum, weighted accumulate (6)."""
     per_offset = 2 + 2 * (2 * pr + 1) + 6
     return (2 * sr + 1) ** 2 * per_offset
+
+
+def cnn_flops_per_pixel():
+    """Multiply-adds x 2 of the 10-layer network per pixel: 1->64, 8 x 64->64,
+    64->1, 3 x 3 taps."""
+    return 2 * 9 * (64 + 8 * 64 * 64 + 64)
 
 
 class HipEvents:
@@ -78,48 +106,73 @@ class HipEvents:
             self.L.hipEventDestroy(self.arr[k])
 
 
+def _phantom_job(a):
+    from paper_1609_04661_amd import synth
+    n, seed, pixel_mm, inserts = a
+    return synth.ellipse_phantom(n, seed, pixel_mm=pixel_mm, inserts=inserts).astype("float32")
+
+
+def make_phantoms(jobs):
+    """Phantoms on host cores, in a worker pool forked before this process
+    touches the GPU."""
+    procs = max(1, min(16, os.cpu_count() or 1, len(jobs)))
+    with mp.get_context("fork").Pool(procs) as pool:
+        return pool.map(_phantom_job, jobs)
+
+
 def cpu_baseline(geom, mu, y, fro2, iters):
-    """The FP64 oracle on the same inputs, `iters` iterations, host cores."""
+    """The FP64 oracle on the same inputs: `iters` iterations on all host
+    threads, and one iteration on one thread."""
+    from oracle import _lib as olib
     from oracle import denoisers as oden
     from oracle import gamp as ogamp
     from oracle import radon
     R = radon.Radon(geom)
-    t0 = time.perf_counter()
-    ogamp.dgamp_ct(R, y, CFG["i0"], fro2, iters, oden.NLM, dict(CFG["nlm"]),
-                   CFG["probe_seed"], eta_x=CFG["eta"], eta_s=CFG["eta"])
-    dt = time.perf_counter() - t0
-    cores = int(os.environ.get("OMP_NUM_THREADS") or os.cpu_count() or 1)
+
+    def run(n):
+        t0 = time.perf_counter()
+        ogamp.dgamp_ct(R, y, CFG["i0"], fro2, n, oden.NLM, dict(CFG["nlm"]),
+                       CFG["probe_seed"], eta_x=CFG["eta"], eta_s=CFG["eta"])
+        return time.perf_counter() - t0
+
+    cores = olib.set_threads(0)  # query
+    olib.set_threads(cores)
+    dt = run(iters)
+    olib.set_threads(1)
+    dt1 = run(1)
+    olib.set_threads(cores)
     return dict(value=iters / dt, unit="iter/s", cores=cores, kind="oracle",
                 sample="%d D-GAMP-CT iterations of the same 512x512 / 64-view workload "
                        "(FP64, C loops with OpenMP over %d threads, numpy FFTs), %.1f s"
-                % (iters, cores, dt))
+                % (iters, cores, dt),
+                one_thread_iter_per_s=1.0 / dt1)
 
 
-def main():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=50)
-    ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--cpu-iters", type=int, default=3)
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    args = ap.parse_args()
-    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path "
-              "(see DESIGN.md for how the work would shard)", file=sys.stderr)
-        sys.exit(2)
+def sync_time(fn, reps):
+    import torch
+    out = []
+    for _ in range(reps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        fn()
+        torch.cuda.synchronize()
+        out.append(time.perf_counter() - t0)
+    return statistics.median(out)
 
+
+def first_reaching(curve, target):
+    for k, v in enumerate(curve):
+        if v == v and v >= target:
+            return k + 1
+    return None
+
+
+def headline(api, synth, args, mu, results):
     import numpy as np
     import torch
-
-    from paper_1609_04661_amd import api, synth
-
-    assert torch.cuda.is_available(), "bench.py needs a GPU"
-    torch.cuda.set_device(0)
-    api.load()
     geom = synth.c2_geometry()
     plan = api.Plan(geom)
     I, N, M = plan.I, plan.N, plan.M
-    mu = synth.ellipse_phantom(I, CFG["seed"])
     mu_d = torch.as_tensor(mu, dtype=torch.float32).cuda()
     z = api.ct_project(plan, mu_d)
     torch.cuda.synchronize()
@@ -129,29 +182,29 @@ def main():
     params = api.make_params(api.DEN_NLM, **CFG["nlm"])
     work = plan.workspace(api.OP_DGAMP)
     mu_out = torch.empty((I, I), dtype=torch.float32, device="cuda")
+    kw = dict(probe_seed=CFG["probe_seed"], eta_x=CFG["eta"], eta_s=CFG["eta"])
 
     def run(n, events=None, log=None):
         st = api.DgampState(plan, CFG["tau_x0"])
-        api.dgamp_iterate(plan, y_d, st, n, fro2, CFG["i0"], api.DEN_NLM, params,
-                          probe_seed=CFG["probe_seed"], eta_x=CFG["eta"], eta_s=CFG["eta"],
-                          mu_out=mu_out, log=log, work=work, phase_events=events)
+        api.dgamp_iterate(plan, y_d, st, n, fro2, CFG["i0"], api.DEN_NLM, params, mu_out=mu_out,
+                          log=log, work=work, phase_events=events, **kw)
         return st
 
-    # warm-up (separate state)
-    run(args.warmup)
-    torch.cuda.synchronize()
-
     K = args.steps
+    wev = HipEvents(max(args.warmup, 1) * (api.NPHASES + 1))
+    wlog = torch.zeros(max(args.warmup, 1) * api.LOG_STRIDE, dtype=torch.float64, device="cuda")
+    run(args.warmup, events=wev.arr, log=wlog)
+    torch.cuda.synchronize()
+    wev.close()
+
     ev = HipEvents(K * (api.NPHASES + 1))
     log = torch.zeros(K * api.LOG_STRIDE, dtype=torch.float64, device="cuda")
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     st = run(K, events=ev.arr, log=log)
     torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    elapsed = t1 - t0
+    elapsed = time.perf_counter() - t0
     status = float(st.scal[api.S_STATUS].item())
-
     phase_ms = {name: [] for name in api.PHASES}
     for it in range(K):
         base = it * (api.NPHASES + 1)
@@ -159,50 +212,219 @@ def main():
             phase_ms[name].append(ev.ms(base + k, base + k + 1))
     ev.close()
     avg = {k: float(np.mean(v)) for k, v in phase_ms.items()}
-
     mu_hat = mu_out.cpu().double().numpy()
-    with np.errstate(all="ignore"):
-        mse = float(np.mean((mu_hat - mu) ** 2))
-        psnr = 10 * math.log10(float(mu.max()) ** 2 / mse) if mse > 0 and math.isfinite(mse) else None
+    psnr = float(api.dg_psnr(mu_out, mu_d).item())
 
-    nlm_flops = nlm_flops_per_pixel(CFG["nlm"]["pr"], CFG["nlm"]["sr"]) * N * 2  # r and r + eps b
-    den_s = avg["denoise"] * 1e-3
-    achieved_tflops = nlm_flops / den_s / 1e12
+    # the same K iterations replayed from a graph (state reset included)
+    gst = api.DgampState(plan, CFG["tau_x0"])
+    G = api.DgampGraph(plan, y_d, gst, K, fro2, CFG["i0"], api.DEN_NLM, params,
+                       tau_x0=CFG["tau_x0"], mu_out=mu_out, work=work, **kw)
+    G.launch()
+    graph_s = sync_time(G.launch, args.reps)
+
+    nlm_flops = nlm_flops_per_pixel(CFG["nlm"]["pr"], CFG["nlm"]["sr"]) * N * 2  # r, r + eps b
+    achieved_tflops = nlm_flops / (avg["denoise"] * 1e-3) / 1e12
     a_bytes = 4.0 * (N + M)
-    res = {
-        "metric": METRIC,
+    results.update({
         "value": K / elapsed,
-        "unit": "iter/s",
-        "n_gpus": 1,
-        "steps": K,
-        "warmup": args.warmup,
         "ms_per_step": 1e3 * elapsed / K,
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f32",
-        "data": "synthetic",
-        "config": {"workload": "D-GAMP-CT 512x512, parallel 64 views x 729 bins, I0=1e5, "
-                               "NLM 5x5/21x21 denoiser, MC divergence (1 Rademacher probe)",
-                   "image": I, "views": geom["n_views"], "bins": geom["n_bins"],
-                   "i0": CFG["i0"], "damping": CFG["eta"], "parallelism": "single GPU"},
-        "roofline": {"bound": "alu", "kernel": "nlm_kernel",
+        "roofline": {"bound": "alu", "kernel": "nlm_kernel<2>",
                      "achieved": achieved_tflops, "peak": FP32_VECTOR_TFLOPS,
                      "unit": "TFLOP/s", "frac": achieved_tflops / FP32_VECTOR_TFLOPS,
-                     "traffic": None},
+                     "traffic": NLM_TRAFFIC_BYTES,
+                     "traffic_algorithmic": 4.0 * 3 * N},
+        "graph_ms_per_step": 1e3 * graph_s / K,
+        "graph_iter_per_s": K / graph_s,
         "phases_ms": avg,
         "A_GBps_algorithmic": a_bytes / (avg["project"] * 1e-3) / 1e9,
         "At_GBps_algorithmic": a_bytes / (avg["backproject"] * 1e-3) / 1e9,
-        "A_At_frac_of_hbm_peak": (2 * a_bytes / ((avg["project"] + avg["backproject"]) * 1e-3) / 1e9)
-        / HBM_PEAK_GBS,
+        "A_At_frac_of_hbm_peak": (2 * a_bytes / ((avg["project"] + avg["backproject"]) * 1e-3)
+                                  / 1e9) / HBM_PEAK_GBS,
         "psnr_db_after_steps": psnr,
         "nonfinite_pixels": int((~np.isfinite(mu_hat)).sum()),
         "final_log": dict(zip(api.LOG_FIELDS, [float(v) for v in
                                                log.view(K, api.LOG_STRIDE)[-1].cpu().numpy()])),
         "status": status,
-    }
+    })
+    return dict(plan=plan, y=y, y_d=y_d, fro2=fro2, mu_d=mu_d, work=work, geom=geom)
+
+
+def learned_vs_plain(api, args, h):
+    """PSNR after every iteration for NLM and the CNN (same inputs, damping and
+    probes); ms per iteration from graph replays of the whole run."""
+    import torch
+    plan, y_d, fro2, mu_d, work = h["plan"], h["y_d"], h["fro2"], h["mu_d"], h["work"]
+    T = args.learned_iters
+    net = api.CnnNet.load_file(WEIGHTS)
+    kinds = {"plain_nlm": (api.DEN_NLM, api.make_params(api.DEN_NLM, **CFG["nlm"])),
+             "learned_cnn": (api.DEN_CNN, api.make_params(api.DEN_CNN, net=net, n_pixels=plan.N))}
+    kw = dict(probe_seed=CFG["probe_seed"], eta_x=CFG["eta"], eta_s=CFG["eta"])
+    out, curves = {}, {}
+    mu_out = torch.empty((plan.I, plan.I), dtype=torch.float32, device="cuda")
+    for name, (kind, params) in kinds.items():
+        st = api.DgampState(plan, CFG["tau_x0"])
+        ps = torch.empty(T, dtype=torch.float64, device="cuda")
+        for t in range(T):
+            api.dgamp_iterate(plan, y_d, st, 1, fro2, CFG["i0"], kind, params, mu_out=mu_out,
+                              work=work, **kw)
+            api.dg_psnr(mu_out, mu_d, out=ps[t:t + 1])
+        curves[name] = [float(v) for v in ps.cpu().numpy()]
+        gst = api.DgampState(plan, CFG["tau_x0"])
+        G = api.DgampGraph(plan, y_d, gst, T, fro2, CFG["i0"], kind, params, tau_x0=CFG["tau_x0"],
+                           mu_out=mu_out, work=work, **kw)
+        G.launch()
+        s = sync_time(G.launch, args.reps)
+        c = curves[name]
+        out[name] = dict(ms_per_iter=1e3 * s / T, iter_per_s=T / s, psnr_final=c[-1],
+                         psnr_best=max(v for v in c if v == v),
+                         psnr_every_5=[round(v, 3) for v in c[4::5]],
+                         status=float(gst.scal[api.S_STATUS].item()))
+    target = out["plain_nlm"]["psnr_final"]
+    k_l = first_reaching(curves["learned_cnn"], target)
+    t_plain = T * out["plain_nlm"]["ms_per_iter"]
+    res = dict(iterations=T, damping=CFG["eta"], target_psnr_db=target, plain=out["plain_nlm"],
+               learned=out["learned_cnn"], learned_iters_to_target=k_l,
+               plain_ms_to_target=t_plain)
+    if k_l is not None:
+        t_l = k_l * out["learned_cnn"]["ms_per_iter"]
+        res["learned_ms_to_target"] = t_l
+        res["time_to_equal_psnr_speedup"] = t_plain / t_l
+    res["raw_iter_rate_ratio"] = out["learned_cnn"]["iter_per_s"] / out["plain_nlm"]["iter_per_s"]
+    res["cnn_tflops_per_iter"] = 2 * cnn_flops_per_pixel() * plan.N / 1e12
+    return res
+
+
+def run_batch(api, synth, slices, phantoms, den, T, reps, autotune, net=None):
+    """One batch: counts from the library's projector, Hutchinson fro2 per
+    slice, graph of the whole T-iteration run; returns timing and PSNRs."""
+    import numpy as np
+    import torch
+    B = api.Batch([s["geom"] for s in slices])
+    y_parts, fro2 = [], []
+    cache = {}
+    for s, mu in zip(slices, phantoms):
+        key = tuple(sorted(s["geom"].items()))
+        if key not in cache:
+            P = api.Plan(s["geom"])
+            cache[key] = (P, float(api.dg_fro2_hutchinson(P, CFG["fro2_probes"], 99).item()))
+        P, f2 = cache[key]
+        z = api.ct_project(P, torch.as_tensor(mu).cuda())
+        torch.cuda.synchronize()
+        y_parts.append(torch.as_tensor(synth.poisson_counts(z.cpu().double().numpy(), s["i0"],
+                                                            s["seed"]), dtype=torch.float32)
+                       .reshape(-1))
+        fro2.append(f2)
+    del cache
+    y = torch.cat(y_parts).cuda()
+    mu_true = torch.cat([torch.as_tensor(m).reshape(-1) for m in phantoms]).cuda()
+    mu_out = torch.empty(B.totN, dtype=torch.float32, device="cuda")
+    if den == "cnn":
+        params = api.make_params(api.DEN_CNN, net=net, n_pixels=B.totN)
+        kind = api.DEN_CNN
+    else:
+        params = api.make_params(api.DEN_NLM, **CFG["nlm"])
+        kind = api.DEN_NLM
+    B.bind(y, [s["i0"] for s in slices], fro2, kind, params, mu_out)
+    variant = B.autotune(reps=5) if autotune else B.projector_variant
+    G = B.graph(T, tau_x0=CFG["tau_x0"], probe_seed=CFG["probe_seed"], eta_x=CFG["eta"],
+                eta_s=CFG["eta"])
+    G.launch()
+    s = sync_time(G.launch, reps)
+    ps = torch.empty(B.n, dtype=torch.float64, device="cuda")
+    for k in range(B.n):
+        api.dg_psnr(B.image(mu_out, k), B.image(mu_true, k), out=ps[k:k + 1])
+    ps = ps.cpu().numpy()
+    status = B.scal.view(B.n, api.NSCAL)[:, api.S_STATUS].cpu().numpy()
+    sides = [s["geom"]["n"] for s in slices]
+    return dict(slices=B.n, iterations=T, ms_per_run=1e3 * s, ms_per_batch_iter=1e3 * s / T,
+                slice_iter_per_s=B.n * T / s, pixels=int(B.totN), rays=int(B.totM),
+                megapixel_iter_per_s=B.totN * T / s / 1e6, projector_variant=variant,
+                sides_histogram={str(v): sides.count(v) for v in sorted(set(sides))},
+                psnr_db_mean=float(np.nanmean(ps)), psnr_db_min=float(np.nanmin(ps)),
+                slices_with_status=int((status != 0).sum()))
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--reps", type=int, default=5, help="graph replays (median)")
+    ap.add_argument("--cpu-iters", type=int, default=12)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--only-headline", action="store_true",
+                    help="skip the learned, batched and fan-beam figures")
+    ap.add_argument("--parts", default="headline,learned,batch,fan",
+                    help="comma-separated subset of headline,learned,batch,fan")
+    ap.add_argument("--learned-iters", type=int, default=50)
+    ap.add_argument("--calibrate-copy-mib", type=int, default=0,
+                    help="first copy this many MiB device-to-device 3 times (a kernel of known "
+                         "traffic for scaling hardware byte counters)")
+    args = ap.parse_args()
+    parts = set(p.strip() for p in args.parts.split(",") if p.strip())
+    if args.only_headline:
+        parts = {"headline"}
+    parts.add("headline")
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+              "(see DESIGN.md for how the work would shard)", file=sys.stderr)
+        sys.exit(2)
+
+    from paper_1609_04661_amd import synth
+    c3 = synth.batch_slices(C3["seed"], C3["slices"])
+    c5 = synth.c5_slices(C5["seed"], C5["slices"])
+    jobs = [(512, CFG["seed"], 1.0, 0)]
+    if "batch" in parts:
+        jobs += [(s["geom"]["n"], s["seed"], 1.0, 0) for s in c3]
+    if "fan" in parts:
+        jobs += [(1024, s["seed"], 0.5, s["inserts"]) for s in c5]
+    phantoms = make_phantoms(jobs)
+
+    import numpy as np
+    import torch
+
+    from paper_1609_04661_amd import api
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+    api.load()
+    if args.calibrate_copy_mib > 0:
+        n = args.calibrate_copy_mib * (1 << 20) // 4
+        src = torch.ones(n, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+
+    res = {"metric": METRIC, "value": None, "unit": "iter/s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": None, "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+           "config": {"workload": "D-GAMP-CT 512x512, parallel 64 views x 729 bins, I0=1e5, "
+                                  "NLM 5x5/21x21 denoiser, MC divergence (1 Rademacher probe)",
+                      "image": 512, "views": 64, "bins": 729, "i0": CFG["i0"],
+                      "damping": CFG["eta"], "parallelism": "single GPU"}}
+    mu = phantoms[0].astype(np.float64)
+    h = headline(api, synth, args, mu, res)
+    if "learned" in parts:
+        print("learned vs plain", file=sys.stderr, flush=True)
+        res["learned_vs_plain"] = learned_vs_plain(api, args, h)
+    if "batch" in parts:
+        print("batch_uneven", file=sys.stderr, flush=True)
+        res["batch_uneven"] = run_batch(api, synth, c3, phantoms[1:1 + len(c3)], "nlm",
+                                        C3["iters"], args.reps, autotune=True)
+    if "fan" in parts:
+        print("fan_lowdose", file=sys.stderr, flush=True)
+        net = api.CnnNet.load_file(WEIGHTS)
+        p5 = phantoms[len(phantoms) - len(c5):]
+        fan = run_batch(api, synth, c5, p5, "cnn", C5["iters"], max(1, args.reps // 2),
+                        autotune=True, net=net)
+        fan["cnn_tflops_achieved_upper"] = (2 * cnn_flops_per_pixel() * fan["pixels"]
+                                            / (fan["ms_per_batch_iter"] * 1e-3) / 1e12)
+        fan["plain_nlm"] = run_batch(api, synth, c5, p5, "nlm", C5["iters"], 1, autotune=False)
+        res["fan_lowdose"] = fan
     if not args.no_cpu_baseline:
-        res["cpu_baseline"] = cpu_baseline(geom, mu, y, fro2, args.cpu_iters)
+        print("cpu baseline", file=sys.stderr, flush=True)
+        res["cpu_baseline"] = cpu_baseline(h["geom"], mu, h["y"], h["fro2"], args.cpu_iters)
     print(json.dumps(res))
 
 

@@ -254,6 +254,15 @@ dg_status dg_graph_destroy(dg_graph* g);
 dg_status dg_fro2_hutchinson(const dg_plan* plan, int32_t n_probes, uint64_t seed,
                              double* out, void* work, void* stream);
 
+/* Reconstruction PSNR as Sec. 6 reports it: 10 log10(peak^2 / MSE), peak =
+ * max(0, max_i ref_i) (attenuation images are non-negative), MSE over all n
+ * pixels, FP64 accumulation; written to *out (device double).  est, ref:
+ * device FP32, n >= 1; work: dg_psnr_workspace_bytes() device bytes.  A zero
+ * MSE gives +inf, non-finite input NaN.                                     */
+size_t dg_psnr_workspace_bytes(void);
+dg_status dg_psnr(int64_t n, const float* est, const float* ref, double* out, void* work,
+                  void* stream);
+
 /* ------------------------------------------------------------------ batch
  * Many independent slices in one set of launches (not in the paper, whose
  * method reconstructs one slice at a time; every slice runs exactly the

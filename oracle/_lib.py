@@ -47,8 +47,20 @@ def lib():
         L.oracle_nlm.argtypes = [ctypes.c_int, _D, ctypes.c_double, ctypes.c_int, ctypes.c_int,
                                  ctypes.c_double, _D]
         L.oracle_nlm.restype = None
+        L.oracle_set_threads.argtypes = [ctypes.c_int]
+        L.oracle_set_threads.restype = None
+        L.oracle_max_threads.argtypes = []
+        L.oracle_max_threads.restype = ctypes.c_int
         _lib = L
     return _lib
+
+
+def set_threads(n):
+    """Threads of the C core's OpenMP loops; returns the previous count."""
+    L = lib()
+    prev = int(L.oracle_max_threads())
+    L.oracle_set_threads(int(n))
+    return prev
 
 
 def dptr(a):

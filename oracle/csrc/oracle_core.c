@@ -198,3 +198,8 @@ void oracle_nlm(int I, const double *r, double sigma, int pr, int sr,
     }
   }
 }
+
+/* Thread count of the OpenMP loops above (timing of the oracle only). */
+#include <omp.h>
+void oracle_set_threads(int n) { omp_set_num_threads(n > 0 ? n : 1); }
+int oracle_max_threads(void) { return omp_get_max_threads(); }

@@ -35,7 +35,8 @@ EXPORTS = ("dg_plan_create", "dg_plan_destroy", "dg_workspace_bytes", "dg_channe
            "dg_batch_workspace_bytes", "dg_batch_bind", "dg_batch_state_init",
            "dgamp_batch_iterate", "dg_batch_graph_create", "dg_batch_autotune",
            "dg_batch_projector_variant", "dg_plan_autotune", "dg_plan_projector_variant",
-           "dg_batch_set_projector_variant", "dg_plan_set_projector_variant")
+           "dg_batch_set_projector_variant", "dg_plan_set_projector_variant",
+           "dg_psnr_workspace_bytes", "dg_psnr")
 
 
 class DgError(RuntimeError):
@@ -132,6 +133,8 @@ def load():
         "dg_plan_projector_variant": ([_VP], i32),
         "dg_batch_set_projector_variant": ([_VP, i32], i32),
         "dg_plan_set_projector_variant": ([_VP, i32], i32),
+        "dg_psnr_workspace_bytes": ([], sz),
+        "dg_psnr": ([i64, _VP, _VP, _VP, _VP, _VP], i32),
     }
     missing = set(EXPORTS) - set(sig)
     if missing:
@@ -373,6 +376,24 @@ class DgampGraph:
                 self._h = None
         except Exception:
             pass
+
+
+_psnr_work = {}
+
+
+def dg_psnr(est, ref, out=None):
+    """PSNR (dB) of est against ref on the device; returns a 1-element FP64 tensor."""
+    n = ref.numel()
+    if out is None:
+        out = torch.empty(1, dtype=torch.float64, device="cuda")
+    dev = torch.cuda.current_device()
+    if dev not in _psnr_work:
+        _psnr_work[dev] = torch.empty(int(_lib.dg_psnr_workspace_bytes()), dtype=torch.uint8,
+                                      device="cuda")
+    _check(_lib.dg_psnr(n, _ptr(est, torch.float32, n, "est"), _ptr(ref, torch.float32, n, "ref"),
+                        _ptr(out, torch.float64, 1, "out"),
+                        _ptr(_psnr_work[dev], torch.uint8, None, "work"), _stream()))
+    return out
 
 
 class Batch:

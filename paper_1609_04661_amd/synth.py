@@ -135,3 +135,14 @@ def batch_slices(seed, n_slices=64):
         out.append(dict(geom=geometry(PARALLEL, n, 1.0, nv, nb, math.pi), i0=i0,
                         seed=seed + k))
     return out
+
+
+def c5_slices(seed, n_slices=16):
+    """The fan-beam low-dose batch: every slice the C5 geometry at I0 = 5e3,
+    with 1-5 high-attenuation inserts drawn per slice."""
+    out = []
+    for k in range(n_slices):
+        rng = np.random.Generator(np.random.PCG64(seed + k))
+        out.append(dict(geom=c5_geometry(), i0=5e3, seed=seed + k,
+                        inserts=int(rng.integers(1, 6))))
+    return out

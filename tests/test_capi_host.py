@@ -89,3 +89,10 @@ def test_batch_entry_points_reject_bad_arguments():
     assert L.dg_plan_projector_variant(None) == -1
     assert L.dg_plan_autotune(None, None, None, None, 1, None) == -1
     assert L.dg_last_error()
+
+
+def test_psnr_rejects_bad_arguments():
+    L = api.load()
+    assert L.dg_psnr_workspace_bytes() >= 8
+    assert L.dg_psnr(0, None, None, None, None, None) == -1
+    assert L.dg_psnr(10, None, None, None, None, None) == -1

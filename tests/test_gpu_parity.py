@@ -186,13 +186,15 @@ def test_haar_matches_oracle(gpu_lib, I):
     assert abs(float(host(div)[0]) - div_ref) <= 2e-3
 
 
-@pytest.mark.parametrize("I", [64, 100])
-def test_nlm_matches_oracle(gpu_lib, I):
+@pytest.mark.parametrize("I,noise,tau", [(64, 0.004, 1.6e-5), (100, 0.004, 1.6e-5),
+                                         (256, 3.0, 9.0), (1024, 0.05, 2.5e-3)])
+def test_nlm_matches_oracle(gpu_lib, I, noise, tau):
+    """Small and large sides (tile tails, 1024 x 1024) and both noise regimes
+    (weights near 1 everywhere at sigma^2 = tau = 9)."""
     g = synth.geometry(synth.PARALLEL, I, 1.0, 4, I + 1, math.pi)
     P = gpu_lib.Plan(g)
-    r = synth.ellipse_phantom(I, 6) + 0.004 * np.random.default_rng(2).standard_normal((I, I))
+    r = synth.ellipse_phantom(I, 6) + noise * np.random.default_rng(2).standard_normal((I, I))
     r32 = r.astype(np.float32).astype(np.float64)
-    tau = 1.6e-5
     x, div = gpu_lib.denoise(P, gpu_lib.DEN_NLM, gpu_lib.make_params(gpu_lib.DEN_NLM),
                              cu(r32), cu([tau], torch.float64), probe_seed=5, iteration=1)
     x_ref = oden.nlm(r32, tau)
@@ -266,3 +268,16 @@ def test_dgamp_c2_first_iterations_match_oracle(gpu_lib, plans):
     assert rel_l2(out_mu, ref_mu) <= 1e-3
     for t in range(T):
         assert abs(log[t, 2] - ref_log[t]["tau_r"]) <= 1e-4 * ref_log[t]["tau_r"]
+
+
+@pytest.mark.parametrize("n", [1, 4096, 1000003])
+def test_psnr_matches_oracle(gpu_lib, n):
+    """Device PSNR (FP64 sums of FP32 inputs) against the oracle's definition
+    on the same FP32 values: equal to 1e-9 dB (only the summation order
+    differs); identical images give +inf."""
+    rng = np.random.default_rng(n)
+    ref = rng.random(n).astype(np.float32) * 0.05
+    est = (ref + rng.standard_normal(n).astype(np.float32) * 1e-3).astype(np.float32)
+    got = float(gpu_lib.dg_psnr(cu(est), cu(ref)).item())
+    assert abs(got - metrics.psnr(est, ref)) <= 1e-9, (got, metrics.psnr(est, ref))
+    assert math.isinf(float(gpu_lib.dg_psnr(cu(ref), cu(ref)).item()))
