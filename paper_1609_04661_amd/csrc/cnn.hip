@@ -25,10 +25,10 @@ typedef __bf16 bf16;
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
 typedef float floatx4 __attribute__((ext_vector_type(4)));
+typedef float floatx16 __attribute__((ext_vector_type(16)));
 
 static constexpr int kC = 64, kMid = 8;
 static constexpr int kTile = 16, kHalo = kTile + 2;
-static constexpr int kPix = 72;  // LDS pixel stride in bf16 (64 + 8 pad: conflict-free 16-lane reads)
 
 // ------------------------------------------------------------- layouts
 
@@ -112,179 +112,348 @@ __global__ void cnn_pack_kernel(const float* __restrict__ m, char* __restrict__ 
 
 // ------------------------------------------------------------- layers
 
-// Input layer 1 -> 64, one thread per pixel.
+// Input layer 1 -> 64.  Eight lanes per pixel: lane c8 computes output
+// channels 8 c8 .. 8 c8 + 7 and stores them as one 16-byte chunk, so a
+// wavefront writes 8 whole pixels (1 KiB) contiguously.  Each thread keeps
+// its 72 weights and 8 biases in registers and walks pixels with a grid
+// stride.
 //   mode 0: out = relu(conv(in) + b0)
-//   mode 1: out = conv(in) * (mask > 0)          (tangent / no bias)
+//   mode 1: out = conv(b) * (mask > 0), b the Rademacher probe (tangent pass)
 __global__ void __launch_bounds__(256)
 cnn_in_kernel(const float* __restrict__ in, const void* __restrict__ packed,
               const bf16* __restrict__ mask, bf16* __restrict__ out, int n, int H, int W,
-              int mode, uint64_t seed, int iter, int probe_input) {
-  const int64_t pix = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int64_t npix = (int64_t)n * H * W;
-  if (pix >= npix) return;
+              int mode, uint64_t seed, int iter) {
   const Packed P = unpack(packed);
-  const int img = (int)(pix / ((int64_t)H * W));
-  const int rem = (int)(pix % ((int64_t)H * W));
-  const int y = rem / W, x = rem % W;
-  float v[9];
+  const int c8 = threadIdx.x & 7;
+  float w[8][9], b[8];
 #pragma unroll
-  for (int t = 0; t < 9; ++t) {
-    const int yy = y + t / 3 - 1, xx = x + t % 3 - 1;
-    float val = 0.0f;
-    if (yy >= 0 && yy < H && xx >= 0 && xx < W) {
-      const int64_t q = (int64_t)img * H * W + (int64_t)yy * W + xx;
-      // probe_input: the input is the Rademacher probe b itself
-      val = probe_input ? probe_sign(seed, iter, (uint64_t)(q - (int64_t)img * H * W)) : in[q];
-    }
-    v[t] = val;
+  for (int j = 0; j < 8; ++j) {
+    b[j] = mode == 0 ? P.b0[c8 * 8 + j] : 0.0f;
+#pragma unroll
+    for (int t = 0; t < 9; ++t) w[j][t] = P.w0[(c8 * 8 + j) * 9 + t];
   }
-  bf16* o = out + pix * kC;
-  const bf16* mk = mask ? mask + pix * kC : nullptr;
-  for (int c0 = 0; c0 < kC; c0 += 8) {
-    bf16x8 pack;
+  // 32-bit index arithmetic (the host limits a call to n H W < 2^31 pixels)
+  const unsigned HW = (unsigned)H * (unsigned)W, npix = (unsigned)n * HW;
+  const unsigned stride = gridDim.x * (blockDim.x >> 3);
+  // whole 8-lane groups share a pixel, so they run the same iterations
+  for (unsigned pix = (blockIdx.x * blockDim.x + threadIdx.x) >> 3; pix < npix; pix += stride) {
+    const unsigned img = pix / HW;
+    const int rem = (int)(pix - img * HW);
+    const int y = rem / W, x = rem - y * W;
+    float v[9];
+    if (mode == 0) {
+#pragma unroll
+      for (int t = 0; t < 9; ++t) {
+        const int yy = y + t / 3 - 1, xx = x + t % 3 - 1;
+        v[t] = (yy >= 0 && yy < H && xx >= 0 && xx < W) ? in[(int64_t)img * HW + yy * W + xx]
+                                                        : 0.0f;
+      }
+    } else {
+      // probe values of the 9 neighbours: lane c8 hashes tap c8, every lane
+      // tap 8; taps 0..7 are shared within the 8-lane group
+      auto probe_at = [&](int t) {
+        const int yy = y + t / 3 - 1, xx = x + t % 3 - 1;
+        return (yy >= 0 && yy < H && xx >= 0 && xx < W)
+                   ? probe_sign(seed, iter, (uint64_t)((int64_t)yy * W + xx))
+                   : 0.0f;
+      };
+      const float pv = probe_at(c8);
+#pragma unroll
+      for (int t = 0; t < 8; ++t) v[t] = __shfl(pv, t, 8);
+      v[8] = probe_at(8);
+    }
+    bf16x8 mk;
+    if (mode != 0) mk = *(const bf16x8*)(mask + (int64_t)pix * kC + c8 * 8);
+    bf16x8 pk;
 #pragma unroll
     for (int j = 0; j < 8; ++j) {
-      const int co = c0 + j;
-      float acc = mode == 0 ? P.b0[co] : 0.0f;
+      float acc = b[j];
 #pragma unroll
-      for (int t = 0; t < 9; ++t) acc = __fmaf_rn(P.w0[co * 9 + t], v[t], acc);
+      for (int t = 0; t < 9; ++t) acc = __fmaf_rn(w[j][t], v[t], acc);
       if (mode == 0)
         acc = fmaxf(acc, 0.0f);
       else
-        acc = ((float)mk[co] > 0.0f) ? acc : 0.0f;
-      pack[j] = (bf16)acc;
+        acc = ((float)mk[j] > 0.0f) ? acc : 0.0f;
+      pk[j] = (bf16)acc;
     }
-    *(bf16x8*)(o + c0) = pack;
+    *(bf16x8*)(out + (int64_t)pix * kC + c8 * 8) = pk;
   }
+}
+
+static unsigned int in_grid(int64_t npix) {
+  const int64_t g = (npix * 8 + 255) / 256;
+  return (unsigned int)(g < 2048 ? g : 2048);
 }
 
 // 64 -> 64 layer on MFMA.
 //   mode 0: out = relu(conv(in, Wl) + bl)
 //   mode 1: out = conv(in, Wl) * (mask > 0)
 // W: bf16[9][64 out][64 in].
-__global__ void __launch_bounds__(256)
+//
+// One 512-thread workgroup per compute unit (two wavefronts per SIMD) walks
+// output tiles of kMidTH x kMidTW pixels.  The layer's weights (72 KiB) are
+// staged in LDS once per workgroup; each tile's input halo ((kMidTH+2) x
+// (kMidTW+2) pixels x 64 channels, 76.5 KiB) is staged per tile, all of a
+// thread's loads in flight at once.  Both LDS arrays store 16-byte channel
+// chunks XOR-swizzled by the row index (chunk c of row p at c ^ (p & 7)), so
+// the lanes that read one fragment row hit distinct 16-byte bank groups.
+// Wavefront w computes tile rows 4w .. 4w+3 for all 64 output channels with
+// v_mfma_f32_16x16x32_bf16: per K-step (tap, 32-channel half) 4 weight
+// fragments and 4 pixel fragments feed 16 MFMAs; the compiler shares the
+// pixel fragments of a row between the three taps of one column.  (The
+// 32 x 32 x 16 form has a higher peak, but in this tiling it moves more LDS
+// bytes per MFMA and measured slower.)
+static constexpr int kMidThreads = 512, kMidWaves = kMidThreads / 64;
+static constexpr int kMidTH = 32, kMidTW = 16;
+static constexpr int kMidHH = kMidTH + 2, kMidHW = kMidTW + 2;
+static constexpr int kMidRows = kMidTH / kMidWaves;  // tile rows per wavefront
+static constexpr int kHaloChunks = kMidHH * kMidHW * 8;
+static constexpr int kHaloRounds = (kHaloChunks + kMidThreads - 1) / kMidThreads;
+
+__device__ __forceinline__ int swz(int row, int chunk) { return (row << 3) + (chunk ^ (row & 7)); }
+
+__host__ __device__ inline int mid_tiles(int n, int H, int W) {
+  return n * ((H + kMidTH - 1) / kMidTH) * ((W + kMidTW - 1) / kMidTW);
+}
+
+// Load one tile's halo into registers (zero outside the image); interior
+// tiles skip the per-chunk bounds tests.
+__device__ __forceinline__ void halo_fetch(const bf16* __restrict__ in, int tile, int tiles_x,
+                                           int tiles_y, int H, int W, bf16x8 (&hr)[kHaloRounds]) {
+  const int img = tile / (tiles_x * tiles_y);
+  const int trem = tile % (tiles_x * tiles_y);
+  const int y0 = (trem / tiles_x) * kMidTH - 1, x0 = (trem % tiles_x) * kMidTW - 1;
+  const bf16* base = in + ((int64_t)img * H * W + (int64_t)y0 * W + x0) * kC;
+  const bool interior = y0 >= 0 && x0 >= 0 && y0 + kMidHH <= H && x0 + kMidHW <= W;
+#pragma unroll
+  for (int q = 0; q < kHaloRounds; ++q) {
+    const int e = q * kMidThreads + threadIdx.x;
+    const int pix = e >> 3, ch = e & 7;
+    const int hy = pix / kMidHW, hx = pix - hy * kMidHW;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) hr[q][j] = (bf16)0.0f;
+    const bool inb = (q + 1 < kHaloRounds || e < kHaloChunks) &&
+                     (interior || ((unsigned)(y0 + hy) < (unsigned)H && (unsigned)(x0 + hx) < (unsigned)W));
+    if (inb) hr[q] = *(const bf16x8*)(base + ((int64_t)hy * W + hx) * kC + ch * 8);
+  }
+}
+
+__device__ __forceinline__ void halo_store(bf16x8* sX, const bf16x8 (&hr)[kHaloRounds]) {
+#pragma unroll
+  for (int q = 0; q < kHaloRounds; ++q) {
+    const int e = q * kMidThreads + threadIdx.x;
+    if (e < kHaloChunks) sX[swz(e >> 3, e & 7)] = hr[q];
+  }
+}
+
+template <int MODE>
+__global__ void __launch_bounds__(kMidThreads)
 cnn_mid_kernel(const bf16* __restrict__ in, const bf16* __restrict__ Wt,
                const float* __restrict__ bias, const bf16* __restrict__ mask,
-               bf16* __restrict__ out, int n, int H, int W, int mode) {
-  __shared__ __attribute__((aligned(16))) bf16 sIn[kHalo * kHalo * kPix];
-  const int tiles_x = (W + kTile - 1) / kTile, tiles_y = (H + kTile - 1) / kTile;
-  const int img = blockIdx.x / (tiles_x * tiles_y);
-  const int trem = blockIdx.x % (tiles_x * tiles_y);
-  const int y0 = (trem / tiles_x) * kTile, x0 = (trem % tiles_x) * kTile;
-  const int64_t ibase = (int64_t)img * H * W;
-  // stage the halo tile: 18 x 18 pixels x 8 chunks of 16 bytes
-  for (int e = threadIdx.x; e < kHalo * kHalo * 8; e += blockDim.x) {
-    const int pix = e >> 3, ch = (e & 7) * 8;
-    const int yy = y0 - 1 + pix / kHalo, xx = x0 - 1 + pix % kHalo;
-    bf16x8 v;
-    if (yy >= 0 && yy < H && xx >= 0 && xx < W) {
-      v = *(const bf16x8*)(in + (ibase + (int64_t)yy * W + xx) * kC + ch);
-    } else {
-#pragma unroll
-      for (int j = 0; j < 8; ++j) v[j] = (bf16)0.0f;
-    }
-    *(bf16x8*)(sIn + pix * kPix + ch) = v;
-  }
-  __syncthreads();
+               bf16* __restrict__ out, int n, int H, int W) {
+  __shared__ bf16x8 sW[9 * 64 * 8];            // [tap][co] rows of 8 chunks
+  __shared__ bf16x8 sX[kMidHH * kMidHW * 8];   // [halo pixel] rows of 8 chunks
+  __shared__ floatx4 sB[16];                   // biases (mode 0)
+  const int tiles_x = (W + kMidTW - 1) / kMidTW, tiles_y = (H + kMidTH - 1) / kMidTH;
+  const int ntiles = n * tiles_x * tiles_y;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int lr = lane & 15, lk = (lane >> 4) * 8;  // row/col within a 16 tile, k offset
-  floatx4 acc[4][4];
+  const int lr = lane & 15, lq = lane >> 4;  // fragment row (pixel / co) and k chunk
+  bf16x8 hr[kHaloRounds];
+  int tile = blockIdx.x;
+  {
+    // weights and the first halo: every load is issued before the first LDS
+    // store, so the staging costs one memory latency
+    constexpr int kRounds = 9 * 64 * 8 / kMidThreads;
+    bf16x8 wr[kRounds];
 #pragma unroll
-  for (int a = 0; a < 4; ++a)
+    for (int q = 0; q < kRounds; ++q)
+      wr[q] = *(const bf16x8*)(Wt + (int64_t)(q * kMidThreads + threadIdx.x) * 8);
+    if (tile < ntiles) halo_fetch(in, tile, tiles_x, tiles_y, H, W, hr);
+    if (MODE == 0 && threadIdx.x < 16)
+      sB[threadIdx.x] = floatx4{bias[threadIdx.x * 4], bias[threadIdx.x * 4 + 1],
+                                bias[threadIdx.x * 4 + 2], bias[threadIdx.x * 4 + 3]};
 #pragma unroll
-    for (int b = 0; b < 4; ++b) acc[a][b] = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
-  for (int tap = 0; tap < 9; ++tap) {
-    const int ty = tap / 3, tx = tap % 3;
+    for (int q = 0; q < kRounds; ++q) {
+      const int e = q * kMidThreads + threadIdx.x;
+      sW[swz(e >> 3, e & 7)] = wr[q];
+    }
+  }
+  if (tile < ntiles) halo_store(sX, hr);
+  __syncthreads();
+  for (; tile < ntiles; tile += gridDim.x) {
+    const int img = tile / (tiles_x * tiles_y);
+    const int trem = tile % (tiles_x * tiles_y);
+    const int y0 = (trem / tiles_x) * kMidTH, x0 = (trem % tiles_x) * kMidTW;
+    const int64_t ibase = (int64_t)img * H * W;
+    const int next = tile + gridDim.x;
+    floatx4 acc[kMidRows][4];
 #pragma unroll
-    for (int half = 0; half < 2; ++half) {
-      bf16x8 af[4], bfr[4];
+    for (int a = 0; a < kMidRows; ++a)
 #pragma unroll
-      for (int ct = 0; ct < 4; ++ct)
-        af[ct] = *(const bf16x8*)(Wt + ((int64_t)(tap * 64 + ct * 16 + lr) * 64 + half * 32 + lk));
+      for (int b = 0; b < 4; ++b) acc[a][b] = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
-      for (int rr = 0; rr < 4; ++rr) {
-        const int py = wave * 4 + rr + ty, px = lr + tx;  // halo coordinates
-        bfr[rr] = *(const bf16x8*)(sIn + (py * kHalo + px) * kPix + half * 32 + lk);
+    for (int tap = 0; tap < 9; ++tap) {
+      const int ty = tap / 3, tx = tap % 3;
+#pragma unroll
+      for (int half = 0; half < 2; ++half) {
+        const int chunk = half * 4 + lq;
+        bf16x8 af[4], bfr[kMidRows];
+#pragma unroll
+        for (int ct = 0; ct < 4; ++ct) af[ct] = sW[swz(tap * 64 + ct * 16 + lr, chunk)];
+#pragma unroll
+        for (int rr = 0; rr < kMidRows; ++rr)
+          bfr[rr] = sX[swz((wave * kMidRows + rr + ty) * kMidHW + lr + tx, chunk)];
+#pragma unroll
+        for (int rr = 0; rr < kMidRows; ++rr)
+#pragma unroll
+          for (int ct = 0; ct < 4; ++ct)
+            acc[rr][ct] =
+                __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[ct], bfr[rr], acc[rr][ct], 0, 0, 0);
       }
+    }
+    // C layout: lane holds pixel column lr, output channels ct*16 + 4*lq + j.
+    bf16x4 m4[kMidRows][4];
+    if (MODE != 0) {
 #pragma unroll
-      for (int rr = 0; rr < 4; ++rr)
+      for (int rr = 0; rr < kMidRows; ++rr) {
+        const int yy = y0 + wave * kMidRows + rr, xx = x0 + lr;
+        const bool ok = yy < H && xx < W;
+        const int64_t pbase = (ibase + (int64_t)(ok ? yy : 0) * W + (ok ? xx : 0)) * kC;
 #pragma unroll
         for (int ct = 0; ct < 4; ++ct)
-          acc[rr][ct] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[ct], bfr[rr], acc[rr][ct], 0, 0, 0);
-    }
-  }
-  // C layout: lane holds pixel column lr, output channels ct*16 + 4*(lane>>4) + j
-#pragma unroll
-  for (int rr = 0; rr < 4; ++rr) {
-    const int yy = y0 + wave * 4 + rr, xx = x0 + lr;
-    if (yy >= H || xx >= W) continue;
-    const int64_t pbase = (ibase + (int64_t)yy * W + xx) * kC;
-#pragma unroll
-    for (int ct = 0; ct < 4; ++ct) {
-      const int co = ct * 16 + (lane >> 4) * 4;
-      bf16x4 o4;
-      if (mode == 0) {
-#pragma unroll
-        for (int j = 0; j < 4; ++j) o4[j] = (bf16)fmaxf(acc[rr][ct][j] + bias[co + j], 0.0f);
-      } else {
-        const bf16x4 m4 = *(const bf16x4*)(mask + pbase + co);
-#pragma unroll
-        for (int j = 0; j < 4; ++j) o4[j] = (bf16)(((float)m4[j] > 0.0f) ? acc[rr][ct][j] : 0.0f);
+          m4[rr][ct] = *(const bf16x4*)(mask + pbase + ct * 16 + lq * 4);
       }
-      *(bf16x4*)(out + pbase + co) = o4;
+    }
+#pragma unroll
+    for (int rr = 0; rr < kMidRows; ++rr) {
+      const int yy = y0 + wave * kMidRows + rr, xx = x0 + lr;
+      if (yy >= H || xx >= W) continue;
+      const int64_t pbase = (ibase + (int64_t)yy * W + xx) * kC;
+#pragma unroll
+      for (int ct = 0; ct < 4; ++ct) {
+        bf16x4 o4;
+        const floatx4 b4 = (MODE == 0) ? sB[ct * 4 + lq] : floatx4{0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          if (MODE == 0)
+            o4[j] = (bf16)fmaxf(acc[rr][ct][j] + b4[j], 0.0f);
+          else
+            o4[j] = (bf16)(((float)m4[rr][ct][j] > 0.0f) ? acc[rr][ct][j] : 0.0f);
+        }
+        *(bf16x4*)(out + pbase + ct * 16 + lq * 4) = o4;
+      }
+    }
+    if (next < ntiles) {
+      halo_fetch(in, next, tiles_x, tiles_y, H, W, hr);
+      __syncthreads();  // every wavefront is done reading this tile's halo
+      halo_store(sX, hr);
+      __syncthreads();
     }
   }
 }
 
-// Output layer 64 -> 1.
+// One workgroup per compute unit (the kernel's LDS use admits no second),
+// never more workgroups than tiles.
+static unsigned int mid_grid(int n, int H, int W) {
+  const int t = mid_tiles(n, H, W);
+  return (unsigned int)(t < 256 ? t : 256);
+}
+
+// Output layer 64 -> 1, 16 x 16 output tiles (grid stride).  Pass 1: for
+// every pixel q of the 18 x 18 halo, d_t(q) = act[q] . w9[t] for the 9 taps
+// t, eight lanes per pixel (8 channels each, coalesced 16-byte loads)
+// reduced across the eight lanes; pass 2: f(p) = b9 + sum_t d_t(p + off_t).
 //   mode 0 (primal):   out = r - (conv(act) + b9)
 //   mode 1 (tangent):  out = xden + eps * (b - conv(act)), so that
 //                      b^T (out - xden) / (N eps) = b^T J_D b / N
 //   mode 2 (training): f = conv(act) + b9; res = r - f - clean;
 //                      out = g_f = -2 res / count; loss partial per block
+static constexpr int kOutT = 16, kOutH = kOutT + 2;
+
+__host__ __device__ inline int out_tiles(int n, int H, int W) {
+  return n * ((H + kOutT - 1) / kOutT) * ((W + kOutT - 1) / kOutT);
+}
+
 __global__ void __launch_bounds__(256)
 cnn_out_kernel(const bf16* __restrict__ act, const void* __restrict__ packed,
                const float* __restrict__ r, const float* __restrict__ xden,
                const float* __restrict__ clean, float* __restrict__ out, int n, int H, int W,
                int mode, const double* __restrict__ eps_ptr, int eps_stride, uint64_t seed,
                int iter, double* __restrict__ loss_partials, double inv_count) {
+  __shared__ float sd[kOutH * kOutH][9];
   __shared__ double red[4];
-  const int64_t pix = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int64_t npix = (int64_t)n * H * W;
   const Packed P = unpack(packed);
+  const int c8 = threadIdx.x & 7;
+  float wv[9][8];
+#pragma unroll
+  for (int t = 0; t < 9; ++t)
+#pragma unroll
+    for (int j = 0; j < 8; ++j) wv[t][j] = P.w9[t * 64 + c8 * 8 + j];
+  const int tiles_x = (W + kOutT - 1) / kOutT, tiles_y = (H + kOutT - 1) / kOutT;
+  const int ntiles = n * tiles_x * tiles_y;
+  const int64_t HW = (int64_t)H * W;
   double lsum = 0.0;
-  if (pix < npix) {
-    const int img = (int)(pix / ((int64_t)H * W));
-    const int rem = (int)(pix % ((int64_t)H * W));
-    const int y = rem / W, x = rem % W;
-    float f = (mode == 1) ? 0.0f : P.b9[0];
-    for (int t = 0; t < 9; ++t) {
-      const int yy = y + t / 3 - 1, xx = x + t % 3 - 1;
-      if (yy < 0 || yy >= H || xx < 0 || xx >= W) continue;
-      const bf16* a = act + ((int64_t)img * H * W + (int64_t)yy * W + xx) * kC;
-      const float* w = P.w9 + t * 64;
+  for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+    const int img = tile / (tiles_x * tiles_y);
+    const int trem = tile % (tiles_x * tiles_y);
+    const int y0 = (trem / tiles_x) * kOutT, x0 = (trem % tiles_x) * kOutT;
+    const int64_t ibase = (int64_t)img * HW;
+    __syncthreads();  // the previous tile's pass 2 is done with sd
+    // c8 = e & 7 stays the thread's own channel group (256 is a multiple of 8)
+    for (int e = threadIdx.x; e < kOutH * kOutH * 8; e += blockDim.x) {
+      const int q = e >> 3;
+      const int yy = y0 - 1 + q / kOutH, xx = x0 - 1 + q % kOutH;
+      float part[9];
 #pragma unroll
-      for (int c0 = 0; c0 < kC; c0 += 8) {
-        const bf16x8 v = *(const bf16x8*)(a + c0);
+      for (int t = 0; t < 9; ++t) part[t] = 0.0f;
+      if (yy >= 0 && yy < H && xx >= 0 && xx < W) {
+        const bf16x8 a = *(const bf16x8*)(act + (ibase + (int64_t)yy * W + xx) * kC + c8 * 8);
 #pragma unroll
-        for (int j = 0; j < 8; ++j) f = __fmaf_rn(w[c0 + j], (float)v[j], f);
+        for (int j = 0; j < 8; ++j) {
+          const float av = (float)a[j];
+#pragma unroll
+          for (int t = 0; t < 9; ++t) part[t] = __fmaf_rn(wv[t][j], av, part[t]);
+        }
+      }
+#pragma unroll
+      for (int t = 0; t < 9; ++t) {
+        float v = part[t];
+        v += __shfl_xor(v, 1, 8);
+        v += __shfl_xor(v, 2, 8);
+        v += __shfl_xor(v, 4, 8);
+        if (c8 == 0) sd[q][t] = v;
       }
     }
-    if (mode == 0) {
-      out[pix] = r[pix] - f;
-    } else if (mode == 1) {
-      const float b = probe_sign(seed, iter, (uint64_t)rem);
-      out[pix] = __fmaf_rn((float)eps_ptr[(int64_t)img * eps_stride], b - f, xden[pix]);
-    } else {
-      const float res = r[pix] - f - clean[pix];
-      lsum = (double)res * (double)res;
-      out[pix] = (float)(-2.0 * (double)res * inv_count);
+    __syncthreads();
+    const int ty = threadIdx.x / kOutT, tx = threadIdx.x % kOutT;
+    const int y = y0 + ty, x = x0 + tx;
+    if (y < H && x < W) {
+      float f = (mode == 1) ? 0.0f : P.b9[0];
+#pragma unroll
+      for (int t = 0; t < 9; ++t) f += sd[(ty + t / 3) * kOutH + tx + t % 3][t];
+      const int64_t rem = (int64_t)y * W + x, pix = ibase + rem;
+      if (mode == 0) {
+        out[pix] = r[pix] - f;
+      } else if (mode == 1) {
+        const float b = probe_sign(seed, iter, (uint64_t)rem);
+        out[pix] = __fmaf_rn((float)eps_ptr[(int64_t)img * eps_stride], b - f, xden[pix]);
+      } else {
+        const float res = r[pix] - f - clean[pix];
+        lsum += (double)res * (double)res;
+        out[pix] = (float)(-2.0 * (double)res * inv_count);
+      }
     }
   }
   if (mode == 2) {
     const double bs = block_sum(lsum, red);
     if (threadIdx.x == 0) loss_partials[blockIdx.x] = bs;
   }
+}
+
+// Workgroups of the output layer (loss partials in mode 2: one per workgroup).
+static unsigned int out_grid(int n, int H, int W) {
+  const int t = out_tiles(n, H, W);
+  return (unsigned int)(t < 2048 ? t : 2048);
 }
 
 // ------------------------------------------------------------- backward
@@ -567,18 +736,19 @@ static dg_status cnn_forward(const void* packed, const float* r, float* out, int
                              CnnWork& w, hipStream_t st) {
   const Packed P = unpack(packed);
   const int64_t npix = (int64_t)n * H * W;
-  hipLaunchKernelGGL(cnn_in_kernel, dim3(g256(npix)), dim3(256), 0, st, r, packed,
-                     (const bf16*)nullptr, w.act[0], n, H, W, 0, (uint64_t)0, 0, 0);
+  DG_ARG_CHECK(npix < ((int64_t)1 << 31), "CNN: at most 2^31 - 1 pixels per call");
+  hipLaunchKernelGGL(cnn_in_kernel, dim3(in_grid(npix)), dim3(256), 0, st, r, packed,
+                     (const bf16*)nullptr, w.act[0], n, H, W, 0, (uint64_t)0, 0);
   DG_LAUNCH_CHECK("cnn_in_kernel");
-  const int tiles = n * ((H + kTile - 1) / kTile) * ((W + kTile - 1) / kTile);
+  const unsigned int tiles = mid_grid(n, H, W);
   for (int l = 0; l < kMid; ++l) {
-    hipLaunchKernelGGL(cnn_mid_kernel, dim3(tiles), dim3(256), 0, st, w.act[l],
+    hipLaunchKernelGGL(cnn_mid_kernel<0>, dim3(tiles), dim3(kMidThreads), 0, st, w.act[l],
                        P.wm + (size_t)l * 9 * 64 * 64, P.bm + l * 64, (const bf16*)nullptr,
-                       w.act[l + 1], n, H, W, 0);
+                       w.act[l + 1], n, H, W);
     DG_LAUNCH_CHECK("cnn_mid_kernel");
   }
   if (out) {
-    hipLaunchKernelGGL(cnn_out_kernel, dim3(g256(npix)), dim3(256), 0, st, w.act[8], packed, r,
+    hipLaunchKernelGGL(cnn_out_kernel, dim3(out_grid(n, H, W)), dim3(256), 0, st, w.act[8], packed, r,
                        (const float*)nullptr, (const float*)nullptr, out, n, H, W, 0,
                        (const double*)nullptr, 0, (uint64_t)0, 0, (double*)nullptr, 0.0);
     DG_LAUNCH_CHECK("cnn_out_kernel");
@@ -593,19 +763,20 @@ static dg_status cnn_tangent(const void* packed, const float* xden, float* xpert
                              int H, int W, CnnWork& w, hipStream_t st) {
   const Packed P = unpack(packed);
   const int64_t npix = (int64_t)n * H * W;
-  hipLaunchKernelGGL(cnn_in_kernel, dim3(g256(npix)), dim3(256), 0, st, (const float*)nullptr,
-                     packed, w.act[0], w.tan[0], n, H, W, 1, seed, iter, 1);
+  DG_ARG_CHECK(npix < ((int64_t)1 << 31), "CNN: at most 2^31 - 1 pixels per call");
+  hipLaunchKernelGGL(cnn_in_kernel, dim3(in_grid(npix)), dim3(256), 0, st, (const float*)nullptr,
+                     packed, w.act[0], w.tan[0], n, H, W, 1, seed, iter);
   DG_LAUNCH_CHECK("cnn_in_kernel<tangent>");
-  const int tiles = n * ((H + kTile - 1) / kTile) * ((W + kTile - 1) / kTile);
+  const unsigned int tiles = mid_grid(n, H, W);
   int cur = 0;
   for (int l = 0; l < kMid; ++l) {
-    hipLaunchKernelGGL(cnn_mid_kernel, dim3(tiles), dim3(256), 0, st, w.tan[cur],
+    hipLaunchKernelGGL(cnn_mid_kernel<1>, dim3(tiles), dim3(kMidThreads), 0, st, w.tan[cur],
                        P.wm + (size_t)l * 9 * 64 * 64, (const float*)nullptr, w.act[l + 1],
-                       w.tan[cur ^ 1], n, H, W, 1);
+                       w.tan[cur ^ 1], n, H, W);
     DG_LAUNCH_CHECK("cnn_mid_kernel<tangent>");
     cur ^= 1;
   }
-  hipLaunchKernelGGL(cnn_out_kernel, dim3(g256(npix)), dim3(256), 0, st, w.tan[cur], packed,
+  hipLaunchKernelGGL(cnn_out_kernel, dim3(out_grid(n, H, W)), dim3(256), 0, st, w.tan[cur], packed,
                      (const float*)nullptr, xden, (const float*)nullptr, xpert, n, H, W, 1, eps,
                      eps_stride, seed, iter, (double*)nullptr, 0.0);
   DG_LAUNCH_CHECK("cnn_out_kernel<tangent>");
@@ -688,12 +859,12 @@ extern "C" dg_status dg_cnn_train_step(const float* noisy, const float* clean, i
   if (rc != DG_OK) return rc;
   // loss and dL/df
   const unsigned int gb = g256(npix);
-  DG_ARG_CHECK(gb <= 65536, "dg_cnn_train_step: batch too large");
-  hipLaunchKernelGGL(cnn_out_kernel, dim3(gb), dim3(256), 0, st, cw.act[8], packed, noisy,
+  const unsigned int ot = out_grid(n, h, w);
+  hipLaunchKernelGGL(cnn_out_kernel, dim3(ot), dim3(256), 0, st, cw.act[8], packed, noisy,
                      (const float*)nullptr, clean, cw.f, n, h, w, 2, (const double*)nullptr, 0,
                      (uint64_t)0, 0, cw.dpart, 1.0 / (double)npix);
   DG_LAUNCH_CHECK("cnn_out_kernel<train>");
-  hipLaunchKernelGGL(cnn_loss_finish, dim3(1), dim3(256), 0, st, cw.dpart, (int)gb,
+  hipLaunchKernelGGL(cnn_loss_finish, dim3(1), dim3(256), 0, st, cw.dpart, (int)ot,
                      1.0 / (double)npix, loss_out);
   DG_LAUNCH_CHECK("cnn_loss_finish");
   // output layer: weight grads, then g8
@@ -707,7 +878,7 @@ extern "C" dg_status dg_cnn_train_step(const float* noisy, const float* clean, i
   hipLaunchKernelGGL(cnn_out_bwd_kernel, dim3(gb), dim3(256), 0, st, cw.f, packed, cw.act[8],
                      cw.tan[0], n, h, w);
   DG_LAUNCH_CHECK("cnn_out_bwd_kernel");
-  const int tiles = n * ((h + kTile - 1) / kTile) * ((w + kTile - 1) / kTile);
+  const unsigned int tiles = mid_grid(n, h, w);
   int cur = 0;  // cw.tan[cur] = gradient w.r.t. the (post-ReLU-masked) output of layer l+1
   for (int l = kMid - 1; l >= 0; --l) {
     // weight gradient of mid layer l: g = tan[cur] (masked), input act[l]
@@ -719,9 +890,9 @@ extern "C" dg_status dg_cnn_train_step(const float* noisy, const float* clean, i
     hipLaunchKernelGGL(cnn_scatter_mid, dim3(g256(9 * 64 * 64 + 64)), dim3(256), 0, st, cw.red,
                        grad, l);
     // data gradient into layer l's input (masked by its ReLU pattern)
-    hipLaunchKernelGGL(cnn_mid_kernel, dim3(tiles), dim3(256), 0, st, cw.tan[cur],
+    hipLaunchKernelGGL(cnn_mid_kernel<1>, dim3(tiles), dim3(kMidThreads), 0, st, cw.tan[cur],
                        P.wmt + (size_t)l * 9 * 64 * 64, (const float*)nullptr, cw.act[l],
-                       cw.tan[cur ^ 1], n, h, w, 1);
+                       cw.tan[cur ^ 1], n, h, w);
     DG_LAUNCH_CHECK("cnn_mid_kernel<bwd>");
     cur ^= 1;
   }
