@@ -23,6 +23,15 @@ static constexpr int kBpBlockX = 64, kBpBlockY = 4;
 // one view, so their reads stay coalesced), and the SEGS partial sums are
 // added in a fixed order.  Splitting the march gives SEGS times more
 // wavefronts to hide memory latency than one thread per ray.
+//
+// The march is unrolled by kMarch steps: the addresses and weights of both
+// candidates of every step are formed first (out-of-range candidates read a
+// clamped in-bounds pixel with weight 0), so 2 kMarch loads are in flight
+// before the first multiply-add.  The accumulation order (k ascending,
+// candidate p0 before p0 + 1) and every weight are those of ray_weight, so
+// A and A^T stay exact transposes of one another.
+static constexpr int kMarch = 8;
+
 template <int SEGS>
 __device__ void project_body(const ProjArgs& A, int blk, float (*part)[kRaysPerBlock]) {
   const int lane = threadIdx.x % kRaysPerBlock, seg = threadIdx.x / kRaysPerBlock;
@@ -38,6 +47,7 @@ __device__ void project_body(const ProjArgs& A, int blk, float (*part)[kRaysPerB
     // major_rows: the buffer read is laid out with the major index as its row.
     const bool major_rows = steep || (A.img_t != nullptr);
     const float* base = (steep || A.img_t == nullptr) ? A.img : A.img_t;
+    const int sk = major_rows ? I : 1, sp = major_rows ? 1 : I;
 
     // Major-index range where q(k) lies in (-1, I): candidates exist only there.
     int k0 = 0, k1 = I - 1;
@@ -55,24 +65,45 @@ __device__ void project_body(const ProjArgs& A, int blk, float (*part)[kRaysPerB
     const int ka = k0 + seg * chunk;
     const int kb = min(k1, ka + chunk - 1);
     int64_t q = L.q0_fx + L.m_fx * (int64_t)ka;  // exact: advanced by m_fx per step
-#pragma unroll 2
-    for (int k = ka; k <= kb; ++k, q += L.m_fx) {
+    // an axis-aligned ray keeps its cross coordinate: constant weights
+    const bool axis = (L.m == 0.0f);
+    float wc0 = 0.0f, wc1 = 0.0f;
+    if (axis) {
       int p0;
       float f;
       split_fx(q, &p0, &f);
+      wc0 = chord_fraction(f, L.m, L.inv_r);
+      wc1 = chord_fraction(1.0f - f, L.m, L.inv_r);
+    }
+    const float hw = __fmaf_rn(0.5f, fabsf(L.m), 0.5f);
+    for (int k = ka; k <= kb; k += kMarch) {
+      float v[2 * kMarch], w[2 * kMarch];
 #pragma unroll
-      for (int d = 0; d < 2; ++d) {
-        const int p = p0 + d;
-        if (p >= 0 && p < I) {
-          const float w = chord_fraction(d ? 1.0f - f : f, L.m, L.inv_r);
-          float v;
-          if (major_rows)
-            v = base[(int64_t)k * I + p];
-          else
-            v = base[(int64_t)p * I + k];  // flat ray without a transposed copy
-          acc = __fmaf_rn(w, v, acc);
+      for (int u = 0; u < kMarch; ++u) {
+        const int kk = k + u;
+        int p0;
+        float f;
+        split_fx(q, &p0, &f);
+        q += L.m_fx;
+        // chord_fraction's general branch, written out so both candidates of
+        // all steps are formed before any load is consumed
+        float g0 = fminf(fmaxf(__fmul_rn(hw - f, L.inv_r), 0.0f), 1.0f);
+        const float d1 = 1.0f - f;
+        float g1 = fminf(fmaxf(__fmul_rn(hw - d1, L.inv_r), 0.0f), 1.0f);
+        if (axis) {
+          g0 = wc0;
+          g1 = wc1;
         }
+        const bool live = kk <= kb;
+        w[2 * u] = (live && (unsigned)p0 < (unsigned)I) ? g0 : 0.0f;
+        w[2 * u + 1] = (live && (unsigned)(p0 + 1) < (unsigned)I) ? g1 : 0.0f;
+        const int kc = min(kk, kb);
+        const int pc0 = min(max(p0, 0), I - 1), pc1 = min(max(p0 + 1, 0), I - 1);
+        v[2 * u] = base[kc * sk + pc0 * sp];
+        v[2 * u + 1] = base[kc * sk + pc1 * sp];
       }
+#pragma unroll
+      for (int e = 0; e < 2 * kMarch; ++e) acc = __fmaf_rn(w[e], v[e], acc);
     }
   }
   part[seg][lane] = acc;
@@ -113,6 +144,14 @@ __device__ __forceinline__ float ray_weight(const RayLine& L, int i, int j) {
 }
 
 // bx, by: block coordinates of a (kBpBlockX x kBpBlockY) pixel block.
+// Views are taken kBpViews at a time: the footprint of the pixel in every
+// view of the group is found first and the ray records and sinogram values
+// of up to 3 bins per view are requested together (clamped in-bounds index,
+// weight 0 when the bin is outside the footprint), then accumulated in the
+// order view, bin; a footprint of more than 3 bins (possible only for very
+// short fan-beam source distances) finishes in a plain loop.
+static constexpr int kBpViews = 4, kBpBins = 3;
+
 __device__ void backproject_body(const BpArgs& A, int bx, int by) {
   const int I = A.I;
   const int j = bx * kBpBlockX + threadIdx.x;
@@ -121,28 +160,54 @@ __device__ void backproject_body(const BpArgs& A, int bx, int by) {
   const float x = (float)j - 0.5f * (float)(I - 1);
   const float y = 0.5f * (float)(I - 1) - (float)i;
   float acc = 0.0f;
-  for (int k = 0; k < A.nv; ++k) {
-    const ViewInfo v = A.views[k];
-    float u, hw;
-    if (!A.fan) {
-      u = __fmaf_rn(v.a, x, __fmaf_rn(v.b, y, v.c));
-      hw = v.hw;
-    } else {
-      const float dx = x - v.a, dy = y - v.b;
-      const float along = v.cx * dx + v.cy * dy;
-      const float cr = v.cx * dy - v.cy * dx;
-      const float dist = sqrtf(dx * dx + dy * dy);
-      const float gam = atan2f(cr, along);
-      u = __fmaf_rn(gam, v.inv_dg, v.c);
-      hw = asinf(fminf(A.half_diag / dist, 1.0f)) * v.inv_dg * 1.001f + 1e-3f;
+  for (int k0 = 0; k0 < A.nv; k0 += kBpViews) {
+    int bb[kBpViews], be[kBpViews];
+    RayLine L[kBpViews][kBpBins];
+    float sv[kBpViews][kBpBins];
+#pragma unroll
+    for (int g = 0; g < kBpViews; ++g) {
+      const int k = k0 + g;
+      bb[g] = 0;
+      be[g] = -1;
+      if (k < A.nv) {
+        const ViewInfo v = A.views[k];
+        float u, hw;
+        if (!A.fan) {
+          u = __fmaf_rn(v.a, x, __fmaf_rn(v.b, y, v.c));
+          hw = v.hw;
+        } else {
+          const float dx = x - v.a, dy = y - v.b;
+          const float along = v.cx * dx + v.cy * dy;
+          const float cr = v.cx * dy - v.cy * dx;
+          const float dist = sqrtf(dx * dx + dy * dy);
+          const float gam = atan2f(cr, along);
+          u = __fmaf_rn(gam, v.inv_dg, v.c);
+          hw = asinf(fminf(A.half_diag / dist, 1.0f)) * v.inv_dg * 1.001f + 1e-3f;
+        }
+        bb[g] = max((int)ceilf(u - hw), 0);
+        be[g] = min((int)floorf(u + hw), A.nb - 1);
+      }
+      const int kc = min(k, A.nv - 1);
+      const int64_t row = (int64_t)kc * A.nb;
+#pragma unroll
+      for (int c = 0; c < kBpBins; ++c) {
+        const int b = min(max(bb[g] + c, 0), A.nb - 1);
+        L[g][c] = A.rays[row + b];
+        sv[g][c] = A.sino[row + b];
+      }
     }
-    int b0 = (int)ceilf(u - hw), b1 = (int)floorf(u + hw);
-    b0 = max(b0, 0);
-    b1 = min(b1, A.nb - 1);
-    const int64_t row = (int64_t)k * A.nb;
-    for (int b = b0; b <= b1; ++b) {
-      const RayLine L = A.rays[row + b];
-      acc = __fmaf_rn(ray_weight(L, i, j), A.sino[row + b], acc);
+#pragma unroll
+    for (int g = 0; g < kBpViews; ++g) {
+#pragma unroll
+      for (int c = 0; c < kBpBins; ++c) {
+        const float wgt = (bb[g] + c <= be[g]) ? ray_weight(L[g][c], i, j) : 0.0f;
+        acc = __fmaf_rn(wgt, sv[g][c], acc);
+      }
+      if (be[g] - bb[g] + 1 > kBpBins) {
+        const int64_t row = (int64_t)(k0 + g) * A.nb;
+        for (int b = bb[g] + kBpBins; b <= be[g]; ++b)
+          acc = __fmaf_rn(ray_weight(A.rays[row + b], i, j), A.sino[row + b], acc);
+      }
     }
   }
   A.img[(int64_t)i * I + j] = acc;
