@@ -43,6 +43,8 @@ unsigned int backproject_blocks(int I);
 unsigned int channel_grid(int64_t M);
 unsigned int red_grid(int64_t N);
 unsigned int nlm_blocks(int I);
+int prec_row_blocks(int I);
+int prec_col_blocks(int I);
 dg_status launch_fill(float* p, int64_t n, float v, hipStream_t st);
 
 static size_t a256(size_t x) { return (x + 255) & ~(size_t)255; }
@@ -201,8 +203,8 @@ extern "C" dg_status dg_batch_create(const dg_geom* geoms, int32_t n, dg_batch**
     b->img_off[s + 1] = b->img_off[s] + p->N;
     b->sino_off[s + 1] = b->sino_off[s] + p->M;
     b->spec_off[s + 1] = b->spec_off[s] + (int64_t)(I / 2 + 1) * I;
-    b->pre_rows[s + 1] = b->pre_rows[s] + I / 2;
-    b->pre_cols[s + 1] = b->pre_cols[s] + I / 2 + 1;
+    b->pre_rows[s + 1] = b->pre_rows[s] + prec_row_blocks(I);
+    b->pre_cols[s + 1] = b->pre_cols[s] + prec_col_blocks(I);
     b->pre_proj[s + 1] = b->pre_proj[s] + (int)project_blocks(p->M);
     b->pre_chan[s + 1] = b->pre_chan[s] + (int)channel_grid(p->M);
     b->pre_bp[s + 1] = b->pre_bp[s] + (int)backproject_blocks(I);
@@ -301,7 +303,7 @@ extern "C" dg_status dg_batch_bind(dg_batch* b, const float* y, const double* i0
     ri_r[k] = RowsInvArgs{sp, p->twiddle, I, PREC_UPDATE_R, r + io, nullptr, x + io, sc, fp};
     ri_out[k] = RowsInvArgs{sp, p->twiddle, I, PREC_PLAIN, mu_out ? mu_out + io : mu + io, nullptr,
                             nullptr, nullptr, nullptr};
-    eps[k] = EpsArgs{fp, I / 2, eps_rel, sc + DG_S_EPS};
+    eps[k] = EpsArgs{fp, prec_row_blocks(I), eps_rel, sc + DG_S_EPS};
     proj[k] = ProjArgs{p->rays, mu + io, mu_t + io, z + so, I, p->M};
     chan[k] = ChanArgs{p->M, z + so, y + so, s + so, nullptr, nullptr, sc, nullptr, i0[k], fro2[k],
                        (double)p->N, dp, b->pre_chan[k + 1] - b->pre_chan[k]};

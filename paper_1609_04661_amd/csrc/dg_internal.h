@@ -191,6 +191,10 @@ __device__ __forceinline__ int slice_of(const int* __restrict__ prefix, int n, i
   return lo;
 }
 
+// Fourth word of a raw buffer resource on this architecture (no format
+// conversion; out-of-range offsets read 0 and drop writes).
+static constexpr int kBufferWord3 = 0x00020000;
+
 // Host-side helpers.
 inline unsigned int grid_for(int64_t n, int block, int64_t cap = 65535) {
   int64_t g = (n + block - 1) / block;

@@ -6,9 +6,10 @@
 //   rows' : complex-to-real inverse row transforms, two rows per FFT, with
 //           an optional fused epilogue r = x + tau_r * (filtered image) and
 //           the max |r| reduction that sets the Monte-Carlo step.
-// Each FFT runs inside one workgroup in LDS as a Stockham autosort
-// transform with radix-4, radix-2 and (for I = 3 * 2^k) one radix-3 stage;
-// twiddles come from a table computed in FP64 at plan time.
+// Each FFT runs inside one wavefront in LDS (four per workgroup, no
+// workgroup barrier inside a transform) as a Stockham autosort transform
+// with radix-4, radix-2 and (for I = 3 * 2^k) one radix-3 stage; twiddles
+// come from a table computed in FP64 at plan time, staged in LDS.
 // The symbol is c(k)^(-1/2) = (|k| / I)^(1/2) for V^-1 and its inverse for
 // V, with |k| the integer frequency radius and c(0) = 4 ln(1 + sqrt 2) I.
 #include <cmath>
@@ -17,8 +18,10 @@
 
 namespace dg {
 
-static constexpr int kFftThreads = 256;
+static constexpr int kFftWaves = 4;                 // one FFT per wavefront
+static constexpr int kFftThreads = 64 * kFftWaves;
 static constexpr int kMaxFft = 1024;
+static constexpr int kRowsPerBlock = 2 * kFftWaves;  // real rows per row-pass workgroup
 
 __device__ __forceinline__ float2 cmul(float2 a, float2 b) {
   return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
@@ -30,153 +33,241 @@ __device__ __forceinline__ float2 rot(float2 a, bool inv) {
   return inv ? make_float2(-a.y, a.x) : make_float2(a.y, -a.x);
 }
 
-// In-LDS complex FFT of length L on buf0 (result in buf0), scratch buf1.
-// Unnormalised; inverse uses conjugate twiddles.  All threads of the block
-// must call it.
-__device__ void lds_fft(float2* buf0, float2* buf1, int L, const float2* __restrict__ tw,
-                        bool inv) {
+// Order this wavefront's LDS accesses: writes before the barrier are seen
+// by reads after it in every lane of the wavefront.
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// One Stockham stage of radix R (compile-time, so the butterfly lives in
+// registers): reads src, writes dst.
+template <int R>
+__device__ __forceinline__ void fft_stage(const float2* src, float2* dst, int L, int Ns, int lgNs,
+                                          const float2* tw, bool inv) {
+  const int lane = threadIdx.x & 63;
+  const int LR = L / R;
+  const int step = L / (Ns * R);  // twiddle-table stride; r k step < L
+  for (int j = lane; j < LR; j += 64) {
+    const int k = j & (Ns - 1);
+    float2 v[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) v[r] = src[j + r * LR];
+#pragma unroll
+    for (int r = 1; r < R; ++r) {
+      float2 w = tw[r * k * step];
+      if (inv) w.y = -w.y;
+      v[r] = cmul(v[r], w);
+    }
+    if constexpr (R == 2) {
+      float2 a = v[0], b = v[1];
+      v[0] = cadd(a, b);
+      v[1] = csub(a, b);
+    } else if constexpr (R == 4) {
+      float2 a0 = cadd(v[0], v[2]), a1 = csub(v[0], v[2]);
+      float2 b0 = cadd(v[1], v[3]), b1 = rot(csub(v[1], v[3]), inv);
+      v[0] = cadd(a0, b0);
+      v[2] = csub(a0, b0);
+      v[1] = cadd(a1, b1);
+      v[3] = csub(a1, b1);
+    } else {  // R == 3
+      const float s3 = 0.86602540378443864676f;
+      float2 t1 = cadd(v[1], v[2]);
+      float2 t2 = make_float2(v[0].x - 0.5f * t1.x, v[0].y - 0.5f * t1.y);
+      float2 d = csub(v[1], v[2]);
+      float2 t3 = rot(make_float2(s3 * d.x, s3 * d.y), inv);
+      v[0] = cadd(v[0], t1);
+      v[1] = cadd(t2, t3);
+      v[2] = csub(t2, t3);
+    }
+    const int idxD = ((j >> lgNs) << lgNs) * R + k;  // (j / Ns) Ns R + k
+#pragma unroll
+    for (int r = 0; r < R; ++r) dst[idxD + r * Ns] = v[r];
+  }
+}
+
+// In-LDS complex FFT of length L by one wavefront on buf0 (result in buf0),
+// scratch buf1, twiddles tw[j] = exp(-2 pi i j / L) in LDS.  Unnormalised;
+// the inverse uses conjugate twiddles.  Stockham autosort stages of radix 4
+// while possible, then 2, and the radix-3 stage (L = 3 * 2^a) last, so the
+// stride Ns is a power of two wherever it divides.
+__device__ void wave_fft(float2* buf0, float2* buf1, int L, const float2* tw, bool inv) {
+  const int lane = threadIdx.x & 63;
   float2* src = buf0;
   float2* dst = buf1;
-  int Ns = 1;
-  int rem = L;
+  int Ns = 1, lgNs = 0, rem = L;
   while (rem > 1) {
     int R;
-    if (rem % 3 == 0)
-      R = 3;
-    else if (rem % 4 == 0)
+    if (rem % 4 == 0) {
       R = 4;
-    else
+      fft_stage<4>(src, dst, L, Ns, lgNs, tw, inv);
+    } else if (rem % 2 == 0) {
       R = 2;
-    const int LR = L / R;
-    const int step = L / (Ns * R);  // twiddle-table stride
-    for (int j = threadIdx.x; j < LR; j += blockDim.x) {
-      const int k = j % Ns;
-      float2 v[4];
-      for (int r = 0; r < R; ++r) v[r] = src[j + r * LR];
-      for (int r = 1; r < R; ++r) {
-        float2 w = tw[(r * k * step) % L];
-        if (inv) w.y = -w.y;
-        v[r] = cmul(v[r], w);
-      }
-      if (R == 2) {
-        float2 a = v[0], b = v[1];
-        v[0] = cadd(a, b);
-        v[1] = csub(a, b);
-      } else if (R == 4) {
-        float2 a0 = cadd(v[0], v[2]), a1 = csub(v[0], v[2]);
-        float2 b0 = cadd(v[1], v[3]), b1 = rot(csub(v[1], v[3]), inv);
-        v[0] = cadd(a0, b0);
-        v[2] = csub(a0, b0);
-        v[1] = cadd(a1, b1);
-        v[3] = csub(a1, b1);
-      } else {  // R == 3
-        const float s3 = 0.86602540378443864676f;
-        float2 t1 = cadd(v[1], v[2]);
-        float2 t2 = make_float2(v[0].x - 0.5f * t1.x, v[0].y - 0.5f * t1.y);
-        float2 d = csub(v[1], v[2]);
-        float2 t3 = rot(make_float2(s3 * d.x, s3 * d.y), inv);
-        v[0] = cadd(v[0], t1);
-        v[1] = cadd(t2, t3);
-        v[2] = csub(t2, t3);
-      }
-      const int idxD = (j / Ns) * Ns * R + k;
-      for (int r = 0; r < R; ++r) dst[idxD + r * Ns] = v[r];
+      fft_stage<2>(src, dst, L, Ns, lgNs, tw, inv);
+    } else {
+      R = 3;
+      fft_stage<3>(src, dst, L, Ns, lgNs, tw, inv);
     }
-    __syncthreads();
+    wave_sync();
     float2* t = src;
     src = dst;
     dst = t;
     Ns *= R;
+    lgNs += (R == 4) ? 2 : 1;  // unused after the radix-3 stage
     rem /= R;
   }
   if (src != buf0) {
-    for (int j = threadIdx.x; j < L; j += blockDim.x) buf0[j] = src[j];
-    __syncthreads();
+    for (int j = lane; j < L; j += 64) buf0[j] = src[j];
+    wave_sync();
   }
 }
 
-// Forward row pass: rows 2m, 2m+1 packed as one complex row; the two real
+// buf[w][1] also holds two half spectra of I/2 + 1 entries each, hence the
+// padding beyond kMaxFft.
+struct FftShared {
+  float2 tw[kMaxFft];
+  float2 buf[kFftWaves][2][kMaxFft + 8];
+  float red[kFftWaves];
+};
+
+__device__ __forceinline__ void load_twiddles(FftShared& S, const float2* __restrict__ tw, int I) {
+  for (int t = threadIdx.x; t < I; t += blockDim.x) S.tw[t] = tw[t];
+  __syncthreads();
+}
+
+// Forward row pass, workgroup blk: real rows 8 blk .. 8 blk + 7, wavefront w
+// packs rows 2m, 2m+1 (m = 4 blk + w) as one complex row.  The two real
 // spectra are separated by conjugate symmetry and stored column-major as
-// spec[k][row], k = 0..I/2.
-__device__ void rows_fwd_body(const RowsFwdArgs& A, int m, float2* a, float2* b) {
-  const int I = A.I;
-  const float* r0 = A.in + (int64_t)(2 * m) * I;
-  const float* r1 = r0 + I;
-  for (int t = threadIdx.x; t < I; t += blockDim.x) a[t] = make_float2(r0[t], r1[t]);
+// spec[k][row], k = 0..I/2; the workgroup writes its 8 rows of every k as
+// one contiguous 64-byte run.
+__device__ void rows_fwd_body(const RowsFwdArgs& A, int blk, FftShared& S) {
+  const int I = A.I, lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int half = I / 2 + 1;
+  load_twiddles(S, A.tw, I);
+  const int m = blk * kFftWaves + w;
+  float2* a = S.buf[w][0];
+  float2* b = S.buf[w][1];
+  if (2 * m < I) {
+    const float* r0 = A.in + (int64_t)(2 * m) * I;
+    const float* r1 = r0 + I;
+    for (int t = lane; t < I; t += 64) a[t] = make_float2(r0[t], r1[t]);
+    wave_sync();
+    wave_fft(a, b, I, S.tw, false);
+    for (int k = lane; k < half; k += 64) {
+      float2 Z = a[k], Zc = a[(I - k) % I];
+      Zc.y = -Zc.y;
+      float2 Xa = make_float2(0.5f * (Z.x + Zc.x), 0.5f * (Z.y + Zc.y));
+      float2 d = make_float2(0.5f * (Z.x - Zc.x), 0.5f * (Z.y - Zc.y));
+      b[k] = Xa;
+      b[half + k] = make_float2(d.y, -d.x);  // d / i
+    }
+  }
   __syncthreads();
-  lds_fft(a, b, I, A.tw, false);
-  for (int k = threadIdx.x; k <= I / 2; k += blockDim.x) {
-    float2 Z = a[k], Zc = a[(I - k) % I];
-    Zc.y = -Zc.y;
-    float2 Xa = make_float2(0.5f * (Z.x + Zc.x), 0.5f * (Z.y + Zc.y));
-    float2 d = make_float2(0.5f * (Z.x - Zc.x), 0.5f * (Z.y - Zc.y));
-    float2 Xb = make_float2(d.y, -d.x);  // d / i
-    float2* col = A.spec + (int64_t)k * I;
-    col[2 * m] = Xa;
-    col[2 * m + 1] = Xb;
+  for (int idx = threadIdx.x; idx < half * kRowsPerBlock; idx += blockDim.x) {
+    const int k = idx >> 3, c = idx & 7;
+    const int row = blk * kRowsPerBlock + c;
+    if (row < I) A.spec[(int64_t)k * I + row] = S.buf[c >> 1][1][(c & 1) * half + k];
   }
 }
 
-// Column pass with the symbol multiply.
-__device__ void cols_body(const ColsArgs& A, int kx, float2* a, float2* b) {
-  const int I = A.I;
+// Column pass with the symbol multiply: wavefront w of workgroup blk takes
+// column frequency kx = 4 blk + w.
+__device__ void cols_body(const ColsArgs& A, int blk, FftShared& S) {
+  const int I = A.I, lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  load_twiddles(S, A.tw, I);
+  const int kx = blk * kFftWaves + w;
+  if (kx > I / 2) return;
+  float2* a = S.buf[w][0];
+  float2* b = S.buf[w][1];
   float2* col = A.spec + (int64_t)kx * I;
-  for (int t = threadIdx.x; t < I; t += blockDim.x) a[t] = col[t];
-  __syncthreads();
-  lds_fft(a, b, I, A.tw, false);
+  for (int t = lane; t < I; t += 64) a[t] = col[t];
+  wave_sync();
+  wave_fft(a, b, I, S.tw, false);
   const float dc = 3.52549435174692f * (float)I;  // 4 ln(1 + sqrt 2) I
-  for (int t = threadIdx.x; t < I; t += blockDim.x) {
+  for (int t = lane; t < I; t += 64) {
     const int ky = (t <= I / 2) ? t : t - I;
     const float k2 = (float)(kx * kx + ky * ky);
     float c = (k2 > 0.0f) ? (float)I / sqrtf(k2) : dc;  // 1/|rho|
     float h = (A.dir > 0) ? rsqrtf(c) : sqrtf(c);
     a[t] = make_float2(a[t].x * h, a[t].y * h);
   }
-  __syncthreads();
-  lds_fft(a, b, I, A.tw, true);
-  for (int t = threadIdx.x; t < I; t += blockDim.x) col[t] = a[t];
+  wave_sync();
+  wave_fft(a, b, I, S.tw, true);
+  for (int t = lane; t < I; t += 64) col[t] = a[t];
 }
 
-// Inverse row pass (two real rows per complex FFT) with epilogue.
-__device__ void rows_inv_body(const RowsInvArgs& A, int m, float2* a, float2* b, float* red) {
-  const int I = A.I;
-  for (int t = threadIdx.x; t < I; t += blockDim.x) {
-    float2 ya, yb;
-    if (t <= I / 2) {
-      ya = A.spec[(int64_t)t * I + 2 * m];
-      yb = A.spec[(int64_t)t * I + 2 * m + 1];
-    } else {
-      ya = A.spec[(int64_t)(I - t) * I + 2 * m];
-      yb = A.spec[(int64_t)(I - t) * I + 2 * m + 1];
-      ya.y = -ya.y;
-      yb.y = -yb.y;
-    }
-    a[t] = make_float2(ya.x - yb.y, ya.y + yb.x);  // ya + i yb
+// Inverse row pass (two real rows per complex FFT) with epilogue; workgroup
+// blk owns real rows 8 blk .. 8 blk + 7 and reads / writes them (including
+// the transposed copy) in contiguous runs.
+__device__ void rows_inv_body(const RowsInvArgs& A, int blk, FftShared& S) {
+  const int I = A.I, lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int half = I / 2 + 1;
+  load_twiddles(S, A.tw, I);
+  for (int idx = threadIdx.x; idx < half * kRowsPerBlock; idx += blockDim.x) {
+    const int k = idx >> 3, c = idx & 7;
+    const int row = blk * kRowsPerBlock + c;
+    S.buf[c >> 1][1][(c & 1) * half + k] =
+        row < I ? A.spec[(int64_t)k * I + row] : make_float2(0.0f, 0.0f);
   }
   __syncthreads();
-  lds_fft(a, b, I, A.tw, true);
+  const int m = blk * kFftWaves + w;
+  float2* a = S.buf[w][0];
+  float2* b = S.buf[w][1];
+  const bool live = 2 * m < I;
   const float scale = 1.0f / ((float)I * (float)I);
   const bool upd = A.epilogue == PREC_UPDATE_R;
   const float tau_r = upd ? (float)A.scal[DG_S_TAU_R] : 0.0f;
   float amax = 0.0f;
-  for (int t = threadIdx.x; t < I; t += blockDim.x) {
-    float v0 = a[t].x * scale, v1 = a[t].y * scale;
-    const int64_t i0 = (int64_t)(2 * m) * I + t, i1 = i0 + I;
-    if (upd) {
-      v0 = __fmaf_rn(tau_r, v0, A.x[i0]);
-      v1 = __fmaf_rn(tau_r, v1, A.x[i1]);
-      amax = fmaxf(amax, fmaxf(fabsf(v0), fabsf(v1)));
+  if (live) {
+    for (int t = lane; t < I; t += 64) {
+      float2 ya, yb;
+      if (t < half) {
+        ya = b[t];
+        yb = b[half + t];
+      } else {
+        ya = b[I - t];
+        yb = b[half + I - t];
+        ya.y = -ya.y;
+        yb.y = -yb.y;
+      }
+      a[t] = make_float2(ya.x - yb.y, ya.y + yb.x);  // ya + i yb
     }
-    A.out[i0] = v0;
-    A.out[i1] = v1;
-    if (A.out_t) {
-      A.out_t[(int64_t)t * I + 2 * m] = v0;
-      A.out_t[(int64_t)t * I + 2 * m + 1] = v1;
+    wave_sync();
+    wave_fft(a, b, I, S.tw, true);
+    for (int t = lane; t < I; t += 64) {
+      float v0 = a[t].x * scale, v1 = a[t].y * scale;
+      const int64_t i0 = (int64_t)(2 * m) * I + t, i1 = i0 + I;
+      if (upd) {
+        v0 = __fmaf_rn(tau_r, v0, A.x[i0]);
+        v1 = __fmaf_rn(tau_r, v1, A.x[i1]);
+        amax = fmaxf(amax, fmaxf(fabsf(v0), fabsf(v1)));
+      }
+      A.out[i0] = v0;
+      A.out[i1] = v1;
+      b[t] = make_float2(v0, v1);  // staged for the transposed copy
+    }
+  }
+  if (A.out_t) {
+    __syncthreads();
+    for (int idx = threadIdx.x; idx < I * kRowsPerBlock; idx += blockDim.x) {
+      const int t = idx >> 3, c = idx & 7;
+      const int row = blk * kRowsPerBlock + c;
+      if (row < I) {
+        const float2 v = S.buf[c >> 1][1][t];
+        A.out_t[(int64_t)t * I + row] = (c & 1) ? v.y : v.x;
+      }
     }
   }
   if (upd) {
-    float bm = block_max(amax, red);
-    if (threadIdx.x == 0) A.partials[m] = bm;
+    const float wm = wave_max(amax);
+    if (lane == 0) S.red[w] = wm;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      float bm = 0.0f;
+      for (int q = 0; q < kFftWaves; ++q) bm = fmaxf(bm, S.red[q]);
+      A.partials[blk] = bm;
+    }
   }
 }
 
@@ -189,36 +280,34 @@ __device__ void eps_body(const EpsArgs& A, float* red) {
 }
 
 __global__ void __launch_bounds__(kFftThreads) prec_rows_fwd(RowsFwdArgs A) {
-  __shared__ float2 a[kMaxFft], b[kMaxFft];
-  rows_fwd_body(A, blockIdx.x, a, b);
+  __shared__ FftShared S;
+  rows_fwd_body(A, blockIdx.x, S);
 }
 __global__ void __launch_bounds__(kFftThreads)
 prec_rows_fwd_batch(const RowsFwdArgs* __restrict__ T, const int* __restrict__ prefix, int n) {
-  __shared__ float2 a[kMaxFft], b[kMaxFft];
+  __shared__ FftShared S;
   const int s = slice_of(prefix, n, blockIdx.x);
-  rows_fwd_body(T[s], blockIdx.x - prefix[s], a, b);
+  rows_fwd_body(T[s], blockIdx.x - prefix[s], S);
 }
 __global__ void __launch_bounds__(kFftThreads) prec_cols(ColsArgs A) {
-  __shared__ float2 a[kMaxFft], b[kMaxFft];
-  cols_body(A, blockIdx.x, a, b);
+  __shared__ FftShared S;
+  cols_body(A, blockIdx.x, S);
 }
 __global__ void __launch_bounds__(kFftThreads)
 prec_cols_batch(const ColsArgs* __restrict__ T, const int* __restrict__ prefix, int n) {
-  __shared__ float2 a[kMaxFft], b[kMaxFft];
+  __shared__ FftShared S;
   const int s = slice_of(prefix, n, blockIdx.x);
-  cols_body(T[s], blockIdx.x - prefix[s], a, b);
+  cols_body(T[s], blockIdx.x - prefix[s], S);
 }
 __global__ void __launch_bounds__(kFftThreads) prec_rows_inv(RowsInvArgs A) {
-  __shared__ float2 a[kMaxFft], b[kMaxFft];
-  __shared__ float red[kFftThreads / 64];
-  rows_inv_body(A, blockIdx.x, a, b, red);
+  __shared__ FftShared S;
+  rows_inv_body(A, blockIdx.x, S);
 }
 __global__ void __launch_bounds__(kFftThreads)
 prec_rows_inv_batch(const RowsInvArgs* __restrict__ T, const int* __restrict__ prefix, int n) {
-  __shared__ float2 a[kMaxFft], b[kMaxFft];
-  __shared__ float red[kFftThreads / 64];
+  __shared__ FftShared S;
   const int s = slice_of(prefix, n, blockIdx.x);
-  rows_inv_body(T[s], blockIdx.x - prefix[s], a, b, red);
+  rows_inv_body(T[s], blockIdx.x - prefix[s], S);
 }
 __global__ void __launch_bounds__(256) eps_finish_kernel(EpsArgs A) {
   __shared__ float red[4];
@@ -228,6 +317,10 @@ __global__ void __launch_bounds__(256) eps_finish_batch(const EpsArgs* __restric
   __shared__ float red[4];
   eps_body(T[blockIdx.x], red);
 }
+
+// Workgroups of the row passes and of the column pass for side I.
+int prec_row_blocks(int I) { return (I + kRowsPerBlock - 1) / kRowsPerBlock; }
+int prec_col_blocks(int I) { return (I / 2 + 1 + kFftWaves - 1) / kFftWaves; }
 
 dg_status launch_eps_finish(const float* partials, int n, double eps_rel, double* eps_out,
                             hipStream_t s) {
@@ -267,16 +360,16 @@ dg_status launch_precondition(const dg_plan* p, const PrecArgs& a, hipStream_t s
   }
   const int I = p->I;
   RowsFwdArgs f{a.in, a.spec, p->twiddle, I};
-  hipLaunchKernelGGL(prec_rows_fwd, dim3(I / 2), dim3(kFftThreads), 0, s, f);
+  hipLaunchKernelGGL(prec_rows_fwd, dim3(prec_row_blocks(I)), dim3(kFftThreads), 0, s, f);
   DG_LAUNCH_CHECK("prec_rows_fwd");
   ColsArgs c{a.spec, p->twiddle, I, a.dir};
-  hipLaunchKernelGGL(prec_cols, dim3(I / 2 + 1), dim3(kFftThreads), 0, s, c);
+  hipLaunchKernelGGL(prec_cols, dim3(prec_col_blocks(I)), dim3(kFftThreads), 0, s, c);
   DG_LAUNCH_CHECK("prec_cols");
   RowsInvArgs r{a.spec, p->twiddle, I, a.epilogue, a.out, a.out_t, a.x, a.scal, a.partials};
-  hipLaunchKernelGGL(prec_rows_inv, dim3(I / 2), dim3(kFftThreads), 0, s, r);
+  hipLaunchKernelGGL(prec_rows_inv, dim3(prec_row_blocks(I)), dim3(kFftThreads), 0, s, r);
   DG_LAUNCH_CHECK("prec_rows_inv");
   if (a.epilogue == PREC_UPDATE_R)
-    return launch_eps_finish(a.partials, I / 2, a.eps_rel, a.scal_out + DG_S_EPS, s);
+    return launch_eps_finish(a.partials, prec_row_blocks(I), a.eps_rel, a.scal_out + DG_S_EPS, s);
   return DG_OK;
 }
 

@@ -24,10 +24,10 @@ static constexpr int kBpBlockX = 64, kBpBlockY = 4;
 // added in a fixed order.  Splitting the march gives SEGS times more
 // wavefronts to hide memory latency than one thread per ray.
 //
-// The march is unrolled by kMarch steps: the addresses and weights of both
-// candidates of every step are formed first (out-of-range candidates read a
-// clamped in-bounds pixel with weight 0), so 2 kMarch loads are in flight
-// before the first multiply-add.  The accumulation order (k ascending,
+// The march is unrolled by kMarch steps: the offsets and weights of both
+// candidates of every step are formed first, so 2 kMarch loads are in flight
+// before the first multiply-add.  Out-of-range candidates get an offset past
+// the end of the buffer, which a raw buffer load returns as 0.  The accumulation order (k ascending,
 // candidate p0 before p0 + 1) and every weight are those of ray_weight, so
 // A and A^T stay exact transposes of one another.
 static constexpr int kMarch = 8;
@@ -42,11 +42,32 @@ __device__ void project_body(const ProjArgs& A, int blk, float (*part)[kRaysPerB
   if (r < A.M) {
     L = A.rays[r];
     const bool steep = L.pl < 0.0f;
+    // One raw buffer resource (wavefront-uniform) spans the image and, when
+    // it lies within 4 GiB of it, the transposed copy.
+    const char* pi = (const char*)A.img;
+    const char* pt = (const char*)A.img_t;
+    const uint64_t nbytes = (uint64_t)I * (uint64_t)I * 4u;
+    const char* lo = pi;
+    uint64_t span = nbytes;
+    unsigned di = 0, dt = 0;
+    bool use_t = pt != nullptr;
+    if (use_t) {
+      const char* lo2 = pi < pt ? pi : pt;
+      const uint64_t dist = (uint64_t)((pi < pt ? pt : pi) - lo2);
+      if (dist + nbytes <= 0xfffffff0ull) {
+        lo = lo2;
+        di = (unsigned)(pi - lo2);
+        dt = (unsigned)(pt - lo2);
+        span = dist + nbytes;
+      } else {
+        use_t = false;
+      }
+    }
     // Pixel (row i, col j).  Steep: major = row, cross = col -> img[k*I + p].
     // Flat: major = col, cross = row -> img[p*I + k] = img_t[k*I + p].
     // major_rows: the buffer read is laid out with the major index as its row.
-    const bool major_rows = steep || (A.img_t != nullptr);
-    const float* base = (steep || A.img_t == nullptr) ? A.img : A.img_t;
+    const bool major_rows = steep || use_t;
+    const unsigned boff = (steep || !use_t) ? di : dt;
     const int sk = major_rows ? I : 1, sp = major_rows ? 1 : I;
 
     // Major-index range where q(k) lies in (-1, I): candidates exist only there.
@@ -76,6 +97,11 @@ __device__ void project_body(const ProjArgs& A, int blk, float (*part)[kRaysPerB
       wc1 = chord_fraction(1.0f - f, L.m, L.inv_r);
     }
     const float hw = __fmaf_rn(0.5f, fabsf(L.m), 0.5f);
+    // raw buffer loads: 32-bit byte offsets, and an offset past the image
+    // (used for candidates outside it) reads 0
+    const __amdgpu_buffer_rsrc_t img =
+        __builtin_amdgcn_make_buffer_rsrc((void*)lo, (short)0, (int)(unsigned)span, kBufferWord3);
+    const unsigned skb = (unsigned)sk * 4u, spb = (unsigned)sp * 4u;
     for (int k = ka; k <= kb; k += kMarch) {
       float v[2 * kMarch], w[2 * kMarch];
 #pragma unroll
@@ -94,13 +120,14 @@ __device__ void project_body(const ProjArgs& A, int blk, float (*part)[kRaysPerB
           g0 = wc0;
           g1 = wc1;
         }
+        w[2 * u] = g0;
+        w[2 * u + 1] = g1;
         const bool live = kk <= kb;
-        w[2 * u] = (live && (unsigned)p0 < (unsigned)I) ? g0 : 0.0f;
-        w[2 * u + 1] = (live && (unsigned)(p0 + 1) < (unsigned)I) ? g1 : 0.0f;
-        const int kc = min(kk, kb);
-        const int pc0 = min(max(p0, 0), I - 1), pc1 = min(max(p0 + 1, 0), I - 1);
-        v[2 * u] = base[kc * sk + pc0 * sp];
-        v[2 * u + 1] = base[kc * sk + pc1 * sp];
+        const unsigned o0 = boff + (unsigned)kk * skb + (unsigned)p0 * spb;
+        const unsigned off0 = (live && (unsigned)p0 < (unsigned)I) ? o0 : 0xffffffffu;
+        const unsigned off1 = (live && (unsigned)(p0 + 1) < (unsigned)I) ? o0 + spb : 0xffffffffu;
+        v[2 * u] = __int_as_float(__builtin_amdgcn_raw_buffer_load_b32(img, off0, 0, 0));
+        v[2 * u + 1] = __int_as_float(__builtin_amdgcn_raw_buffer_load_b32(img, off1, 0, 0));
       }
 #pragma unroll
       for (int e = 0; e < 2 * kMarch; ++e) acc = __fmaf_rn(w[e], v[e], acc);
