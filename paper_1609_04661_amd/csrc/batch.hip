@@ -308,7 +308,7 @@ extern "C" dg_status dg_batch_bind(dg_batch* b, const float* y, const double* i0
     chan[k] = ChanArgs{p->M, z + so, y + so, s + so, nullptr, nullptr, sc, nullptr, i0[k], fro2[k],
                        (double)p->N, dp, b->pre_chan[k + 1] - b->pre_chan[k]};
     bp[k] = BpArgs{p->rays, p->views, s + so, g + io, I, p->nv, p->nb,
-                   p->g.kind == DG_GEOM_FAN ? 1 : 0, (float)p->half_diag_px};
+                   p->g.kind == DG_GEOM_FAN ? 1 : 0, (float)p->half_diag_px, p->vrays, p->q0fx};
     if (den_kind == DG_DEN_NLM)
       nlm[k] = NlmArgs{r + io, xden + io, xpert + io, I, np->search_radius,
                        sc + DG_S_TAU_R, sc + DG_S_EPS, (float)np->hfac};

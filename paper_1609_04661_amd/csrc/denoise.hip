@@ -85,9 +85,12 @@ __device__ void nlm_body(const NlmArgs& Ar, int bx, int by, int img, uint64_t se
     return;
   }
   const float sig2 = (float)tau_r;
-  const float inv_h2 = 1.0f / (hfac * hfac * sig2);
-  const float inv_np = 1.0f / (float)((2 * P + 1) * (2 * P + 1));
-  const float two_s2 = 2.0f * sig2;
+  // w = exp(-max(S / n_p - 2 sigma^2, 0) / h^2) = 2^-max(c1 S - c2, 0) with
+  // c1 = log2(e) / (n_p h^2) and c2 = log2(e) 2 sigma^2 / h^2 (S the patch
+  // sum of squared differences over n_p pixels, h = hfac sigma)
+  const float l2e_h2 = 1.4426950408889634f / (hfac * hfac * sig2);
+  const float c1 = l2e_h2 / (float)((2 * P + 1) * (2 * P + 1));
+  const float c2 = l2e_h2 * 2.0f * sig2;
   float own[WY][WX];
 #pragma unroll
   for (int a = 0; a < WY; ++a)
@@ -132,8 +135,7 @@ __device__ void nlm_body(const NlmArgs& Ar, int bx, int by, int img, uint64_t se
 #pragma unroll
       for (int a = 0; a < BY; ++a) {
         if (a > 0) v += h[a + 2 * P][c] - h[a - 1][c];
-        const float arg = fmaxf(__fmaf_rn(v, inv_np, -two_s2), 0.0f) * inv_h2;
-        const float w = __expf(-arg);
+        const float w = __builtin_amdgcn_exp2f(-fmaxf(__fmaf_rn(v, c1, -c2), 0.0f));
         wsum[a][c] += w;
         acc[a][c] = __fmaf_rn(w, cen[a][c], acc[a][c]);
       }

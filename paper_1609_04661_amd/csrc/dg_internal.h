@@ -64,6 +64,12 @@ struct ViewInfo {
   float a, b, c, hw;
   float cx, cy, inv_dg, pad;  // fan: unit vector towards iso, 1/dgamma [1/rad]
 };
+// Parallel beam: the slope terms every ray of a view shares (copies of the
+// view's RayLine fields), so the back-projector reads only q0_fx per ray.
+struct ViewRay {
+  int64_t m_fx;
+  float m, inv_r, pl, pad;
+};
 
 }  // namespace dg
 
@@ -79,6 +85,8 @@ struct dg_plan {
   int64_t N, M;
   dg::RayLine* rays;     // device, M
   dg::ViewInfo* views;   // device, nv
+  dg::ViewRay* vrays;    // device, nv (parallel beam only, else null)
+  int64_t* q0fx;         // device, M: rays[i].q0_fx (parallel beam only, else null)
   float2* twiddle;       // device, I: exp(-2 pi i t / I)
   int fft_ok;            // I supported by the FFT kernels
   double half_diag_px;   // sqrt(2)/2 (fan candidate search)
@@ -219,6 +227,8 @@ struct BpArgs {
   float* img;
   int I, nv, nb, fan;
   float half_diag;
+  const ViewRay* vrays;  // parallel beam: per-view slope terms
+  const int64_t* q0fx;   // parallel beam: per-ray q0_fx
 };
 // Output channel argument block (per slice).  Standalone: zp = p, s_out,
 // tau_p_ptr, tau_s_out.  Fused: zp = z, s_io = s (in: s_prev, out: s), scal.

@@ -168,9 +168,25 @@ extern "C" dg_status dg_plan_create(const dg_geom* g, dg_plan** out) {
   p->rays = nullptr;
   p->views = nullptr;
   p->twiddle = nullptr;
+  p->vrays = nullptr;
+  p->q0fx = nullptr;
+  // parallel beam: compact copies for the back-projector
+  std::vector<ViewRay> vr;
+  std::vector<int64_t> q0;
+  if (g->kind == DG_GEOM_PARALLEL) {
+    vr.resize((size_t)p->nv);
+    q0.resize((size_t)p->M);
+    for (int k = 0; k < p->nv; ++k) {
+      const RayLine& L = rays[(size_t)k * p->nb];
+      vr[k] = ViewRay{L.m_fx, L.m, L.inv_r, L.pl, 0.0f};
+    }
+    for (size_t i = 0; i < q0.size(); ++i) q0[i] = rays[i].q0_fx;
+  }
   if ((e = hipMalloc(&p->rays, sizeof(RayLine) * rays.size())) != hipSuccess ||
       (e = hipMalloc(&p->views, sizeof(ViewInfo) * views.size())) != hipSuccess ||
-      (e = hipMalloc(&p->twiddle, sizeof(float2) * tw.size())) != hipSuccess) {
+      (e = hipMalloc(&p->twiddle, sizeof(float2) * tw.size())) != hipSuccess ||
+      (!vr.empty() && (e = hipMalloc(&p->vrays, sizeof(ViewRay) * vr.size())) != hipSuccess) ||
+      (!q0.empty() && (e = hipMalloc(&p->q0fx, sizeof(int64_t) * q0.size())) != hipSuccess)) {
     dg_plan_destroy(p);
     hip_fail(e, "dg_plan_create: hipMalloc");
     return DG_ERR_NOMEM;
@@ -180,7 +196,11 @@ extern "C" dg_status dg_plan_create(const dg_geom* g, dg_plan** out) {
       (e = hipMemcpy(p->views, views.data(), sizeof(ViewInfo) * views.size(),
                      hipMemcpyHostToDevice)) != hipSuccess ||
       (e = hipMemcpy(p->twiddle, tw.data(), sizeof(float2) * tw.size(), hipMemcpyHostToDevice)) !=
-          hipSuccess) {
+          hipSuccess ||
+      (!vr.empty() && (e = hipMemcpy(p->vrays, vr.data(), sizeof(ViewRay) * vr.size(),
+                                     hipMemcpyHostToDevice)) != hipSuccess) ||
+      (!q0.empty() && (e = hipMemcpy(p->q0fx, q0.data(), sizeof(int64_t) * q0.size(),
+                                     hipMemcpyHostToDevice)) != hipSuccess)) {
     dg_plan_destroy(p);
     return hip_fail(e, "dg_plan_create: hipMemcpy");
   }
@@ -193,6 +213,8 @@ extern "C" dg_status dg_plan_destroy(dg_plan* p) {
   if (p->rays) (void)hipFree(p->rays);
   if (p->views) (void)hipFree(p->views);
   if (p->twiddle) (void)hipFree(p->twiddle);
+  if (p->vrays) (void)hipFree(p->vrays);
+  if (p->q0fx) (void)hipFree(p->q0fx);
   delete p;
   return DG_OK;
 }

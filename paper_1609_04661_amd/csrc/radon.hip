@@ -156,18 +156,22 @@ project_batch(const ProjArgs* __restrict__ T, const int* __restrict__ prefix, in
   project_body<SEGS>(T[s], blockIdx.x - prefix[s], part);
 }
 
-// Weight of pixel (i, j) on ray L: the same fixed-point cross coordinate and
+// Weight of pixel (i, j) on a ray: the same fixed-point cross coordinate and
 // the same fraction formula as the projector, hence the same value.
-__device__ __forceinline__ float ray_weight(const RayLine& L, int i, int j) {
-  const bool steep = L.pl < 0.0f;
+__device__ __forceinline__ float ray_weight_parts(int64_t q0_fx, int64_t m_fx, float m, float inv_r,
+                                                  float pl, int i, int j) {
+  const bool steep = pl < 0.0f;
   const int k = steep ? i : j;
   const int p = steep ? j : i;
   int p0;
   float f;
-  split_fx(L.q0_fx + L.m_fx * (int64_t)k, &p0, &f);
-  if (p == p0) return fabsf(L.pl) * chord_fraction(f, L.m, L.inv_r);
-  if (p == p0 + 1) return fabsf(L.pl) * chord_fraction(1.0f - f, L.m, L.inv_r);
+  split_fx(q0_fx + m_fx * (int64_t)k, &p0, &f);
+  if (p == p0) return fabsf(pl) * chord_fraction(f, m, inv_r);
+  if (p == p0 + 1) return fabsf(pl) * chord_fraction(1.0f - f, m, inv_r);
   return 0.0f;
+}
+__device__ __forceinline__ float ray_weight(const RayLine& L, int i, int j) {
+  return ray_weight_parts(L.q0_fx, L.m_fx, L.m, L.inv_r, L.pl, i, j);
 }
 
 // bx, by: block coordinates of a (kBpBlockX x kBpBlockY) pixel block.
@@ -187,6 +191,49 @@ __device__ void backproject_body(const BpArgs& A, int bx, int by) {
   const float x = (float)j - 0.5f * (float)(I - 1);
   const float y = 0.5f * (float)(I - 1) - (float)i;
   float acc = 0.0f;
+  if (!A.fan) {
+    // parallel beam: a view's rays share their slope terms, so a candidate
+    // bin costs one 8-byte q0_fx and one sinogram value
+    for (int k0 = 0; k0 < A.nv; k0 += kBpViews) {
+      int bb[kBpViews], be[kBpViews];
+      int64_t q[kBpViews][kBpBins];
+      float sv[kBpViews][kBpBins];
+#pragma unroll
+      for (int g = 0; g < kBpViews; ++g) {
+        const int k = min(k0 + g, A.nv - 1);
+        const ViewInfo v = A.views[k];
+        const float u = __fmaf_rn(v.a, x, __fmaf_rn(v.b, y, v.c));
+        bb[g] = max((int)ceilf(u - v.hw), 0);
+        be[g] = (k0 + g < A.nv) ? min((int)floorf(u + v.hw), A.nb - 1) : -1;
+        const int64_t row = (int64_t)k * A.nb;
+#pragma unroll
+        for (int c = 0; c < kBpBins; ++c) {
+          const int b = min(bb[g] + c, A.nb - 1);
+          q[g][c] = A.q0fx[row + b];
+          sv[g][c] = A.sino[row + b];
+        }
+      }
+#pragma unroll
+      for (int g = 0; g < kBpViews; ++g) {
+        const int k = min(k0 + g, A.nv - 1);
+        const ViewRay vr = A.vrays[k];
+#pragma unroll
+        for (int c = 0; c < kBpBins; ++c) {
+          const float wgt = (bb[g] + c <= be[g])
+                                ? ray_weight_parts(q[g][c], vr.m_fx, vr.m, vr.inv_r, vr.pl, i, j)
+                                : 0.0f;
+          acc = __fmaf_rn(wgt, sv[g][c], acc);
+        }
+        if (be[g] - bb[g] + 1 > kBpBins) {
+          const int64_t row = (int64_t)(k0 + g) * A.nb;
+          for (int b = bb[g] + kBpBins; b <= be[g]; ++b)
+            acc = __fmaf_rn(ray_weight(A.rays[row + b], i, j), A.sino[row + b], acc);
+        }
+      }
+    }
+    A.img[(int64_t)i * I + j] = acc;
+    return;
+  }
   for (int k0 = 0; k0 < A.nv; k0 += kBpViews) {
     int bb[kBpViews], be[kBpViews];
     RayLine L[kBpViews][kBpBins];
@@ -198,19 +245,13 @@ __device__ void backproject_body(const BpArgs& A, int bx, int by) {
       be[g] = -1;
       if (k < A.nv) {
         const ViewInfo v = A.views[k];
-        float u, hw;
-        if (!A.fan) {
-          u = __fmaf_rn(v.a, x, __fmaf_rn(v.b, y, v.c));
-          hw = v.hw;
-        } else {
-          const float dx = x - v.a, dy = y - v.b;
-          const float along = v.cx * dx + v.cy * dy;
-          const float cr = v.cx * dy - v.cy * dx;
-          const float dist = sqrtf(dx * dx + dy * dy);
-          const float gam = atan2f(cr, along);
-          u = __fmaf_rn(gam, v.inv_dg, v.c);
-          hw = asinf(fminf(A.half_diag / dist, 1.0f)) * v.inv_dg * 1.001f + 1e-3f;
-        }
+        const float dx = x - v.a, dy = y - v.b;
+        const float along = v.cx * dx + v.cy * dy;
+        const float cr = v.cx * dy - v.cy * dx;
+        const float dist = sqrtf(dx * dx + dy * dy);
+        const float gam = atan2f(cr, along);
+        const float u = __fmaf_rn(gam, v.inv_dg, v.c);
+        const float hw = asinf(fminf(A.half_diag / dist, 1.0f)) * v.inv_dg * 1.001f + 1e-3f;
         bb[g] = max((int)ceilf(u - hw), 0);
         be[g] = min((int)floorf(u + hw), A.nb - 1);
       }
@@ -329,7 +370,7 @@ dg_status launch_backproject(const dg_plan* p, const float* sino, float* img, hi
   dim3 grid((p->I + kBpBlockX - 1) / kBpBlockX, (p->I + kBpBlockY - 1) / kBpBlockY);
   dim3 block(kBpBlockX, kBpBlockY);
   BpArgs A{p->rays, p->views, sino, img, p->I, p->nv, p->nb, p->g.kind == DG_GEOM_FAN ? 1 : 0,
-           (float)p->half_diag_px};
+           (float)p->half_diag_px, p->vrays, p->q0fx};
   hipLaunchKernelGGL(backproject_kernel, grid, block, 0, s, A);
   DG_LAUNCH_CHECK("backproject_kernel");
   return DG_OK;
