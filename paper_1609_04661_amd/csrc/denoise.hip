@@ -39,15 +39,21 @@ __device__ __forceinline__ int reflect_idx(int k, int I) {
 }
 
 // Non-local means, register-blocked.  A workgroup owns a 32 x 32 output
-// tile and stages the tile plus its search and patch halos in LDS.  Each of
-// its 4 wavefronts takes every 4th search offset; each thread owns a 2-wide,
-// 8-tall block of outputs and keeps the (8 + 2P) x (2 + 2P) input pixels its
-// patches cover in registers.  Per offset it reads the shifted region row by
-// row from LDS, forms the squared differences, box-sums them horizontally and
-// then vertically with sliding sums (all in registers, no barrier), and turns
-// each sum into a weight.  The four wavefronts' partial sums are added in a
-// fixed order at the end.
+// tile and stages the tile plus its search and patch halos in LDS.  Its
+// kNlmWaves wavefronts split the rows oi of the search window; each thread
+// owns a 2-wide, 8-tall block of outputs and keeps the (8 + 2P) x (2 + 2P)
+// input pixels its patches cover in registers (own).  Along a row of the
+// search window (oj = -S .. S) the shifted region slides right by one
+// column per offset, so it lives in a ring of registers and only its new
+// column is read from LDS (8 + 2P values per offset instead of
+// (8 + 2P) (2 + 2P)); the ring slot of a column is static because the oj
+// loop is unrolled by the ring width.  Per offset the thread forms the
+// squared differences, box-sums them horizontally and then vertically with
+// sliding sums, and turns each sum into a weight.  The wavefronts' partial
+// sums are added in a fixed order at the end.
 static constexpr int kNlmBX = 2, kNlmBY = 8;
+static constexpr int kNlmWaves = 3;  // 21 search rows (S = 10) split 7 / 7 / 7
+static constexpr int kNlmThreads = 64 * kNlmWaves;
 template <int P>
 __device__ void nlm_body(const NlmArgs& Ar, int bx, int by, int img, uint64_t seed, int iter,
                          float* R, float (*red)[64][2 * kNlmBX * kNlmBY]) {
@@ -101,47 +107,61 @@ __device__ void nlm_body(const NlmArgs& Ar, int bx, int by, int img, uint64_t se
   for (int a = 0; a < BY; ++a)
 #pragma unroll
     for (int c = 0; c < BX; ++c) wsum[a][c] = acc[a][c] = 0.0f;
-  const int nside = 2 * S + 1, noff = nside * nside;
-  for (int oidx = g; oidx < noff; oidx += 4) {
-    const int oi = oidx / nside - S, oj = oidx % nside - S;
-    float h[WY][BX];
-    float cen[BY][BX];
+  const int nside = 2 * S + 1;
+  for (int oi = g - S; oi <= S; oi += kNlmWaves) {
+    // shifted region of step t = oj + S: column c of it is LDS column
+    // ox0 + t + c of row S + oy0 + a + oi, held in ring slot (t + c) % WX
+    const float* rowbase = R + (S + oy0 + oi) * kNlmPitch + ox0;
+    float win[WY][WX];
 #pragma unroll
-    for (int a = 0; a < WY; ++a) {
-      const float* row = R + (S + oy0 + a + oi) * kNlmPitch + S + ox0 + oj;
-      float d[WX];
+    for (int a = 0; a < WY; ++a)
 #pragma unroll
-      for (int c = 0; c < WX; ++c) {
-        const float v = row[c];
-        const float dd = own[a][c] - v;
-        d[c] = dd * dd;
-        if (a >= P && a < P + BY && c >= P && c < P + BX) cen[a - P][c - P] = v;
-      }
-      float sacc = 0.0f;
+      for (int c = 0; c < WX - 1; ++c) win[a][c] = rowbase[a * kNlmPitch + c];
+    for (int t0 = 0; t0 < nside; t0 += WX) {
 #pragma unroll
-      for (int q = 0; q <= 2 * P; ++q) sacc += d[q];
-      h[a][0] = sacc;
+      for (int tau = 0; tau < WX; ++tau) {
+        const int t = t0 + tau;
+        if (t < nside) {  // wavefront-uniform
 #pragma unroll
-      for (int c = 1; c < BX; ++c) {
-        sacc += d[c + 2 * P] - d[c - 1];
-        h[a][c] = sacc;
-      }
-    }
+          for (int a = 0; a < WY; ++a)
+            win[a][(tau + WX - 1) % WX] = rowbase[a * kNlmPitch + t + WX - 1];
+          float h[WY][BX];
 #pragma unroll
-    for (int c = 0; c < BX; ++c) {
-      float v = 0.0f;
+          for (int a = 0; a < WY; ++a) {
+            float d[WX];
 #pragma unroll
-      for (int q = 0; q <= 2 * P; ++q) v += h[q][c];
+            for (int c = 0; c < WX; ++c) {
+              const float dd = own[a][c] - win[a][(tau + c) % WX];
+              d[c] = dd * dd;
+            }
+            float sacc = 0.0f;
 #pragma unroll
-      for (int a = 0; a < BY; ++a) {
-        if (a > 0) v += h[a + 2 * P][c] - h[a - 1][c];
-        const float w = __builtin_amdgcn_exp2f(-fmaxf(__fmaf_rn(v, c1, -c2), 0.0f));
-        wsum[a][c] += w;
-        acc[a][c] = __fmaf_rn(w, cen[a][c], acc[a][c]);
+            for (int q = 0; q <= 2 * P; ++q) sacc += d[q];
+            h[a][0] = sacc;
+#pragma unroll
+            for (int c = 1; c < BX; ++c) {
+              sacc += d[c + 2 * P] - d[c - 1];
+              h[a][c] = sacc;
+            }
+          }
+#pragma unroll
+          for (int c = 0; c < BX; ++c) {
+            float v = 0.0f;
+#pragma unroll
+            for (int q = 0; q <= 2 * P; ++q) v += h[q][c];
+#pragma unroll
+            for (int a = 0; a < BY; ++a) {
+              if (a > 0) v += h[a + 2 * P][c] - h[a - 1][c];
+              const float w = __builtin_amdgcn_exp2f(-fmaxf(__fmaf_rn(v, c1, -c2), 0.0f));
+              wsum[a][c] += w;
+              acc[a][c] = __fmaf_rn(w, win[a + P][(tau + c + P) % WX], acc[a][c]);
+            }
+          }
+        }
       }
     }
   }
-  // add the four wavefronts' partial sums in a fixed order
+  // add the wavefronts' partial sums in a fixed order
 #pragma unroll
   for (int a = 0; a < BY; ++a)
 #pragma unroll
@@ -150,12 +170,11 @@ __device__ void nlm_body(const NlmArgs& Ar, int bx, int by, int img, uint64_t se
       red[g][lane][2 * (a * BX + c) + 1] = acc[a][c];
     }
   __syncthreads();
-  // every thread finalises 4 of its block's 16 outputs: thread (g, lane) takes
-  // outputs k = g, g+4, g+8, g+12 of block `lane`
-  for (int k = g; k < BX * BY; k += 4) {
+  // thread (g, lane) finalises outputs k = g, g + kNlmWaves, ... of block `lane`
+  for (int k = g; k < BX * BY; k += kNlmWaves) {
     float ws = 0.0f, ac = 0.0f;
 #pragma unroll
-    for (int gg = 0; gg < 4; ++gg) {
+    for (int gg = 0; gg < kNlmWaves; ++gg) {
       ws += red[gg][lane][2 * k];
       ac += red[gg][lane][2 * k + 1];
     }
@@ -166,17 +185,17 @@ __device__ void nlm_body(const NlmArgs& Ar, int bx, int by, int img, uint64_t se
 }
 
 template <int P>
-__global__ void __launch_bounds__(256) nlm_kernel(NlmArgs A, uint64_t seed, int iter) {
+__global__ void __launch_bounds__(kNlmThreads) nlm_kernel(NlmArgs A, uint64_t seed, int iter) {
   __shared__ float R[kNlmRegion * kNlmPitch];
-  __shared__ float red[4][64][2 * kNlmBX * kNlmBY];
+  __shared__ float red[kNlmWaves][64][2 * kNlmBX * kNlmBY];
   nlm_body<P>(A, blockIdx.x, blockIdx.y, blockIdx.z, seed, iter, R, red);
 }
 template <int P>
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(kNlmThreads)
 nlm_batch(const NlmArgs* __restrict__ T, const int* __restrict__ prefix, int n, uint64_t seed,
           int iter) {
   __shared__ float R[kNlmRegion * kNlmPitch];
-  __shared__ float red[4][64][2 * kNlmBX * kNlmBY];
+  __shared__ float red[kNlmWaves][64][2 * kNlmBX * kNlmBY];
   const int s = slice_of(prefix, n, blockIdx.x);
   const NlmArgs A = T[s];
   const int local = blockIdx.x - prefix[s];
@@ -454,13 +473,13 @@ dg_status launch_denoiser(const dg_plan* p, int kind, const void* params, const 
     NlmArgs A{r, x_den, x_pert, p->I, np->search_radius, tau_r, eps, (float)np->hfac};
     switch (np->patch_radius) {
       case 1:
-        hipLaunchKernelGGL(nlm_kernel<1>, grid, dim3(256), 0, st, A, seed, iter);
+        hipLaunchKernelGGL(nlm_kernel<1>, grid, dim3(kNlmThreads), 0, st, A, seed, iter);
         break;
       case 2:
-        hipLaunchKernelGGL(nlm_kernel<2>, grid, dim3(256), 0, st, A, seed, iter);
+        hipLaunchKernelGGL(nlm_kernel<2>, grid, dim3(kNlmThreads), 0, st, A, seed, iter);
         break;
       default:
-        hipLaunchKernelGGL(nlm_kernel<3>, grid, dim3(256), 0, st, A, seed, iter);
+        hipLaunchKernelGGL(nlm_kernel<3>, grid, dim3(kNlmThreads), 0, st, A, seed, iter);
         break;
     }
     DG_LAUNCH_CHECK("nlm_kernel");
@@ -501,13 +520,13 @@ dg_status launch_nlm_batch(int P, const NlmArgs* T, const int* prefix, int n, in
                            uint64_t seed, int iter, hipStream_t st) {
   switch (P) {
     case 1:
-      hipLaunchKernelGGL(nlm_batch<1>, dim3(total), dim3(256), 0, st, T, prefix, n, seed, iter);
+      hipLaunchKernelGGL(nlm_batch<1>, dim3(total), dim3(kNlmThreads), 0, st, T, prefix, n, seed, iter);
       break;
     case 2:
-      hipLaunchKernelGGL(nlm_batch<2>, dim3(total), dim3(256), 0, st, T, prefix, n, seed, iter);
+      hipLaunchKernelGGL(nlm_batch<2>, dim3(total), dim3(kNlmThreads), 0, st, T, prefix, n, seed, iter);
       break;
     default:
-      hipLaunchKernelGGL(nlm_batch<3>, dim3(total), dim3(256), 0, st, T, prefix, n, seed, iter);
+      hipLaunchKernelGGL(nlm_batch<3>, dim3(total), dim3(kNlmThreads), 0, st, T, prefix, n, seed, iter);
       break;
   }
   DG_LAUNCH_CHECK("nlm_batch");
