@@ -217,6 +217,9 @@ typedef struct dgamp_opts {
                               and after each phase of every iteration:
                               V^-1 x | A | channel | A^T | V^-1 g + r update |
                               denoiser | divergence + tau_x                   */
+  uint32_t phase_mask;     /* 0: record every mark; else only the marks k
+                              (0..DG_NPHASES) with bit k set (fewer event
+                              records inside a timed run)                     */
 } dgamp_opts;
 #define DG_NPHASES 7
 typedef struct dgamp_state {

@@ -70,7 +70,7 @@ class DgampOpts(ctypes.Structure):
                 ("probe_seed", ctypes.c_uint64), ("eps_rel", ctypes.c_double),
                 ("eta_x", ctypes.c_double), ("eta_s", ctypes.c_double),
                 ("onsager", ctypes.c_int32), ("channel_mode", ctypes.c_int32),
-                ("phase_events", ctypes.c_void_p)]
+                ("phase_events", ctypes.c_void_p), ("phase_mask", ctypes.c_uint32)]
 
 
 class DgampStateC(ctypes.Structure):
@@ -312,22 +312,24 @@ class DgampState:
 
 
 def make_opts(n_iter, fro2, i0, den_kind, den_params, probe_seed=0, eps_rel=1e-3, eta_x=1.0,
-              eta_s=1.0, onsager=True, channel_mode=CHANNEL_LAPLACE, phase_events=None):
+              eta_s=1.0, onsager=True, channel_mode=CHANNEL_LAPLACE, phase_events=None,
+              phase_mask=0):
     return DgampOpts(n_iter=int(n_iter), den_kind=int(den_kind),
                      den_params=ctypes.cast(ctypes.pointer(den_params), ctypes.c_void_p),
                      fro2=float(fro2), i0=float(i0), probe_seed=int(probe_seed),
                      eps_rel=float(eps_rel), eta_x=float(eta_x), eta_s=float(eta_s),
                      onsager=1 if onsager else 0, channel_mode=int(channel_mode),
                      phase_events=ctypes.cast(phase_events, ctypes.c_void_p)
-                     if phase_events is not None else None)
+                     if phase_events is not None else None, phase_mask=int(phase_mask))
 
 
 def dgamp_iterate(plan, y, state, n_iter, fro2, i0, den_kind, den_params, probe_seed=0,
                   eps_rel=1e-3, eta_x=1.0, eta_s=1.0, onsager=True, channel_mode=CHANNEL_LAPLACE,
-                  mu_out=None, log=None, work=None, phase_events=None):
-    """phase_events: optional ctypes array of n_iter * (NPHASES + 1) hipEvent_t handles."""
+                  mu_out=None, log=None, work=None, phase_events=None, phase_mask=0):
+    """phase_events: optional ctypes array of n_iter * (NPHASES + 1) hipEvent_t handles;
+    phase_mask: 0 records every mark, else only marks k with bit k set."""
     opts = make_opts(n_iter, fro2, i0, den_kind, den_params, probe_seed, eps_rel, eta_x, eta_s,
-                     onsager, channel_mode, phase_events)
+                     onsager, channel_mode, phase_events, phase_mask)
     if work is None:
         work = plan.workspace(OP_DGAMP)
     if log is not None and log.numel() < n_iter * LOG_STRIDE:

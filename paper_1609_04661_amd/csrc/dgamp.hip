@@ -184,8 +184,10 @@ extern "C" dg_status dgamp_iterate(const dg_plan* p, const float* y, const dgamp
   if ((rc = launch_zero_u32(w.counters, 8, s)) != DG_OK) return rc;
   const double N = (double)p->N;
   hipEvent_t* ev = (hipEvent_t*)o->phase_events;
+  const uint32_t pmask = o->phase_mask;
   auto mark = [&](int it, int k) -> dg_status {
-    if (ev) DG_HIP(hipEventRecord(ev[(size_t)it * (DG_NPHASES + 1) + k], s));
+    if (ev && (pmask == 0 || ((pmask >> k) & 1u)))
+      DG_HIP(hipEventRecord(ev[(size_t)it * (DG_NPHASES + 1) + k], s));
     return DG_OK;
   };
   for (int it = 0; it < o->n_iter; ++it) {
