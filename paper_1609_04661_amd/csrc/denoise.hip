@@ -40,7 +40,8 @@ __device__ __forceinline__ int reflect_idx(int k, int I) {
 
 // Non-local means, register-blocked.  A workgroup owns a 32 x 32 output
 // tile and stages the tile plus its search and patch halos in LDS.  Its
-// kNlmWaves wavefronts split the rows oi of the search window; each thread
+// kNlmWaves wavefronts split the rows oi of the search window (more, shorter
+// wavefronts hide LDS and exp latency better than few long ones); each thread
 // owns a 2-wide, 8-tall block of outputs and keeps the (8 + 2P) x (2 + 2P)
 // input pixels its patches cover in registers (own).  Along a row of the
 // search window (oj = -S .. S) the shifted region slides right by one
@@ -52,7 +53,7 @@ __device__ __forceinline__ int reflect_idx(int k, int I) {
 // sliding sums, and turns each sum into a weight.  The wavefronts' partial
 // sums are added in a fixed order at the end.
 static constexpr int kNlmBX = 2, kNlmBY = 8;
-static constexpr int kNlmWaves = 3;  // 21 search rows (S = 10) split 7 / 7 / 7
+static constexpr int kNlmWaves = 7;  // 21 search rows (S = 10): 3 per wavefront
 static constexpr int kNlmThreads = 64 * kNlmWaves;
 template <int P>
 __device__ void nlm_body(const NlmArgs& Ar, int bx, int by, int img, uint64_t seed, int iter,
