@@ -21,14 +21,14 @@
 namespace dg {
 
 dg_status launch_prec_batch(int pass, const void* table, const int* prefix, int n, int total,
-                            hipStream_t s);
+                            int fin_t, double fin_eta, hipStream_t s);
 dg_status launch_project_batch(int variant, const ProjArgs* T, const int* prefix, int n, int total,
                                hipStream_t s);
 dg_status launch_project_variant(int variant, const ProjArgs& A, hipStream_t s);
 dg_status launch_backproject_batch(const BpArgs* T, const int* prefix, int n, int total,
                                    hipStream_t s);
 dg_status launch_channel_batch(const ChanArgs* T, const int* prefix, int n, int total, int mode,
-                               double eta_s, int onsager, int t, hipStream_t st);
+                               double eta_s, int onsager, int t, int finish, hipStream_t st);
 dg_status launch_nlm_batch(int P, const NlmArgs* T, const int* prefix, int n, int total,
                            uint64_t seed, int iter, hipStream_t st);
 dg_status launch_div_batch(const DivArgs* T, const int* prefix, int n, int total, uint64_t seed,
@@ -295,8 +295,7 @@ extern "C" dg_status dg_batch_bind(dg_batch* b, const float* y, const double* i0
     double* sc = scal + (size_t)k * DG_NSCAL;
     double* dp = dpart + (size_t)k * kPartMax;
     float* fp = fpart + (size_t)k * kPartMax;
-    rf_x[k] = RowsFwdArgs{x + io, sp, p->twiddle, I};
-    rf_g[k] = RowsFwdArgs{g + io, sp, p->twiddle, I};
+    rf_x[k] = RowsFwdArgs{x + io, sp, p->twiddle, I, 0, ChanArgs{}};
     cols[k] = ColsArgs{sp, p->twiddle, I, 1};
     ri_mu[k] = RowsInvArgs{sp, p->twiddle, I, PREC_PLAIN, mu + io, mu_t + io, nullptr, nullptr,
                            nullptr};
@@ -307,11 +306,14 @@ extern "C" dg_status dg_batch_bind(dg_batch* b, const float* y, const double* i0
     proj[k] = ProjArgs{p->rays, mu + io, mu_t + io, z + so, I, p->M};
     chan[k] = ChanArgs{p->M, z + so, y + so, s + so, nullptr, nullptr, sc, nullptr, i0[k], fro2[k],
                        (double)p->N, dp, b->pre_chan[k + 1] - b->pre_chan[k]};
+    // the channel finish runs in the slice's first row workgroup of V^-1 g
+    rf_g[k] = RowsFwdArgs{g + io, sp, p->twiddle, I, 1, chan[k]};
     bp[k] = BpArgs{p->rays, p->views, s + so, g + io, I, p->nv, p->nb,
                    p->g.kind == DG_GEOM_FAN ? 1 : 0, (float)p->half_diag_px, p->vrays, p->q0fx};
-    if (den_kind == DG_DEN_NLM)
-      nlm[k] = NlmArgs{r + io, xden + io, xpert + io, I, np->search_radius,
-                       sc + DG_S_TAU_R, sc + DG_S_EPS, (float)np->hfac};
+    if (den_kind == DG_DEN_NLM)  // NLM also finishes the Monte-Carlo step
+      nlm[k] = NlmArgs{r + io,           xden + io, xpert + io,       I,
+                       np->search_radius, sc + DG_S_TAU_R, sc + DG_S_EPS, (float)np->hfac,
+                       fp,               prec_row_blocks(I), eps_rel,   sc + DG_S_EPS};
     dv[k] = DivArgs{p->N, xden + io, xpert + io, x + io, sc + DG_S_EPS, nullptr, sc, dp,
                     b->pre_div[k + 1] - b->pre_div[k]};
   }
@@ -353,13 +355,16 @@ extern "C" dg_status dg_batch_state_init(dg_batch* b, double tau_x0, void* strea
 }
 
 static dg_status batch_precondition(dg_batch* b, const RowsFwdArgs* rf, const RowsInvArgs* ri,
-                                    hipStream_t st) {
+                                    int fin_t, double fin_eta, hipStream_t st) {
   const int n = b->n;
   dg_status rc;
-  if ((rc = launch_prec_batch(0, rf, b->d_pre_rows, n, b->pre_rows[n], st)) != DG_OK) return rc;
-  if ((rc = launch_prec_batch(1, b->t_cols, b->d_pre_cols, n, b->pre_cols[n], st)) != DG_OK)
+  if ((rc = launch_prec_batch(0, rf, b->d_pre_rows, n, b->pre_rows[n], fin_t, fin_eta, st)) !=
+      DG_OK)
     return rc;
-  return launch_prec_batch(2, ri, b->d_pre_rows, n, b->pre_rows[n], st);
+  if ((rc = launch_prec_batch(1, b->t_cols, b->d_pre_cols, n, b->pre_cols[n], 0, 0.0, st)) !=
+      DG_OK)
+    return rc;
+  return launch_prec_batch(2, ri, b->d_pre_rows, n, b->pre_rows[n], 0, 0.0, st);
 }
 
 extern "C" dg_status dgamp_batch_iterate(dg_batch* b, int32_t n_iter, int32_t t0,
@@ -377,17 +382,19 @@ extern "C" dg_status dgamp_batch_iterate(dg_batch* b, int32_t n_iter, int32_t t0
   dg_status rc;
   for (int it = 0; it < n_iter; ++it) {
     const int t = t0 + it;
-    if ((rc = batch_precondition(b, b->t_rf_x, b->t_ri_mu, st)) != DG_OK) return rc;
+    if ((rc = batch_precondition(b, b->t_rf_x, b->t_ri_mu, 0, 0.0, st)) != DG_OK) return rc;
     if ((rc = launch_project_batch(b->proj_variant, b->t_proj, b->d_pre_proj, n, b->pre_proj[n],
                                    st)) != DG_OK)
       return rc;
     if ((rc = launch_channel_batch(b->t_chan, b->d_pre_chan, n, b->pre_chan[n], channel_mode, eta_s,
-                                   onsager, t, st)) != DG_OK)
+                                   onsager, t, 0, st)) != DG_OK)
       return rc;
     if ((rc = launch_backproject_batch(b->t_bp, b->d_pre_bp, n, b->pre_bp[n], st)) != DG_OK)
       return rc;
-    if ((rc = batch_precondition(b, b->t_rf_g, b->t_ri_r, st)) != DG_OK) return rc;
-    if ((rc = launch_prec_batch(3, b->t_eps, nullptr, n, n, st)) != DG_OK) return rc;
+    if ((rc = batch_precondition(b, b->t_rf_g, b->t_ri_r, t, eta_s, st)) != DG_OK) return rc;
+    if (b->den_kind != DG_DEN_NLM &&
+        (rc = launch_prec_batch(3, b->t_eps, nullptr, n, n, 0, 0.0, st)) != DG_OK)
+      return rc;
     if (b->den_kind == DG_DEN_NLM) {
       rc = launch_nlm_batch(b->nlm.patch_radius, b->t_nlm, b->d_pre_nlm, n, b->pre_nlm[n],
                             probe_seed, t, st);
@@ -400,7 +407,7 @@ extern "C" dg_status dgamp_batch_iterate(dg_batch* b, int32_t n_iter, int32_t t0
                                st)) != DG_OK)
       return rc;
   }
-  if (write_mu) return batch_precondition(b, b->t_rf_x, b->t_ri_out, st);
+  if (write_mu) return batch_precondition(b, b->t_rf_x, b->t_ri_out, 0, 0.0, st);
   return DG_OK;
 }
 

@@ -112,30 +112,6 @@ __device__ void channel_body(const ChanArgs& A, int blk, int mode, double eta_s,
   if (threadIdx.x == 0) A.partials[blk] = bs;
 }
 
-// tau_s (and in the iteration: its damping, tau_p, tau_r, status) from the
-// per-block partial sums.
-template <bool kFused>
-__device__ void channel_finish_body(const ChanArgs& A, double eta_s, int t, double* red) {
-  if (kFused && A.scal[DG_S_STATUS] != 0.0) return;
-  const double tot = finish_sum(A.partials, A.nblk, red);
-  if (threadIdx.x == 0) {
-    const double tau_p = kFused ? A.fro2 * A.scal[DG_S_TAU_X] / (double)A.M : *A.tau_p_ptr;
-    double tau_s = tot / ((double)A.M * tau_p);
-    if (kFused) {
-      double* scal = A.scal;
-      if (t > 0) tau_s = eta_s * tau_s + (1.0 - eta_s) * scal[DG_S_TAU_S];
-      const double tau_r = A.N / (A.fro2 * tau_s);
-      scal[DG_S_TAU_P] = tau_p;
-      scal[DG_S_TAU_S] = tau_s;
-      scal[DG_S_TAU_R] = tau_r;
-      if (!(tau_s > 0.0) || !isfinite(tau_s) || !(tau_r > 0.0) || !isfinite(tau_r))
-        scal[DG_S_STATUS] = (double)(t + 1);
-    } else {
-      *A.tau_s_out = tau_s;
-    }
-  }
-}
-
 template <bool kFused>
 __global__ void __launch_bounds__(kChanBlock)
 channel_kernel(ChanArgs A, int mode, double eta_s, int onsager, int t) {
@@ -162,26 +138,37 @@ channel_finish_batch(const ChanArgs* __restrict__ T, double eta_s, int t) {
 
 unsigned int channel_grid(int64_t M) { return grid_for(M, kChanBlock, kChanMaxBlocks); }
 
+// Inside the iteration.  With finish = 0 the caller finishes the channel
+// later (channel_finish_body on *out_args); the arguments are returned in
+// out_args either way.
 dg_status launch_channel_fused(int64_t M, const float* z, const float* y, float* s, double* scal,
                                double i0, int mode, double fro2, double N, double eta_s,
-                               int onsager, int t, double* partials, hipStream_t st) {
+                               int onsager, int t, double* partials, int finish,
+                               ChanArgs* out_args, hipStream_t st) {
   const unsigned int g = channel_grid(M);
   ChanArgs A{M, z, y, s, nullptr, nullptr, scal, nullptr, i0, fro2, N, partials, (int)g};
+  if (out_args) *out_args = A;
   hipLaunchKernelGGL(channel_kernel<true>, dim3(g), dim3(kChanBlock), 0, st, A, mode, eta_s,
                      onsager, t);
   DG_LAUNCH_CHECK("channel_kernel<fused>");
-  hipLaunchKernelGGL(channel_finish<true>, dim3(1), dim3(256), 0, st, A, eta_s, t);
-  DG_LAUNCH_CHECK("channel_finish<fused>");
+  if (finish) {
+    hipLaunchKernelGGL(channel_finish<true>, dim3(1), dim3(256), 0, st, A, eta_s, t);
+    DG_LAUNCH_CHECK("channel_finish<fused>");
+  }
   return DG_OK;
 }
 
+// finish = 0: the finish runs later, inside the first row pass of the
+// next preconditioner application.
 dg_status launch_channel_batch(const ChanArgs* T, const int* prefix, int n, int total, int mode,
-                               double eta_s, int onsager, int t, hipStream_t st) {
+                               double eta_s, int onsager, int t, int finish, hipStream_t st) {
   hipLaunchKernelGGL(channel_batch, dim3(total), dim3(kChanBlock), 0, st, T, prefix, n, mode, eta_s,
                      onsager, t);
   DG_LAUNCH_CHECK("channel_batch");
-  hipLaunchKernelGGL(channel_finish_batch, dim3(n), dim3(256), 0, st, T, eta_s, t);
-  DG_LAUNCH_CHECK("channel_finish_batch");
+  if (finish) {
+    hipLaunchKernelGGL(channel_finish_batch, dim3(n), dim3(256), 0, st, T, eta_s, t);
+    DG_LAUNCH_CHECK("channel_finish_batch");
+  }
   return DG_OK;
 }
 

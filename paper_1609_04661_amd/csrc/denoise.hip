@@ -68,7 +68,24 @@ __device__ void nlm_body(const NlmArgs& Ar, int bx, int by, int img, uint64_t se
   const int ty0 = by * kNlmTile, tx0 = bx * kNlmTile;
   const int H0 = S + P;
   const int WR = kNlmTile + 2 * H0;
-  const float eps = img ? (float)(*Ar.eps) : 0.0f;
+  float eps = 0.0f;
+  if (Ar.eps_part) {
+    // Monte-Carlo step from the preconditioner's per-workgroup max |r|
+    // (finished here rather than in a launch of its own); red is free yet
+    float* sh = &red[0][0][0];
+    const float gm = finish_max(Ar.eps_part, Ar.eps_n, sh);
+    if (threadIdx.x == 0) {
+      double e = Ar.eps_rel * (double)gm;
+      e = e > 1e-12 ? e : 1e-12;
+      if (bx == 0 && by == 0 && img == 0) *Ar.eps_out = e;
+      sh[32] = (float)e;
+    }
+    __syncthreads();
+    eps = img ? sh[32] : 0.0f;
+    __syncthreads();
+  } else if (img) {
+    eps = (float)(*Ar.eps);
+  }
   for (int e = threadIdx.x; e < WR * WR; e += blockDim.x) {
     const int ri = e / WR, rj = e % WR;
     const int gi = reflect_idx(ty0 - H0 + ri, I), gj = reflect_idx(tx0 - H0 + rj, I);
@@ -466,12 +483,19 @@ dg_status check_denoise_params(const dg_plan* p, int kind, const void* params) {
 // Runs D on r (into x_den) and, when probed, on r + eps b (into x_pert).
 dg_status launch_denoiser(const dg_plan* p, int kind, const void* params, const float* r,
                           const double* tau_r, const double* eps, uint64_t seed, int iter,
-                          float* x_den, float* x_pert, hipStream_t st) {
+                          float* x_den, float* x_pert, hipStream_t st, const EpsFinish* ef) {
   const int nimg = x_pert ? 2 : 1;
   if (kind == DG_DEN_NLM) {
     const dg_nlm_params* np = (const dg_nlm_params*)params;
     dim3 grid((p->I + kNlmTile - 1) / kNlmTile, (p->I + kNlmTile - 1) / kNlmTile, nimg);
-    NlmArgs A{r, x_den, x_pert, p->I, np->search_radius, tau_r, eps, (float)np->hfac};
+    NlmArgs A{r,       x_den, x_pert, p->I, np->search_radius, tau_r, eps, (float)np->hfac,
+              nullptr, 0,     0.0,    nullptr};
+    if (ef) {
+      A.eps_part = ef->part;
+      A.eps_n = ef->n;
+      A.eps_rel = ef->eps_rel;
+      A.eps_out = ef->out;
+    }
     switch (np->patch_radius) {
       case 1:
         hipLaunchKernelGGL(nlm_kernel<1>, grid, dim3(kNlmThreads), 0, st, A, seed, iter);
@@ -584,7 +608,8 @@ extern "C" dg_status denoise(const dg_plan* p, int32_t kind, const void* params,
   if (kind == DG_DEN_CNN) {
     rc = cnn_launch_denoise(p, params, r, w.eps, probe_seed, iter, x_out, xpert, nullptr, st);
   } else {
-    rc = launch_denoiser(p, kind, params, r, tau_r, w.eps, probe_seed, iter, x_out, xpert, st);
+    rc = launch_denoiser(p, kind, params, r, tau_r, w.eps, probe_seed, iter, x_out, xpert, st,
+                         nullptr);
   }
   if (rc != DG_OK) return rc;
   if (div_out)

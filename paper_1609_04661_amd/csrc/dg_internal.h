@@ -246,6 +246,32 @@ struct ChanArgs {
   int nblk;  // blocks of the channel launch for this slice
 };
 
+// tau_s (and in the iteration: its damping, tau_p, tau_r, status) from the
+// output channel's per-block partial sums; one workgroup, result written by
+// thread 0.  Lives here so that a later kernel of the iteration can finish
+// the channel without a launch of its own.
+template <bool kFused>
+__device__ void channel_finish_body(const ChanArgs& A, double eta_s, int t, double* red) {
+  if (kFused && A.scal[DG_S_STATUS] != 0.0) return;
+  const double tot = finish_sum(A.partials, A.nblk, red);
+  if (threadIdx.x == 0) {
+    const double tau_p = kFused ? A.fro2 * A.scal[DG_S_TAU_X] / (double)A.M : *A.tau_p_ptr;
+    double tau_s = tot / ((double)A.M * tau_p);
+    if (kFused) {
+      double* scal = A.scal;
+      if (t > 0) tau_s = eta_s * tau_s + (1.0 - eta_s) * scal[DG_S_TAU_S];
+      const double tau_r = A.N / (A.fro2 * tau_s);
+      scal[DG_S_TAU_P] = tau_p;
+      scal[DG_S_TAU_S] = tau_s;
+      scal[DG_S_TAU_R] = tau_r;
+      if (!(tau_s > 0.0) || !isfinite(tau_s) || !(tau_r > 0.0) || !isfinite(tau_r))
+        scal[DG_S_STATUS] = (double)(t + 1);
+    } else {
+      *A.tau_s_out = tau_s;
+    }
+  }
+}
+
 // Non-local-means argument block (per slice): image 0 = r, image 1 = r + eps b.
 struct NlmArgs {
   const float* r;
@@ -255,6 +281,20 @@ struct NlmArgs {
   const double* tau_r;
   const double* eps;
   float hfac;
+  // optional: finish the Monte-Carlo step here instead of in a separate
+  // launch: eps = max(eps_rel * max(eps_part[0..eps_n)), 1e-12), written to
+  // *eps_out by the slice's first workgroup (then eps above is unused)
+  const float* eps_part;
+  int eps_n;
+  double eps_rel;
+  double* eps_out;
+};
+// Where a denoiser launch may finish the Monte-Carlo step itself.
+struct EpsFinish {
+  const float* part;
+  int n;
+  double eps_rel;
+  double* out;
 };
 // Divergence argument block (per slice).
 struct DivArgs {
@@ -286,6 +326,8 @@ struct RowsFwdArgs {
   float2* spec;
   const float2* tw;
   int I;
+  int fin;        // 1: the first workgroup also finishes the output channel
+  ChanArgs chan;  // (tau_s, tau_r from the channel's partial sums)
 };
 struct ColsArgs {
   float2* spec;
@@ -322,6 +364,11 @@ struct PrecArgs {
   const double* scal;    // PREC_UPDATE_R: tau_r = scal[DG_S_TAU_R]
   double* scal_out;      // PREC_UPDATE_R: eps written to scal_out[DG_S_EPS]
   double eps_rel;
+  int eps_elsewhere;     // PREC_UPDATE_R: leave the eps finish to the denoiser
+  int fin;               // 1: finish the output channel in the first row workgroup
+  ChanArgs chan;
+  double fin_eta;
+  int fin_t;
   float* partials;       // PREC_UPDATE_R: per-block max |r| (I/2 floats)
 };
 dg_status launch_precondition(const dg_plan* p, const PrecArgs& a, hipStream_t s);

@@ -16,11 +16,13 @@ namespace dg {
 dg_status launch_zero_u32(unsigned int* p, int n, hipStream_t st);
 dg_status launch_channel_fused(int64_t M, const float* z, const float* y, float* s, double* scal,
                                double i0, int mode, double fro2, double N, double eta_s,
-                               int onsager, int t, double* partials, hipStream_t st);
+                               int onsager, int t, double* partials, int finish,
+                               ChanArgs* out_args, hipStream_t st);
 dg_status check_denoise_params(const dg_plan* p, int kind, const void* params);
 dg_status launch_denoiser(const dg_plan* p, int kind, const void* params, const float* r,
                           const double* tau_r, const double* eps, uint64_t seed, int iter,
-                          float* x_den, float* x_pert, hipStream_t st);
+                          float* x_den, float* x_pert, hipStream_t st, const EpsFinish* ef);
+int prec_row_blocks(int I);
 dg_status launch_div(const dg_plan* p, const float* xden, const float* xpert, float* x,
                      const double* eps, double* div_out, double* scal, int mode, uint64_t seed,
                      int iter, double eta_x, int t, double* partials, hipStream_t st);
@@ -204,12 +206,16 @@ extern "C" dg_status dgamp_iterate(const dg_plan* p, const float* y, const dgamp
     if ((rc = mark(it, 1)) != DG_OK) return rc;
     if ((rc = launch_project(p, w.mu, w.mu_t, w.z, s)) != DG_OK) return rc;
     if ((rc = mark(it, 2)) != DG_OK) return rc;
+    // the channel's finish (tau_s, tau_r) runs in the first row workgroup of
+    // the next preconditioner application, and NLM finishes the MC step
+    ChanArgs chan;
     if ((rc = launch_channel_fused(p->M, w.z, y, st->s, st->scal, o->i0, o->channel_mode, o->fro2,
-                                   N, o->eta_s, o->onsager, t, w.dpart, s)) != DG_OK)
+                                   N, o->eta_s, o->onsager, t, w.dpart, 0, &chan, s)) != DG_OK)
       return rc;
     if ((rc = mark(it, 3)) != DG_OK) return rc;
     if ((rc = launch_backproject(p, st->s, w.g, s)) != DG_OK) return rc;
     if ((rc = mark(it, 4)) != DG_OK) return rc;
+    const bool nlm = o->den_kind == DG_DEN_NLM;
     PrecArgs b{};
     b.in = w.g;
     b.out = w.r;
@@ -222,16 +228,22 @@ extern "C" dg_status dgamp_iterate(const dg_plan* p, const float* y, const dgamp
     b.scal_out = st->scal;
     b.eps_rel = o->eps_rel;
     b.partials = w.fpart;
+    b.eps_elsewhere = nlm ? 1 : 0;
+    b.fin = 1;
+    b.chan = chan;
+    b.fin_eta = o->eta_s;
+    b.fin_t = t;
     if ((rc = launch_precondition(p, b, s)) != DG_OK) return rc;
     if ((rc = mark(it, 5)) != DG_OK) return rc;
     const double* tau_r = st->scal + DG_S_TAU_R;
     const double* eps = st->scal + DG_S_EPS;
+    const EpsFinish ef{w.fpart, prec_row_blocks(p->I), o->eps_rel, st->scal + DG_S_EPS};
     if (o->den_kind == DG_DEN_CNN)
       rc = cnn_launch_denoise(p, o->den_params, w.r, eps, o->probe_seed, t, w.xden, w.xpert,
                               nullptr, s);
     else
       rc = launch_denoiser(p, o->den_kind, o->den_params, w.r, tau_r, eps, o->probe_seed, t,
-                           w.xden, w.xpert, s);
+                           w.xden, w.xpert, s, nlm ? &ef : nullptr);
     if (rc != DG_OK) return rc;
     if ((rc = mark(it, 6)) != DG_OK) return rc;
     if ((rc = launch_div(p, w.xden, w.xpert, st->x, eps, nullptr, st->scal, 1, o->probe_seed, t,

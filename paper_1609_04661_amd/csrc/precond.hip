@@ -129,6 +129,7 @@ struct FftShared {
   float2 tw[kMaxFft];
   float2 buf[kFftWaves][2][kMaxFft + 8];
   float red[kFftWaves];
+  double dred[kFftWaves];
 };
 
 __device__ __forceinline__ void load_twiddles(FftShared& S, const float2* __restrict__ tw, int I) {
@@ -141,9 +142,12 @@ __device__ __forceinline__ void load_twiddles(FftShared& S, const float2* __rest
 // spectra are separated by conjugate symmetry and stored column-major as
 // spec[k][row], k = 0..I/2; the workgroup writes its 8 rows of every k as
 // one contiguous 64-byte run.
-__device__ void rows_fwd_body(const RowsFwdArgs& A, int blk, FftShared& S) {
+__device__ void rows_fwd_body(const RowsFwdArgs& A, int blk, FftShared& S, int fin_t,
+                              double fin_eta) {
   const int I = A.I, lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int half = I / 2 + 1;
+  // the output channel's finish (tau_s, tau_r), saving it a launch of its own
+  if (A.fin && blk == 0) channel_finish_body<true>(A.chan, fin_eta, fin_t, S.dred);
   load_twiddles(S, A.tw, I);
   const int m = blk * kFftWaves + w;
   float2* a = S.buf[w][0];
@@ -279,15 +283,17 @@ __device__ void eps_body(const EpsArgs& A, float* red) {
   }
 }
 
-__global__ void __launch_bounds__(kFftThreads) prec_rows_fwd(RowsFwdArgs A) {
+__global__ void __launch_bounds__(kFftThreads)
+prec_rows_fwd(RowsFwdArgs A, int fin_t, double fin_eta) {
   __shared__ FftShared S;
-  rows_fwd_body(A, blockIdx.x, S);
+  rows_fwd_body(A, blockIdx.x, S, fin_t, fin_eta);
 }
 __global__ void __launch_bounds__(kFftThreads)
-prec_rows_fwd_batch(const RowsFwdArgs* __restrict__ T, const int* __restrict__ prefix, int n) {
+prec_rows_fwd_batch(const RowsFwdArgs* __restrict__ T, const int* __restrict__ prefix, int n,
+                    int fin_t, double fin_eta) {
   __shared__ FftShared S;
   const int s = slice_of(prefix, n, blockIdx.x);
-  rows_fwd_body(T[s], blockIdx.x - prefix[s], S);
+  rows_fwd_body(T[s], blockIdx.x - prefix[s], S, fin_t, fin_eta);
 }
 __global__ void __launch_bounds__(kFftThreads) prec_cols(ColsArgs A) {
   __shared__ FftShared S;
@@ -331,11 +337,11 @@ dg_status launch_eps_finish(const float* partials, int n, double eps_rel, double
 }
 
 dg_status launch_prec_batch(int pass, const void* table, const int* prefix, int n, int total,
-                            hipStream_t s) {
+                            int fin_t, double fin_eta, hipStream_t s) {
   switch (pass) {
     case 0:
       hipLaunchKernelGGL(prec_rows_fwd_batch, dim3(total), dim3(kFftThreads), 0, s,
-                         (const RowsFwdArgs*)table, prefix, n);
+                         (const RowsFwdArgs*)table, prefix, n, fin_t, fin_eta);
       break;
     case 1:
       hipLaunchKernelGGL(prec_cols_batch, dim3(total), dim3(kFftThreads), 0, s,
@@ -359,8 +365,9 @@ dg_status launch_precondition(const dg_plan* p, const PrecArgs& a, hipStream_t s
     return DG_ERR_UNSUPPORTED;
   }
   const int I = p->I;
-  RowsFwdArgs f{a.in, a.spec, p->twiddle, I};
-  hipLaunchKernelGGL(prec_rows_fwd, dim3(prec_row_blocks(I)), dim3(kFftThreads), 0, s, f);
+  RowsFwdArgs f{a.in, a.spec, p->twiddle, I, a.fin, a.chan};
+  hipLaunchKernelGGL(prec_rows_fwd, dim3(prec_row_blocks(I)), dim3(kFftThreads), 0, s, f, a.fin_t,
+                     a.fin_eta);
   DG_LAUNCH_CHECK("prec_rows_fwd");
   ColsArgs c{a.spec, p->twiddle, I, a.dir};
   hipLaunchKernelGGL(prec_cols, dim3(prec_col_blocks(I)), dim3(kFftThreads), 0, s, c);
@@ -368,7 +375,7 @@ dg_status launch_precondition(const dg_plan* p, const PrecArgs& a, hipStream_t s
   RowsInvArgs r{a.spec, p->twiddle, I, a.epilogue, a.out, a.out_t, a.x, a.scal, a.partials};
   hipLaunchKernelGGL(prec_rows_inv, dim3(prec_row_blocks(I)), dim3(kFftThreads), 0, s, r);
   DG_LAUNCH_CHECK("prec_rows_inv");
-  if (a.epilogue == PREC_UPDATE_R)
+  if (a.epilogue == PREC_UPDATE_R && !a.eps_elsewhere)
     return launch_eps_finish(a.partials, prec_row_blocks(I), a.eps_rel, a.scal_out + DG_S_EPS, s);
   return DG_OK;
 }
