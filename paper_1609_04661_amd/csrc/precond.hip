@@ -64,6 +64,38 @@ __device__ __forceinline__ void fft_stage(const float2* src, float2* dst, int L,
       float2 a = v[0], b = v[1];
       v[0] = cadd(a, b);
       v[1] = csub(a, b);
+    } else if constexpr (R == 8) {
+      // radix 2 x 4: a_n = v_n + v_{n+4} gives the even outputs, b_n =
+      // (v_n - v_{n+4}) w8^n the odd ones, each through a 4-point DFT
+      const float r2 = 0.70710678118654752440f;
+      float2 a[4], b[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        a[q] = cadd(v[q], v[q + 4]);
+        b[q] = csub(v[q], v[q + 4]);
+      }
+      // b1 *= w8, b2 *= w8^2 = -/+ i, b3 *= w8^3 (forward w8 = (1 - i)/sqrt2)
+      {
+        const float2 t = b[1];
+        b[1] = inv ? make_float2(r2 * (t.x - t.y), r2 * (t.x + t.y))
+                   : make_float2(r2 * (t.x + t.y), r2 * (t.y - t.x));
+        b[2] = rot(b[2], inv);
+        const float2 u = b[3];
+        b[3] = inv ? make_float2(-r2 * (u.x + u.y), r2 * (u.x - u.y))
+                   : make_float2(r2 * (u.y - u.x), -r2 * (u.x + u.y));
+      }
+      float2 e0 = cadd(a[0], a[2]), e1 = csub(a[0], a[2]);
+      float2 e2 = cadd(a[1], a[3]), e3 = rot(csub(a[1], a[3]), inv);
+      float2 o0 = cadd(b[0], b[2]), o1 = csub(b[0], b[2]);
+      float2 o2 = cadd(b[1], b[3]), o3 = rot(csub(b[1], b[3]), inv);
+      v[0] = cadd(e0, e2);
+      v[4] = csub(e0, e2);
+      v[2] = cadd(e1, e3);
+      v[6] = csub(e1, e3);
+      v[1] = cadd(o0, o2);
+      v[5] = csub(o0, o2);
+      v[3] = cadd(o1, o3);
+      v[7] = csub(o1, o3);
     } else if constexpr (R == 4) {
       float2 a0 = cadd(v[0], v[2]), a1 = csub(v[0], v[2]);
       float2 b0 = cadd(v[1], v[3]), b1 = rot(csub(v[1], v[3]), inv);
@@ -89,9 +121,9 @@ __device__ __forceinline__ void fft_stage(const float2* src, float2* dst, int L,
 
 // In-LDS complex FFT of length L by one wavefront on buf0 (result in buf0),
 // scratch buf1, twiddles tw[j] = exp(-2 pi i j / L) in LDS.  Unnormalised;
-// the inverse uses conjugate twiddles.  Stockham autosort stages of radix 4
-// while possible, then 2, and the radix-3 stage (L = 3 * 2^a) last, so the
-// stride Ns is a power of two wherever it divides.
+// the inverse uses conjugate twiddles.  Stockham autosort stages of radix 8
+// while possible, then 4 and 2, and the radix-3 stage (L = 3 * 2^a) last, so
+// the stride Ns is a power of two wherever it divides.
 __device__ void wave_fft(float2* buf0, float2* buf1, int L, const float2* tw, bool inv) {
   const int lane = threadIdx.x & 63;
   float2* src = buf0;
@@ -99,7 +131,10 @@ __device__ void wave_fft(float2* buf0, float2* buf1, int L, const float2* tw, bo
   int Ns = 1, lgNs = 0, rem = L;
   while (rem > 1) {
     int R;
-    if (rem % 4 == 0) {
+    if (rem % 8 == 0) {
+      R = 8;
+      fft_stage<8>(src, dst, L, Ns, lgNs, tw, inv);
+    } else if (rem % 4 == 0) {
       R = 4;
       fft_stage<4>(src, dst, L, Ns, lgNs, tw, inv);
     } else if (rem % 2 == 0) {
@@ -114,7 +149,7 @@ __device__ void wave_fft(float2* buf0, float2* buf1, int L, const float2* tw, bo
     src = dst;
     dst = t;
     Ns *= R;
-    lgNs += (R == 4) ? 2 : 1;  // unused after the radix-3 stage
+    lgNs += (R == 8) ? 3 : ((R == 4) ? 2 : 1);  // unused after the radix-3 stage
     rem /= R;
   }
   if (src != buf0) {

@@ -118,8 +118,10 @@ def test_projector_edge_rays_half_weight(gpu_lib):
         assert sorted(set(np.round(out[out > 0], 12))) == [0.5]
 
 
-@pytest.mark.parametrize("I", [64, 96, 384, 512])
+@pytest.mark.parametrize("I", [8, 12, 64, 96, 256, 384, 512, 768, 1024])
 def test_precondition_matches_oracle(gpu_lib, I):
+    """Every stage mix of the wavefront FFT (radix 8/4/2, radix 3 last) and
+    row-workgroup tails (I not a multiple of 8)."""
     g = synth.geometry(synth.PARALLEL, I, 1.0, 4, I + 1, math.pi)
     P = gpu_lib.Plan(g)
     x = np.random.default_rng(I).standard_normal((I, I))
