@@ -183,6 +183,9 @@ def headline(api, synth, args, mu, results):
     work = plan.workspace(api.OP_DGAMP)
     mu_out = torch.empty((I, I), dtype=torch.float32, device="cuda")
     kw = dict(probe_seed=CFG["probe_seed"], eta_x=CFG["eta"], eta_s=CFG["eta"])
+    # the library's autotuner picks the projector's march segmentation for
+    # this geometry (untimed, before the warm-up)
+    results["projector_variant"] = plan.autotune(mu_d, mu_d.t().contiguous(), reps=10)
 
     def run(n, events=None, log=None, mask=0):
         st = api.DgampState(plan, CFG["tau_x0"])

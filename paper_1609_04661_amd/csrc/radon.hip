@@ -30,7 +30,7 @@ static constexpr int kBpBlockX = 64, kBpBlockY = 4;
 // the end of the buffer, which a raw buffer load returns as 0.  The accumulation order (k ascending,
 // candidate p0 before p0 + 1) and every weight are those of ray_weight, so
 // A and A^T stay exact transposes of one another.
-static constexpr int kMarch = 8;
+static constexpr int kMarch = 16;
 
 template <int SEGS>
 __device__ void project_body(const ProjArgs& A, int blk, float (*part)[kRaysPerBlock]) {
@@ -102,15 +102,21 @@ __device__ void project_body(const ProjArgs& A, int blk, float (*part)[kRaysPerB
     const __amdgpu_buffer_rsrc_t img =
         __builtin_amdgcn_make_buffer_rsrc((void*)lo, (short)0, (int)(unsigned)span, kBufferWord3);
     const unsigned skb = (unsigned)sk * 4u, spb = (unsigned)sp * 4u;
+    unsigned koff = boff + (unsigned)ka * skb;  // byte offset of major index k
+    uint32_t qlo = (uint32_t)(uint64_t)q, qhi = (uint32_t)((uint64_t)q >> 32);
+    const uint32_t mlo = (uint32_t)(uint64_t)L.m_fx, mhi = (uint32_t)((uint64_t)L.m_fx >> 32);
     for (int k = ka; k <= kb; k += kMarch) {
       float v[2 * kMarch], w[2 * kMarch];
 #pragma unroll
       for (int u = 0; u < kMarch; ++u) {
         const int kk = k + u;
-        int p0;
-        float f;
-        split_fx(q, &p0, &f);
-        q += L.m_fx;
+        // q in 32.32 fixed point as two words; advancing it is one add with
+        // carry, and floor(q), q - floor(q) are its words (split_fx)
+        const int p0 = (int)qhi;
+        const float f = (float)qlo * 2.3283064365386962890625e-10f;  // 2^-32
+        const uint32_t nlo = qlo + mlo;
+        qhi += mhi + (nlo < qlo ? 1u : 0u);
+        qlo = nlo;
         // chord_fraction's general branch, written out so both candidates of
         // all steps are formed before any load is consumed
         float g0 = fminf(fmaxf(__fmul_rn(hw - f, L.inv_r), 0.0f), 1.0f);
@@ -123,9 +129,12 @@ __device__ void project_body(const ProjArgs& A, int blk, float (*part)[kRaysPerB
         w[2 * u] = g0;
         w[2 * u + 1] = g1;
         const bool live = kk <= kb;
-        const unsigned o0 = boff + (unsigned)kk * skb + (unsigned)p0 * spb;
-        const unsigned off0 = (live && (unsigned)p0 < (unsigned)I) ? o0 : 0xffffffffu;
-        const unsigned off1 = (live && (unsigned)(p0 + 1) < (unsigned)I) ? o0 + spb : 0xffffffffu;
+        // 24-bit multiply (full rate): p0 + 1 lies in [0, I] whenever an
+        // offset is used; koff advances by skb per step
+        const unsigned o1 = koff + __umul24((unsigned)(p0 + 1), spb);
+        koff += skb;
+        const unsigned off0 = (live && (unsigned)p0 < (unsigned)I) ? o1 - spb : 0xffffffffu;
+        const unsigned off1 = (live && (unsigned)(p0 + 1) < (unsigned)I) ? o1 : 0xffffffffu;
         v[2 * u] = __int_as_float(__builtin_amdgcn_raw_buffer_load_b32(img, off0, 0, 0));
         v[2 * u + 1] = __int_as_float(__builtin_amdgcn_raw_buffer_load_b32(img, off1, 0, 0));
       }
