@@ -233,3 +233,72 @@ def test_batch_autotune_keeps_results(gpu_lib, data):
     B.state_init(1.0)
     B.iterate(N_ITER, probe_seed=SEED, eta_x=ETA, eta_s=ETA, write_mu=True)
     check_slices_equal(api, B, data, mu_out, singles)
+
+
+def _phantom(n, seed, pixel_mm=1.0, inserts=0):
+    return synth.ellipse_phantom(n, seed, pixel_mm=pixel_mm, inserts=inserts).astype(np.float32)
+
+
+def _full_size_inputs(api, slices):
+    """Counts from the library's projector (the oracle projector is too slow
+    at these sizes for a parity test), fro2 by Hutchinson with 8 probes."""
+    data = []
+    for s in slices:
+        g = s["geom"]
+        mu = _phantom(g["n"], s["seed"], g["pixel_mm"], s.get("inserts", 0))
+        P = api.Plan(g)
+        z = host(api.ct_project(P, torch.as_tensor(mu).cuda()))
+        y = synth.poisson_counts(z, s["i0"], s["seed"])
+        fro2 = float(api.dg_fro2_hutchinson(P, 8, 99).item())
+        data.append(dict(g=g, i0=s["i0"], mu=mu, y=y, plan=P, fro2=fro2))
+    return data
+
+
+def test_uneven_batch_full_sizes_equal_single_slices(gpu_lib):
+    """Eight slices of the 64-slice uneven workload at their real sizes
+    (sides 256/384/512, 32/64/128 views), NLM, 3 iterations with the
+    workload's damping: every slice equals its own single-slice run."""
+    api = gpu_lib
+    slices = synth.batch_slices(1003, 64)[:8]
+    data = _full_size_inputs(api, slices)
+    params = api.make_params(api.DEN_NLM)
+    B, y = make_batch(api, data)
+    mu_out = torch.empty(B.totN, dtype=torch.float32, device="cuda")
+    B.bind(y, [d["i0"] for d in data], [d["fro2"] for d in data], api.DEN_NLM, params, mu_out)
+    B.autotune(reps=2)
+    for d in data:
+        d["plan"].projector_variant = B.projector_variant
+    singles = [single_run(api, d, api.DEN_NLM, params, n_iter=3, eta=0.15) for d in data]
+    B.state_init(1.0)
+    B.iterate(3, probe_seed=SEED, eta_x=0.15, eta_s=0.15, write_mu=True)
+    check_slices_equal(api, B, data, mu_out, singles)
+
+
+def test_fan_lowdose_batch_full_size_learned_equals_single(gpu_lib):
+    """Two slices of the 16 x 1024^2 fan-beam low-dose workload (0.5 mm
+    pixels, 128 views over 360 degrees, I0 = 5e3, inserts) with the trained
+    CNN, 2 iterations: each equals its single-slice run, and both graph
+    replays equal the eager run."""
+    api = gpu_lib
+    import os
+    wpath = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))),
+                         "paper_1609_04661_amd", "weights", "cnn_c2_x_space.safetensors")
+    net = api.CnnNet.load_file(wpath)
+    slices = synth.c5_slices(1005, 2)
+    data = _full_size_inputs(api, slices)
+    singles = []
+    for d in data:
+        p1 = api.make_params(api.DEN_CNN, net=net, n_pixels=d["plan"].N)
+        singles.append(single_run(api, d, api.DEN_CNN, p1, n_iter=2, eta=0.15))
+    B, y = make_batch(api, data)
+    pb = api.make_params(api.DEN_CNN, net=net, n_pixels=B.totN)
+    mu_out = torch.empty(B.totN, dtype=torch.float32, device="cuda")
+    B.bind(y, [d["i0"] for d in data], [d["fro2"] for d in data], api.DEN_CNN, pb, mu_out)
+    B.state_init(1.0)
+    B.iterate(2, probe_seed=SEED, eta_x=0.15, eta_s=0.15, write_mu=True)
+    check_slices_equal(api, B, data, mu_out, singles)
+    G = B.graph(2, tau_x0=1.0, probe_seed=SEED, eta_x=0.15, eta_s=0.15)
+    for _ in range(2):
+        mu_out.zero_()
+        G.launch()
+        check_slices_equal(api, B, data, mu_out, singles)
