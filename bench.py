@@ -309,6 +309,49 @@ def learned_vs_plain(api, args, h):
     return res
 
 
+def ablation(api, h, T=50):
+    """Sec. 7 style variants on the headline inputs (NLM): the Onsager term
+    off, the damping the paper's toolbox runs used (eta_s 0.95, eta_x 0.65),
+    and Algorithm 1 undamped, beside the configured run.  For each: the final
+    PSNR, and how the variance the recursion predicts for x (tau_x) compares
+    with the actual error of x against x_true = V mu (state-evolution check),
+    as 10 log10(tau_x / MSE_x) averaged over iterations 5..T-1."""
+    import numpy as np
+    import torch
+    plan, y_d, fro2, mu_d, work = h["plan"], h["y_d"], h["fro2"], h["mu_d"], h["work"]
+    params = api.make_params(api.DEN_NLM, **CFG["nlm"])
+    x_true = torch.empty_like(mu_d)
+    api.ct_precondition(plan, -1, mu_d, out=x_true, work=plan.workspace(api.OP_PRECOND))
+    peak = max(float(x_true.max().item()), 0.0)
+    variants = {"configured": dict(eta_x=CFG["eta"], eta_s=CFG["eta"], onsager=True),
+                "no_onsager": dict(eta_x=CFG["eta"], eta_s=CFG["eta"], onsager=False),
+                "toolbox_damping": dict(eta_x=0.65, eta_s=0.95, onsager=True),
+                "undamped": dict(eta_x=1.0, eta_s=1.0, onsager=True)}
+    out = {}
+    mu_out = torch.empty((plan.I, plan.I), dtype=torch.float32, device="cuda")
+    for name, v in variants.items():
+        st = api.DgampState(plan, CFG["tau_x0"])
+        log = torch.zeros(T * api.LOG_STRIDE, dtype=torch.float64, device="cuda")
+        px = torch.empty(T, dtype=torch.float64, device="cuda")
+        for t in range(T):
+            api.dgamp_iterate(plan, y_d, st, 1, fro2, CFG["i0"], api.DEN_NLM, params,
+                              probe_seed=CFG["probe_seed"], eps_rel=1e-3,
+                              log=log[t * api.LOG_STRIDE:(t + 1) * api.LOG_STRIDE],
+                              mu_out=mu_out if t == T - 1 else None, work=work, **v)
+            api.dg_psnr(st.x, x_true, out=px[t:t + 1])
+        psnr_mu = float(api.dg_psnr(mu_out, mu_d).item())
+        L = log.view(T, api.LOG_STRIDE).cpu().numpy()
+        px = px.cpu().numpy()
+        with np.errstate(all="ignore"):
+            mse_x = peak * peak / np.power(10.0, px / 10.0)
+            gap = 10.0 * np.log10(L[:, api.S_TAU_X] / mse_x)
+        ok = np.isfinite(gap[5:])
+        out[name] = dict(psnr_db=psnr_mu, status=float(st.scal[api.S_STATUS].item()),
+                         se_gap_db_mean=float(np.mean(gap[5:][ok])) if ok.any() else None,
+                         se_gap_db_last=float(gap[-1]) if np.isfinite(gap[-1]) else None)
+    return out
+
+
 def run_batch(api, synth, slices, phantoms, den, T, reps, autotune, net=None):
     """One batch: counts from the library's projector, Hutchinson fro2 per
     slice, graph of the whole T-iteration run; returns timing and PSNRs."""
@@ -369,8 +412,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--only-headline", action="store_true",
                     help="skip the learned, batched and fan-beam figures")
-    ap.add_argument("--parts", default="headline,learned,batch,fan",
-                    help="comma-separated subset of headline,learned,batch,fan")
+    ap.add_argument("--parts", default="headline,learned,batch,fan,ablation",
+                    help="comma-separated subset of headline,learned,batch,fan,ablation")
     ap.add_argument("--learned-iters", type=int, default=50)
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="first copy this many MiB device-to-device 3 times (a kernel of known "
@@ -423,6 +466,9 @@ def main():
     if "learned" in parts:
         print("learned vs plain", file=sys.stderr, flush=True)
         res["learned_vs_plain"] = learned_vs_plain(api, args, h)
+    if "ablation" in parts:
+        print("ablation", file=sys.stderr, flush=True)
+        res["ablation"] = ablation(api, h)
     if "batch" in parts:
         print("batch_uneven", file=sys.stderr, flush=True)
         res["batch_uneven"] = run_batch(api, synth, c3, phantoms[1:1 + len(c3)], "nlm",

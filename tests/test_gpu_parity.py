@@ -221,12 +221,14 @@ def c1_inputs():
     return g, R, mu, y, fro2
 
 
-def run_gpu_dgamp(gpu_lib, plan, y, fro2, i0, T, kind, params, seed, eta, tau_x0=1.0):
+def run_gpu_dgamp(gpu_lib, plan, y, fro2, i0, T, kind, params, seed, eta, tau_x0=1.0,
+                  onsager=True, channel_mode=0):
     st = gpu_lib.DgampState(plan, tau_x0)
     mu = torch.empty((plan.I, plan.I), dtype=torch.float32, device="cuda")
     log = torch.zeros(T * gpu_lib.LOG_STRIDE, dtype=torch.float64, device="cuda")
     gpu_lib.dgamp_iterate(plan, cu(y), st, T, fro2, i0, kind, params, probe_seed=seed,
-                          eta_x=eta, eta_s=eta, mu_out=mu, log=log)
+                          eta_x=eta, eta_s=eta, onsager=onsager, channel_mode=channel_mode,
+                          mu_out=mu, log=log)
     return host(mu), host(log).reshape(T, gpu_lib.LOG_STRIDE), st
 
 
@@ -244,6 +246,24 @@ def test_dgamp_c1_psnr_matches_oracle(gpu_lib, plans):
     for t in range(3):
         for k, name in enumerate(("tau_p", "tau_s", "tau_r")):
             assert abs(log[t, k] - ref_log[t][name]) <= 1e-3 * abs(ref_log[t][name]), (t, name)
+
+
+@pytest.mark.parametrize("onsager,mode", [(False, 0), (True, 1)])
+def test_dgamp_variants_match_oracle(gpu_lib, plans, onsager, mode):
+    """The ablation variants through the same C ABI: Onsager term off, and the
+    mode-only channel (no Laplace moment corrections), each against the
+    oracle's run of the same variant (C1, Haar, 10 iterations)."""
+    g, R, mu, y, fro2 = c1_inputs()
+    T, eta, seed = 10, 0.5, 5
+    ref_mu, ref_log, _ = ogamp.dgamp_ct(R, y, 1e4, fro2, T, oden.HAAR, dict(alpha=1.5), seed,
+                                        onsager=onsager, channel_kind=mode, eta_x=eta, eta_s=eta)
+    out_mu, log, st = run_gpu_dgamp(gpu_lib, plans["c1"], y, fro2, 1e4, T, gpu_lib.DEN_HAAR,
+                                    gpu_lib.make_params(gpu_lib.DEN_HAAR, alpha=1.5), seed, eta,
+                                    onsager=onsager, channel_mode=mode)
+    assert float(host(st.scal)[gpu_lib.S_STATUS]) == 0.0
+    assert abs(metrics.psnr(out_mu, mu) - metrics.psnr(ref_mu, mu)) <= 0.1
+    for t in range(3):
+        assert abs(log[t, 2] - ref_log[t]["tau_r"]) <= 1e-3 * abs(ref_log[t]["tau_r"]), t
 
 
 def test_dgamp_deterministic(gpu_lib, plans):
