@@ -55,7 +55,7 @@ CFG = dict(i0=1e5, seed=1002, probe_seed=7, eta=0.15, tau_x0=1.0, fro2_probes=16
 # counter passes (FETCH_SIZE, WRITE_SIZE) scaled by a 256 MiB copy kernel
 # (profiles/dgamp_c2_512x512_64views_hbm_traffic.md).  Set to None whenever
 # that kernel changes until the counters are taken again.
-NLM_TRAFFIC_BYTES = 5.357e6
+NLM_TRAFFIC_BYTES = 5.365e6
 C3 = dict(seed=1003, slices=64, iters=30)
 C5 = dict(seed=1005, slices=16, iters=50)
 
