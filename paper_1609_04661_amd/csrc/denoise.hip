@@ -49,10 +49,12 @@ __device__ __forceinline__ int reflect_idx(int k, int I) {
 // column is read from LDS (8 + 2P values per offset instead of
 // (8 + 2P) (2 + 2P)); the ring slot of a column is static because the oj
 // loop is unrolled by the ring width.  Per offset the thread forms the
-// squared differences, box-sums them horizontally and then vertically with
-// sliding sums, and turns each sum into a weight.  The wavefronts' partial
+// differences, sums their squares along each row (the two outputs of a row
+// share the middle 2P squares, accumulated with fused multiply-adds), sums
+// those vertically with a sliding sum, and turns each sum into a weight.  The wavefronts' partial
 // sums are added in a fixed order at the end.
 static constexpr int kNlmBX = 2, kNlmBY = 8;
+static_assert(kNlmBX == 2, "the row sums below are written for two outputs per row");
 static constexpr int kNlmWaves = 7;  // 21 search rows (S = 10): 3 per wavefront
 static constexpr int kNlmThreads = 64 * kNlmWaves;
 template <int P>
@@ -148,19 +150,14 @@ __device__ void nlm_body(const NlmArgs& Ar, int bx, int by, int img, uint64_t se
           for (int a = 0; a < WY; ++a) {
             float d[WX];
 #pragma unroll
-            for (int c = 0; c < WX; ++c) {
-              const float dd = own[a][c] - win[a][(tau + c) % WX];
-              d[c] = dd * dd;
-            }
-            float sacc = 0.0f;
+            for (int c = 0; c < WX; ++c) d[c] = own[a][c] - win[a][(tau + c) % WX];
+            // the two outputs' row sums share the squares of d[1 .. 2P]:
+            // one multiply and 2P + 1 fused multiply-adds for both
+            float mid = d[1] * d[1];
 #pragma unroll
-            for (int q = 0; q <= 2 * P; ++q) sacc += d[q];
-            h[a][0] = sacc;
-#pragma unroll
-            for (int c = 1; c < BX; ++c) {
-              sacc += d[c + 2 * P] - d[c - 1];
-              h[a][c] = sacc;
-            }
+            for (int q = 2; q <= 2 * P; ++q) mid = __fmaf_rn(d[q], d[q], mid);
+            h[a][0] = __fmaf_rn(d[0], d[0], mid);
+            h[a][1] = __fmaf_rn(d[2 * P + 1], d[2 * P + 1], mid);
           }
 #pragma unroll
           for (int c = 0; c < BX; ++c) {

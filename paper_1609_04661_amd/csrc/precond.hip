@@ -22,6 +22,7 @@ static constexpr int kFftWaves = 4;                 // one FFT per wavefront
 static constexpr int kFftThreads = 64 * kFftWaves;
 static constexpr int kMaxFft = 1024;
 static constexpr int kRowsPerBlock = 2 * kFftWaves;  // real rows per row-pass workgroup
+static constexpr int kPerLane = kMaxFft / 64;        // row / column entries per lane
 
 __device__ __forceinline__ float2 cmul(float2 a, float2 b) {
   return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
@@ -181,16 +182,34 @@ __device__ void rows_fwd_body(const RowsFwdArgs& A, int blk, FftShared& S, int f
                               double fin_eta) {
   const int I = A.I, lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int half = I / 2 + 1;
+  const int m = blk * kFftWaves + w;
+  const bool live = 2 * m < I;
+  // the two rows go to registers first, so their loads are in flight while
+  // the twiddles are staged and the channel finish runs
+  float ra[kPerLane], rb[kPerLane];
+  if (live) {
+    const float* r0 = A.in + (int64_t)(2 * m) * I;
+    const float* r1 = r0 + I;
+#pragma unroll
+    for (int q = 0; q < kPerLane; ++q) {
+      const int t = lane + 64 * q;
+      if (t < I) {
+        ra[q] = r0[t];
+        rb[q] = r1[t];
+      }
+    }
+  }
   // the output channel's finish (tau_s, tau_r), saving it a launch of its own
   if (A.fin && blk == 0) channel_finish_body<true>(A.chan, fin_eta, fin_t, S.dred);
   load_twiddles(S, A.tw, I);
-  const int m = blk * kFftWaves + w;
   float2* a = S.buf[w][0];
   float2* b = S.buf[w][1];
-  if (2 * m < I) {
-    const float* r0 = A.in + (int64_t)(2 * m) * I;
-    const float* r1 = r0 + I;
-    for (int t = lane; t < I; t += 64) a[t] = make_float2(r0[t], r1[t]);
+  if (live) {
+#pragma unroll
+    for (int q = 0; q < kPerLane; ++q) {
+      const int t = lane + 64 * q;
+      if (t < I) a[t] = make_float2(ra[q], rb[q]);
+    }
     wave_sync();
     wave_fft(a, b, I, S.tw, false);
     for (int k = lane; k < half; k += 64) {
@@ -214,13 +233,27 @@ __device__ void rows_fwd_body(const RowsFwdArgs& A, int blk, FftShared& S, int f
 // column frequency kx = 4 blk + w.
 __device__ void cols_body(const ColsArgs& A, int blk, FftShared& S) {
   const int I = A.I, lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  load_twiddles(S, A.tw, I);
   const int kx = blk * kFftWaves + w;
-  if (kx > I / 2) return;
+  const bool live = kx <= I / 2;
+  float2* col = A.spec + (int64_t)kx * I;
+  // the column's loads are in flight while the twiddles are staged
+  float2 cv[kPerLane];
+  if (live) {
+#pragma unroll
+    for (int q = 0; q < kPerLane; ++q) {
+      const int t = lane + 64 * q;
+      if (t < I) cv[q] = col[t];
+    }
+  }
+  load_twiddles(S, A.tw, I);
+  if (!live) return;
   float2* a = S.buf[w][0];
   float2* b = S.buf[w][1];
-  float2* col = A.spec + (int64_t)kx * I;
-  for (int t = lane; t < I; t += 64) a[t] = col[t];
+#pragma unroll
+  for (int q = 0; q < kPerLane; ++q) {
+    const int t = lane + 64 * q;
+    if (t < I) a[t] = cv[q];
+  }
   wave_sync();
   wave_fft(a, b, I, S.tw, false);
   const float dc = 3.52549435174692f * (float)I;  // 4 ln(1 + sqrt 2) I
@@ -242,20 +275,43 @@ __device__ void cols_body(const ColsArgs& A, int blk, FftShared& S) {
 __device__ void rows_inv_body(const RowsInvArgs& A, int blk, FftShared& S) {
   const int I = A.I, lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int half = I / 2 + 1;
-  load_twiddles(S, A.tw, I);
-  for (int idx = threadIdx.x; idx < half * kRowsPerBlock; idx += blockDim.x) {
+  const int m = blk * kFftWaves + w;
+  const bool live = 2 * m < I;
+  const bool upd = A.epilogue == PREC_UPDATE_R;
+  // every global load of the workgroup (its spectrum block and, for the r
+  // update, its rows of x) is issued before the twiddles are staged
+  constexpr int kSpecPer = (kMaxFft / 2 + 1) * kRowsPerBlock / kFftThreads + 1;
+  float2 sv[kSpecPer];
+#pragma unroll
+  for (int q = 0; q < kSpecPer; ++q) {
+    const int idx = threadIdx.x + kFftThreads * q;
     const int k = idx >> 3, c = idx & 7;
     const int row = blk * kRowsPerBlock + c;
-    S.buf[c >> 1][1][(c & 1) * half + k] =
-        row < I ? A.spec[(int64_t)k * I + row] : make_float2(0.0f, 0.0f);
+    sv[q] = make_float2(0.0f, 0.0f);
+    if (idx < half * kRowsPerBlock && row < I) sv[q] = A.spec[(int64_t)k * I + row];
+  }
+  float xa[kPerLane], xb[kPerLane];
+  if (upd && live) {
+#pragma unroll
+    for (int q = 0; q < kPerLane; ++q) {
+      const int t = lane + 64 * q;
+      if (t < I) {
+        xa[q] = A.x[(int64_t)(2 * m) * I + t];
+        xb[q] = A.x[(int64_t)(2 * m + 1) * I + t];
+      }
+    }
+  }
+  load_twiddles(S, A.tw, I);
+#pragma unroll
+  for (int q = 0; q < kSpecPer; ++q) {
+    const int idx = threadIdx.x + kFftThreads * q;
+    const int k = idx >> 3, c = idx & 7;
+    if (idx < half * kRowsPerBlock) S.buf[c >> 1][1][(c & 1) * half + k] = sv[q];
   }
   __syncthreads();
-  const int m = blk * kFftWaves + w;
   float2* a = S.buf[w][0];
   float2* b = S.buf[w][1];
-  const bool live = 2 * m < I;
   const float scale = 1.0f / ((float)I * (float)I);
-  const bool upd = A.epilogue == PREC_UPDATE_R;
   const float tau_r = upd ? (float)A.scal[DG_S_TAU_R] : 0.0f;
   float amax = 0.0f;
   if (live) {
@@ -274,12 +330,15 @@ __device__ void rows_inv_body(const RowsInvArgs& A, int blk, FftShared& S) {
     }
     wave_sync();
     wave_fft(a, b, I, S.tw, true);
-    for (int t = lane; t < I; t += 64) {
+#pragma unroll
+    for (int q = 0; q < kPerLane; ++q) {
+      const int t = lane + 64 * q;
+      if (t >= I) continue;
       float v0 = a[t].x * scale, v1 = a[t].y * scale;
       const int64_t i0 = (int64_t)(2 * m) * I + t, i1 = i0 + I;
       if (upd) {
-        v0 = __fmaf_rn(tau_r, v0, A.x[i0]);
-        v1 = __fmaf_rn(tau_r, v1, A.x[i1]);
+        v0 = __fmaf_rn(tau_r, v0, xa[q]);
+        v1 = __fmaf_rn(tau_r, v1, xb[q]);
         amax = fmaxf(amax, fmaxf(fabsf(v0), fabsf(v1)));
       }
       A.out[i0] = v0;
