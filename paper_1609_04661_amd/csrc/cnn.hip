@@ -112,77 +112,92 @@ __global__ void cnn_pack_kernel(const float* __restrict__ m, char* __restrict__ 
 
 // ------------------------------------------------------------- layers
 
-// Input layer 1 -> 64.  Eight lanes per pixel: lane c8 computes output
-// channels 8 c8 .. 8 c8 + 7 and stores them as one 16-byte chunk, so a
-// wavefront writes 8 whole pixels (1 KiB) contiguously.  Each thread keeps
-// its 72 weights and 8 biases in registers and walks pixels with a grid
-// stride.
+// Input layer 1 -> 64 on v_mfma_f32_16x16x4_f32 (FP32 image, BF16-rounded
+// weights held as FP32, FP32 accumulation): a wavefront takes 16 pixels at a
+// time; M = 16 output channels (4 blocks), N = the 16 pixels, K = 4 taps
+// (3 steps cover the 9 taps, the rest zero).  Lane (l % 16, l / 16) loads
+// the input of pixel l % 16 at taps l / 16, 4 + l / 16, 8 (+ zeros) and
+// receives 4 channels of each block for pixel l % 16.
 //   mode 0: out = relu(conv(in) + b0)
-//   mode 1: out = conv(b) * (mask > 0), b the Rademacher probe (tangent pass)
+//   mode 2: also the tangent: out_t = conv(b) * (out > 0), b the Rademacher
+//           probe (same MFMAs on the probe values)
 __global__ void __launch_bounds__(256)
 cnn_in_kernel(const float* __restrict__ in, const void* __restrict__ packed,
-              const bf16* __restrict__ mask, bf16* __restrict__ out, int n, int H, int W,
-              int mode, uint64_t seed, int iter) {
+              bf16* __restrict__ out, bf16* __restrict__ out_t, int n, int H, int W, int mode,
+              uint64_t seed, int iter) {
   const Packed P = unpack(packed);
-  const int c8 = threadIdx.x & 7;
-  float w[8][9], b[8];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int lr = lane & 15, lq = lane >> 4;
+  const bool tng = mode == 2;
+  // row m of block ct computes channel 32 (ct / 2) + 8 (m / 4) + 4 (ct % 2) + m % 4,
+  // so that blocks 2P and 2P + 1 give a lane the 8 consecutive channels
+  // 32 P + 8 (l / 16) .. + 7 of its pixel: one 16-byte store
+  float wa[4][3];
+  floatx4 bias[4];
 #pragma unroll
-  for (int j = 0; j < 8; ++j) {
-    b[j] = mode == 0 ? P.b0[c8 * 8 + j] : 0.0f;
+  for (int ct = 0; ct < 4; ++ct) {
+    const int ch = 32 * (ct >> 1) + 8 * (lr >> 2) + 4 * (ct & 1) + (lr & 3);
 #pragma unroll
-    for (int t = 0; t < 9; ++t) w[j][t] = P.w0[(c8 * 8 + j) * 9 + t];
+    for (int s = 0; s < 3; ++s) {
+      const int tap = 4 * s + lq;
+      wa[ct][s] = tap < 9 ? P.w0[ch * 9 + tap] : 0.0f;
+    }
+#pragma unroll
+    for (int j = 0; j < 4; ++j) bias[ct][j] = P.b0[32 * (ct >> 1) + 8 * lq + 4 * (ct & 1) + j];
   }
   // 32-bit index arithmetic (the host limits a call to n H W < 2^31 pixels)
   const unsigned HW = (unsigned)H * (unsigned)W, npix = (unsigned)n * HW;
-  const unsigned stride = gridDim.x * (blockDim.x >> 3);
-  // whole 8-lane groups share a pixel, so they run the same iterations
-  for (unsigned pix = (blockIdx.x * blockDim.x + threadIdx.x) >> 3; pix < npix; pix += stride) {
-    const unsigned img = pix / HW;
-    const int rem = (int)(pix - img * HW);
+  const unsigned ngroups = (npix + 15) / 16;
+  for (unsigned grp = blockIdx.x * 4 + wave; grp < ngroups; grp += gridDim.x * 4) {
+    const unsigned pix = grp * 16 + lr;
+    const bool live = pix < npix;
+    const unsigned img = live ? pix / HW : 0;
+    const int rem = live ? (int)(pix - img * HW) : 0;
     const int y = rem / W, x = rem - y * W;
-    float v[9];
-    if (mode == 0) {
+    float v[3], pb[3];
 #pragma unroll
-      for (int t = 0; t < 9; ++t) {
-        const int yy = y + t / 3 - 1, xx = x + t % 3 - 1;
-        v[t] = (yy >= 0 && yy < H && xx >= 0 && xx < W) ? in[(int64_t)img * HW + yy * W + xx]
-                                                        : 0.0f;
+    for (int s = 0; s < 3; ++s) {
+      const int tap = 4 * s + lq;
+      const int yy = y + tap / 3 - 1, xx = x + tap % 3 - 1;
+      const bool ok = live && tap < 9 && yy >= 0 && yy < H && xx >= 0 && xx < W;
+      v[s] = ok ? in[(int64_t)img * HW + yy * W + xx] : 0.0f;
+      pb[s] = 0.0f;
+      if (tng && ok) pb[s] = probe_sign(seed, iter, (uint64_t)((int64_t)yy * W + xx));
+    }
+#pragma unroll
+    for (int P2 = 0; P2 < 2; ++P2) {
+      bf16x8 o8, t8;
+#pragma unroll
+      for (int b = 0; b < 2; ++b) {
+        const int ct = 2 * P2 + b;
+        floatx4 cf = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+        for (int s = 0; s < 3; ++s)
+          cf = __builtin_amdgcn_mfma_f32_16x16x4f32(wa[ct][s], v[s], cf, 0, 0, 0);
+#pragma unroll
+        for (int j = 0; j < 4; ++j) o8[4 * b + j] = (bf16)fmaxf(cf[j] + bias[ct][j], 0.0f);
+        if (tng) {
+          floatx4 tf = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+          for (int s = 0; s < 3; ++s)
+            tf = __builtin_amdgcn_mfma_f32_16x16x4f32(wa[ct][s], pb[s], tf, 0, 0, 0);
+#pragma unroll
+          for (int j = 0; j < 4; ++j)
+            t8[4 * b + j] = (bf16)(((float)o8[4 * b + j] > 0.0f) ? tf[j] : 0.0f);
+        }
       }
-    } else {
-      // probe values of the 9 neighbours: lane c8 hashes tap c8, every lane
-      // tap 8; taps 0..7 are shared within the 8-lane group
-      auto probe_at = [&](int t) {
-        const int yy = y + t / 3 - 1, xx = x + t % 3 - 1;
-        return (yy >= 0 && yy < H && xx >= 0 && xx < W)
-                   ? probe_sign(seed, iter, (uint64_t)((int64_t)yy * W + xx))
-                   : 0.0f;
-      };
-      const float pv = probe_at(c8);
-#pragma unroll
-      for (int t = 0; t < 8; ++t) v[t] = __shfl(pv, t, 8);
-      v[8] = probe_at(8);
+      // this lane's output column is pixel grp * 16 + lr (= pix)
+      if (live) {
+        *(bf16x8*)(out + (int64_t)pix * kC + 32 * P2 + 8 * lq) = o8;
+        if (tng) *(bf16x8*)(out_t + (int64_t)pix * kC + 32 * P2 + 8 * lq) = t8;
+      }
     }
-    bf16x8 mk;
-    if (mode != 0) mk = *(const bf16x8*)(mask + (int64_t)pix * kC + c8 * 8);
-    bf16x8 pk;
-#pragma unroll
-    for (int j = 0; j < 8; ++j) {
-      float acc = b[j];
-#pragma unroll
-      for (int t = 0; t < 9; ++t) acc = __fmaf_rn(w[j][t], v[t], acc);
-      if (mode == 0)
-        acc = fmaxf(acc, 0.0f);
-      else
-        acc = ((float)mk[j] > 0.0f) ? acc : 0.0f;
-      pk[j] = (bf16)acc;
-    }
-    *(bf16x8*)(out + (int64_t)pix * kC + c8 * 8) = pk;
   }
 }
 
 static unsigned int in_grid(int64_t npix) {
-  const int64_t g = (npix * 8 + 255) / 256;
-  return (unsigned int)(g < 2048 ? g : 2048);
+  const int64_t g = (npix + 63) / 64;  // four 16-pixel groups per workgroup
+  return (unsigned int)(g < 4096 ? g : 4096);
 }
 
 // 64 -> 64 layer on MFMA.
@@ -211,6 +226,16 @@ static constexpr int kHaloChunks = kMidHH * kMidHW * 8;
 static constexpr int kHaloRounds = (kHaloChunks + kMidThreads - 1) / kMidThreads;
 
 __device__ __forceinline__ int swz(int row, int chunk) { return (row << 3) + (chunk ^ (row & 7)); }
+
+// Output-channel order of the MFMA blocks: row m of block ct (LDS weight row
+// 16 ct + m of a tap) computes channel 32 (ct / 2) + 8 (m / 4) + 4 (ct % 2)
+// + m % 4, so blocks 2P and 2P + 1 give a lane (l % 16, l / 16) the 8
+// consecutive channels 32 P + 8 (l / 16) .. + 7 of its pixel (one 16-byte
+// store).  w_row maps a packed weight row (tap, channel) to its LDS row.
+__device__ __forceinline__ int w_row(int row) {
+  const int tap = row >> 6, co = row & 63;
+  return tap * 64 + (2 * (co >> 5) + ((co >> 2) & 1)) * 16 + 4 * ((co >> 3) & 3) + (co & 3);
+}
 
 __host__ __device__ inline int mid_tiles(int n, int H, int W) {
   return n * ((H + kMidTH - 1) / kMidTH) * ((W + kMidTW - 1) / kMidTW);
@@ -275,7 +300,7 @@ cnn_mid_kernel(const bf16* __restrict__ in, const bf16* __restrict__ Wt,
 #pragma unroll
     for (int q = 0; q < kRounds; ++q) {
       const int e = q * kMidThreads + threadIdx.x;
-      sW[swz(e >> 3, e & 7)] = wr[q];
+      sW[swz(w_row(e >> 3), e & 7)] = wr[q];
     }
   }
   if (tile < ntiles) halo_store(sX, hr);
@@ -311,8 +336,9 @@ cnn_mid_kernel(const bf16* __restrict__ in, const bf16* __restrict__ Wt,
                 __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[ct], bfr[rr], acc[rr][ct], 0, 0, 0);
       }
     }
-    // C layout: lane holds pixel column lr, output channels ct*16 + 4*lq + j.
-    bf16x4 m4[kMidRows][4];
+    // C layout: lane holds pixel column lr; blocks 2P, 2P + 1 hold its
+    // channels 32 P + 8 lq .. + 7 (see w_row)
+    bf16x8 m8[kMidRows][2];
     if (MODE != 0) {
 #pragma unroll
       for (int rr = 0; rr < kMidRows; ++rr) {
@@ -320,8 +346,8 @@ cnn_mid_kernel(const bf16* __restrict__ in, const bf16* __restrict__ Wt,
         const bool ok = yy < H && xx < W;
         const int64_t pbase = (ibase + (int64_t)(ok ? yy : 0) * W + (ok ? xx : 0)) * kC;
 #pragma unroll
-        for (int ct = 0; ct < 4; ++ct)
-          m4[rr][ct] = *(const bf16x4*)(mask + pbase + ct * 16 + lq * 4);
+        for (int P2 = 0; P2 < 2; ++P2)
+          m8[rr][P2] = *(const bf16x8*)(mask + pbase + 32 * P2 + 8 * lq);
       }
     }
 #pragma unroll
@@ -330,17 +356,21 @@ cnn_mid_kernel(const bf16* __restrict__ in, const bf16* __restrict__ Wt,
       if (yy >= H || xx >= W) continue;
       const int64_t pbase = (ibase + (int64_t)yy * W + xx) * kC;
 #pragma unroll
-      for (int ct = 0; ct < 4; ++ct) {
-        bf16x4 o4;
-        const floatx4 b4 = (MODE == 0) ? sB[ct * 4 + lq] : floatx4{0.0f, 0.0f, 0.0f, 0.0f};
+      for (int P2 = 0; P2 < 2; ++P2) {
+        bf16x8 o8;
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-          if (MODE == 0)
-            o4[j] = (bf16)fmaxf(acc[rr][ct][j] + b4[j], 0.0f);
-          else
-            o4[j] = (bf16)(((float)m4[rr][ct][j] > 0.0f) ? acc[rr][ct][j] : 0.0f);
+        for (int b = 0; b < 2; ++b) {
+          const int ct = 2 * P2 + b;
+          const floatx4 b4 = (MODE == 0) ? sB[8 * P2 + 2 * lq + b] : floatx4{0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+          for (int j = 0; j < 4; ++j) {
+            if (MODE == 0)
+              o8[4 * b + j] = (bf16)fmaxf(acc[rr][ct][j] + b4[j], 0.0f);
+            else
+              o8[4 * b + j] = (bf16)(((float)m8[rr][P2][4 * b + j] > 0.0f) ? acc[rr][ct][j] : 0.0f);
+          }
         }
-        *(bf16x4*)(out + pbase + ct * 16 + lq * 4) = o4;
+        *(bf16x8*)(out + pbase + 32 * P2 + 8 * lq) = o8;
       }
     }
     if (next < ntiles) {
@@ -359,36 +389,201 @@ static unsigned int mid_grid(int n, int H, int W) {
   return (unsigned int)(t < 256 ? t : 256);
 }
 
+// The forward layer and its tangent in one pass (denoiser inference):
+//   out  = relu(conv(in, Wl) + bl)
+//   outt = conv(int, Wl) * (out > 0)
+// Same K order and MFMA as cnn_mid_kernel, so both outputs are bitwise those
+// of the two separate passes; the tangent's ReLU pattern comes from the
+// forward result in registers instead of a reread of the stored activation,
+// and every weight fragment read from LDS feeds both images.  Tiles are
+// 16 x 16 (two halos of 18 x 18 pixels x 64 channels next to the 72 KiB of
+// weights); wavefront w computes tile rows 2w, 2w + 1 of both images.
+static constexpr int kDualT = 16, kDualH = kDualT + 2;
+static constexpr int kDualRows = kDualT / kMidWaves;                // 2
+static constexpr int kDualChunks = kDualH * kDualH * 8;            // per image
+static constexpr int kDualRounds = (2 * kDualChunks + kMidThreads - 1) / kMidThreads;
+
+__host__ __device__ inline int dual_tiles(int n, int H, int W) {
+  return n * ((H + kDualT - 1) / kDualT) * ((W + kDualT - 1) / kDualT);
+}
+
+__device__ __forceinline__ void dual_fetch(const bf16* __restrict__ in0, const bf16* __restrict__ in1,
+                                           int tile, int tiles_x, int tiles_y, int H, int W,
+                                           bf16x8 (&hr)[kDualRounds]) {
+  const int img = tile / (tiles_x * tiles_y);
+  const int trem = tile % (tiles_x * tiles_y);
+  const int y0 = (trem / tiles_x) * kDualT - 1, x0 = (trem % tiles_x) * kDualT - 1;
+  const int64_t off = ((int64_t)img * H * W + (int64_t)y0 * W + x0) * kC;
+  const bool interior = y0 >= 0 && x0 >= 0 && y0 + kDualH <= H && x0 + kDualH <= W;
+#pragma unroll
+  for (int q = 0; q < kDualRounds; ++q) {
+    const int e = q * kMidThreads + threadIdx.x;
+    const int which = e >= kDualChunks;
+    const int e2 = e - which * kDualChunks;
+    const int pix = e2 >> 3, ch = e2 & 7;
+    const int hy = pix / kDualH, hx = pix - hy * kDualH;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) hr[q][j] = (bf16)0.0f;
+    const bool inb = e < 2 * kDualChunks &&
+                     (interior || ((unsigned)(y0 + hy) < (unsigned)H && (unsigned)(x0 + hx) < (unsigned)W));
+    if (inb) hr[q] = *(const bf16x8*)((which ? in1 : in0) + off + ((int64_t)hy * W + hx) * kC + ch * 8);
+  }
+}
+
+__device__ __forceinline__ void dual_store(bf16x8* sX, const bf16x8 (&hr)[kDualRounds]) {
+#pragma unroll
+  for (int q = 0; q < kDualRounds; ++q) {
+    const int e = q * kMidThreads + threadIdx.x;
+    const int which = e >= kDualChunks;
+    const int e2 = e - which * kDualChunks;
+    if (e < 2 * kDualChunks) sX[which * kDualChunks + swz(e2 >> 3, e2 & 7)] = hr[q];
+  }
+}
+
+__global__ void __launch_bounds__(kMidThreads)
+cnn_mid_dual_kernel(const bf16* __restrict__ in, const bf16* __restrict__ int_,
+                    const bf16* __restrict__ Wt, const float* __restrict__ bias,
+                    bf16* __restrict__ out, bf16* __restrict__ outt, int n, int H, int W) {
+  __shared__ bf16x8 sW[9 * 64 * 8];          // [tap][co] rows of 8 chunks
+  __shared__ bf16x8 sX[2 * kDualChunks];     // two halos, [image][pixel] rows of 8 chunks
+  __shared__ floatx4 sB[16];
+  const int tiles_x = (W + kDualT - 1) / kDualT, tiles_y = (H + kDualT - 1) / kDualT;
+  const int ntiles = n * tiles_x * tiles_y;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int lr = lane & 15, lq = lane >> 4;
+  bf16x8 hr[kDualRounds];
+  int tile = blockIdx.x;
+  {
+    constexpr int kRounds = 9 * 64 * 8 / kMidThreads;
+    bf16x8 wr[kRounds];
+#pragma unroll
+    for (int q = 0; q < kRounds; ++q)
+      wr[q] = *(const bf16x8*)(Wt + (int64_t)(q * kMidThreads + threadIdx.x) * 8);
+    if (tile < ntiles) dual_fetch(in, int_, tile, tiles_x, tiles_y, H, W, hr);
+    if (threadIdx.x < 16)
+      sB[threadIdx.x] = floatx4{bias[threadIdx.x * 4], bias[threadIdx.x * 4 + 1],
+                                bias[threadIdx.x * 4 + 2], bias[threadIdx.x * 4 + 3]};
+#pragma unroll
+    for (int q = 0; q < kRounds; ++q) {
+      const int e = q * kMidThreads + threadIdx.x;
+      sW[swz(w_row(e >> 3), e & 7)] = wr[q];
+    }
+  }
+  if (tile < ntiles) dual_store(sX, hr);
+  __syncthreads();
+  for (; tile < ntiles; tile += gridDim.x) {
+    const int img = tile / (tiles_x * tiles_y);
+    const int trem = tile % (tiles_x * tiles_y);
+    const int y0 = (trem / tiles_x) * kDualT, x0 = (trem % tiles_x) * kDualT;
+    const int64_t ibase = (int64_t)img * H * W;
+    const int next = tile + gridDim.x;
+    floatx4 acc[2][kDualRows][4];
+#pragma unroll
+    for (int m = 0; m < 2; ++m)
+#pragma unroll
+      for (int a = 0; a < kDualRows; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) acc[m][a][b] = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+    for (int tap = 0; tap < 9; ++tap) {
+      const int ty = tap / 3, tx = tap % 3;
+#pragma unroll
+      for (int half = 0; half < 2; ++half) {
+        const int chunk = half * 4 + lq;
+        bf16x8 af[4], bfr[2][kDualRows];
+#pragma unroll
+        for (int ct = 0; ct < 4; ++ct) af[ct] = sW[swz(tap * 64 + ct * 16 + lr, chunk)];
+#pragma unroll
+        for (int m = 0; m < 2; ++m)
+#pragma unroll
+          for (int rr = 0; rr < kDualRows; ++rr)
+            bfr[m][rr] = sX[m * kDualChunks +
+                            swz((wave * kDualRows + rr + ty) * kDualH + lr + tx, chunk)];
+#pragma unroll
+        for (int m = 0; m < 2; ++m)
+#pragma unroll
+          for (int rr = 0; rr < kDualRows; ++rr)
+#pragma unroll
+            for (int ct = 0; ct < 4; ++ct)
+              acc[m][rr][ct] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[ct], bfr[m][rr],
+                                                                       acc[m][rr][ct], 0, 0, 0);
+      }
+    }
+#pragma unroll
+    for (int rr = 0; rr < kDualRows; ++rr) {
+      const int yy = y0 + wave * kDualRows + rr, xx = x0 + lr;
+      if (yy >= H || xx >= W) continue;
+      const int64_t pbase = (ibase + (int64_t)yy * W + xx) * kC;
+#pragma unroll
+      for (int P2 = 0; P2 < 2; ++P2) {
+        bf16x8 o8, t8;
+#pragma unroll
+        for (int b = 0; b < 2; ++b) {
+          const int ct = 2 * P2 + b;
+          const floatx4 b4 = sB[8 * P2 + 2 * lq + b];
+#pragma unroll
+          for (int j = 0; j < 4; ++j) {
+            o8[4 * b + j] = (bf16)fmaxf(acc[0][rr][ct][j] + b4[j], 0.0f);
+            t8[4 * b + j] = (bf16)(((float)o8[4 * b + j] > 0.0f) ? acc[1][rr][ct][j] : 0.0f);
+          }
+        }
+        *(bf16x8*)(out + pbase + 32 * P2 + 8 * lq) = o8;
+        *(bf16x8*)(outt + pbase + 32 * P2 + 8 * lq) = t8;
+      }
+    }
+    if (next < ntiles) {
+      dual_fetch(in, int_, next, tiles_x, tiles_y, H, W, hr);
+      __syncthreads();  // every wavefront is done reading this tile's halos
+      dual_store(sX, hr);
+      __syncthreads();
+    }
+  }
+}
+
+static unsigned int dual_grid(int n, int H, int W) {
+  const int t = dual_tiles(n, H, W);
+  return (unsigned int)(t < 256 ? t : 256);
+}
+
 // Output layer 64 -> 1, 16 x 16 output tiles (grid stride).  Pass 1: for
-// every pixel q of the 18 x 18 halo, d_t(q) = act[q] . w9[t] for the 9 taps
-// t, eight lanes per pixel (8 channels each, coalesced 16-byte loads)
-// reduced across the eight lanes; pass 2: f(p) = b9 + sum_t d_t(p + off_t).
+// every pixel q of the 18 x 18 halo, the 9 tap dot products
+// d_t(q) = act[q] . w9[t] on v_mfma_f32_16x16x32_bf16 (M = 16 tap rows of
+// which 9 are used, N = 16 halo pixels, K = 2 x 32 channels; the B fragment
+// of a lane is one 16-byte channel chunk of one pixel, as stored), into LDS;
+// pass 2: f(p) = b9 + sum_t d_t(p + off_t).  All halo loads of a tile are
+// issued before the first is used.
 //   mode 0 (primal):   out = r - (conv(act) + b9)
-//   mode 1 (tangent):  out = xden + eps * (b - conv(act)), so that
-//                      b^T (out - xden) / (N eps) = b^T J_D b / N
 //   mode 2 (training): f = conv(act) + b9; res = r - f - clean;
 //                      out = g_f = -2 res / count; loss partial per block
+//   mode 3 (denoiser with its tangent): out = r - (conv(act) + b9) and
+//                      out2 = out + eps (b - conv(actt)), so that
+//                      b^T (out2 - out) / (N eps) = b^T J_D b / N
 static constexpr int kOutT = 16, kOutH = kOutT + 2;
+static constexpr int kOutGroups = (kOutH * kOutH + 15) / 16;  // 16-pixel groups per halo
+static constexpr int kOutPerWave = (2 * kOutGroups + 3) / 4;   // both images, 4 wavefronts
 
 __host__ __device__ inline int out_tiles(int n, int H, int W) {
   return n * ((H + kOutT - 1) / kOutT) * ((W + kOutT - 1) / kOutT);
 }
 
 __global__ void __launch_bounds__(256)
-cnn_out_kernel(const bf16* __restrict__ act, const void* __restrict__ packed,
-               const float* __restrict__ r, const float* __restrict__ xden,
-               const float* __restrict__ clean, float* __restrict__ out, int n, int H, int W,
-               int mode, const double* __restrict__ eps_ptr, int eps_stride, uint64_t seed,
-               int iter, double* __restrict__ loss_partials, double inv_count) {
-  __shared__ float sd[kOutH * kOutH][9];
+cnn_out_kernel(const bf16* __restrict__ act, const bf16* __restrict__ actt,
+               const void* __restrict__ packed, const float* __restrict__ r,
+               const float* __restrict__ clean, float* __restrict__ out, float* __restrict__ out2,
+               int n, int H, int W, int mode, const double* __restrict__ eps_ptr, int eps_stride,
+               uint64_t seed, int iter, double* __restrict__ loss_partials, double inv_count) {
+  __shared__ float sd[2][kOutH * kOutH][9];
   __shared__ double red[4];
   const Packed P = unpack(packed);
-  const int c8 = threadIdx.x & 7;
-  float wv[9][8];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int lr = lane & 15, lq = lane >> 4;
+  bf16x8 wa[2];  // A fragments: tap lr (zero beyond 8), channel chunks lq and 4 + lq
 #pragma unroll
-  for (int t = 0; t < 9; ++t)
+  for (int h = 0; h < 2; ++h)
 #pragma unroll
-    for (int j = 0; j < 8; ++j) wv[t][j] = P.w9[t * 64 + c8 * 8 + j];
+    for (int j = 0; j < 8; ++j)
+      wa[h][j] = (bf16)(lr < 9 ? P.w9[lr * 64 + (h * 4 + lq) * 8 + j] : 0.0f);
+  const int ntask = (mode == 3 ? 2 : 1) * kOutGroups;
   const int tiles_x = (W + kOutT - 1) / kOutT, tiles_y = (H + kOutT - 1) / kOutT;
   const int ntiles = n * tiles_x * tiles_y;
   const int64_t HW = (int64_t)H * W;
@@ -398,49 +593,62 @@ cnn_out_kernel(const bf16* __restrict__ act, const void* __restrict__ packed,
     const int trem = tile % (tiles_x * tiles_y);
     const int y0 = (trem / tiles_x) * kOutT, x0 = (trem % tiles_x) * kOutT;
     const int64_t ibase = (int64_t)img * HW;
-    __syncthreads();  // the previous tile's pass 2 is done with sd
-    // c8 = e & 7 stays the thread's own channel group (256 is a multiple of 8)
-    for (int e = threadIdx.x; e < kOutH * kOutH * 8; e += blockDim.x) {
-      const int q = e >> 3;
+    bf16x8 hv[kOutPerWave][2];
+#pragma unroll
+    for (int k = 0; k < kOutPerWave; ++k) {
+      const int task = wave + 4 * k;
+      const int which = task >= kOutGroups;
+      const int q = (task - which * kOutGroups) * 16 + lr;
       const int yy = y0 - 1 + q / kOutH, xx = x0 - 1 + q % kOutH;
-      float part[9];
 #pragma unroll
-      for (int t = 0; t < 9; ++t) part[t] = 0.0f;
-      if (yy >= 0 && yy < H && xx >= 0 && xx < W) {
-        const bf16x8 a = *(const bf16x8*)(act + (ibase + (int64_t)yy * W + xx) * kC + c8 * 8);
+      for (int h = 0; h < 2; ++h)
 #pragma unroll
-        for (int j = 0; j < 8; ++j) {
-          const float av = (float)a[j];
-#pragma unroll
-          for (int t = 0; t < 9; ++t) part[t] = __fmaf_rn(wv[t][j], av, part[t]);
-        }
+        for (int j = 0; j < 8; ++j) hv[k][h][j] = (bf16)0.0f;
+      if (task < ntask && q < kOutH * kOutH && yy >= 0 && yy < H && xx >= 0 && xx < W) {
+        const bf16* src = (which ? actt : act) + (ibase + (int64_t)yy * W + xx) * kC;
+        hv[k][0] = *(const bf16x8*)(src + lq * 8);
+        hv[k][1] = *(const bf16x8*)(src + (4 + lq) * 8);
       }
+    }
+    __syncthreads();  // the previous tile's pass 2 is done with sd
 #pragma unroll
-      for (int t = 0; t < 9; ++t) {
-        float v = part[t];
-        v += __shfl_xor(v, 1, 8);
-        v += __shfl_xor(v, 2, 8);
-        v += __shfl_xor(v, 4, 8);
-        if (c8 == 0) sd[q][t] = v;
+    for (int k = 0; k < kOutPerWave; ++k) {
+      const int task = wave + 4 * k;
+      if (task >= ntask) break;  // wavefront-uniform
+      const int which = task >= kOutGroups;
+      const int q = (task - which * kOutGroups) * 16 + lr;
+      floatx4 d = {0.0f, 0.0f, 0.0f, 0.0f};
+      d = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wa[0], hv[k][0], d, 0, 0, 0);
+      d = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wa[1], hv[k][1], d, 0, 0, 0);
+      // this lane holds taps 4 lq .. 4 lq + 3 of halo pixel q
+      if (q < kOutH * kOutH) {
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+          if (4 * lq + j < 9) sd[which][q][4 * lq + j] = d[j];
       }
     }
     __syncthreads();
     const int ty = threadIdx.x / kOutT, tx = threadIdx.x % kOutT;
     const int y = y0 + ty, x = x0 + tx;
     if (y < H && x < W) {
-      float f = (mode == 1) ? 0.0f : P.b9[0];
+      float f = P.b9[0];
 #pragma unroll
-      for (int t = 0; t < 9; ++t) f += sd[(ty + t / 3) * kOutH + tx + t % 3][t];
+      for (int t = 0; t < 9; ++t) f += sd[0][(ty + t / 3) * kOutH + tx + t % 3][t];
       const int64_t rem = (int64_t)y * W + x, pix = ibase + rem;
-      if (mode == 0) {
-        out[pix] = r[pix] - f;
-      } else if (mode == 1) {
-        const float b = probe_sign(seed, iter, (uint64_t)rem);
-        out[pix] = __fmaf_rn((float)eps_ptr[(int64_t)img * eps_stride], b - f, xden[pix]);
-      } else {
+      if (mode == 2) {
         const float res = r[pix] - f - clean[pix];
         lsum += (double)res * (double)res;
         out[pix] = (float)(-2.0 * (double)res * inv_count);
+      } else {
+        const float d0 = r[pix] - f;
+        out[pix] = d0;
+        if (mode == 3) {
+          float g = 0.0f;
+#pragma unroll
+          for (int t = 0; t < 9; ++t) g += sd[1][(ty + t / 3) * kOutH + tx + t % 3][t];
+          const float b = probe_sign(seed, iter, (uint64_t)rem);
+          out2[pix] = __fmaf_rn((float)eps_ptr[(int64_t)img * eps_stride], b - g, d0);
+        }
       }
     }
   }
@@ -738,7 +946,7 @@ static dg_status cnn_forward(const void* packed, const float* r, float* out, int
   const int64_t npix = (int64_t)n * H * W;
   DG_ARG_CHECK(npix < ((int64_t)1 << 31), "CNN: at most 2^31 - 1 pixels per call");
   hipLaunchKernelGGL(cnn_in_kernel, dim3(in_grid(npix)), dim3(256), 0, st, r, packed,
-                     (const bf16*)nullptr, w.act[0], n, H, W, 0, (uint64_t)0, 0);
+                     w.act[0], (bf16*)nullptr, n, H, W, 0, (uint64_t)0, 0);
   DG_LAUNCH_CHECK("cnn_in_kernel");
   const unsigned int tiles = mid_grid(n, H, W);
   for (int l = 0; l < kMid; ++l) {
@@ -748,38 +956,11 @@ static dg_status cnn_forward(const void* packed, const float* r, float* out, int
     DG_LAUNCH_CHECK("cnn_mid_kernel");
   }
   if (out) {
-    hipLaunchKernelGGL(cnn_out_kernel, dim3(out_grid(n, H, W)), dim3(256), 0, st, w.act[8], packed, r,
-                       (const float*)nullptr, (const float*)nullptr, out, n, H, W, 0,
-                       (const double*)nullptr, 0, (uint64_t)0, 0, (double*)nullptr, 0.0);
+    hipLaunchKernelGGL(cnn_out_kernel, dim3(out_grid(n, H, W)), dim3(256), 0, st, w.act[8],
+                       (const bf16*)nullptr, packed, r, (const float*)nullptr, out, (float*)nullptr,
+                       n, H, W, 0, (const double*)nullptr, 0, (uint64_t)0, 0, (double*)nullptr, 0.0);
     DG_LAUNCH_CHECK("cnn_out_kernel");
   }
-  return DG_OK;
-}
-
-// Tangent pass with the primal ReLU pattern: x_pert = x_den + eps (b - J_f b),
-// for n images (eps of image k at eps[k * eps_stride]).
-static dg_status cnn_tangent(const void* packed, const float* xden, float* xpert,
-                             const double* eps, int eps_stride, uint64_t seed, int iter, int n,
-                             int H, int W, CnnWork& w, hipStream_t st) {
-  const Packed P = unpack(packed);
-  const int64_t npix = (int64_t)n * H * W;
-  DG_ARG_CHECK(npix < ((int64_t)1 << 31), "CNN: at most 2^31 - 1 pixels per call");
-  hipLaunchKernelGGL(cnn_in_kernel, dim3(in_grid(npix)), dim3(256), 0, st, (const float*)nullptr,
-                     packed, w.act[0], w.tan[0], n, H, W, 1, seed, iter);
-  DG_LAUNCH_CHECK("cnn_in_kernel<tangent>");
-  const unsigned int tiles = mid_grid(n, H, W);
-  int cur = 0;
-  for (int l = 0; l < kMid; ++l) {
-    hipLaunchKernelGGL(cnn_mid_kernel<1>, dim3(tiles), dim3(kMidThreads), 0, st, w.tan[cur],
-                       P.wm + (size_t)l * 9 * 64 * 64, (const float*)nullptr, w.act[l + 1],
-                       w.tan[cur ^ 1], n, H, W);
-    DG_LAUNCH_CHECK("cnn_mid_kernel<tangent>");
-    cur ^= 1;
-  }
-  hipLaunchKernelGGL(cnn_out_kernel, dim3(out_grid(n, H, W)), dim3(256), 0, st, w.tan[cur], packed,
-                     (const float*)nullptr, xden, (const float*)nullptr, xpert, n, H, W, 1, eps,
-                     eps_stride, seed, iter, (double*)nullptr, 0.0);
-  DG_LAUNCH_CHECK("cnn_out_kernel<tangent>");
   return DG_OK;
 }
 
@@ -792,6 +973,33 @@ dg_status cnn_check_params(const dg_plan* p, const void* params) {
   return DG_OK;
 }
 
+// Denoiser and tangent together: x_den = r - f(r) and x_pert = x_den +
+// eps (b - J_f b) with every layer's forward and tangent in one launch.
+static dg_status cnn_denoise_dual(const void* packed, const float* r, float* xden, float* xpert,
+                                  const double* eps, int eps_stride, uint64_t seed, int iter, int n,
+                                  int H, int W, CnnWork& w, hipStream_t st) {
+  const Packed P = unpack(packed);
+  const int64_t npix = (int64_t)n * H * W;
+  DG_ARG_CHECK(npix < ((int64_t)1 << 31), "CNN: at most 2^31 - 1 pixels per call");
+  hipLaunchKernelGGL(cnn_in_kernel, dim3(in_grid(npix)), dim3(256), 0, st, r, packed, w.act[0],
+                     w.tan[0], n, H, W, 2, seed, iter);
+  DG_LAUNCH_CHECK("cnn_in_kernel<dual>");
+  const unsigned int tiles = dual_grid(n, H, W);
+  int cur = 0;
+  for (int l = 0; l < kMid; ++l) {
+    hipLaunchKernelGGL(cnn_mid_dual_kernel, dim3(tiles), dim3(kMidThreads), 0, st, w.act[l],
+                       w.tan[cur], P.wm + (size_t)l * 9 * 64 * 64, P.bm + l * 64, w.act[l + 1],
+                       w.tan[cur ^ 1], n, H, W);
+    DG_LAUNCH_CHECK("cnn_mid_dual_kernel");
+    cur ^= 1;
+  }
+  hipLaunchKernelGGL(cnn_out_kernel, dim3(out_grid(n, H, W)), dim3(256), 0, st, w.act[8],
+                     w.tan[cur], packed, r, (const float*)nullptr, xden, xpert, n, H, W, 3, eps,
+                     eps_stride, seed, iter, (double*)nullptr, 0.0);
+  DG_LAUNCH_CHECK("cnn_out_kernel<dual>");
+  return DG_OK;
+}
+
 dg_status cnn_launch_denoise(const dg_plan* p, const void* params, const float* r,
                              const double* eps, uint64_t seed, int iter, float* x_den,
                              float* x_pert, double* div_dot_out, hipStream_t st) {
@@ -799,9 +1007,8 @@ dg_status cnn_launch_denoise(const dg_plan* p, const void* params, const float* 
   const dg_cnn_params* cp = (const dg_cnn_params*)params;
   CnnWork w;
   cnn_work_layout((int64_t)p->N, cp->work, &w);
-  dg_status rc = cnn_forward(cp->weights, r, x_den, 1, p->I, p->I, w, st);
-  if (rc != DG_OK || !x_pert) return rc;
-  return cnn_tangent(cp->weights, x_den, x_pert, eps, 0, seed, iter, 1, p->I, p->I, w, st);
+  if (!x_pert) return cnn_forward(cp->weights, r, x_den, 1, p->I, p->I, w, st);
+  return cnn_denoise_dual(cp->weights, r, x_den, x_pert, eps, 0, seed, iter, 1, p->I, p->I, w, st);
 }
 
 // n slices of one image size, stored back to back (r, x_den, x_pert); the
@@ -812,9 +1019,8 @@ dg_status cnn_launch_denoise_batch(const void* params, const float* r, const dou
   const dg_cnn_params* cp = (const dg_cnn_params*)params;
   CnnWork w;
   cnn_work_layout((int64_t)n * I * I, cp->work, &w);
-  dg_status rc = cnn_forward(cp->weights, r, x_den, n, I, I, w, st);
-  if (rc != DG_OK) return rc;
-  return cnn_tangent(cp->weights, x_den, x_pert, scal_eps, eps_stride, seed, iter, n, I, I, w, st);
+  return cnn_denoise_dual(cp->weights, r, x_den, x_pert, scal_eps, eps_stride, seed, iter, n, I, I,
+                          w, st);
 }
 
 }  // namespace dg
@@ -860,9 +1066,9 @@ extern "C" dg_status dg_cnn_train_step(const float* noisy, const float* clean, i
   // loss and dL/df
   const unsigned int gb = g256(npix);
   const unsigned int ot = out_grid(n, h, w);
-  hipLaunchKernelGGL(cnn_out_kernel, dim3(ot), dim3(256), 0, st, cw.act[8], packed, noisy,
-                     (const float*)nullptr, clean, cw.f, n, h, w, 2, (const double*)nullptr, 0,
-                     (uint64_t)0, 0, cw.dpart, 1.0 / (double)npix);
+  hipLaunchKernelGGL(cnn_out_kernel, dim3(ot), dim3(256), 0, st, cw.act[8], (const bf16*)nullptr,
+                     packed, noisy, clean, cw.f, (float*)nullptr, n, h, w, 2, (const double*)nullptr,
+                     0, (uint64_t)0, 0, cw.dpart, 1.0 / (double)npix);
   DG_LAUNCH_CHECK("cnn_out_kernel<train>");
   hipLaunchKernelGGL(cnn_loss_finish, dim3(1), dim3(256), 0, st, cw.dpart, (int)ot,
                      1.0 / (double)npix, loss_out);

@@ -84,8 +84,11 @@ def test_cnn_gradients_match_oracle(gpu_lib):
         assert rw <= 0.015 * depth + 0.005 and cw >= 0.99 and cb >= 0.99, stats
 
 
-def test_cnn_denoise_and_tangent_divergence(gpu_lib):
-    I = 48
+@pytest.mark.parametrize("I", [48, 70])
+def test_cnn_denoise_and_tangent_divergence(gpu_lib, I):
+    """The fused forward + tangent passes of the denoiser (a ragged tile tail
+    at 70): D(r) bitwise equal to the forward-only kernels, f and the tangent
+    divergence against the oracle."""
     g = synth.geometry(synth.PARALLEL, I, 1.0, 4, I + 1, math.pi)
     plan = gpu_lib.Plan(g)
     net = gpu_lib.CnnNet(seed=7)
@@ -96,6 +99,9 @@ def test_cnn_denoise_and_tangent_divergence(gpu_lib):
                              torch.ones(1, dtype=torch.float64, device="cuda"), probe_seed=11,
                              iteration=2)
     torch.cuda.synchronize()
+    x_fwd = net.forward(torch.as_tensor(r, dtype=torch.float32).cuda()[None])[0]
+    torch.cuda.synchronize()
+    assert torch.equal(x, x_fwd.reshape(x.shape))
     x_ref = ocnn.denoise(r, params)
     f_ref = r - x_ref
     f_gpu = r - x.cpu().double().numpy()
