@@ -30,7 +30,8 @@ dg_status launch_backproject_batch(const BpArgs* T, const int* prefix, int n, in
 dg_status launch_channel_batch(const ChanArgs* T, const int* prefix, int n, int total, int mode,
                                double eta_s, int onsager, int t, int finish, hipStream_t st);
 dg_status launch_nlm_batch(int P, const NlmArgs* T, const int* prefix, int n, int total,
-                           uint64_t seed, int iter, hipStream_t st);
+                           uint64_t seed, int iter, double eta_x, int t, hipStream_t st);
+dg_status launch_div_finish_batch(const DivArgs* T, int n, double eta_x, int t, hipStream_t st);
 dg_status launch_div_batch(const DivArgs* T, const int* prefix, int n, int total, uint64_t seed,
                            int iter, double eta_x, int t, hipStream_t st);
 dg_status check_denoise_params(const dg_plan* p, int kind, const void* params);
@@ -97,6 +98,7 @@ struct dg_batch {
   BpArgs* t_bp = nullptr;
   NlmArgs* t_nlm = nullptr;
   DivArgs* t_div = nullptr;
+  DivArgs* t_divn = nullptr;  // the NLM-fused divergence's finish
   // bound buffers
   bool bound = false;
   float *x = nullptr, *s = nullptr, *mu_out = nullptr;
@@ -110,7 +112,8 @@ struct dg_batch {
 };
 
 static size_t batch_work_layout(const dg_batch* b, void* base, char** parts) {
-  // parts: spec, mu, mu_t, z, g, r, xden, xpert, dpart, fpart
+  // parts: spec, mu, mu_t, z, g, r, xden, xpert, dpart, fpart, npart (NLM
+  // divergence partials, per-slice offsets pre_nlm)
   char* c = (char*)base;
   size_t off = 0;
   auto take = [&](size_t bytes) {
@@ -119,7 +122,7 @@ static size_t batch_work_layout(const dg_batch* b, void* base, char** parts) {
     return p;
   };
   const size_t nb = sizeof(float) * (size_t)b->totN, mb = sizeof(float) * (size_t)b->totM;
-  char* tmp[10];
+  char* tmp[11];
   tmp[0] = take(sizeof(float2) * (size_t)b->totSpec);
   tmp[1] = take(nb);
   tmp[2] = take(nb);
@@ -130,14 +133,15 @@ static size_t batch_work_layout(const dg_batch* b, void* base, char** parts) {
   tmp[7] = take(nb);
   tmp[8] = take(sizeof(double) * (size_t)kPartMax * b->n);
   tmp[9] = take(sizeof(float) * (size_t)kPartMax * b->n);
+  tmp[10] = take(sizeof(double) * (size_t)b->pre_nlm[b->n]);
   if (parts)
-    for (int k = 0; k < 10; ++k) parts[k] = tmp[k];
+    for (int k = 0; k < 11; ++k) parts[k] = tmp[k];
   return off;
 }
 
 static void free_tables(dg_batch* b) {
   void* ptrs[] = {b->t_rf_x, b->t_rf_g, b->t_cols, b->t_ri_mu, b->t_ri_r, b->t_ri_out, b->t_eps,
-                  b->t_proj, b->t_chan, b->t_bp,  b->t_nlm,  b->t_div};
+                  b->t_proj, b->t_chan, b->t_bp,  b->t_nlm,  b->t_div, b->t_divn};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   b->t_rf_x = b->t_rf_g = nullptr;
@@ -149,6 +153,7 @@ static void free_tables(dg_batch* b) {
   b->t_bp = nullptr;
   b->t_nlm = nullptr;
   b->t_div = nullptr;
+  b->t_divn = nullptr;
 }
 
 extern "C" dg_status dg_batch_destroy(dg_batch* b) {
@@ -264,7 +269,7 @@ extern "C" dg_status dg_batch_bind(dg_batch* b, const float* y, const double* i0
     set_error("dg_batch_bind: batched runs support the NLM and CNN denoisers");
     return DG_ERR_UNSUPPORTED;
   }
-  char* parts[10];
+  char* parts[11];
   batch_work_layout(b, work, parts);
   float2* spec = (float2*)parts[0];
   float* mu = (float*)parts[1];
@@ -276,6 +281,7 @@ extern "C" dg_status dg_batch_bind(dg_batch* b, const float* y, const double* i0
   float* xpert = (float*)parts[7];
   double* dpart = (double*)parts[8];
   float* fpart = (float*)parts[9];
+  double* npart = (double*)parts[10];
   const int n = b->n;
   std::vector<RowsFwdArgs> rf_x(n), rf_g(n);
   std::vector<ColsArgs> cols(n);
@@ -285,7 +291,7 @@ extern "C" dg_status dg_batch_bind(dg_batch* b, const float* y, const double* i0
   std::vector<ChanArgs> chan(n);
   std::vector<BpArgs> bp(n);
   std::vector<NlmArgs> nlm(n);
-  std::vector<DivArgs> dv(n);
+  std::vector<DivArgs> dv(n), dvn(n);
   const dg_nlm_params* np = (const dg_nlm_params*)den_params;
   for (int k = 0; k < n; ++k) {
     const dg_plan* p = b->plans[k];
@@ -295,7 +301,14 @@ extern "C" dg_status dg_batch_bind(dg_batch* b, const float* y, const double* i0
     double* sc = scal + (size_t)k * DG_NSCAL;
     double* dp = dpart + (size_t)k * kPartMax;
     float* fp = fpart + (size_t)k * kPartMax;
-    rf_x[k] = RowsFwdArgs{x + io, sp, p->twiddle, I, 0, ChanArgs{}};
+    // with NLM, V^-1 x's first row workgroup finishes the previous
+    // iteration's divergence step (from the NLM workgroups' partials)
+    double* np_k = npart + b->pre_nlm[k];
+    const int nb_k = b->pre_nlm[k + 1] - b->pre_nlm[k];
+    rf_x[k] = RowsFwdArgs{x + io, sp, p->twiddle, I, 0, ChanArgs{},
+                          den_kind == DG_DEN_NLM
+                              ? DivFinish{np_k, nb_k, (double)p->N, sc + DG_S_EPS, sc}
+                              : DivFinish{}};
     cols[k] = ColsArgs{sp, p->twiddle, I, 1};
     ri_mu[k] = RowsInvArgs{sp, p->twiddle, I, PREC_PLAIN, mu + io, mu_t + io, nullptr, nullptr,
                            nullptr};
@@ -307,15 +320,18 @@ extern "C" dg_status dg_batch_bind(dg_batch* b, const float* y, const double* i0
     chan[k] = ChanArgs{p->M, z + so, y + so, s + so, nullptr, nullptr, sc, nullptr, i0[k], fro2[k],
                        (double)p->N, dp, b->pre_chan[k + 1] - b->pre_chan[k]};
     // the channel finish runs in the slice's first row workgroup of V^-1 g
-    rf_g[k] = RowsFwdArgs{g + io, sp, p->twiddle, I, 1, chan[k]};
+    rf_g[k] = RowsFwdArgs{g + io, sp, p->twiddle, I, 1, chan[k], DivFinish{}};
     bp[k] = BpArgs{p->rays, p->views, s + so, g + io, I, p->nv, p->nb,
                    p->g.kind == DG_GEOM_FAN ? 1 : 0, (float)p->half_diag_px, p->vrays, p->q0fx};
-    if (den_kind == DG_DEN_NLM)  // NLM also finishes the Monte-Carlo step
+    // NLM also finishes the Monte-Carlo step and performs the divergence step
+    if (den_kind == DG_DEN_NLM)
       nlm[k] = NlmArgs{r + io,           xden + io, xpert + io,       I,
                        np->search_radius, sc + DG_S_TAU_R, sc + DG_S_EPS, (float)np->hfac,
-                       fp,               prec_row_blocks(I), eps_rel,   sc + DG_S_EPS};
+                       fp,               prec_row_blocks(I), eps_rel,   sc + DG_S_EPS,
+                       x + io,           sc,        np_k};
     dv[k] = DivArgs{p->N, xden + io, xpert + io, x + io, sc + DG_S_EPS, nullptr, sc, dp,
                     b->pre_div[k + 1] - b->pre_div[k]};
+    dvn[k] = DivArgs{p->N, xden + io, xpert + io, x + io, sc + DG_S_EPS, nullptr, sc, np_k, nb_k};
   }
   free_tables(b);
   dg_status rc;
@@ -324,7 +340,8 @@ extern "C" dg_status dg_batch_bind(dg_batch* b, const float* y, const double* i0
       (rc = upload(ri_r, &b->t_ri_r)) != DG_OK || (rc = upload(ri_out, &b->t_ri_out)) != DG_OK ||
       (rc = upload(eps, &b->t_eps)) != DG_OK || (rc = upload(proj, &b->t_proj)) != DG_OK ||
       (rc = upload(chan, &b->t_chan)) != DG_OK || (rc = upload(bp, &b->t_bp)) != DG_OK ||
-      (rc = upload(nlm, &b->t_nlm)) != DG_OK || (rc = upload(dv, &b->t_div)) != DG_OK)
+      (rc = upload(nlm, &b->t_nlm)) != DG_OK || (rc = upload(dv, &b->t_div)) != DG_OK ||
+      (rc = upload(dvn, &b->t_divn)) != DG_OK)
     return rc;
   b->x = x;
   b->s = s;
@@ -380,9 +397,13 @@ extern "C" dg_status dgamp_batch_iterate(dg_batch* b, int32_t n_iter, int32_t t0
   hipStream_t st = (hipStream_t)stream;
   const int n = b->n;
   dg_status rc;
+  const bool nlm = b->den_kind == DG_DEN_NLM;
   for (int it = 0; it < n_iter; ++it) {
     const int t = t0 + it;
-    if ((rc = batch_precondition(b, b->t_rf_x, b->t_ri_mu, 0, 0.0, st)) != DG_OK) return rc;
+    // (with NLM, also the scalar finish of iteration t - 1's divergence step)
+    if ((rc = batch_precondition(b, b->t_rf_x, b->t_ri_mu, nlm && it > 0 ? t - 1 : -1, eta_x,
+                                 st)) != DG_OK)
+      return rc;
     if ((rc = launch_project_batch(b->proj_variant, b->t_proj, b->d_pre_proj, n, b->pre_proj[n],
                                    st)) != DG_OK)
       return rc;
@@ -396,18 +417,21 @@ extern "C" dg_status dgamp_batch_iterate(dg_batch* b, int32_t n_iter, int32_t t0
         (rc = launch_prec_batch(3, b->t_eps, nullptr, n, n, 0, 0.0, st)) != DG_OK)
       return rc;
     if (b->den_kind == DG_DEN_NLM) {
+      // the divergence step runs inside the NLM launch
       rc = launch_nlm_batch(b->nlm.patch_radius, b->t_nlm, b->d_pre_nlm, n, b->pre_nlm[n],
-                            probe_seed, t, st);
+                            probe_seed, t, eta_x, t, st);
     } else {
       rc = cnn_launch_denoise_batch(&b->cnn, b->r, b->scal + DG_S_EPS, DG_NSCAL, probe_seed, t,
                                     b->xden, b->xpert, n, b->uniform_I, st);
+      if (rc == DG_OK)
+        rc = launch_div_batch(b->t_div, b->d_pre_div, n, b->pre_div[n], probe_seed, t, eta_x, t,
+                              st);
     }
     if (rc != DG_OK) return rc;
-    if ((rc = launch_div_batch(b->t_div, b->d_pre_div, n, b->pre_div[n], probe_seed, t, eta_x, t,
-                               st)) != DG_OK)
-      return rc;
   }
-  if (write_mu) return batch_precondition(b, b->t_rf_x, b->t_ri_out, 0, 0.0, st);
+  const int t_last = nlm && n_iter > 0 ? t0 + n_iter - 1 : -1;
+  if (write_mu) return batch_precondition(b, b->t_rf_x, b->t_ri_out, t_last, eta_x, st);
+  if (t_last >= 0) return launch_div_finish_batch(b->t_divn, n, eta_x, t_last, st);
   return DG_OK;
 }
 

@@ -57,59 +57,16 @@ static constexpr int kNlmBX = 2, kNlmBY = 8;
 static_assert(kNlmBX == 2, "the row sums below are written for two outputs per row");
 static constexpr int kNlmWaves = 7;  // 21 search rows (S = 10): 3 per wavefront
 static constexpr int kNlmThreads = 64 * kNlmWaves;
-template <int P>
-__device__ void nlm_body(const NlmArgs& Ar, int bx, int by, int img, uint64_t seed, int iter,
-                         float* R, float (*red)[64][2 * kNlmBX * kNlmBY]) {
+// The search loop and the per-output normalisation of nlm_body.
+template <int P, class Emit>
+__device__ __forceinline__ void nlm_search(const NlmArgs& Ar, const float* R,
+                                           float (*red)[64][2 * kNlmBX * kNlmBY], int ox0, int oy0,
+                                           int g, int lane, double tau_r, int ty0, int tx0,
+                                           Emit& emit) {
   constexpr int BX = kNlmBX, BY = kNlmBY;
   constexpr int WX = BX + 2 * P, WY = BY + 2 * P;
-  const float* __restrict__ r = Ar.r;
   const int I = Ar.I, S = Ar.S;
-  const double* __restrict__ tau_r_ptr = Ar.tau_r;
   const float hfac = Ar.hfac;
-  float* out = img ? Ar.out1 : Ar.out0;
-  const int ty0 = by * kNlmTile, tx0 = bx * kNlmTile;
-  const int H0 = S + P;
-  const int WR = kNlmTile + 2 * H0;
-  float eps = 0.0f;
-  if (Ar.eps_part) {
-    // Monte-Carlo step from the preconditioner's per-workgroup max |r|
-    // (finished here rather than in a launch of its own); red is free yet
-    float* sh = &red[0][0][0];
-    const float gm = finish_max(Ar.eps_part, Ar.eps_n, sh);
-    if (threadIdx.x == 0) {
-      double e = Ar.eps_rel * (double)gm;
-      e = e > 1e-12 ? e : 1e-12;
-      if (bx == 0 && by == 0 && img == 0) *Ar.eps_out = e;
-      sh[32] = (float)e;
-    }
-    __syncthreads();
-    eps = img ? sh[32] : 0.0f;
-    __syncthreads();
-  } else if (img) {
-    eps = (float)(*Ar.eps);
-  }
-  for (int e = threadIdx.x; e < WR * WR; e += blockDim.x) {
-    const int ri = e / WR, rj = e % WR;
-    const int gi = reflect_idx(ty0 - H0 + ri, I), gj = reflect_idx(tx0 - H0 + rj, I);
-    const int64_t gidx = (int64_t)gi * I + gj;
-    float v = r[gidx];
-    if (img) v = __fmaf_rn(eps, probe_sign(seed, iter, (uint64_t)gidx), v);
-    R[ri * kNlmPitch + rj] = v;
-  }
-  __syncthreads();
-  const int lane = threadIdx.x & 63, g = threadIdx.x >> 6;
-  const int ox0 = (lane & 15) * BX, oy0 = (lane >> 4) * BY;  // tile-relative block origin
-  const double tau_r = *tau_r_ptr;
-  if (!(tau_r > 0.0)) {  // sigma = 0: identity
-    if (g == 0)
-      for (int a = 0; a < BY; ++a)
-        for (int c = 0; c < BX; ++c) {
-          const int gy = ty0 + oy0 + a, gx = tx0 + ox0 + c;
-          if (gy < I && gx < I)
-            out[(int64_t)gy * I + gx] = R[(H0 + oy0 + a) * kNlmPitch + H0 + ox0 + c];
-        }
-    return;
-  }
   const float sig2 = (float)tau_r;
   // w = exp(-max(S / n_p - 2 sigma^2, 0) / h^2) = 2^-max(c1 S - c2, 0) with
   // c1 = log2(e) / (n_p h^2) and c2 = log2(e) 2 sigma^2 / h^2 (S the patch
@@ -195,27 +152,111 @@ __device__ void nlm_body(const NlmArgs& Ar, int bx, int by, int img, uint64_t se
     }
     const int a = k / BX, c = k % BX;
     const int gy = ty0 + oy0 + a, gx = tx0 + ox0 + c;
-    if (gy < I && gx < I) out[(int64_t)gy * I + gx] = ac / ws;
+    if (gy < I && gx < I) emit(gy, gx, ac / ws);
   }
 }
 
 template <int P>
-__global__ void __launch_bounds__(kNlmThreads) nlm_kernel(NlmArgs A, uint64_t seed, int iter) {
+__device__ void nlm_body(const NlmArgs& Ar, int bx, int by, int img, uint64_t seed, int iter,
+                         double eta_x, int t, float* R, float (*red)[64][2 * kNlmBX * kNlmBY]) {
+  __shared__ double dsh[kNlmWaves + 1];
+  constexpr int BX = kNlmBX, BY = kNlmBY;
+  const float* __restrict__ r = Ar.r;
+  const int I = Ar.I, S = Ar.S;
+  const double* __restrict__ tau_r_ptr = Ar.tau_r;
+  float* out = img ? Ar.out1 : Ar.out0;
+  const int ty0 = by * kNlmTile, tx0 = bx * kNlmTile;
+  const int H0 = S + P;
+  const int WR = kNlmTile + 2 * H0;
+  // fused divergence: off once the status word is set (the recursion is
+  // frozen, as in the separate divergence pass)
+  const bool fuse = Ar.x != nullptr && Ar.scal[DG_S_STATUS] == 0.0;
+  float eps = 0.0f;
+  double eps_d = 0.0;
+  if (Ar.eps_part) {
+    // Monte-Carlo step from the preconditioner's per-workgroup max |r|
+    // (finished here rather than in a launch of its own); red is free yet
+    float* sh = &red[0][0][0];
+    const float gm = finish_max(Ar.eps_part, Ar.eps_n, sh);
+    if (threadIdx.x == 0) {
+      double e = Ar.eps_rel * (double)gm;
+      e = e > 1e-12 ? e : 1e-12;
+      if (bx == 0 && by == 0 && img == 0) *Ar.eps_out = e;
+      dsh[0] = e;
+    }
+    __syncthreads();
+    eps_d = dsh[0];
+    eps = img ? (float)eps_d : 0.0f;
+    __syncthreads();
+  } else if (img || fuse) {
+    eps_d = *Ar.eps;
+    if (img) eps = (float)eps_d;
+  }
+  for (int e = threadIdx.x; e < WR * WR; e += blockDim.x) {
+    const int ri = e / WR, rj = e % WR;
+    const int gi = reflect_idx(ty0 - H0 + ri, I), gj = reflect_idx(tx0 - H0 + rj, I);
+    const int64_t gidx = (int64_t)gi * I + gj;
+    float v = r[gidx];
+    if (img) v = __fmaf_rn(eps, probe_sign(seed, iter, (uint64_t)gidx), v);
+    R[ri * kNlmPitch + rj] = v;
+  }
+  __syncthreads();
+  const int lane = threadIdx.x & 63, g = threadIdx.x >> 6;
+  const int ox0 = (lane & 15) * BX, oy0 = (lane >> 4) * BY;  // tile-relative block origin
+  const double tau_r = *tau_r_ptr;
+  // an output value: stored, and with the fused divergence, x damped towards
+  // D(r) (image 0) and -+ b v added to this thread's partial
+  const float eta = (float)eta_x;
+  double dacc = 0.0;
+  auto emit = [&](int gy, int gx, float v) {
+    const int64_t gidx = (int64_t)gy * I + gx;
+    out[gidx] = v;
+    if (fuse) {
+      const float b = probe_sign(seed, iter, (uint64_t)gidx);
+      if (img) {
+        dacc += (double)(b * v);
+      } else {
+        dacc -= (double)(b * v);
+        Ar.x[gidx] = (t > 0) ? __fmaf_rn(eta, v, (1.0f - eta) * Ar.x[gidx]) : v;
+      }
+    }
+  };
+  if (!(tau_r > 0.0)) {  // sigma = 0: identity
+    if (g == 0)
+      for (int a = 0; a < BY; ++a)
+        for (int c = 0; c < BX; ++c) {
+          const int gy = ty0 + oy0 + a, gx = tx0 + ox0 + c;
+          if (gy < I && gx < I) emit(gy, gx, R[(H0 + oy0 + a) * kNlmPitch + H0 + ox0 + c]);
+        }
+  } else {
+    nlm_search<P>(Ar, R, red, ox0, oy0, g, lane, tau_r, ty0, tx0, emit);
+  }
+  if (!fuse) return;
+  // the workgroup's partial of b^T (D(r + eps b) - D(r)); the next launch
+  // sums them (DivFinish)
+  const double bs = block_sum(dacc, dsh);
+  const int g2 = (I + kNlmTile - 1) / kNlmTile;
+  if (threadIdx.x == 0) Ar.div_part[(img * g2 + by) * g2 + bx] = bs;
+}
+
+template <int P>
+__global__ void __launch_bounds__(kNlmThreads)
+nlm_kernel(NlmArgs A, uint64_t seed, int iter, double eta_x, int t) {
   __shared__ float R[kNlmRegion * kNlmPitch];
   __shared__ float red[kNlmWaves][64][2 * kNlmBX * kNlmBY];
-  nlm_body<P>(A, blockIdx.x, blockIdx.y, blockIdx.z, seed, iter, R, red);
+  nlm_body<P>(A, blockIdx.x, blockIdx.y, blockIdx.z, seed, iter, eta_x, t, R, red);
 }
 template <int P>
 __global__ void __launch_bounds__(kNlmThreads)
 nlm_batch(const NlmArgs* __restrict__ T, const int* __restrict__ prefix, int n, uint64_t seed,
-          int iter) {
+          int iter, double eta_x, int t) {
   __shared__ float R[kNlmRegion * kNlmPitch];
   __shared__ float red[kNlmWaves][64][2 * kNlmBX * kNlmBY];
   const int s = slice_of(prefix, n, blockIdx.x);
   const NlmArgs A = T[s];
   const int local = blockIdx.x - prefix[s];
   const int g = (A.I + kNlmTile - 1) / kNlmTile;
-  nlm_body<P>(A, local % g, (local / g) % g, local / (g * g), seed, iter, R, red);
+  nlm_body<P>(A, local % g, (local / g) % g, local / (g * g), seed, iter, eta_x, t, R, red);
 }
 
 // Haar: one workgroup per B x B block (B = 2^J), dynamic LDS of B*B floats.
@@ -351,19 +392,10 @@ __device__ void div_finish_body(const DivArgs& A, int mode, double eta_x, int t,
   if (mode == 1 && A.scal[DG_S_STATUS] != 0.0) return;
   const double tot = finish_sum(A.partials, A.nblk, red);
   if (threadIdx.x == 0) {
-    const double div = tot / ((double)A.N * (*A.eps));
-    if (mode == 0) {
-      *A.div_out = div;
-    } else {
-      double* scal = A.scal;
-      const double tau_r = scal[DG_S_TAU_R];
-      double tau_x = div > 0.0 ? tau_r * div : 1e-12 * tau_r;
-      if (!(div > 0.0)) scal[DG_S_CLAMPS] += 1.0;
-      if (t > 0) tau_x = eta_x * tau_x + (1.0 - eta_x) * scal[DG_S_TAU_X];
-      scal[DG_S_DIV] = div;
-      scal[DG_S_TAU_X] = tau_x;
-      if (!isfinite(div) || !(tau_x > 0.0) || !isfinite(tau_x)) scal[DG_S_STATUS] = (double)(t + 1);
-    }
+    if (mode == 0)
+      *A.div_out = tot / ((double)A.N * (*A.eps));
+    else
+      div_update_scalars(tot, (double)A.N, *A.eps, A.scal, eta_x, t);
   }
 }
 
@@ -478,9 +510,11 @@ dg_status check_denoise_params(const dg_plan* p, int kind, const void* params) {
 }
 
 // Runs D on r (into x_den) and, when probed, on r + eps b (into x_pert).
+// NLM with `df` (both images) also performs the divergence step (see NlmArgs).
 dg_status launch_denoiser(const dg_plan* p, int kind, const void* params, const float* r,
                           const double* tau_r, const double* eps, uint64_t seed, int iter,
-                          float* x_den, float* x_pert, hipStream_t st, const EpsFinish* ef) {
+                          float* x_den, float* x_pert, hipStream_t st, const EpsFinish* ef,
+                          const DivFuse* df) {
   const int nimg = x_pert ? 2 : 1;
   if (kind == DG_DEN_NLM) {
     const dg_nlm_params* np = (const dg_nlm_params*)params;
@@ -493,15 +527,24 @@ dg_status launch_denoiser(const dg_plan* p, int kind, const void* params, const 
       A.eps_rel = ef->eps_rel;
       A.eps_out = ef->out;
     }
+    double eta_x = 0.0;
+    int t = 0;
+    if (df && x_pert) {
+      A.x = df->x;
+      A.scal = df->scal;
+      A.div_part = df->part;
+      eta_x = df->eta_x;
+      t = df->t;
+    }
     switch (np->patch_radius) {
       case 1:
-        hipLaunchKernelGGL(nlm_kernel<1>, grid, dim3(kNlmThreads), 0, st, A, seed, iter);
+        hipLaunchKernelGGL(nlm_kernel<1>, grid, dim3(kNlmThreads), 0, st, A, seed, iter, eta_x, t);
         break;
       case 2:
-        hipLaunchKernelGGL(nlm_kernel<2>, grid, dim3(kNlmThreads), 0, st, A, seed, iter);
+        hipLaunchKernelGGL(nlm_kernel<2>, grid, dim3(kNlmThreads), 0, st, A, seed, iter, eta_x, t);
         break;
       default:
-        hipLaunchKernelGGL(nlm_kernel<3>, grid, dim3(kNlmThreads), 0, st, A, seed, iter);
+        hipLaunchKernelGGL(nlm_kernel<3>, grid, dim3(kNlmThreads), 0, st, A, seed, iter, eta_x, t);
         break;
     }
     DG_LAUNCH_CHECK("nlm_kernel");
@@ -533,22 +576,32 @@ dg_status launch_div(const dg_plan* p, const float* xden, const float* xpert, fl
   return DG_OK;
 }
 
+// The divergence step's scalar finish (mode 1) alone, one workgroup.
+dg_status launch_div_finish(const DivArgs& A, double eta_x, int t, hipStream_t st) {
+  hipLaunchKernelGGL(div_finish, dim3(1), dim3(256), 0, st, A, 1, eta_x, t);
+  DG_LAUNCH_CHECK("div_finish");
+  return DG_OK;
+}
+
 unsigned int nlm_blocks(int I) {
   const int g = (I + kNlmTile - 1) / kNlmTile;
   return (unsigned int)(g * g * 2);
 }
 
 dg_status launch_nlm_batch(int P, const NlmArgs* T, const int* prefix, int n, int total,
-                           uint64_t seed, int iter, hipStream_t st) {
+                           uint64_t seed, int iter, double eta_x, int t, hipStream_t st) {
   switch (P) {
     case 1:
-      hipLaunchKernelGGL(nlm_batch<1>, dim3(total), dim3(kNlmThreads), 0, st, T, prefix, n, seed, iter);
+      hipLaunchKernelGGL(nlm_batch<1>, dim3(total), dim3(kNlmThreads), 0, st, T, prefix, n, seed,
+                         iter, eta_x, t);
       break;
     case 2:
-      hipLaunchKernelGGL(nlm_batch<2>, dim3(total), dim3(kNlmThreads), 0, st, T, prefix, n, seed, iter);
+      hipLaunchKernelGGL(nlm_batch<2>, dim3(total), dim3(kNlmThreads), 0, st, T, prefix, n, seed,
+                         iter, eta_x, t);
       break;
     default:
-      hipLaunchKernelGGL(nlm_batch<3>, dim3(total), dim3(kNlmThreads), 0, st, T, prefix, n, seed, iter);
+      hipLaunchKernelGGL(nlm_batch<3>, dim3(total), dim3(kNlmThreads), 0, st, T, prefix, n, seed,
+                         iter, eta_x, t);
       break;
   }
   DG_LAUNCH_CHECK("nlm_batch");
@@ -560,6 +613,13 @@ dg_status launch_div_batch(const DivArgs* T, const int* prefix, int n, int total
   hipLaunchKernelGGL(div_batch, dim3(total), dim3(kRedBlock), 0, st, T, prefix, n, seed, iter,
                      eta_x, t);
   DG_LAUNCH_CHECK("div_batch");
+  hipLaunchKernelGGL(div_finish_batch, dim3(n), dim3(256), 0, st, T, eta_x, t);
+  DG_LAUNCH_CHECK("div_finish_batch");
+  return DG_OK;
+}
+
+// The divergence step's scalar finish alone for n slices (one workgroup each).
+dg_status launch_div_finish_batch(const DivArgs* T, int n, double eta_x, int t, hipStream_t st) {
   hipLaunchKernelGGL(div_finish_batch, dim3(n), dim3(256), 0, st, T, eta_x, t);
   DG_LAUNCH_CHECK("div_finish_batch");
   return DG_OK;
@@ -606,7 +666,7 @@ extern "C" dg_status denoise(const dg_plan* p, int32_t kind, const void* params,
     rc = cnn_launch_denoise(p, params, r, w.eps, probe_seed, iter, x_out, xpert, nullptr, st);
   } else {
     rc = launch_denoiser(p, kind, params, r, tau_r, w.eps, probe_seed, iter, x_out, xpert, st,
-                         nullptr);
+                         nullptr, nullptr);
   }
   if (rc != DG_OK) return rc;
   if (div_out)

@@ -288,6 +288,14 @@ struct NlmArgs {
   int eps_n;
   double eps_rel;
   double* eps_out;
+  // optional, inside the iteration (x == nullptr: not fused): the divergence
+  // step's per-pixel part in the same launch.  Image 0 workgroups damp x
+  // with D(r) and add -b.D(r), image 1 workgroups add b.D(r + eps b), each
+  // into its own FP64 partial (div_part[(img g + by) g + bx], g workgroups
+  // per side); the scalar finish (DivFinish) runs in the next launch.
+  float* x;
+  double* scal;
+  double* div_part;
 };
 // Where a denoiser launch may finish the Monte-Carlo step itself.
 struct EpsFinish {
@@ -296,6 +304,49 @@ struct EpsFinish {
   double eps_rel;
   double* out;
 };
+// Where a non-local-means launch may take over the per-pixel part of the
+// divergence step (the separate divergence pass is then skipped): see
+// NlmArgs.
+struct DivFuse {
+  float* x;
+  double* scal;
+  double* part;  // one FP64 partial per NLM workgroup of the slice
+  double eta_x;
+  int t;
+};
+// The divergence step's scalar finish from those partials, done by the first
+// row workgroup of the next preconditioner application (part == nullptr:
+// nothing pending).
+struct DivFinish {
+  const double* part;
+  int nblk;
+  double N;
+  const double* eps;
+  double* scal;
+};
+
+// The scalar part of the divergence step (Alg. 1 step 4): div =
+// b^T (D(r + eps b) - D(r)) / (N eps) from the total, then the damped tau_x
+// and the status word (t + 1 on a non-finite or non-positive result).
+__device__ __forceinline__ void div_update_scalars(double tot, double N, double eps, double* scal,
+                                                   double eta_x, int t) {
+  const double div = tot / (N * eps);
+  const double tau_r = scal[DG_S_TAU_R];
+  double tau_x = div > 0.0 ? tau_r * div : 1e-12 * tau_r;
+  if (!(div > 0.0)) scal[DG_S_CLAMPS] += 1.0;
+  if (t > 0) tau_x = eta_x * tau_x + (1.0 - eta_x) * scal[DG_S_TAU_X];
+  scal[DG_S_DIV] = div;
+  scal[DG_S_TAU_X] = tau_x;
+  if (!isfinite(div) || !(tau_x > 0.0) || !isfinite(tau_x)) scal[DG_S_STATUS] = (double)(t + 1);
+}
+
+__device__ __forceinline__ void div_finish_pending(const DivFinish& F, double eta_x, int t,
+                                                   double* red) {
+  if (F.scal[DG_S_STATUS] != 0.0) return;
+  const double tot = finish_sum(F.part, F.nblk, red);
+  if (threadIdx.x == 0) div_update_scalars(tot, F.N, *F.eps, F.scal, eta_x, t);
+}
+
 // Divergence argument block (per slice).
 struct DivArgs {
   int64_t N;
@@ -328,6 +379,7 @@ struct RowsFwdArgs {
   int I;
   int fin;        // 1: the first workgroup also finishes the output channel
   ChanArgs chan;  // (tau_s, tau_r from the channel's partial sums)
+  DivFinish dv;   // else, with fin_t >= 0: it finishes a pending divergence step
 };
 struct ColsArgs {
   float2* spec;
@@ -367,8 +419,9 @@ struct PrecArgs {
   int eps_elsewhere;     // PREC_UPDATE_R: leave the eps finish to the denoiser
   int fin;               // 1: finish the output channel in the first row workgroup
   ChanArgs chan;
-  double fin_eta;
-  int fin_t;
+  DivFinish dv;          // fin == 0, fin_t >= 0: finish a pending divergence step there
+  double fin_eta;        // eta_s (channel) or eta_x (divergence)
+  int fin_t;             // the iteration being finished
   float* partials;       // PREC_UPDATE_R: per-block max |r| (I/2 floats)
 };
 dg_status launch_precondition(const dg_plan* p, const PrecArgs& a, hipStream_t s);

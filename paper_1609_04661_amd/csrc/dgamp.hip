@@ -13,7 +13,6 @@
 
 namespace dg {
 
-dg_status launch_zero_u32(unsigned int* p, int n, hipStream_t st);
 dg_status launch_channel_fused(int64_t M, const float* z, const float* y, float* s, double* scal,
                                double i0, int mode, double fro2, double N, double eta_s,
                                int onsager, int t, double* partials, int finish,
@@ -21,7 +20,10 @@ dg_status launch_channel_fused(int64_t M, const float* z, const float* y, float*
 dg_status check_denoise_params(const dg_plan* p, int kind, const void* params);
 dg_status launch_denoiser(const dg_plan* p, int kind, const void* params, const float* r,
                           const double* tau_r, const double* eps, uint64_t seed, int iter,
-                          float* x_den, float* x_pert, hipStream_t st, const EpsFinish* ef);
+                          float* x_den, float* x_pert, hipStream_t st, const EpsFinish* ef,
+                          const DivFuse* df);
+unsigned int nlm_blocks(int I);
+dg_status launch_div_finish(const DivArgs& A, double eta_x, int t, hipStream_t st);
 int prec_row_blocks(int I);
 dg_status launch_div(const dg_plan* p, const float* xden, const float* xpert, float* x,
                      const double* eps, double* div_out, double* scal, int mode, uint64_t seed,
@@ -38,8 +40,8 @@ static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 static constexpr int kMaxBlocks = 1024;
 
 struct IterWork {
-  unsigned int* counters;  // 8
   double* dpart;
+  double* npart;  // divergence partials of the NLM workgroups
   float* fpart;
   float *mu, *mu_t, *z, *g, *r, *xden, *xpert;
   float2* spec;
@@ -54,8 +56,8 @@ static size_t iter_work_layout(const dg_plan* p, void* base, IterWork* w) {
     return ptr;
   };
   IterWork t;
-  t.counters = (unsigned int*)take(256);
   t.dpart = (double*)take(sizeof(double) * kMaxBlocks);
+  t.npart = (double*)take(sizeof(double) * nlm_blocks(p->I));
   t.fpart = (float*)take(sizeof(float) * kMaxBlocks);
   const size_t nb = sizeof(float) * (size_t)p->N, mb = sizeof(float) * (size_t)p->M;
   t.mu = (float*)take(nb);
@@ -183,13 +185,25 @@ extern "C" dg_status dgamp_iterate(const dg_plan* p, const float* y, const dgamp
   hipStream_t s = (hipStream_t)stream;
   IterWork w;
   iter_work_layout(p, work, &w);
-  if ((rc = launch_zero_u32(w.counters, 8, s)) != DG_OK) return rc;
   const double N = (double)p->N;
   hipEvent_t* ev = (hipEvent_t*)o->phase_events;
   const uint32_t pmask = o->phase_mask;
   auto mark = [&](int it, int k) -> dg_status {
     if (ev && (pmask == 0 || ((pmask >> k) & 1u)))
       DG_HIP(hipEventRecord(ev[(size_t)it * (DG_NPHASES + 1) + k], s));
+    return DG_OK;
+  };
+  const bool nlm = o->den_kind == DG_DEN_NLM;
+  // with NLM the divergence step's scalar finish of iteration t runs in the
+  // first row workgroup of the next V^-1 x (or of the final V^-1 x for
+  // mu_out, or in a finish launch of its own after the last iteration)
+  const DivFinish pending{w.npart, (int)nlm_blocks(p->I), N, st->scal + DG_S_EPS, st->scal};
+  auto log_it = [&](int it) -> dg_status {
+    if (log) {
+      hipLaunchKernelGGL(log_copy, dim3(1), dim3(64), 0, s, st->scal,
+                         log + (size_t)it * DG_LOG_STRIDE);
+      DG_LAUNCH_CHECK("log_copy");
+    }
     return DG_OK;
   };
   for (int it = 0; it < o->n_iter; ++it) {
@@ -202,7 +216,14 @@ extern "C" dg_status dgamp_iterate(const dg_plan* p, const float* y, const dgamp
     a.spec = w.spec;
     a.dir = 1;
     a.epilogue = PREC_PLAIN;
+    a.fin_t = -1;
+    if (nlm && it > 0) {
+      a.dv = pending;
+      a.fin_t = t - 1;
+      a.fin_eta = o->eta_x;
+    }
     if ((rc = launch_precondition(p, a, s)) != DG_OK) return rc;
+    if (nlm && it > 0 && (rc = log_it(it - 1)) != DG_OK) return rc;
     if ((rc = mark(it, 1)) != DG_OK) return rc;
     if ((rc = launch_project(p, w.mu, w.mu_t, w.z, s)) != DG_OK) return rc;
     if ((rc = mark(it, 2)) != DG_OK) return rc;
@@ -215,7 +236,6 @@ extern "C" dg_status dgamp_iterate(const dg_plan* p, const float* y, const dgamp
     if ((rc = mark(it, 3)) != DG_OK) return rc;
     if ((rc = launch_backproject(p, st->s, w.g, s)) != DG_OK) return rc;
     if ((rc = mark(it, 4)) != DG_OK) return rc;
-    const bool nlm = o->den_kind == DG_DEN_NLM;
     PrecArgs b{};
     b.in = w.g;
     b.out = w.r;
@@ -238,24 +258,26 @@ extern "C" dg_status dgamp_iterate(const dg_plan* p, const float* y, const dgamp
     const double* tau_r = st->scal + DG_S_TAU_R;
     const double* eps = st->scal + DG_S_EPS;
     const EpsFinish ef{w.fpart, prec_row_blocks(p->I), o->eps_rel, st->scal + DG_S_EPS};
+    const DivFuse df{st->x, st->scal, w.npart, o->eta_x, t};
     if (o->den_kind == DG_DEN_CNN)
       rc = cnn_launch_denoise(p, o->den_params, w.r, eps, o->probe_seed, t, w.xden, w.xpert,
                               nullptr, s);
     else
       rc = launch_denoiser(p, o->den_kind, o->den_params, w.r, tau_r, eps, o->probe_seed, t,
-                           w.xden, w.xpert, s, nlm ? &ef : nullptr);
+                           w.xden, w.xpert, s, nlm ? &ef : nullptr, nlm ? &df : nullptr);
     if (rc != DG_OK) return rc;
     if ((rc = mark(it, 6)) != DG_OK) return rc;
-    if ((rc = launch_div(p, w.xden, w.xpert, st->x, eps, nullptr, st->scal, 1, o->probe_seed, t,
-                         o->eta_x, t, w.dpart, s)) != DG_OK)
-      return rc;
-    if ((rc = mark(it, 7)) != DG_OK) return rc;
-    if (log) {
-      hipLaunchKernelGGL(log_copy, dim3(1), dim3(64), 0, s, st->scal,
-                         log + (size_t)it * DG_LOG_STRIDE);
-      DG_LAUNCH_CHECK("log_copy");
+    // NLM performs the divergence step's per-pixel part in its own launch
+    if (!nlm) {
+      if ((rc = launch_div(p, w.xden, w.xpert, st->x, eps, nullptr, st->scal, 1, o->probe_seed, t,
+                           o->eta_x, t, w.dpart, s)) != DG_OK)
+        return rc;
+      if ((rc = log_it(it)) != DG_OK) return rc;
     }
+    if ((rc = mark(it, 7)) != DG_OK) return rc;
   }
+  const int t_last = st->t + o->n_iter - 1;
+  const bool finish = nlm && o->n_iter > 0;
   st->t += o->n_iter;
   if (mu_out) {
     PrecArgs a{};
@@ -264,8 +286,19 @@ extern "C" dg_status dgamp_iterate(const dg_plan* p, const float* y, const dgamp
     a.spec = w.spec;
     a.dir = 1;
     a.epilogue = PREC_PLAIN;
+    a.fin_t = -1;
+    if (finish) {
+      a.dv = pending;
+      a.fin_t = t_last;
+      a.fin_eta = o->eta_x;
+    }
     if ((rc = launch_precondition(p, a, s)) != DG_OK) return rc;
+  } else if (finish) {
+    const DivArgs A{p->N, w.xden, w.xpert, st->x, st->scal + DG_S_EPS, nullptr, st->scal,
+                    w.npart, (int)nlm_blocks(p->I)};
+    if ((rc = launch_div_finish(A, o->eta_x, t_last, s)) != DG_OK) return rc;
   }
+  if (finish && (rc = log_it(o->n_iter - 1)) != DG_OK) return rc;
   return DG_OK;
 }
 
@@ -281,7 +314,6 @@ extern "C" dg_status dg_fro2_hutchinson(const dg_plan* p, int32_t n_probes, uint
   IterWork w;
   iter_work_layout(p, work, &w);
   dg_status rc;
-  if ((rc = launch_zero_u32(w.counters, 8, s)) != DG_OK) return rc;
   hipLaunchKernelGGL(set_f64, dim3(1), dim3(64), 0, s, out, 0.0);
   DG_LAUNCH_CHECK("set_f64");
   for (int k = 0; k < n_probes; ++k) {

@@ -199,8 +199,14 @@ __device__ void rows_fwd_body(const RowsFwdArgs& A, int blk, FftShared& S, int f
       }
     }
   }
-  // the output channel's finish (tau_s, tau_r), saving it a launch of its own
-  if (A.fin && blk == 0) channel_finish_body<true>(A.chan, fin_eta, fin_t, S.dred);
+  // the output channel's finish (tau_s, tau_r), or a pending divergence
+  // step's, saving it a launch of its own
+  if (blk == 0) {
+    if (A.fin)
+      channel_finish_body<true>(A.chan, fin_eta, fin_t, S.dred);
+    else if (A.dv.part && fin_t >= 0)
+      div_finish_pending(A.dv, fin_eta, fin_t, S.dred);
+  }
   load_twiddles(S, A.tw, I);
   float2* a = S.buf[w][0];
   float2* b = S.buf[w][1];
@@ -459,7 +465,7 @@ dg_status launch_precondition(const dg_plan* p, const PrecArgs& a, hipStream_t s
     return DG_ERR_UNSUPPORTED;
   }
   const int I = p->I;
-  RowsFwdArgs f{a.in, a.spec, p->twiddle, I, a.fin, a.chan};
+  RowsFwdArgs f{a.in, a.spec, p->twiddle, I, a.fin, a.chan, a.dv};
   hipLaunchKernelGGL(prec_rows_fwd, dim3(prec_row_blocks(I)), dim3(kFftThreads), 0, s, f, a.fin_t,
                      a.fin_eta);
   DG_LAUNCH_CHECK("prec_rows_fwd");
