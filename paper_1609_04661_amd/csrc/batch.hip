@@ -23,12 +23,10 @@ namespace dg {
 dg_status launch_prec_batch(int pass, const void* table, const int* prefix, int n, int total,
                             int fin_t, double fin_eta, hipStream_t s);
 dg_status launch_project_batch(int variant, const ProjArgs* T, const int* prefix, int n, int total,
-                               hipStream_t s);
+                               const ChanRun& cr, hipStream_t s);
 dg_status launch_project_variant(int variant, const ProjArgs& A, hipStream_t s);
 dg_status launch_backproject_batch(const BpArgs* T, const int* prefix, int n, int total,
                                    hipStream_t s);
-dg_status launch_channel_batch(const ChanArgs* T, const int* prefix, int n, int total, int mode,
-                               double eta_s, int onsager, int t, int finish, hipStream_t st);
 dg_status launch_nlm_batch(int P, const NlmArgs* T, const int* prefix, int n, int total,
                            uint64_t seed, int iter, double eta_x, int t, hipStream_t st);
 dg_status launch_div_finish_batch(const DivArgs* T, int n, double eta_x, int t, hipStream_t st);
@@ -41,7 +39,6 @@ dg_status cnn_launch_denoise_batch(const void* params, const float* r, const dou
                                    float* x_pert, int n, int I, hipStream_t st);
 unsigned int project_blocks(int64_t M);
 unsigned int backproject_blocks(int I);
-unsigned int channel_grid(int64_t M);
 unsigned int red_grid(int64_t N);
 unsigned int nlm_blocks(int I);
 int prec_row_blocks(int I);
@@ -77,11 +74,10 @@ struct dg_batch {
   int64_t totN = 0, totM = 0, totSpec = 0;
   int uniform_I = 0;  // side when all slices share it, else 0
   // per-phase block prefixes (host + device)
-  std::vector<int> pre_rows, pre_cols, pre_proj, pre_chan, pre_bp, pre_nlm, pre_div;
+  std::vector<int> pre_rows, pre_cols, pre_proj, pre_bp, pre_nlm, pre_div;
   int* d_pre_rows = nullptr;
   int* d_pre_cols = nullptr;
   int* d_pre_proj = nullptr;
-  int* d_pre_chan = nullptr;
   int* d_pre_bp = nullptr;
   int* d_pre_nlm = nullptr;
   int* d_pre_div = nullptr;
@@ -99,6 +95,7 @@ struct dg_batch {
   NlmArgs* t_nlm = nullptr;
   DivArgs* t_div = nullptr;
   DivArgs* t_divn = nullptr;  // the NLM-fused divergence's finish
+  ProjArgs* t_projc = nullptr;  // the projector with the output channel fused in
   // bound buffers
   bool bound = false;
   float *x = nullptr, *s = nullptr, *mu_out = nullptr;
@@ -113,7 +110,8 @@ struct dg_batch {
 
 static size_t batch_work_layout(const dg_batch* b, void* base, char** parts) {
   // parts: spec, mu, mu_t, z, g, r, xden, xpert, dpart, fpart, npart (NLM
-  // divergence partials, per-slice offsets pre_nlm)
+  // divergence partials, per-slice offsets pre_nlm), ppart (the projector's
+  // fused-channel partials, offsets pre_proj)
   char* c = (char*)base;
   size_t off = 0;
   auto take = [&](size_t bytes) {
@@ -122,7 +120,7 @@ static size_t batch_work_layout(const dg_batch* b, void* base, char** parts) {
     return p;
   };
   const size_t nb = sizeof(float) * (size_t)b->totN, mb = sizeof(float) * (size_t)b->totM;
-  char* tmp[11];
+  char* tmp[12];
   tmp[0] = take(sizeof(float2) * (size_t)b->totSpec);
   tmp[1] = take(nb);
   tmp[2] = take(nb);
@@ -134,14 +132,16 @@ static size_t batch_work_layout(const dg_batch* b, void* base, char** parts) {
   tmp[8] = take(sizeof(double) * (size_t)kPartMax * b->n);
   tmp[9] = take(sizeof(float) * (size_t)kPartMax * b->n);
   tmp[10] = take(sizeof(double) * (size_t)b->pre_nlm[b->n]);
+  tmp[11] = take(sizeof(double) * (size_t)b->pre_proj[b->n]);
   if (parts)
-    for (int k = 0; k < 11; ++k) parts[k] = tmp[k];
+    for (int k = 0; k < 12; ++k) parts[k] = tmp[k];
   return off;
 }
 
 static void free_tables(dg_batch* b) {
   void* ptrs[] = {b->t_rf_x, b->t_rf_g, b->t_cols, b->t_ri_mu, b->t_ri_r, b->t_ri_out, b->t_eps,
-                  b->t_proj, b->t_chan, b->t_bp,  b->t_nlm,  b->t_div, b->t_divn};
+                  b->t_proj, b->t_chan, b->t_bp,  b->t_nlm,  b->t_div, b->t_divn,
+                  b->t_projc};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   b->t_rf_x = b->t_rf_g = nullptr;
@@ -154,12 +154,13 @@ static void free_tables(dg_batch* b) {
   b->t_nlm = nullptr;
   b->t_div = nullptr;
   b->t_divn = nullptr;
+  b->t_projc = nullptr;
 }
 
 extern "C" dg_status dg_batch_destroy(dg_batch* b) {
   if (!b) return DG_OK;
   free_tables(b);
-  int* pres[] = {b->d_pre_rows, b->d_pre_cols, b->d_pre_proj, b->d_pre_chan,
+  int* pres[] = {b->d_pre_rows, b->d_pre_cols, b->d_pre_proj,
                  b->d_pre_bp,   b->d_pre_nlm,  b->d_pre_div};
   for (int* p : pres)
     if (p) (void)hipFree(p);
@@ -182,7 +183,6 @@ extern "C" dg_status dg_batch_create(const dg_geom* geoms, int32_t n, dg_batch**
   mk_prefix(b->pre_rows);
   mk_prefix(b->pre_cols);
   mk_prefix(b->pre_proj);
-  mk_prefix(b->pre_chan);
   mk_prefix(b->pre_bp);
   mk_prefix(b->pre_nlm);
   mk_prefix(b->pre_div);
@@ -211,7 +211,6 @@ extern "C" dg_status dg_batch_create(const dg_geom* geoms, int32_t n, dg_batch**
     b->pre_rows[s + 1] = b->pre_rows[s] + prec_row_blocks(I);
     b->pre_cols[s + 1] = b->pre_cols[s] + prec_col_blocks(I);
     b->pre_proj[s + 1] = b->pre_proj[s] + (int)project_blocks(p->M);
-    b->pre_chan[s + 1] = b->pre_chan[s] + (int)channel_grid(p->M);
     b->pre_bp[s + 1] = b->pre_bp[s] + (int)backproject_blocks(I);
     b->pre_nlm[s + 1] = b->pre_nlm[s] + (int)nlm_blocks(I);
     b->pre_div[s + 1] = b->pre_div[s] + (int)red_grid(p->N);
@@ -223,7 +222,6 @@ extern "C" dg_status dg_batch_create(const dg_geom* geoms, int32_t n, dg_batch**
   if ((rc = upload(b->pre_rows, &b->d_pre_rows)) != DG_OK ||
       (rc = upload(b->pre_cols, &b->d_pre_cols)) != DG_OK ||
       (rc = upload(b->pre_proj, &b->d_pre_proj)) != DG_OK ||
-      (rc = upload(b->pre_chan, &b->d_pre_chan)) != DG_OK ||
       (rc = upload(b->pre_bp, &b->d_pre_bp)) != DG_OK ||
       (rc = upload(b->pre_nlm, &b->d_pre_nlm)) != DG_OK ||
       (rc = upload(b->pre_div, &b->d_pre_div)) != DG_OK) {
@@ -269,7 +267,7 @@ extern "C" dg_status dg_batch_bind(dg_batch* b, const float* y, const double* i0
     set_error("dg_batch_bind: batched runs support the NLM and CNN denoisers");
     return DG_ERR_UNSUPPORTED;
   }
-  char* parts[11];
+  char* parts[12];
   batch_work_layout(b, work, parts);
   float2* spec = (float2*)parts[0];
   float* mu = (float*)parts[1];
@@ -282,12 +280,13 @@ extern "C" dg_status dg_batch_bind(dg_batch* b, const float* y, const double* i0
   double* dpart = (double*)parts[8];
   float* fpart = (float*)parts[9];
   double* npart = (double*)parts[10];
+  double* ppart = (double*)parts[11];
   const int n = b->n;
   std::vector<RowsFwdArgs> rf_x(n), rf_g(n);
   std::vector<ColsArgs> cols(n);
   std::vector<RowsInvArgs> ri_mu(n), ri_r(n), ri_out(n);
   std::vector<EpsArgs> eps(n);
-  std::vector<ProjArgs> proj(n);
+  std::vector<ProjArgs> proj(n), projc(n);
   std::vector<ChanArgs> chan(n);
   std::vector<BpArgs> bp(n);
   std::vector<NlmArgs> nlm(n);
@@ -316,9 +315,13 @@ extern "C" dg_status dg_batch_bind(dg_batch* b, const float* y, const double* i0
     ri_out[k] = RowsInvArgs{sp, p->twiddle, I, PREC_PLAIN, mu_out ? mu_out + io : mu + io, nullptr,
                             nullptr, nullptr, nullptr};
     eps[k] = EpsArgs{fp, prec_row_blocks(I), eps_rel, sc + DG_S_EPS};
-    proj[k] = ProjArgs{p->rays, mu + io, mu_t + io, z + so, I, p->M};
-    chan[k] = ChanArgs{p->M, z + so, y + so, s + so, nullptr, nullptr, sc, nullptr, i0[k], fro2[k],
-                       (double)p->N, dp, b->pre_chan[k + 1] - b->pre_chan[k]};
+    // the output channel runs in the projector's epilogue (projc); proj is
+    // the plain projector the autotuner times
+    chan[k] = ChanArgs{p->M,    nullptr,  y + so,       s + so,       nullptr,
+                       nullptr, sc,       nullptr,      i0[k],        fro2[k],
+                       (double)p->N, ppart + b->pre_proj[k], b->pre_proj[k + 1] - b->pre_proj[k]};
+    proj[k] = ProjArgs{p->rays, mu + io, mu_t + io, z + so, I, p->M, 0, ChanArgs{}};
+    projc[k] = ProjArgs{p->rays, mu + io, mu_t + io, z + so, I, p->M, 1, chan[k]};
     // the channel finish runs in the slice's first row workgroup of V^-1 g
     rf_g[k] = RowsFwdArgs{g + io, sp, p->twiddle, I, 1, chan[k], DivFinish{}};
     bp[k] = BpArgs{p->rays, p->views, s + so, g + io, I, p->nv, p->nb,
@@ -339,6 +342,7 @@ extern "C" dg_status dg_batch_bind(dg_batch* b, const float* y, const double* i0
       (rc = upload(cols, &b->t_cols)) != DG_OK || (rc = upload(ri_mu, &b->t_ri_mu)) != DG_OK ||
       (rc = upload(ri_r, &b->t_ri_r)) != DG_OK || (rc = upload(ri_out, &b->t_ri_out)) != DG_OK ||
       (rc = upload(eps, &b->t_eps)) != DG_OK || (rc = upload(proj, &b->t_proj)) != DG_OK ||
+      (rc = upload(projc, &b->t_projc)) != DG_OK ||
       (rc = upload(chan, &b->t_chan)) != DG_OK || (rc = upload(bp, &b->t_bp)) != DG_OK ||
       (rc = upload(nlm, &b->t_nlm)) != DG_OK || (rc = upload(dv, &b->t_div)) != DG_OK ||
       (rc = upload(dvn, &b->t_divn)) != DG_OK)
@@ -404,11 +408,10 @@ extern "C" dg_status dgamp_batch_iterate(dg_batch* b, int32_t n_iter, int32_t t0
     if ((rc = batch_precondition(b, b->t_rf_x, b->t_ri_mu, nlm && it > 0 ? t - 1 : -1, eta_x,
                                  st)) != DG_OK)
       return rc;
-    if ((rc = launch_project_batch(b->proj_variant, b->t_proj, b->d_pre_proj, n, b->pre_proj[n],
-                                   st)) != DG_OK)
-      return rc;
-    if ((rc = launch_channel_batch(b->t_chan, b->d_pre_chan, n, b->pre_chan[n], channel_mode, eta_s,
-                                   onsager, t, 0, st)) != DG_OK)
+    // A with the output channel in its epilogue
+    const ChanRun cr{channel_mode, onsager, t, eta_s};
+    if ((rc = launch_project_batch(b->proj_variant, b->t_projc, b->d_pre_proj, n, b->pre_proj[n],
+                                   cr, st)) != DG_OK)
       return rc;
     if ((rc = launch_backproject_batch(b->t_bp, b->d_pre_bp, n, b->pre_bp[n], st)) != DG_OK)
       return rc;
@@ -483,11 +486,13 @@ extern "C" dg_status dg_batch_autotune(dg_batch* b, int32_t reps, void* stream) 
   int best_v = b->proj_variant;
   dg_status rc = DG_OK;
   for (int v = 0; v < 3 && rc == DG_OK; ++v) {
-    rc = launch_project_batch(v, b->t_proj, b->d_pre_proj, b->n, b->pre_proj[b->n], st);  // warm
+    rc = launch_project_batch(v, b->t_proj, b->d_pre_proj, b->n, b->pre_proj[b->n], ChanRun{},
+                              st);  // warm
     if (rc != DG_OK) break;
     (void)hipEventRecord(e0, st);
     for (int k = 0; k < reps && rc == DG_OK; ++k)
-      rc = launch_project_batch(v, b->t_proj, b->d_pre_proj, b->n, b->pre_proj[b->n], st);
+      rc = launch_project_batch(v, b->t_proj, b->d_pre_proj, b->n, b->pre_proj[b->n], ChanRun{},
+                                st);
     (void)hipEventRecord(e1, st);
     (void)hipEventSynchronize(e1);
     float ms = 0.0f;
@@ -525,7 +530,7 @@ extern "C" dg_status dg_plan_autotune(dg_plan* p, const float* img, const float*
   int best_v = p->proj_variant;
   dg_status rc = DG_OK;
   for (int v = 0; v < 3 && rc == DG_OK; ++v) {
-    ProjArgs A{p->rays, img, img_t, sino, p->I, p->M};
+    ProjArgs A{p->rays, img, img_t, sino, p->I, p->M, 0, ChanArgs{}};
     rc = launch_project_variant(v, A, st);
     (void)hipEventRecord(e0, st);
     for (int k = 0; k < reps && rc == DG_OK; ++k) rc = launch_project_variant(v, A, st);

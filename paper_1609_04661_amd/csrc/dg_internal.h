@@ -212,14 +212,6 @@ inline unsigned int grid_for(int64_t n, int block, int64_t cap = 65535) {
 }
 
 // Projector / back-projector argument blocks.
-struct ProjArgs {
-  const RayLine* rays;
-  const float* img;
-  const float* img_t;
-  float* sino;
-  int I;
-  int64_t M;
-};
 struct BpArgs {
   const RayLine* rays;
   const ViewInfo* views;
@@ -243,8 +235,78 @@ struct ChanArgs {
   double* tau_s_out;
   double i0, fro2, N;
   double* partials;
-  int nblk;  // blocks of the channel launch for this slice
+  int nblk;  // blocks of the launch that writes the partials, for this slice
 };
+
+// Projector arguments.  With chan_on the projector also applies the output
+// channel to its rays (Alg. 1 step 2, fused form: chan.zp unused, one FP64
+// partial of sum(1 - Var/tau_p) per projector workgroup) instead of storing z.
+struct ProjArgs {
+  const RayLine* rays;
+  const float* img;
+  const float* img_t;
+  float* sino;
+  int I;
+  int64_t M;
+  int chan_on;
+  ChanArgs chan;
+};
+// Per-iteration parameters of a fused output channel.
+struct ChanRun {
+  int mode;
+  int onsager;
+  int t;
+  double eta_s;
+};
+
+struct ChanOut {
+  float s;
+  float one_minus_v;  // 1 - Var/tau_p
+};
+
+// The Poisson output channel for one ray (see channel.hip for the method).
+__device__ __forceinline__ ChanOut poisson_channel(float p, float y, float tau_p, float ln_i0,
+                                                   int mode) {
+  const float ty = tau_p * y;
+  const float ln_tp = logf(tau_p);
+  const float C = ln_i0 - p;  // F(delta) = delta + ln w - ln tau_p - C
+  // starting point: w0 ~ W0(e^xi), xi = ln(tau_p I0) + tau_p y - p
+  const float xi = ln_tp + C + ty;
+  float w0;
+  if (xi > 1.0f) {
+    const float lx = logf(xi);
+    w0 = xi - lx + lx / xi;
+  } else {
+    const float e = expf(fmaxf(xi, -80.0f));
+    w0 = e / (1.0f + e) * (1.0f + 0.5f * e / (1.0f + e));
+  }
+  float delta = w0 - ty;
+  // Halley on F with F' = (w+1)/w and F'' = -1/w^2, written without 1/w so
+  // that no term overflows for small w; Newton when the Halley denominator
+  // is not safely positive.
+#pragma unroll
+  for (int it = 0; it < 5; ++it) {
+    const float w = fmaxf(delta + ty, 1e-30f);
+    const float F = delta + logf(w) - ln_tp - C;
+    const float w1 = w + 1.0f;
+    const float den = 2.0f * w1 * w1 + F;
+    delta -= (den > w1 * w1) ? 2.0f * F * w1 * w / den : F * w / w1;
+  }
+  const float w = fmaxf(delta + ty, 1e-30f);
+  const float u = 1.0f / (1.0f + w);
+  ChanOut o;
+  if (mode == DG_CHANNEL_MODE_ONLY) {
+    o.s = delta / tau_p;
+    o.one_minus_v = 1.0f - u;
+    return o;
+  }
+  const float u2 = u * u;
+  o.s = delta / tau_p + 0.5f * w * u2;
+  float v = u - 0.5f * w * tau_p * u2 * u + w * w * tau_p * u2 * u2;
+  v = fminf(fmaxf(v, 0.0f), 1.0f);
+  o.one_minus_v = 1.0f - v;
+  return o;
+}
 
 // tau_s (and in the iteration: its damping, tau_p, tau_r, status) from the
 // output channel's per-block partial sums; one workgroup, result written by

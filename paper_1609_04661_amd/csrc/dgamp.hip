@@ -13,16 +13,14 @@
 
 namespace dg {
 
-dg_status launch_channel_fused(int64_t M, const float* z, const float* y, float* s, double* scal,
-                               double i0, int mode, double fro2, double N, double eta_s,
-                               int onsager, int t, double* partials, int finish,
-                               ChanArgs* out_args, hipStream_t st);
 dg_status check_denoise_params(const dg_plan* p, int kind, const void* params);
 dg_status launch_denoiser(const dg_plan* p, int kind, const void* params, const float* r,
                           const double* tau_r, const double* eps, uint64_t seed, int iter,
                           float* x_den, float* x_pert, hipStream_t st, const EpsFinish* ef,
                           const DivFuse* df);
 unsigned int nlm_blocks(int I);
+unsigned int project_blocks(int64_t M);
+dg_status launch_project_run(int variant, const ProjArgs& A, const ChanRun& cr, hipStream_t s);
 dg_status launch_div_finish(const DivArgs& A, double eta_x, int t, hipStream_t st);
 int prec_row_blocks(int I);
 dg_status launch_div(const dg_plan* p, const float* xden, const float* xpert, float* x,
@@ -56,7 +54,10 @@ static size_t iter_work_layout(const dg_plan* p, void* base, IterWork* w) {
     return ptr;
   };
   IterWork t;
-  t.dpart = (double*)take(sizeof(double) * kMaxBlocks);
+  // per-workgroup FP64 partials: the projector's (fused channel), the
+  // divergence pass's
+  const size_t np = project_blocks(p->M);
+  t.dpart = (double*)take(sizeof(double) * (np > (size_t)kMaxBlocks ? np : (size_t)kMaxBlocks));
   t.npart = (double*)take(sizeof(double) * nlm_blocks(p->I));
   t.fpart = (float*)take(sizeof(float) * kMaxBlocks);
   const size_t nb = sizeof(float) * (size_t)p->N, mb = sizeof(float) * (size_t)p->M;
@@ -225,14 +226,15 @@ extern "C" dg_status dgamp_iterate(const dg_plan* p, const float* y, const dgamp
     if ((rc = launch_precondition(p, a, s)) != DG_OK) return rc;
     if (nlm && it > 0 && (rc = log_it(it - 1)) != DG_OK) return rc;
     if ((rc = mark(it, 1)) != DG_OK) return rc;
-    if ((rc = launch_project(p, w.mu, w.mu_t, w.z, s)) != DG_OK) return rc;
+    // A with the output channel applied to every ray in the same launch; the
+    // channel's finish (tau_s, tau_r) runs in the first row workgroup of the
+    // next preconditioner application, and NLM finishes the MC step
+    const ChanArgs chan{p->M, nullptr, y,      st->s,   nullptr, nullptr, st->scal,
+                        nullptr, o->i0, o->fro2, N, w.dpart, (int)project_blocks(p->M)};
+    const ProjArgs pa{p->rays, w.mu, w.mu_t, w.z, p->I, p->M, 1, chan};
+    const ChanRun cr{o->channel_mode, o->onsager, t, o->eta_s};
+    if ((rc = launch_project_run(p->proj_variant, pa, cr, s)) != DG_OK) return rc;
     if ((rc = mark(it, 2)) != DG_OK) return rc;
-    // the channel's finish (tau_s, tau_r) runs in the first row workgroup of
-    // the next preconditioner application, and NLM finishes the MC step
-    ChanArgs chan;
-    if ((rc = launch_channel_fused(p->M, w.z, y, st->s, st->scal, o->i0, o->channel_mode, o->fro2,
-                                   N, o->eta_s, o->onsager, t, w.dpart, 0, &chan, s)) != DG_OK)
-      return rc;
     if ((rc = mark(it, 3)) != DG_OK) return rc;
     if ((rc = launch_backproject(p, st->s, w.g, s)) != DG_OK) return rc;
     if ((rc = mark(it, 4)) != DG_OK) return rc;

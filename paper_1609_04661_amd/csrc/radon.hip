@@ -33,7 +33,8 @@ static constexpr int kBpBlockX = 64, kBpBlockY = 4;
 static constexpr int kMarch = 16;
 
 template <int SEGS>
-__device__ void project_body(const ProjArgs& A, int blk, float (*part)[kRaysPerBlock]) {
+__device__ void project_body(const ProjArgs& A, int blk, float (*part)[kRaysPerBlock],
+                             const ChanRun& cr) {
   const int lane = threadIdx.x % kRaysPerBlock, seg = threadIdx.x / kRaysPerBlock;
   const int64_t r = (int64_t)blk * kRaysPerBlock + lane;
   const int I = A.I;
@@ -144,25 +145,51 @@ __device__ void project_body(const ProjArgs& A, int blk, float (*part)[kRaysPerB
   }
   part[seg][lane] = acc;
   __syncthreads();
-  if (seg == 0 && r < A.M) {
-    float t = part[0][lane];
+  if (seg != 0) return;
+  float z = 0.0f;
+  if (r < A.M) {
+    z = part[0][lane];
 #pragma unroll
-    for (int g = 1; g < SEGS; ++g) t += part[g][lane];
-    A.sino[r] = t * fabsf(L.pl);
+    for (int g = 1; g < SEGS; ++g) z += part[g][lane];
+    z *= fabsf(L.pl);
+    if (!A.chan_on) A.sino[r] = z;
   }
+  if (!A.chan_on) return;
+  // fused output channel on wavefront 0 (this workgroup's 64 rays): as
+  // channel_body, frozen once the status word is set
+  const ChanArgs& C = A.chan;
+  if (C.scal[DG_S_STATUS] != 0.0) return;
+  const double tau_p_d = C.fro2 * C.scal[DG_S_TAU_X] / (double)C.M;
+  const float tau_p = (float)tau_p_d;
+  double one_minus_v = 0.0;
+  if (r < A.M) {
+    float p = z;
+    const float s_prev = C.s_io[r];
+    if (cr.onsager) p = __fmaf_rn(-tau_p, s_prev, p);
+    const ChanOut o = poisson_channel(p, C.y[r], tau_p, (float)log(C.i0), cr.mode);
+    float sv = o.s;
+    if (cr.t > 0) {
+      const float eta = (float)cr.eta_s;
+      sv = __fmaf_rn(eta, sv, (1.0f - eta) * s_prev);
+    }
+    C.s_io[r] = sv;
+    one_minus_v = (double)o.one_minus_v;
+  }
+  const double bs = wave_sum(one_minus_v);
+  if (lane == 0) C.partials[blk] = bs;
 }
 
 template <int SEGS>
-__global__ void __launch_bounds__(kRaysPerBlock * SEGS) project_kernel(ProjArgs A) {
+__global__ void __launch_bounds__(kRaysPerBlock * SEGS) project_kernel(ProjArgs A, ChanRun cr) {
   __shared__ float part[SEGS][kRaysPerBlock];
-  project_body<SEGS>(A, blockIdx.x, part);
+  project_body<SEGS>(A, blockIdx.x, part, cr);
 }
 template <int SEGS>
 __global__ void __launch_bounds__(kRaysPerBlock * SEGS)
-project_batch(const ProjArgs* __restrict__ T, const int* __restrict__ prefix, int n) {
+project_batch(const ProjArgs* __restrict__ T, const int* __restrict__ prefix, int n, ChanRun cr) {
   __shared__ float part[SEGS][kRaysPerBlock];
   const int s = slice_of(prefix, n, blockIdx.x);
-  project_body<SEGS>(T[s], blockIdx.x - prefix[s], part);
+  project_body<SEGS>(T[s], blockIdx.x - prefix[s], part, cr);
 }
 
 // Weight of pixel (i, j) on a ray: the same fixed-point cross coordinate and
@@ -328,34 +355,42 @@ unsigned int backproject_blocks(int I) {
   return (unsigned int)(((I + kBpBlockX - 1) / kBpBlockX) * ((I + kBpBlockY - 1) / kBpBlockY));
 }
 
-dg_status launch_project_variant(int variant, const ProjArgs& A, hipStream_t s) {
+// cr applies only when A.chan_on (the fused output channel).
+dg_status launch_project_run(int variant, const ProjArgs& A, const ChanRun& cr, hipStream_t s) {
   const dim3 grid(project_blocks(A.M));
   switch (variant) {
     case 0:
-      hipLaunchKernelGGL(project_kernel<2>, grid, dim3(kRaysPerBlock * 2), 0, s, A);
+      hipLaunchKernelGGL(project_kernel<2>, grid, dim3(kRaysPerBlock * 2), 0, s, A, cr);
       break;
     case 2:
-      hipLaunchKernelGGL(project_kernel<8>, grid, dim3(kRaysPerBlock * 8), 0, s, A);
+      hipLaunchKernelGGL(project_kernel<8>, grid, dim3(kRaysPerBlock * 8), 0, s, A, cr);
       break;
     default:
-      hipLaunchKernelGGL(project_kernel<4>, grid, dim3(kRaysPerBlock * 4), 0, s, A);
+      hipLaunchKernelGGL(project_kernel<4>, grid, dim3(kRaysPerBlock * 4), 0, s, A, cr);
       break;
   }
   DG_LAUNCH_CHECK("project_kernel");
   return DG_OK;
 }
 
+dg_status launch_project_variant(int variant, const ProjArgs& A, hipStream_t s) {
+  return launch_project_run(variant, A, ChanRun{}, s);
+}
+
 dg_status launch_project_batch(int variant, const ProjArgs* T, const int* prefix, int n, int total,
-                               hipStream_t s) {
+                               const ChanRun& cr, hipStream_t s) {
   switch (variant) {
     case 0:
-      hipLaunchKernelGGL(project_batch<2>, dim3(total), dim3(kRaysPerBlock * 2), 0, s, T, prefix, n);
+      hipLaunchKernelGGL(project_batch<2>, dim3(total), dim3(kRaysPerBlock * 2), 0, s, T, prefix, n,
+                         cr);
       break;
     case 2:
-      hipLaunchKernelGGL(project_batch<8>, dim3(total), dim3(kRaysPerBlock * 8), 0, s, T, prefix, n);
+      hipLaunchKernelGGL(project_batch<8>, dim3(total), dim3(kRaysPerBlock * 8), 0, s, T, prefix, n,
+                         cr);
       break;
     default:
-      hipLaunchKernelGGL(project_batch<4>, dim3(total), dim3(kRaysPerBlock * 4), 0, s, T, prefix, n);
+      hipLaunchKernelGGL(project_batch<4>, dim3(total), dim3(kRaysPerBlock * 4), 0, s, T, prefix, n,
+                         cr);
       break;
   }
   DG_LAUNCH_CHECK("project_batch");
@@ -371,7 +406,7 @@ dg_status launch_backproject_batch(const BpArgs* T, const int* prefix, int n, in
 
 dg_status launch_project(const dg_plan* p, const float* img, const float* img_t, float* sino,
                          hipStream_t s) {
-  ProjArgs A{p->rays, img, img_t, sino, p->I, p->M};
+  ProjArgs A{p->rays, img, img_t, sino, p->I, p->M, 0, ChanArgs{}};
   return launch_project_variant(p->proj_variant, A, s);
 }
 
