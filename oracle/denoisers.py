@@ -15,7 +15,17 @@ build's, the paper treats D as a black box):
     (2sr+1)^2 search window, weight exp(-max(d2 - 2 sigma^2, 0)/(hfac sigma)^2),
     sigma = sqrt(tau_r), half-sample symmetric borders), from the C core.
 
+  * prox_tv: the proximal map of isotropic total variation (the paper's
+    second plug-in family, Sec. 6 "Proximal-based TV denoiser"),
+    x = argmin 1/2 ||x - r||^2 + lam TV(x), lam = alpha * sqrt(tau_r), with
+    forward differences and zero difference past the last row / column,
+    approximated by a fixed number K of fast gradient projection steps on
+    the dual problem (Beck & Teboulle 2009): the map D is those K steps.
+
 Parity: haar_soft pinned (orthonormality, exact divergence by brute force);
+prox_tv pinned by special cases (constant images fixed, lam -> 0 identity,
+large lam -> the mean), a one-row image against an exact bounded least
+squares solve of the same dual, and the primal-dual gap of converged runs;
 nlm pinned only by special cases (constant images are fixed points; sigma->0
 is the identity; symmetry under image transposition) -- against the paper it
 is unpinned, the paper's BM3D being a different denoiser.
@@ -30,6 +40,7 @@ from .probe import rademacher
 HAAR = 0
 NLM = 1
 CNN = 2
+TV = 3
 
 SQ2 = math.sqrt(2.0)
 
@@ -107,6 +118,74 @@ def nlm(r, tau_r, pr=2, sr=10, hfac=0.4):
     return out
 
 
+def grad_fwd(x):
+    """Forward differences (g1 down the rows, g2 along the columns), zero past
+    the last row / column."""
+    g1 = np.zeros_like(x)
+    g2 = np.zeros_like(x)
+    g1[:-1, :] = x[1:, :] - x[:-1, :]
+    g2[:, :-1] = x[:, 1:] - x[:, :-1]
+    return g1, g2
+
+
+def grad_adj(p1, p2):
+    """The adjoint of grad_fwd (minus the discrete divergence)."""
+    a = np.zeros_like(p1)
+    a[:-1, :] -= p1[:-1, :]
+    a[1:, :] += p1[:-1, :]
+    a[:, :-1] -= p2[:, :-1]
+    a[:, 1:] += p2[:, :-1]
+    return a
+
+
+def tv_iso(x):
+    g1, g2 = grad_fwd(x)
+    return float(np.sum(np.sqrt(g1 * g1 + g2 * g2)))
+
+
+def fgp_momentum(K):
+    """beta_k = (t_k - 1) / t_{k+1}, t_1 = 1, t_{k+1} = (1 + sqrt(1 + 4 t_k^2)) / 2,
+    for k = 1 .. K."""
+    t, out = 1.0, []
+    for _ in range(K):
+        t1 = (1.0 + math.sqrt(1.0 + 4.0 * t * t)) / 2.0
+        out.append((t - 1.0) / t1)
+        t = t1
+    return out
+
+
+def prox_tv_lam(b, lam, K=50):
+    """K fast-gradient-projection steps on the dual of
+    min_x 1/2 ||x - b||^2 + lam TV(x):  with x(p) = b - lam grad^T p, the dual
+    min_{|p_ij| <= 1} 1/2 ||lam grad^T p - b||^2 has gradient -lam grad x(p)
+    and Lipschitz constant 8 lam^2; each step takes
+        p_k = P(u_k + grad x(u_k) / (8 lam)),  u_{k+1} = p_k + beta_k (p_k - p_{k-1})
+    from p_0 = u_1 = 0, P the pointwise projection onto the unit disc, and
+    returns x(p_K) and p_K."""
+    b = np.asarray(b, dtype=np.float64)
+    p1 = np.zeros_like(b)
+    p2 = np.zeros_like(b)
+    if not lam > 0.0:
+        return b.copy(), (p1, p2)
+    u1, u2 = p1.copy(), p2.copy()
+    for beta in fgp_momentum(K):
+        x = b - lam * grad_adj(u1, u2)
+        g1, g2 = grad_fwd(x)
+        q1 = u1 + g1 / (8.0 * lam)
+        q2 = u2 + g2 / (8.0 * lam)
+        nrm = np.maximum(1.0, np.sqrt(q1 * q1 + q2 * q2))
+        n1, n2 = q1 / nrm, q2 / nrm
+        u1 = n1 + beta * (n1 - p1)
+        u2 = n2 + beta * (n2 - p2)
+        p1, p2 = n1, n2
+    return b - lam * grad_adj(p1, p2), (p1, p2)
+
+
+def prox_tv(r, tau_r, alpha=0.5, iters=50):
+    lam = alpha * math.sqrt(max(tau_r, 0.0))
+    return prox_tv_lam(r, lam, iters)[0]
+
+
 def apply(kind, r, tau_r, params):
     if kind == HAAR:
         return haar_soft(r, tau_r, **params)
@@ -115,6 +194,8 @@ def apply(kind, r, tau_r, params):
     if kind == CNN:
         from . import cnn
         return cnn.denoise(r, params["net"])
+    if kind == TV:
+        return prox_tv(r, tau_r, **params)
     raise ValueError("unknown denoiser kind")
 
 
