@@ -136,17 +136,31 @@ dg_status gamp_poisson_out(int64_t m, const float* p, const float* y, const doub
  *                on detail coefficients (I <= 512, levels = log2 I - 2 by default)
  *   DG_DEN_NLM : non-local means, sigma = sqrt(tau_r)
  *   DG_DEN_CNN : residual CNN (see dg_cnn_params)
+ *   DG_DEN_TV  : proximal isotropic total variation (Sec. 6, "Proximal-based TV
+ *                denoiser"): argmin_x 1/2 ||x - r||^2 + lam TV(x), lam = alpha
+ *                sqrt(tau_r), forward differences with zero difference past the
+ *                last row / column, as `iters` fast gradient projection steps on
+ *                the dual (Beck & Teboulle 2009) from a zero dual; the map is
+ *                those steps.  work: device, dg_tv_workspace_bytes(I*I) bytes,
+ *                owned by the caller, overwritten by every call.
  * r, x_out: I*I floats; tau_r: device double; div_out: device double or NULL
  * (NULL skips the probe evaluation).  work: dg_workspace_bytes(DG_OP_DENOISE). */
 #define DG_DEN_HAAR 0
 #define DG_DEN_NLM 1
 #define DG_DEN_CNN 2
+#define DG_DEN_TV 3
 typedef struct dg_haar_params { double alpha; int32_t levels; /* 0 = log2 I - 2 */ } dg_haar_params;
 typedef struct dg_nlm_params { int32_t patch_radius; int32_t search_radius; double hfac; } dg_nlm_params;
 typedef struct dg_cnn_params {
   const void* weights;  /* device: packed network, dg_cnn_weight_bytes() bytes   */
   void* work;           /* device: dg_cnn_workspace_bytes(I*I) bytes (activations) */
 } dg_cnn_params;
+typedef struct dg_tv_params {
+  double alpha;   /* lam = alpha * sqrt(tau_r), >= 0                            */
+  int32_t iters;  /* fast gradient projection steps, 1 .. 10000                 */
+  void* work;     /* device: dg_tv_workspace_bytes(I*I) bytes (dual state)      */
+} dg_tv_params;
+size_t dg_tv_workspace_bytes(int64_t n_pixels);
 dg_status denoise(const dg_plan* plan, int32_t kind, const void* params, const float* r,
                   const double* tau_r, uint64_t probe_seed, int32_t iter, double eps_rel,
                   float* x_out, double* div_out, void* work, void* stream);

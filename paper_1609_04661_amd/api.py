@@ -16,7 +16,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libdgampct.so")
 
 PARALLEL, FAN = 0, 1
-DEN_HAAR, DEN_NLM, DEN_CNN = 0, 1, 2
+DEN_HAAR, DEN_NLM, DEN_CNN, DEN_TV = 0, 1, 2, 3
 CHANNEL_LAPLACE, CHANNEL_MODE_ONLY = 0, 1
 OP_PRECOND, OP_DENOISE, OP_DGAMP, OP_FRO2 = 0, 1, 2, 3
 NSCAL = 16
@@ -36,7 +36,7 @@ EXPORTS = ("dg_plan_create", "dg_plan_destroy", "dg_workspace_bytes", "dg_channe
            "dgamp_batch_iterate", "dg_batch_graph_create", "dg_batch_autotune",
            "dg_batch_projector_variant", "dg_plan_autotune", "dg_plan_projector_variant",
            "dg_batch_set_projector_variant", "dg_plan_set_projector_variant",
-           "dg_psnr_workspace_bytes", "dg_psnr")
+           "dg_psnr_workspace_bytes", "dg_psnr", "dg_tv_workspace_bytes")
 
 
 class DgError(RuntimeError):
@@ -62,6 +62,10 @@ class NlmParams(ctypes.Structure):
 
 class CnnParams(ctypes.Structure):
     _fields_ = [("weights", ctypes.c_void_p), ("work", ctypes.c_void_p)]
+
+
+class TvParams(ctypes.Structure):
+    _fields_ = [("alpha", ctypes.c_double), ("iters", ctypes.c_int32), ("work", ctypes.c_void_p)]
 
 
 class DgampOpts(ctypes.Structure):
@@ -135,6 +139,7 @@ def load():
         "dg_plan_set_projector_variant": ([_VP, i32], i32),
         "dg_psnr_workspace_bytes": ([], sz),
         "dg_psnr": ([i64, _VP, _VP, _VP, _VP, _VP], i32),
+        "dg_tv_workspace_bytes": ([i64], sz),
     }
     missing = set(EXPORTS) - set(sig)
     if missing:
@@ -275,6 +280,14 @@ def make_params(kind, **kw):
         net = kw["net"]
         return CnnParams(weights=ctypes.c_void_p(net.packed.data_ptr()),
                          work=ctypes.c_void_p(net.work_for(kw["n_pixels"]).data_ptr()))
+    if kind == DEN_TV:
+        # the dual-state buffer lives as long as the params object
+        buf = torch.empty(int(load().dg_tv_workspace_bytes(int(kw["n_pixels"]))), dtype=torch.uint8,
+                          device="cuda")
+        prm = TvParams(alpha=kw.get("alpha", 0.5), iters=kw.get("iters", 50),
+                       work=ctypes.c_void_p(buf.data_ptr()))
+        prm._buf = buf
+        return prm
     raise DgError("unknown denoiser kind")
 
 

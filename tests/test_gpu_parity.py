@@ -303,3 +303,46 @@ def test_psnr_matches_oracle(gpu_lib, n):
     got = float(gpu_lib.dg_psnr(cu(est), cu(ref)).item())
     assert abs(got - metrics.psnr(est, ref)) <= 1e-9, (got, metrics.psnr(est, ref))
     assert math.isinf(float(gpu_lib.dg_psnr(cu(ref), cu(ref)).item()))
+
+
+@pytest.mark.parametrize("I,noise,tau", [(64, 0.004, 1.6e-5), (100, 0.05, 2.5e-3), (512, 0.05, 2.5e-3)])
+def test_prox_tv_matches_oracle(gpu_lib, I, noise, tau):
+    """The proximal-TV denoiser (50 dual steps) and its MC divergence against
+    the oracle's same steps in FP64; a ragged side (100) and the C2 side."""
+    g = synth.geometry(synth.PARALLEL, I, 1.0, 4, I + 1, math.pi)
+    P = gpu_lib.Plan(g)
+    r = synth.ellipse_phantom(I, 8) + noise * np.random.default_rng(3).standard_normal((I, I))
+    r32 = r.astype(np.float32).astype(np.float64)
+    prm = gpu_lib.make_params(gpu_lib.DEN_TV, alpha=0.5, iters=50, n_pixels=I * I)
+    x, div = gpu_lib.denoise(P, gpu_lib.DEN_TV, prm, cu(r32), cu([tau], torch.float64),
+                             probe_seed=9, iteration=2)
+    x_ref = oden.prox_tv(r32, tau, alpha=0.5, iters=50)
+    # FP32 over 50 steps of a non-expansive map: errors stay near a few ulps of |x|
+    assert rel_l2(host(x), x_ref) <= 1e-5, rel_l2(host(x), x_ref)
+    div_ref, _ = oden.mc_divergence(oden.TV, r32, tau, dict(alpha=0.5, iters=50), x_ref, 9, 2)
+    assert abs(float(host(div)[0]) - div_ref) <= 2e-3, (float(host(div)[0]), div_ref)
+
+
+def test_prox_tv_identity_at_zero_variance(gpu_lib, plans):
+    I = 64
+    g = synth.geometry(synth.PARALLEL, I, 1.0, 4, I + 1, math.pi)
+    P = gpu_lib.Plan(g)
+    r = np.random.default_rng(4).standard_normal((I, I)).astype(np.float32)
+    prm = gpu_lib.make_params(gpu_lib.DEN_TV, alpha=0.5, iters=5, n_pixels=I * I)
+    x, _ = gpu_lib.denoise(P, gpu_lib.DEN_TV, prm, cu(r), cu([0.0], torch.float64), with_div=False)
+    assert np.array_equal(host(x), r)
+
+
+def test_dgamp_c1_prox_tv_matches_oracle(gpu_lib, plans):
+    """D-GAMP-CT with the proximal-TV plug-in (C1 inputs, 20 iterations)."""
+    g, R, mu, y, fro2 = c1_inputs()
+    T, eta, seed = 20, 0.5, 13
+    params = dict(alpha=0.5, iters=50)
+    ref_mu, ref_log, _ = ogamp.dgamp_ct(R, y, 1e4, fro2, T, oden.TV, params, seed,
+                                        eta_x=eta, eta_s=eta)
+    out_mu, log, st = run_gpu_dgamp(gpu_lib, plans["c1"], y, fro2, 1e4, T, gpu_lib.DEN_TV,
+                                    gpu_lib.make_params(gpu_lib.DEN_TV, n_pixels=64 * 64, **params),
+                                    seed, eta)
+    assert float(host(st.scal)[gpu_lib.S_STATUS]) == 0.0
+    p_ref, p_gpu = metrics.psnr(ref_mu, mu), metrics.psnr(out_mu, mu)
+    assert abs(p_gpu - p_ref) <= 0.1, (p_gpu, p_ref)
