@@ -50,7 +50,7 @@ WEIGHTS = os.path.join(ROOT, "paper_1609_04661_amd", "weights", "cnn_c2_x_space.
 
 # configured recursion for these workloads (damping of means and variances)
 CFG = dict(i0=1e5, seed=1002, probe_seed=7, eta=0.15, tau_x0=1.0, fro2_probes=16,
-           nlm=dict(pr=2, sr=10, hfac=0.4))
+           nlm=dict(pr=2, sr=10, hfac=0.4), tv=dict(alpha=1.0, iters=50))
 # HBM bytes per launch of nlm_kernel<2> at this workload, from two rocprofv3
 # counter passes (FETCH_SIZE, WRITE_SIZE) scaled by a 256 MiB copy kernel
 # (profiles/dgamp_c2_512x512_64views_hbm_traffic.md).  Set to None whenever
@@ -380,6 +380,42 @@ def ablation(api, h, T=50):
     return out
 
 
+def proxtv(api, args, h, T=50):
+    """The proximal-TV plug-in (NEXT rank 2, Sec. 6) on the headline inputs at
+    the configured damping: PSNR after every iteration, ms per iteration from
+    a graph replay of the whole run, and the iteration at which it reaches
+    the plain (NLM) run's final PSNR."""
+    import torch
+    plan, y_d, fro2, mu_d, work = h["plan"], h["y_d"], h["fro2"], h["mu_d"], h["work"]
+    params = api.make_params(api.DEN_TV, n_pixels=plan.N, **CFG["tv"])
+    kw = dict(probe_seed=CFG["probe_seed"], eta_x=CFG["eta"], eta_s=CFG["eta"])
+    mu_out = torch.empty((plan.I, plan.I), dtype=torch.float32, device="cuda")
+    st = api.DgampState(plan, CFG["tau_x0"])
+    ps = torch.empty(T, dtype=torch.float64, device="cuda")
+    for t in range(T):
+        api.dgamp_iterate(plan, y_d, st, 1, fro2, CFG["i0"], api.DEN_TV, params, mu_out=mu_out,
+                          work=work, **kw)
+        api.dg_psnr(mu_out, mu_d, out=ps[t:t + 1])
+    curve = [float(v) for v in ps.cpu().numpy()]
+    gst = api.DgampState(plan, CFG["tau_x0"])
+    G = api.DgampGraph(plan, y_d, gst, T, fro2, CFG["i0"], api.DEN_TV, params,
+                       tau_x0=CFG["tau_x0"], mu_out=mu_out, work=work, **kw)
+    G.launch()
+    s = sync_time(G.launch, args.reps)
+    out = dict(iterations=T, alpha=CFG["tv"]["alpha"], dual_steps=CFG["tv"]["iters"],
+               damping=CFG["eta"], ms_per_iter=1e3 * s / T, iter_per_s=T / s,
+               psnr_final=curve[-1], psnr_every_5=[round(v, 3) for v in curve[4::5]],
+               status=float(gst.scal[api.S_STATUS].item()))
+    target = h.get("plain_psnr")
+    if target is not None:
+        k = first_reaching(curve, target)
+        out["plain_target_psnr_db"] = target
+        out["iters_to_plain_psnr"] = k
+        if k is not None:
+            out["ms_to_plain_psnr"] = k * out["ms_per_iter"]
+    return out
+
+
 def run_batch(api, synth, slices, phantoms, den, T, reps, autotune, net=None):
     """One batch: counts from the library's projector, Hutchinson fro2 per
     slice, graph of the whole T-iteration run; returns timing and PSNRs."""
@@ -440,8 +476,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--only-headline", action="store_true",
                     help="skip the learned, batched and fan-beam figures")
-    ap.add_argument("--parts", default="headline,learned,batch,fan,ablation",
-                    help="comma-separated subset of headline,learned,batch,fan,ablation")
+    ap.add_argument("--parts", default="headline,learned,batch,fan,ablation,proxtv",
+                    help="comma-separated subset of headline,learned,batch,fan,ablation,proxtv")
     ap.add_argument("--learned-iters", type=int, default=50)
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="first copy this many MiB device-to-device 3 times (a kernel of known "
@@ -497,6 +533,10 @@ def main():
     if "ablation" in parts:
         print("ablation", file=sys.stderr, flush=True)
         res["ablation"] = ablation(api, h)
+    if "proxtv" in parts:
+        print("proxtv", file=sys.stderr, flush=True)
+        h["plain_psnr"] = res["psnr_db_after_steps"] if args.steps == 50 else None
+        res["proxtv"] = proxtv(api, args, h)
     if "batch" in parts:
         print("batch_uneven", file=sys.stderr, flush=True)
         res["batch_uneven"] = run_batch(api, synth, c3, phantoms[1:1 + len(c3)], "nlm",

@@ -63,6 +63,15 @@ def test_workspace_query_null_plan():
     assert L.dg_channel_workspace_bytes(1000) > 0
 
 
+def test_tv_workspace_size():
+    """The proximal-TV dual state: the perturbed input plus p and u, ping and
+    pong, two components, two images: 17 planes of 256-byte-aligned floats."""
+    L = api.load()
+    assert L.dg_tv_workspace_bytes(0) == 0
+    assert L.dg_tv_workspace_bytes(512 * 512) == 17 * 512 * 512 * 4
+    assert L.dg_tv_workspace_bytes(10) == 17 * 256
+
+
 def test_product_path_has_no_cpu_fallback():
     # the binding must not import the oracle and must refuse non-CUDA tensors
     import torch

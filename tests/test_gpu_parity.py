@@ -305,21 +305,25 @@ def test_psnr_matches_oracle(gpu_lib, n):
     assert math.isinf(float(gpu_lib.dg_psnr(cu(ref), cu(ref)).item()))
 
 
-@pytest.mark.parametrize("I,noise,tau", [(64, 0.004, 1.6e-5), (100, 0.05, 2.5e-3), (512, 0.05, 2.5e-3)])
-def test_prox_tv_matches_oracle(gpu_lib, I, noise, tau):
-    """The proximal-TV denoiser (50 dual steps) and its MC divergence against
-    the oracle's same steps in FP64; a ragged side (100) and the C2 side."""
+@pytest.mark.parametrize("I,noise,tau,iters", [(64, 0.004, 1.6e-5, 50), (100, 0.05, 2.5e-3, 50),
+                                               (512, 0.05, 2.5e-3, 50), (70, 0.05, 2.5e-3, 13),
+                                               (40, 0.05, 2.5e-3, 1)])
+def test_prox_tv_matches_oracle(gpu_lib, I, noise, tau, iters):
+    """The proximal-TV denoiser and its MC divergence against the oracle's
+    same dual steps in FP64: ragged sides (100, 70, 40 against 32-pixel
+    tiles), the C2 side, and step counts that are not a multiple of the
+    steps grouped per launch (13, 1)."""
     g = synth.geometry(synth.PARALLEL, I, 1.0, 4, I + 1, math.pi)
     P = gpu_lib.Plan(g)
     r = synth.ellipse_phantom(I, 8) + noise * np.random.default_rng(3).standard_normal((I, I))
     r32 = r.astype(np.float32).astype(np.float64)
-    prm = gpu_lib.make_params(gpu_lib.DEN_TV, alpha=0.5, iters=50, n_pixels=I * I)
+    prm = gpu_lib.make_params(gpu_lib.DEN_TV, alpha=0.5, iters=iters, n_pixels=I * I)
     x, div = gpu_lib.denoise(P, gpu_lib.DEN_TV, prm, cu(r32), cu([tau], torch.float64),
                              probe_seed=9, iteration=2)
-    x_ref = oden.prox_tv(r32, tau, alpha=0.5, iters=50)
+    x_ref = oden.prox_tv(r32, tau, alpha=0.5, iters=iters)
     # FP32 over 50 steps of a non-expansive map: errors stay near a few ulps of |x|
     assert rel_l2(host(x), x_ref) <= 1e-5, rel_l2(host(x), x_ref)
-    div_ref, _ = oden.mc_divergence(oden.TV, r32, tau, dict(alpha=0.5, iters=50), x_ref, 9, 2)
+    div_ref, _ = oden.mc_divergence(oden.TV, r32, tau, dict(alpha=0.5, iters=iters), x_ref, 9, 2)
     assert abs(float(host(div)[0]) - div_ref) <= 2e-3, (float(host(div)[0]), div_ref)
 
 
