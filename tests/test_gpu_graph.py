@@ -41,3 +41,37 @@ def test_graph_replay_equals_eager(gpu_lib, kind):
         assert np.array_equal(out.cpu().numpy(), ref), rep
         assert float(st2.scal[gpu_lib.S_STATUS].item()) == 0.0
         del junk
+
+
+@pytest.mark.parametrize("kind", ["nlm", "tv"])
+def test_split_calls_equal_one_call(gpu_lib, kind):
+    """T iterations in one dgamp_iterate call against T calls of one iteration
+    (with and without mu_out): with NLM the divergence step's scalar finish
+    is deferred into the next V^-1 x or the call's end, so the state, the log
+    rows and mu must not depend on how the iterations are split."""
+    g = synth.c1_geometry()
+    R = radon.Radon(g)
+    mu = synth.ellipse_phantom(64, 1001)
+    y = torch.as_tensor(synth.poisson_counts(R.project(mu), 1e4, 1001), dtype=torch.float32).cuda()
+    fro2 = ogamp.fro2_hutchinson(R, 8, 5)
+    plan = gpu_lib.Plan(g)
+    den = gpu_lib.DEN_NLM if kind == "nlm" else gpu_lib.DEN_TV
+    params = gpu_lib.make_params(den) if kind == "nlm" else gpu_lib.make_params(den, n_pixels=64 * 64)
+    T = 5
+    kw = dict(probe_seed=3, eta_x=0.5, eta_s=0.5)
+    st1 = gpu_lib.DgampState(plan, 1.0)
+    mu1 = torch.empty((64, 64), dtype=torch.float32, device="cuda")
+    log1 = torch.zeros(T * gpu_lib.LOG_STRIDE, dtype=torch.float64, device="cuda")
+    gpu_lib.dgamp_iterate(plan, y, st1, T, fro2, 1e4, den, params, mu_out=mu1, log=log1, **kw)
+    st2 = gpu_lib.DgampState(plan, 1.0)
+    mu2 = torch.empty((64, 64), dtype=torch.float32, device="cuda")
+    log2 = torch.zeros(T * gpu_lib.LOG_STRIDE, dtype=torch.float64, device="cuda")
+    for t in range(T):
+        gpu_lib.dgamp_iterate(plan, y, st2, 1, fro2, 1e4, den, params,
+                              mu_out=mu2 if t % 2 == 0 else None,
+                              log=log2[t * gpu_lib.LOG_STRIDE:(t + 1) * gpu_lib.LOG_STRIDE], **kw)
+    torch.cuda.synchronize()
+    assert torch.equal(st1.x, st2.x) and torch.equal(st1.s, st2.s)
+    assert torch.equal(st1.scal, st2.scal)
+    assert torch.equal(log1, log2)
+    assert torch.equal(mu1, mu2)
