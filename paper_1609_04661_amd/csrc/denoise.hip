@@ -130,7 +130,10 @@ __device__ __forceinline__ void nlm_search(const NlmArgs& Ar, const float* R,
 #pragma unroll
             for (int a = 0; a < BY; ++a) {
               if (a > 0) v += h[a + 2 * P][c] - h[a - 1][c];
-              const float w = __builtin_amdgcn_exp2f(-fmaxf(__fmaf_rn(v, c1, -c2), 0.0f));
+              // 2^-max(y, 0) = min(2^-y, 1): the clamp to [0, 1] folds into
+              // the exp instruction's output modifier
+              const float w =
+                  fminf(fmaxf(__builtin_amdgcn_exp2f(__fmaf_rn(v, -c1, c2)), 0.0f), 1.0f);
               wsum[a][c] += w;
               acc[a][c] = __fmaf_rn(w, win[a + P][(tau + c + P) % WX], acc[a][c]);
             }
