@@ -103,7 +103,6 @@ __device__ void project_body(const ProjArgs& A, int blk, float (*part)[kRaysPerB
     const __amdgpu_buffer_rsrc_t img =
         __builtin_amdgcn_make_buffer_rsrc((void*)lo, (short)0, (int)(unsigned)span, kBufferWord3);
     const unsigned skb = (unsigned)sk * 4u, spb = (unsigned)sp * 4u;
-    unsigned koff = boff + (unsigned)ka * skb;  // byte offset of major index k
     uint32_t qlo = (uint32_t)(uint64_t)q, qhi = (uint32_t)((uint64_t)q >> 32);
     const uint32_t mlo = (uint32_t)(uint64_t)L.m_fx, mhi = (uint32_t)((uint64_t)L.m_fx >> 32);
     for (int k = ka; k <= kb; k += kMarch) {
@@ -130,10 +129,9 @@ __device__ void project_body(const ProjArgs& A, int blk, float (*part)[kRaysPerB
         w[2 * u] = g0;
         w[2 * u + 1] = g1;
         const bool live = kk <= kb;
-        // 24-bit multiply (full rate): p0 + 1 lies in [0, I] whenever an
-        // offset is used; koff advances by skb per step
-        const unsigned o1 = koff + __umul24((unsigned)(p0 + 1), spb);
-        koff += skb;
+        // 24-bit multiplies (full rate): kk < I and p0 + 1 lies in [0, I]
+        // whenever an offset is used, and both strides are at most 4 I bytes
+        const unsigned o1 = boff + __umul24((unsigned)kk, skb) + __umul24((unsigned)(p0 + 1), spb);
         const unsigned off0 = (live && (unsigned)p0 < (unsigned)I) ? o1 - spb : 0xffffffffu;
         const unsigned off1 = (live && (unsigned)(p0 + 1) < (unsigned)I) ? o1 : 0xffffffffu;
         v[2 * u] = __int_as_float(__builtin_amdgcn_raw_buffer_load_b32(img, off0, 0, 0));
