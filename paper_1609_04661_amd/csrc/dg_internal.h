@@ -68,6 +68,8 @@ struct ViewInfo {
 // view's RayLine fields), so the back-projector reads only q0_fx per ray.
 struct ViewRay {
   int64_t m_fx;
+  int64_t q0_fx;  // bin 0's cross coordinate; bin b's is q0_fx + b dq_fx exactly
+  int64_t dq_fx;
   float m, inv_r, pl, pad;
 };
 
@@ -86,7 +88,6 @@ struct dg_plan {
   dg::RayLine* rays;     // device, M
   dg::ViewInfo* views;   // device, nv
   dg::ViewRay* vrays;    // device, nv (parallel beam only, else null)
-  int64_t* q0fx;         // device, M: rays[i].q0_fx (parallel beam only, else null)
   float2* twiddle;       // device, I: exp(-2 pi i t / I)
   int fft_ok;            // I supported by the FFT kernels
   double half_diag_px;   // sqrt(2)/2 (fan candidate search)
@@ -220,7 +221,6 @@ struct BpArgs {
   int I, nv, nb, fan;
   float half_diag;
   const ViewRay* vrays;  // parallel beam: per-view slope terms
-  const int64_t* q0fx;   // parallel beam: per-ray q0_fx
 };
 // Output channel argument block (per slice).  Standalone: zp = p, s_out,
 // tau_p_ptr, tau_s_out.  Fused: zp = z, s_io = s (in: s_prev, out: s), scal.

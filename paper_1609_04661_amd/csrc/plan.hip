@@ -131,6 +131,13 @@ extern "C" dg_status dg_plan_create(const dg_geom* g, dg_plan** out) {
       snapped_cos_sin(th, &c, &s);
       for (int b = 0; b < p->nb; ++b)
         rays[(size_t)k * p->nb + b] = make_ray(c, s, (b - cb) * g->bin_mm, *g);
+      // the cross coordinates of a view's bins form an arithmetic progression;
+      // store it exactly in 32.32 fixed point (bin 0's value plus b steps) so
+      // the back-projector can form them without a table
+      const double step = (std::fabs(s) >= std::fabs(c)) ? -(g->bin_mm / h) / s : (g->bin_mm / h) / c;
+      const int64_t q00 = rays[(size_t)k * p->nb].q0_fx;
+      const int64_t dq = std::llround(step * 4294967296.0);
+      for (int b = 0; b < p->nb; ++b) rays[(size_t)k * p->nb + b].q0_fx = q00 + (int64_t)b * dq;
       ViewInfo& v = views[k];
       v.a = (float)(c * h / g->bin_mm);
       v.b = (float)(s * h / g->bin_mm);
@@ -169,24 +176,20 @@ extern "C" dg_status dg_plan_create(const dg_geom* g, dg_plan** out) {
   p->views = nullptr;
   p->twiddle = nullptr;
   p->vrays = nullptr;
-  p->q0fx = nullptr;
-  // parallel beam: compact copies for the back-projector
+  // parallel beam: per-view slope terms and bin progression for the back-projector
   std::vector<ViewRay> vr;
-  std::vector<int64_t> q0;
   if (g->kind == DG_GEOM_PARALLEL) {
     vr.resize((size_t)p->nv);
-    q0.resize((size_t)p->M);
     for (int k = 0; k < p->nv; ++k) {
       const RayLine& L = rays[(size_t)k * p->nb];
-      vr[k] = ViewRay{L.m_fx, L.m, L.inv_r, L.pl, 0.0f};
+      const int64_t dq = p->nb > 1 ? rays[(size_t)k * p->nb + 1].q0_fx - L.q0_fx : 0;
+      vr[k] = ViewRay{L.m_fx, L.q0_fx, dq, L.m, L.inv_r, L.pl, 0.0f};
     }
-    for (size_t i = 0; i < q0.size(); ++i) q0[i] = rays[i].q0_fx;
   }
   if ((e = hipMalloc(&p->rays, sizeof(RayLine) * rays.size())) != hipSuccess ||
       (e = hipMalloc(&p->views, sizeof(ViewInfo) * views.size())) != hipSuccess ||
       (e = hipMalloc(&p->twiddle, sizeof(float2) * tw.size())) != hipSuccess ||
-      (!vr.empty() && (e = hipMalloc(&p->vrays, sizeof(ViewRay) * vr.size())) != hipSuccess) ||
-      (!q0.empty() && (e = hipMalloc(&p->q0fx, sizeof(int64_t) * q0.size())) != hipSuccess)) {
+      (!vr.empty() && (e = hipMalloc(&p->vrays, sizeof(ViewRay) * vr.size())) != hipSuccess)) {
     dg_plan_destroy(p);
     hip_fail(e, "dg_plan_create: hipMalloc");
     return DG_ERR_NOMEM;
@@ -198,8 +201,6 @@ extern "C" dg_status dg_plan_create(const dg_geom* g, dg_plan** out) {
       (e = hipMemcpy(p->twiddle, tw.data(), sizeof(float2) * tw.size(), hipMemcpyHostToDevice)) !=
           hipSuccess ||
       (!vr.empty() && (e = hipMemcpy(p->vrays, vr.data(), sizeof(ViewRay) * vr.size(),
-                                     hipMemcpyHostToDevice)) != hipSuccess) ||
-      (!q0.empty() && (e = hipMemcpy(p->q0fx, q0.data(), sizeof(int64_t) * q0.size(),
                                      hipMemcpyHostToDevice)) != hipSuccess)) {
     dg_plan_destroy(p);
     return hip_fail(e, "dg_plan_create: hipMemcpy");
@@ -214,7 +215,6 @@ extern "C" dg_status dg_plan_destroy(dg_plan* p) {
   if (p->views) (void)hipFree(p->views);
   if (p->twiddle) (void)hipFree(p->twiddle);
   if (p->vrays) (void)hipFree(p->vrays);
-  if (p->q0fx) (void)hipFree(p->q0fx);
   delete p;
   return DG_OK;
 }

@@ -192,17 +192,25 @@ project_batch(const ProjArgs* __restrict__ T, const int* __restrict__ prefix, in
 
 // Weight of pixel (i, j) on a ray: the same fixed-point cross coordinate and
 // the same fraction formula as the projector, hence the same value.
+// Weight of pixel (i, j) on a ray whose cross coordinate at the pixel's
+// major index is q (32.32 fixed point): p the pixel's cross index.
+__device__ __forceinline__ float ray_weight_q(int64_t q, int p, float m, float inv_r, float pl) {
+  int p0;
+  float f;
+  split_fx(q, &p0, &f);
+  // distance from the line to the pixel's near edge: f for candidate p0,
+  // 1 - f for p0 + 1; any other pixel gets 2, which both forms of
+  // chord_fraction map to 0 (|m| <= 1, so hw <= 1).  Selects, no branches.
+  const float d = (p == p0) ? f : ((p == p0 + 1) ? 1.0f - f : 2.0f);
+  const float hw = __fmaf_rn(0.5f, fabsf(m), 0.5f);
+  const float g = fminf(fmaxf(__fmul_rn(hw - d, inv_r), 0.0f), 1.0f);
+  const float ga = d < 0.5f ? 1.0f : (d == 0.5f ? 0.5f : 0.0f);
+  return fabsf(pl) * (m == 0.0f ? ga : g);
+}
 __device__ __forceinline__ float ray_weight_parts(int64_t q0_fx, int64_t m_fx, float m, float inv_r,
                                                   float pl, int i, int j) {
   const bool steep = pl < 0.0f;
-  const int k = steep ? i : j;
-  const int p = steep ? j : i;
-  int p0;
-  float f;
-  split_fx(q0_fx + m_fx * (int64_t)k, &p0, &f);
-  if (p == p0) return fabsf(pl) * chord_fraction(f, m, inv_r);
-  if (p == p0 + 1) return fabsf(pl) * chord_fraction(1.0f - f, m, inv_r);
-  return 0.0f;
+  return ray_weight_q(q0_fx + m_fx * (int64_t)(steep ? i : j), steep ? j : i, m, inv_r, pl);
 }
 __device__ __forceinline__ float ray_weight(const RayLine& L, int i, int j) {
   return ray_weight_parts(L.q0_fx, L.m_fx, L.m, L.inv_r, L.pl, i, j);
@@ -226,11 +234,11 @@ __device__ void backproject_body(const BpArgs& A, int bx, int by) {
   const float y = 0.5f * (float)(I - 1) - (float)i;
   float acc = 0.0f;
   if (!A.fan) {
-    // parallel beam: a view's rays share their slope terms, so a candidate
-    // bin costs one 8-byte q0_fx and one sinogram value
+    // parallel beam: a view's rays share their slope terms and their cross
+    // coordinates step by dq_fx per bin, so a candidate bin costs one
+    // sinogram value
     for (int k0 = 0; k0 < A.nv; k0 += kBpViews) {
       int bb[kBpViews], be[kBpViews];
-      int64_t q[kBpViews][kBpBins];
       float sv[kBpViews][kBpBins];
 #pragma unroll
       for (int g = 0; g < kBpViews; ++g) {
@@ -241,22 +249,21 @@ __device__ void backproject_body(const BpArgs& A, int bx, int by) {
         be[g] = (k0 + g < A.nv) ? min((int)floorf(u + v.hw), A.nb - 1) : -1;
         const int64_t row = (int64_t)k * A.nb;
 #pragma unroll
-        for (int c = 0; c < kBpBins; ++c) {
-          const int b = min(bb[g] + c, A.nb - 1);
-          q[g][c] = A.q0fx[row + b];
-          sv[g][c] = A.sino[row + b];
-        }
+        for (int c = 0; c < kBpBins; ++c) sv[g][c] = A.sino[row + min(bb[g] + c, A.nb - 1)];
       }
 #pragma unroll
       for (int g = 0; g < kBpViews; ++g) {
         const int k = min(k0 + g, A.nv - 1);
         const ViewRay vr = A.vrays[k];
+        const bool steep = vr.pl < 0.0f;
+        const int p = steep ? j : i;
+        int64_t q = vr.q0_fx + vr.dq_fx * (int64_t)bb[g] + vr.m_fx * (int64_t)(steep ? i : j);
 #pragma unroll
         for (int c = 0; c < kBpBins; ++c) {
-          const float wgt = (bb[g] + c <= be[g])
-                                ? ray_weight_parts(q[g][c], vr.m_fx, vr.m, vr.inv_r, vr.pl, i, j)
-                                : 0.0f;
+          const float wgt =
+              (bb[g] + c <= be[g]) ? ray_weight_q(q, p, vr.m, vr.inv_r, vr.pl) : 0.0f;
           acc = __fmaf_rn(wgt, sv[g][c], acc);
+          q += vr.dq_fx;
         }
         if (be[g] - bb[g] + 1 > kBpBins) {
           const int64_t row = (int64_t)(k0 + g) * A.nb;
@@ -412,7 +419,7 @@ dg_status launch_backproject(const dg_plan* p, const float* sino, float* img, hi
   dim3 grid((p->I + kBpBlockX - 1) / kBpBlockX, (p->I + kBpBlockY - 1) / kBpBlockY);
   dim3 block(kBpBlockX, kBpBlockY);
   BpArgs A{p->rays, p->views, sino, img, p->I, p->nv, p->nb, p->g.kind == DG_GEOM_FAN ? 1 : 0,
-           (float)p->half_diag_px, p->vrays, p->q0fx};
+           (float)p->half_diag_px, p->vrays};
   hipLaunchKernelGGL(backproject_kernel, grid, block, 0, s, A);
   DG_LAUNCH_CHECK("backproject_kernel");
   return DG_OK;
