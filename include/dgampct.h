@@ -330,15 +330,15 @@ dg_status dg_batch_graph_create(dg_batch* b, double tau_x0, int32_t n_iter,
                                 int32_t onsager, int32_t channel_mode, dg_graph** out);
 
 /* ------------------------------------------------------------------ autotune
- * The forward projector splits every ray's march into 2, 4 or 8 segments
- * handled by different lanes (variants 0, 1, 2; default 1).  The variants
+ * The forward projector splits every ray's march into 2, 4, 8 or 16 segments
+ * handled by different lanes (variants 0, 1, 2, 3; default 1).  The variants
  * sum the same chord-weighted pixels in a different order, so sinograms
  * agree to FP32 rounding (relative ~1e-7), not bit for bit.  The autotune
  * calls time each variant `reps` times on the given data (synchronising the
  * stream) and keep the fastest for later calls on the plan or batch; the
  * batch tuner overwrites the batch's z work buffer only, the plan tuner
  * writes `sino` (img_t may be NULL).  The setters restore a stored choice
- * (variant outside 0..2: DG_ERR_ARG).                                       */
+ * (variant outside 0..3: DG_ERR_ARG).                                       */
 dg_status dg_batch_autotune(dg_batch* b, int32_t reps, void* stream);
 int32_t dg_batch_projector_variant(const dg_batch* b);
 dg_status dg_batch_set_projector_variant(dg_batch* b, int32_t variant);

@@ -485,7 +485,7 @@ extern "C" dg_status dg_batch_autotune(dg_batch* b, int32_t reps, void* stream) 
   float best = 1e30f;
   int best_v = b->proj_variant;
   dg_status rc = DG_OK;
-  for (int v = 0; v < 3 && rc == DG_OK; ++v) {
+  for (int v = 0; v < kProjNumVariants && rc == DG_OK; ++v) {
     rc = launch_project_batch(v, b->t_proj, b->d_pre_proj, b->n, b->pre_proj[b->n], ChanRun{},
                               st);  // warm
     if (rc != DG_OK) break;
@@ -513,7 +513,8 @@ extern "C" dg_status dg_batch_autotune(dg_batch* b, int32_t reps, void* stream) 
 extern "C" int32_t dg_batch_projector_variant(const dg_batch* b) { return b ? b->proj_variant : -1; }
 
 extern "C" dg_status dg_batch_set_projector_variant(dg_batch* b, int32_t variant) {
-  DG_ARG_CHECK(b && variant >= 0 && variant < 3, "dg_batch_set_projector_variant: bad argument");
+  DG_ARG_CHECK(b && variant >= 0 && variant < kProjNumVariants,
+               "dg_batch_set_projector_variant: bad argument");
   b->proj_variant = variant;
   for (dg_plan* p : b->plans) p->proj_variant = variant;
   return DG_OK;
@@ -529,7 +530,7 @@ extern "C" dg_status dg_plan_autotune(dg_plan* p, const float* img, const float*
   float best = 1e30f;
   int best_v = p->proj_variant;
   dg_status rc = DG_OK;
-  for (int v = 0; v < 3 && rc == DG_OK; ++v) {
+  for (int v = 0; v < kProjNumVariants && rc == DG_OK; ++v) {
     ProjArgs A{p->rays, img, img_t, sino, p->I, p->M, 0, ChanArgs{}};
     rc = launch_project_variant(v, A, st);
     (void)hipEventRecord(e0, st);
@@ -553,7 +554,8 @@ extern "C" dg_status dg_plan_autotune(dg_plan* p, const float* img, const float*
 extern "C" int32_t dg_plan_projector_variant(const dg_plan* p) { return p ? p->proj_variant : -1; }
 
 extern "C" dg_status dg_plan_set_projector_variant(dg_plan* p, int32_t variant) {
-  DG_ARG_CHECK(p && variant >= 0 && variant < 3, "dg_plan_set_projector_variant: bad argument");
+  DG_ARG_CHECK(p && variant >= 0 && variant < kProjNumVariants,
+               "dg_plan_set_projector_variant: bad argument");
   p->proj_variant = variant;
   return DG_OK;
 }

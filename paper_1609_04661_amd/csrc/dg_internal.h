@@ -423,7 +423,8 @@ struct DivArgs {
 };
 
 // projector variants (march segments per ray) the autotuner chooses from
-static constexpr int kProjSegVariants[3] = {2, 4, 8};
+static constexpr int kProjSegVariants[4] = {2, 4, 8, 16};
+static constexpr int kProjNumVariants = 4;
 static constexpr int kRaysPerBlock = 64;
 
 // Kernels launched by more than one file.

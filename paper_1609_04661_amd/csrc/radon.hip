@@ -19,9 +19,10 @@ namespace dg {
 static constexpr int kBpBlockX = 64, kBpBlockY = 4;
 
 // Block = kRaysPerBlock rays x SEGS segments: wavefront w marches segment w
-// of the rays' major-index range for 64 consecutive rays (consecutive bins of
-// one view, so their reads stay coalesced), and the SEGS partial sums are
-// added in a fixed order.  Splitting the march gives SEGS times more
+// of the union of the major-index ranges of 64 consecutive rays (consecutive
+// bins of one view) in lockstep, so each load instruction reads neighbouring
+// addresses of one buffer row, and the SEGS partial sums are added in a
+// fixed order.  Splitting the march gives SEGS times more
 // wavefronts to hide memory latency than one thread per ray.
 //
 // The march is unrolled by kMarch steps: the offsets and weights of both
@@ -39,9 +40,33 @@ __device__ void project_body(const ProjArgs& A, int blk, float (*part)[kRaysPerB
   const int64_t r = (int64_t)blk * kRaysPerBlock + lane;
   const int I = A.I;
   float acc = 0.0f;
-  RayLine L;
-  if (r < A.M) {
-    L = A.rays[r];
+  RayLine L{};
+  const bool valid = r < A.M;
+  if (valid) L = A.rays[r];
+  // Major-index range where q(k) lies in (-1, I): candidates exist only there.
+  int k0 = I, k1 = -1;  // a lane without a ray adds nothing to the union below
+  if (valid) {
+    k0 = 0;
+    k1 = I - 1;
+    if (L.m != 0.0f) {
+      float ka = (-1.0f - L.q0) / L.m, kb = ((float)I - L.q0) / L.m;
+      float lo = fmaxf(fminf(ka, kb), -2.0f), hi = fminf(fmaxf(ka, kb), (float)I + 1.0f);
+      k0 = max(0, (int)floorf(lo) - 1);
+      k1 = min(I - 1, (int)ceilf(hi) + 1);
+    } else if (!(L.q0 > -1.0f && L.q0 < (float)I)) {
+      k1 = -1;
+    }
+  }
+  // The wavefront marches the union of its 64 rays' ranges in lockstep, so at
+  // every step its lanes read one row of the (major-index-row) buffer: the
+  // neighbouring rays' candidates are neighbouring addresses (coalesced).  A
+  // step outside a ray's own range finds both candidates outside the image
+  // (offset past the buffer, reads 0) and adds w * 0 = 0.
+  for (int o = 32; o > 0; o >>= 1) {
+    k0 = min(k0, __shfl_xor(k0, o, 64));
+    k1 = max(k1, __shfl_xor(k1, o, 64));
+  }
+  if (valid) {
     const bool steep = L.pl < 0.0f;
     // One raw buffer resource (wavefront-uniform) spans the image and, when
     // it lies within 4 GiB of it, the transposed copy.
@@ -71,16 +96,6 @@ __device__ void project_body(const ProjArgs& A, int blk, float (*part)[kRaysPerB
     const unsigned boff = (steep || !use_t) ? di : dt;
     const int sk = major_rows ? I : 1, sp = major_rows ? 1 : I;
 
-    // Major-index range where q(k) lies in (-1, I): candidates exist only there.
-    int k0 = 0, k1 = I - 1;
-    if (L.m != 0.0f) {
-      float ka = (-1.0f - L.q0) / L.m, kb = ((float)I - L.q0) / L.m;
-      float lo = fmaxf(fminf(ka, kb), -2.0f), hi = fminf(fmaxf(ka, kb), (float)I + 1.0f);
-      k0 = max(0, (int)floorf(lo) - 1);
-      k1 = min(I - 1, (int)ceilf(hi) + 1);
-    } else if (!(L.q0 > -1.0f && L.q0 < (float)I)) {
-      k1 = -1;
-    }
     // this wavefront's share of [k0, k1]
     const int len = k1 - k0 + 1;
     const int chunk = (len + SEGS - 1) / SEGS;
@@ -370,6 +385,9 @@ dg_status launch_project_run(int variant, const ProjArgs& A, const ChanRun& cr, 
     case 2:
       hipLaunchKernelGGL(project_kernel<8>, grid, dim3(kRaysPerBlock * 8), 0, s, A, cr);
       break;
+    case 3:
+      hipLaunchKernelGGL(project_kernel<16>, grid, dim3(kRaysPerBlock * 16), 0, s, A, cr);
+      break;
     default:
       hipLaunchKernelGGL(project_kernel<4>, grid, dim3(kRaysPerBlock * 4), 0, s, A, cr);
       break;
@@ -392,6 +410,10 @@ dg_status launch_project_batch(int variant, const ProjArgs* T, const int* prefix
     case 2:
       hipLaunchKernelGGL(project_batch<8>, dim3(total), dim3(kRaysPerBlock * 8), 0, s, T, prefix, n,
                          cr);
+      break;
+    case 3:
+      hipLaunchKernelGGL(project_batch<16>, dim3(total), dim3(kRaysPerBlock * 16), 0, s, T, prefix,
+                         n, cr);
       break;
     default:
       hipLaunchKernelGGL(project_batch<4>, dim3(total), dim3(kRaysPerBlock * 4), 0, s, T, prefix, n,

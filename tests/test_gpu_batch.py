@@ -199,7 +199,7 @@ def test_projector_variants_match_oracle_and_autotune(gpu_lib):
     mu = torch.as_tensor(mu_np, dtype=torch.float32).cuda()
     mu_t = mu.t().contiguous()
     outs = []
-    for v in range(3):
+    for v in range(4):
         P.projector_variant = v
         o = host(api.ct_project(P, mu, mu_t))
         assert np.linalg.norm(o - ref) / np.linalg.norm(ref) <= 1e-5, v
@@ -207,10 +207,10 @@ def test_projector_variants_match_oracle_and_autotune(gpu_lib):
     for o in outs[1:]:
         assert np.linalg.norm(o - outs[0]) / np.linalg.norm(outs[0]) <= 1e-6
     v = P.autotune(mu, mu_t, reps=5)
-    assert v in (0, 1, 2) and P.projector_variant == v
+    assert v in (0, 1, 2, 3) and P.projector_variant == v
     assert np.array_equal(host(api.ct_project(P, mu, mu_t)), outs[v])
     with pytest.raises(api.DgError, match="status -1"):
-        P.projector_variant = 3
+        P.projector_variant = 4
 
 
 def test_batch_autotune_keeps_results(gpu_lib, data):
@@ -222,7 +222,7 @@ def test_batch_autotune_keeps_results(gpu_lib, data):
     mu_out = torch.empty(B.totN, dtype=torch.float32, device="cuda")
     B.bind(y, [d["i0"] for d in data], [d["fro2"] for d in data], api.DEN_NLM, params, mu_out)
     v = B.autotune(reps=3)
-    assert v in (0, 1, 2) and B.projector_variant == v
+    assert v in (0, 1, 2, 3) and B.projector_variant == v
     for d in data:
         d["plan"].projector_variant = v
     try:
