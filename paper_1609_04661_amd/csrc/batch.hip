@@ -25,8 +25,8 @@ dg_status launch_prec_batch(int pass, const void* table, const int* prefix, int 
 dg_status launch_project_batch(int variant, const ProjArgs* T, const int* prefix, int n, int total,
                                const ChanRun& cr, hipStream_t s);
 dg_status launch_project_variant(int variant, const ProjArgs& A, hipStream_t s);
-dg_status launch_backproject_batch(const BpArgs* T, const int* prefix, int n, int total,
-                                   hipStream_t s);
+dg_status launch_backproject_batch(const BpArgs* T, const int* prefix, int n, int total, int mode,
+                                   hipStream_t st);
 dg_status launch_nlm_batch(int P, const NlmArgs* T, const int* prefix, int n, int total,
                            uint64_t seed, int iter, double eta_x, int t, hipStream_t st);
 dg_status launch_div_finish_batch(const DivArgs* T, int n, double eta_x, int t, hipStream_t st);
@@ -106,6 +106,7 @@ struct dg_batch {
   dg_nlm_params nlm{};
   dg_cnn_params cnn{};
   int proj_variant = 1;
+  int bp_mode = 0;  // back-projector kernel: 0 all parallel beam, 1 all fan beam, 2 mixed
 };
 
 static size_t batch_work_layout(const dg_batch* b, void* base, char** parts) {
@@ -204,6 +205,11 @@ extern "C" dg_status dg_batch_create(const dg_geom* geoms, int32_t n, dg_batch**
       return DG_ERR_UNSUPPORTED;
     }
     if (geoms[s].n != b->uniform_I) b->uniform_I = 0;
+    const int kind_mode = geoms[s].kind == DG_GEOM_FAN ? 1 : 0;
+    if (s == 0)
+      b->bp_mode = kind_mode;
+    else if (b->bp_mode != kind_mode)
+      b->bp_mode = 2;
     const int I = p->I;
     b->img_off[s + 1] = b->img_off[s] + p->N;
     b->sino_off[s + 1] = b->sino_off[s] + p->M;
@@ -413,7 +419,8 @@ extern "C" dg_status dgamp_batch_iterate(dg_batch* b, int32_t n_iter, int32_t t0
     if ((rc = launch_project_batch(b->proj_variant, b->t_projc, b->d_pre_proj, n, b->pre_proj[n],
                                    cr, st)) != DG_OK)
       return rc;
-    if ((rc = launch_backproject_batch(b->t_bp, b->d_pre_bp, n, b->pre_bp[n], st)) != DG_OK)
+    if ((rc = launch_backproject_batch(b->t_bp, b->d_pre_bp, n, b->pre_bp[n], b->bp_mode, st)) !=
+        DG_OK)
       return rc;
     if ((rc = batch_precondition(b, b->t_rf_g, b->t_ri_r, t, eta_s, st)) != DG_OK) return rc;
     if (b->den_kind != DG_DEN_NLM &&

@@ -208,11 +208,9 @@ project_batch(const ProjArgs* __restrict__ T, const int* __restrict__ prefix, in
 // Weight of pixel (i, j) on a ray: the same fixed-point cross coordinate and
 // the same fraction formula as the projector, hence the same value.
 // Weight of pixel (i, j) on a ray whose cross coordinate at the pixel's
-// major index is q (32.32 fixed point): p the pixel's cross index.
-__device__ __forceinline__ float ray_weight_q(int64_t q, int p, float m, float inv_r, float pl) {
-  int p0;
-  float f;
-  split_fx(q, &p0, &f);
+// major index is p0 + f (p0 = floor): p the pixel's cross index.
+__device__ __forceinline__ float ray_weight_pf(int p0, float f, int p, float m, float inv_r,
+                                               float pl) {
   // distance from the line to the pixel's near edge: f for candidate p0,
   // 1 - f for p0 + 1; any other pixel gets 2, which both forms of
   // chord_fraction map to 0 (|m| <= 1, so hw <= 1).  Selects, no branches.
@@ -225,7 +223,10 @@ __device__ __forceinline__ float ray_weight_q(int64_t q, int p, float m, float i
 __device__ __forceinline__ float ray_weight_parts(int64_t q0_fx, int64_t m_fx, float m, float inv_r,
                                                   float pl, int i, int j) {
   const bool steep = pl < 0.0f;
-  return ray_weight_q(q0_fx + m_fx * (int64_t)(steep ? i : j), steep ? j : i, m, inv_r, pl);
+  int p0;
+  float f;
+  split_fx(q0_fx + m_fx * (int64_t)(steep ? i : j), &p0, &f);
+  return ray_weight_pf(p0, f, steep ? j : i, m, inv_r, pl);
 }
 __device__ __forceinline__ float ray_weight(const RayLine& L, int i, int j) {
   return ray_weight_parts(L.q0_fx, L.m_fx, L.m, L.inv_r, L.pl, i, j);
@@ -238,8 +239,10 @@ __device__ __forceinline__ float ray_weight(const RayLine& L, int i, int j) {
 // weight 0 when the bin is outside the footprint), then accumulated in the
 // order view, bin; a footprint of more than 3 bins (possible only for very
 // short fan-beam source distances) finishes in a plain loop.
-static constexpr int kBpViews = 4, kBpBins = 3;
+static constexpr int kBpViewsPar = 8, kBpViewsFan = 4, kBpBins = 3;
 
+// MODE 0: parallel beam, 1: fan beam, 2: either (decided per slice).
+template <int MODE>
 __device__ void backproject_body(const BpArgs& A, int bx, int by) {
   const int I = A.I;
   const int j = bx * kBpBlockX + threadIdx.x;
@@ -248,10 +251,11 @@ __device__ void backproject_body(const BpArgs& A, int bx, int by) {
   const float x = (float)j - 0.5f * (float)(I - 1);
   const float y = 0.5f * (float)(I - 1) - (float)i;
   float acc = 0.0f;
-  if (!A.fan) {
+  if (MODE == 0 || (MODE == 2 && !A.fan)) {
     // parallel beam: a view's rays share their slope terms and their cross
     // coordinates step by dq_fx per bin, so a candidate bin costs one
     // sinogram value
+    constexpr int kBpViews = kBpViewsPar;
     for (int k0 = 0; k0 < A.nv; k0 += kBpViews) {
       int bb[kBpViews], be[kBpViews];
       float sv[kBpViews][kBpBins];
@@ -275,8 +279,11 @@ __device__ void backproject_body(const BpArgs& A, int bx, int by) {
         int64_t q = vr.q0_fx + vr.dq_fx * (int64_t)bb[g] + vr.m_fx * (int64_t)(steep ? i : j);
 #pragma unroll
         for (int c = 0; c < kBpBins; ++c) {
+          int p0;
+          float f;
+          split_fx(q, &p0, &f);
           const float wgt =
-              (bb[g] + c <= be[g]) ? ray_weight_q(q, p, vr.m, vr.inv_r, vr.pl) : 0.0f;
+              (bb[g] + c <= be[g]) ? ray_weight_pf(p0, f, p, vr.m, vr.inv_r, vr.pl) : 0.0f;
           acc = __fmaf_rn(wgt, sv[g][c], acc);
           q += vr.dq_fx;
         }
@@ -290,6 +297,8 @@ __device__ void backproject_body(const BpArgs& A, int bx, int by) {
     A.img[(int64_t)i * I + j] = acc;
     return;
   }
+  if (MODE == 0) return;
+  constexpr int kBpViews = kBpViewsFan;
   for (int k0 = 0; k0 < A.nv; k0 += kBpViews) {
     int bb[kBpViews], be[kBpViews];
     RayLine L[kBpViews][kBpBins];
@@ -337,16 +346,18 @@ __device__ void backproject_body(const BpArgs& A, int bx, int by) {
   A.img[(int64_t)i * I + j] = acc;
 }
 
+template <int MODE>
 __global__ void __launch_bounds__(kBpBlockX* kBpBlockY) backproject_kernel(BpArgs A) {
-  backproject_body(A, blockIdx.x, blockIdx.y);
+  backproject_body<MODE>(A, blockIdx.x, blockIdx.y);
 }
+template <int MODE>
 __global__ void __launch_bounds__(kBpBlockX* kBpBlockY)
 backproject_batch(const BpArgs* __restrict__ T, const int* __restrict__ prefix, int n) {
   const int s = slice_of(prefix, n, blockIdx.x);
   const BpArgs A = T[s];
   const int local = blockIdx.x - prefix[s];
   const int gx = (A.I + kBpBlockX - 1) / kBpBlockX;
-  backproject_body(A, local % gx, local / gx);
+  backproject_body<MODE>(A, local % gx, local / gx);
 }
 
 __global__ void transpose_kernel(const float* __restrict__ in, float* __restrict__ out, int I) {
@@ -424,9 +435,16 @@ dg_status launch_project_batch(int variant, const ProjArgs* T, const int* prefix
   return DG_OK;
 }
 
-dg_status launch_backproject_batch(const BpArgs* T, const int* prefix, int n, int total,
+// mode: 0 every slice parallel beam, 1 every slice fan beam, 2 mixed.
+dg_status launch_backproject_batch(const BpArgs* T, const int* prefix, int n, int total, int mode,
                                    hipStream_t s) {
-  hipLaunchKernelGGL(backproject_batch, dim3(total), dim3(kBpBlockX, kBpBlockY), 0, s, T, prefix, n);
+  const dim3 block(kBpBlockX, kBpBlockY);
+  if (mode == 0)
+    hipLaunchKernelGGL(backproject_batch<0>, dim3(total), block, 0, s, T, prefix, n);
+  else if (mode == 1)
+    hipLaunchKernelGGL(backproject_batch<1>, dim3(total), block, 0, s, T, prefix, n);
+  else
+    hipLaunchKernelGGL(backproject_batch<2>, dim3(total), block, 0, s, T, prefix, n);
   DG_LAUNCH_CHECK("backproject_batch");
   return DG_OK;
 }
@@ -442,7 +460,10 @@ dg_status launch_backproject(const dg_plan* p, const float* sino, float* img, hi
   dim3 block(kBpBlockX, kBpBlockY);
   BpArgs A{p->rays, p->views, sino, img, p->I, p->nv, p->nb, p->g.kind == DG_GEOM_FAN ? 1 : 0,
            (float)p->half_diag_px, p->vrays};
-  hipLaunchKernelGGL(backproject_kernel, grid, block, 0, s, A);
+  if (A.fan)
+    hipLaunchKernelGGL(backproject_kernel<1>, grid, block, 0, s, A);
+  else
+    hipLaunchKernelGGL(backproject_kernel<0>, grid, block, 0, s, A);
   DG_LAUNCH_CHECK("backproject_kernel");
   return DG_OK;
 }
