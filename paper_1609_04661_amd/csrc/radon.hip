@@ -239,64 +239,85 @@ __device__ __forceinline__ float ray_weight(const RayLine& L, int i, int j) {
 // weight 0 when the bin is outside the footprint), then accumulated in the
 // order view, bin; a footprint of more than 3 bins (possible only for very
 // short fan-beam source distances) finishes in a plain loop.
-static constexpr int kBpViewsPar = 8, kBpViewsFan = 4, kBpBins = 3;
+static constexpr int kBpViewsPar = 8, kBpViewsFan = 4, kBpBins = 3, kBpSplit = 2;
 
 // MODE 0: parallel beam, 1: fan beam, 2: either (decided per slice).
 template <int MODE>
-__device__ void backproject_body(const BpArgs& A, int bx, int by) {
+__device__ void backproject_body(const BpArgs& A, int bx, int by, float (*red)[kBpBlockX]) {
   const int I = A.I;
   const int j = bx * kBpBlockX + threadIdx.x;
   const int i = by * kBpBlockY + threadIdx.y;
-  if (i >= I || j >= I) return;
+  const bool inside = i < I && j < I;
   const float x = (float)j - 0.5f * (float)(I - 1);
   const float y = 0.5f * (float)(I - 1) - (float)i;
   float acc = 0.0f;
   if (MODE == 0 || (MODE == 2 && !A.fan)) {
     // parallel beam: a view's rays share their slope terms and their cross
     // coordinates step by dq_fx per bin, so a candidate bin costs one
-    // sinogram value
+    // sinogram value.  In the parallel-only kernel kBpSplit threads share a
+    // pixel, each taking a contiguous share of the views (more wavefronts
+    // in flight to hide the gathers); their sums are added in a fixed order.
+    // The runtime-mode kernel walks the same shares in turn and adds their
+    // sums in the same order, so both kernels give identical bits.
     constexpr int kBpViews = kBpViewsPar;
-    for (int k0 = 0; k0 < A.nv; k0 += kBpViews) {
-      int bb[kBpViews], be[kBpViews];
-      float sv[kBpViews][kBpBins];
+    // a wavefront lies in one z slice (blockDim.x is 64); saying so keeps
+    // the view tables in scalar registers
+    const int h = (MODE == 0) ? __builtin_amdgcn_readfirstlane((int)threadIdx.z) : 0;
+    const int h_end = (MODE == 0) ? h + 1 : kBpSplit;
+    for (int hh = h; hh < h_end && inside; ++hh) {
+      const int kbeg = A.nv * hh / kBpSplit, kend = A.nv * (hh + 1) / kBpSplit;
+      float share = 0.0f;
+      for (int k0 = kbeg; k0 < kend; k0 += kBpViews) {
+        int bb[kBpViews], be[kBpViews];
+        float sv[kBpViews][kBpBins];
 #pragma unroll
-      for (int g = 0; g < kBpViews; ++g) {
-        const int k = min(k0 + g, A.nv - 1);
-        const ViewInfo v = A.views[k];
-        const float u = __fmaf_rn(v.a, x, __fmaf_rn(v.b, y, v.c));
-        bb[g] = max((int)ceilf(u - v.hw), 0);
-        be[g] = (k0 + g < A.nv) ? min((int)floorf(u + v.hw), A.nb - 1) : -1;
-        const int64_t row = (int64_t)k * A.nb;
+        for (int g = 0; g < kBpViews; ++g) {
+          const int k = min(k0 + g, kend - 1);
+          const ViewInfo v = A.views[k];
+          const float u = __fmaf_rn(v.a, x, __fmaf_rn(v.b, y, v.c));
+          bb[g] = max((int)ceilf(u - v.hw), 0);
+          be[g] = (k0 + g < kend) ? min((int)floorf(u + v.hw), A.nb - 1) : -1;
+          const int64_t row = (int64_t)k * A.nb;
 #pragma unroll
-        for (int c = 0; c < kBpBins; ++c) sv[g][c] = A.sino[row + min(bb[g] + c, A.nb - 1)];
-      }
-#pragma unroll
-      for (int g = 0; g < kBpViews; ++g) {
-        const int k = min(k0 + g, A.nv - 1);
-        const ViewRay vr = A.vrays[k];
-        const bool steep = vr.pl < 0.0f;
-        const int p = steep ? j : i;
-        int64_t q = vr.q0_fx + vr.dq_fx * (int64_t)bb[g] + vr.m_fx * (int64_t)(steep ? i : j);
-#pragma unroll
-        for (int c = 0; c < kBpBins; ++c) {
-          int p0;
-          float f;
-          split_fx(q, &p0, &f);
-          const float wgt =
-              (bb[g] + c <= be[g]) ? ray_weight_pf(p0, f, p, vr.m, vr.inv_r, vr.pl) : 0.0f;
-          acc = __fmaf_rn(wgt, sv[g][c], acc);
-          q += vr.dq_fx;
+          for (int c = 0; c < kBpBins; ++c) sv[g][c] = A.sino[row + min(bb[g] + c, A.nb - 1)];
         }
-        if (be[g] - bb[g] + 1 > kBpBins) {
-          const int64_t row = (int64_t)(k0 + g) * A.nb;
-          for (int b = bb[g] + kBpBins; b <= be[g]; ++b)
-            acc = __fmaf_rn(ray_weight(A.rays[row + b], i, j), A.sino[row + b], acc);
+#pragma unroll
+        for (int g = 0; g < kBpViews; ++g) {
+          const int k = min(k0 + g, kend - 1);
+          const ViewRay vr = A.vrays[k];
+          const bool steep = vr.pl < 0.0f;
+          const int p = steep ? j : i;
+          int64_t q = vr.q0_fx + vr.dq_fx * (int64_t)bb[g] + vr.m_fx * (int64_t)(steep ? i : j);
+#pragma unroll
+          for (int c = 0; c < kBpBins; ++c) {
+            int p0;
+            float f;
+            split_fx(q, &p0, &f);
+            const float wgt =
+                (bb[g] + c <= be[g]) ? ray_weight_pf(p0, f, p, vr.m, vr.inv_r, vr.pl) : 0.0f;
+            share = __fmaf_rn(wgt, sv[g][c], share);
+            q += vr.dq_fx;
+          }
+          if (be[g] - bb[g] + 1 > kBpBins) {
+            const int64_t row = (int64_t)(k0 + g) * A.nb;
+            for (int b = bb[g] + kBpBins; b <= be[g]; ++b)
+              share = __fmaf_rn(ray_weight(A.rays[row + b], i, j), A.sino[row + b], share);
+          }
         }
       }
+      acc = (hh == 0) ? share : acc + share;
     }
-    A.img[(int64_t)i * I + j] = acc;
+    if (MODE == 0) {
+      static_assert(kBpSplit == 2, "the share sums below are written for two shares");
+      if (h == 1) red[threadIdx.y][threadIdx.x] = acc;
+      __syncthreads();
+      if (h == 0 && inside) A.img[(int64_t)i * I + j] = acc + red[threadIdx.y][threadIdx.x];
+    } else if (inside) {
+      A.img[(int64_t)i * I + j] = acc;
+    }
     return;
   }
+  if (!inside) return;
   if (MODE == 0) return;
   constexpr int kBpViews = kBpViewsFan;
   for (int k0 = 0; k0 < A.nv; k0 += kBpViews) {
@@ -346,18 +367,26 @@ __device__ void backproject_body(const BpArgs& A, int bx, int by) {
   A.img[(int64_t)i * I + j] = acc;
 }
 
-template <int MODE>
-__global__ void __launch_bounds__(kBpBlockX* kBpBlockY) backproject_kernel(BpArgs A) {
-  backproject_body<MODE>(A, blockIdx.x, blockIdx.y);
+// Threads per back-projector workgroup: the parallel-only kernel runs
+// kBpSplit threads per pixel (blockDim.z).
+__host__ __device__ constexpr int bp_threads(int mode) {
+  return kBpBlockX * kBpBlockY * (mode == 0 ? kBpSplit : 1);
 }
 template <int MODE>
-__global__ void __launch_bounds__(kBpBlockX* kBpBlockY)
-backproject_batch(const BpArgs* __restrict__ T, const int* __restrict__ prefix, int n) {
+__global__ void __launch_bounds__(bp_threads(MODE))
+    backproject_kernel(BpArgs A) {
+  __shared__ float red[kBpBlockY][kBpBlockX];
+  backproject_body<MODE>(A, blockIdx.x, blockIdx.y, red);
+}
+template <int MODE>
+__global__ void __launch_bounds__(bp_threads(MODE))
+    backproject_batch(const BpArgs* __restrict__ T, const int* __restrict__ prefix, int n) {
+  __shared__ float red[kBpBlockY][kBpBlockX];
   const int s = slice_of(prefix, n, blockIdx.x);
   const BpArgs A = T[s];
   const int local = blockIdx.x - prefix[s];
   const int gx = (A.I + kBpBlockX - 1) / kBpBlockX;
-  backproject_body<MODE>(A, local % gx, local / gx);
+  backproject_body<MODE>(A, local % gx, local / gx, red);
 }
 
 __global__ void transpose_kernel(const float* __restrict__ in, float* __restrict__ out, int I) {
@@ -440,7 +469,8 @@ dg_status launch_backproject_batch(const BpArgs* T, const int* prefix, int n, in
                                    hipStream_t s) {
   const dim3 block(kBpBlockX, kBpBlockY);
   if (mode == 0)
-    hipLaunchKernelGGL(backproject_batch<0>, dim3(total), block, 0, s, T, prefix, n);
+    hipLaunchKernelGGL(backproject_batch<0>, dim3(total), dim3(kBpBlockX, kBpBlockY, kBpSplit), 0,
+                       s, T, prefix, n);
   else if (mode == 1)
     hipLaunchKernelGGL(backproject_batch<1>, dim3(total), block, 0, s, T, prefix, n);
   else
@@ -463,7 +493,7 @@ dg_status launch_backproject(const dg_plan* p, const float* sino, float* img, hi
   if (A.fan)
     hipLaunchKernelGGL(backproject_kernel<1>, grid, block, 0, s, A);
   else
-    hipLaunchKernelGGL(backproject_kernel<0>, grid, block, 0, s, A);
+    hipLaunchKernelGGL(backproject_kernel<0>, grid, dim3(kBpBlockX, kBpBlockY, kBpSplit), 0, s, A);
   DG_LAUNCH_CHECK("backproject_kernel");
   return DG_OK;
 }
