@@ -229,7 +229,7 @@ __device__ void rows_fwd_body(const RowsFwdArgs& A, int blk, FftShared& S, int f
   }
   __syncthreads();
   for (int idx = threadIdx.x; idx < half * kRowsPerBlock; idx += blockDim.x) {
-    const int k = idx >> 3, c = idx & 7;
+    const int k = idx / kRowsPerBlock, c = idx % kRowsPerBlock;
     const int row = blk * kRowsPerBlock + c;
     if (row < I) A.spec[(int64_t)k * I + row] = S.buf[c >> 1][1][(c & 1) * half + k];
   }
@@ -291,7 +291,7 @@ __device__ void rows_inv_body(const RowsInvArgs& A, int blk, FftShared& S) {
 #pragma unroll
   for (int q = 0; q < kSpecPer; ++q) {
     const int idx = threadIdx.x + kFftThreads * q;
-    const int k = idx >> 3, c = idx & 7;
+    const int k = idx / kRowsPerBlock, c = idx % kRowsPerBlock;
     const int row = blk * kRowsPerBlock + c;
     sv[q] = make_float2(0.0f, 0.0f);
     if (idx < half * kRowsPerBlock && row < I) sv[q] = A.spec[(int64_t)k * I + row];
@@ -311,7 +311,7 @@ __device__ void rows_inv_body(const RowsInvArgs& A, int blk, FftShared& S) {
 #pragma unroll
   for (int q = 0; q < kSpecPer; ++q) {
     const int idx = threadIdx.x + kFftThreads * q;
-    const int k = idx >> 3, c = idx & 7;
+    const int k = idx / kRowsPerBlock, c = idx % kRowsPerBlock;
     if (idx < half * kRowsPerBlock) S.buf[c >> 1][1][(c & 1) * half + k] = sv[q];
   }
   __syncthreads();
@@ -355,7 +355,7 @@ __device__ void rows_inv_body(const RowsInvArgs& A, int blk, FftShared& S) {
   if (A.out_t) {
     __syncthreads();
     for (int idx = threadIdx.x; idx < I * kRowsPerBlock; idx += blockDim.x) {
-      const int t = idx >> 3, c = idx & 7;
+      const int t = idx / kRowsPerBlock, c = idx % kRowsPerBlock;
       const int row = blk * kRowsPerBlock + c;
       if (row < I) {
         const float2 v = S.buf[c >> 1][1][t];

@@ -235,15 +235,17 @@ __device__ __forceinline__ float ray_weight(const RayLine& L, int i, int j) {
 // bx, by: block coordinates of a (kBpBlockX x kBpBlockY) pixel block.
 // Views are taken kBpViews at a time: the footprint of the pixel in every
 // view of the group is found first and the ray records and sinogram values
-// of up to 3 bins per view are requested together (clamped in-bounds index,
-// weight 0 when the bin is outside the footprint), then accumulated in the
-// order view, bin; a footprint of more than 3 bins (possible only for very
-// short fan-beam source distances) finishes in a plain loop.
-static constexpr int kBpViewsPar = 8, kBpViewsFan = 4, kBpBins = 3, kBpSplit = 2;
+// of the first kBpBins (fan) or kBpBinsPar (parallel) bins per view are
+// requested together (clamped in-bounds index, weight 0 when the bin is
+// outside the footprint), then accumulated in the order view, bin; a longer
+// footprint finishes in a plain loop.  A parallel-beam pixel's footprint is
+// (|cos| + |sin|) pixel widths long, so two bins cover it whenever a bin is
+// wider than 1/sqrt(2) pixel; the fan beam magnifies it, hence three.
+static constexpr int kBpViewsPar = 2, kBpViewsFan = 4, kBpBins = 3, kBpBinsPar = 2, kBpSplit = 4;
 
 // MODE 0: parallel beam, 1: fan beam, 2: either (decided per slice).
 template <int MODE>
-__device__ void backproject_body(const BpArgs& A, int bx, int by, float (*red)[kBpBlockX]) {
+__device__ void backproject_body(const BpArgs& A, int bx, int by, float (*red)[kBpBlockY][kBpBlockX]) {
   const int I = A.I;
   const int j = bx * kBpBlockX + threadIdx.x;
   const int i = by * kBpBlockY + threadIdx.y;
@@ -269,7 +271,7 @@ __device__ void backproject_body(const BpArgs& A, int bx, int by, float (*red)[k
       float share = 0.0f;
       for (int k0 = kbeg; k0 < kend; k0 += kBpViews) {
         int bb[kBpViews], be[kBpViews];
-        float sv[kBpViews][kBpBins];
+        float sv[kBpViews][kBpBinsPar];
 #pragma unroll
         for (int g = 0; g < kBpViews; ++g) {
           const int k = min(k0 + g, kend - 1);
@@ -279,7 +281,7 @@ __device__ void backproject_body(const BpArgs& A, int bx, int by, float (*red)[k
           be[g] = (k0 + g < kend) ? min((int)floorf(u + v.hw), A.nb - 1) : -1;
           const int64_t row = (int64_t)k * A.nb;
 #pragma unroll
-          for (int c = 0; c < kBpBins; ++c) sv[g][c] = A.sino[row + min(bb[g] + c, A.nb - 1)];
+          for (int c = 0; c < kBpBinsPar; ++c) sv[g][c] = A.sino[row + min(bb[g] + c, A.nb - 1)];
         }
 #pragma unroll
         for (int g = 0; g < kBpViews; ++g) {
@@ -289,7 +291,7 @@ __device__ void backproject_body(const BpArgs& A, int bx, int by, float (*red)[k
           const int p = steep ? j : i;
           int64_t q = vr.q0_fx + vr.dq_fx * (int64_t)bb[g] + vr.m_fx * (int64_t)(steep ? i : j);
 #pragma unroll
-          for (int c = 0; c < kBpBins; ++c) {
+          for (int c = 0; c < kBpBinsPar; ++c) {
             int p0;
             float f;
             split_fx(q, &p0, &f);
@@ -298,9 +300,9 @@ __device__ void backproject_body(const BpArgs& A, int bx, int by, float (*red)[k
             share = __fmaf_rn(wgt, sv[g][c], share);
             q += vr.dq_fx;
           }
-          if (be[g] - bb[g] + 1 > kBpBins) {
+          if (be[g] - bb[g] + 1 > kBpBinsPar) {
             const int64_t row = (int64_t)(k0 + g) * A.nb;
-            for (int b = bb[g] + kBpBins; b <= be[g]; ++b)
+            for (int b = bb[g] + kBpBinsPar; b <= be[g]; ++b)
               share = __fmaf_rn(ray_weight(A.rays[row + b], i, j), A.sino[row + b], share);
           }
         }
@@ -308,10 +310,13 @@ __device__ void backproject_body(const BpArgs& A, int bx, int by, float (*red)[k
       acc = (hh == 0) ? share : acc + share;
     }
     if (MODE == 0) {
-      static_assert(kBpSplit == 2, "the share sums below are written for two shares");
-      if (h == 1) red[threadIdx.y][threadIdx.x] = acc;
+      if (h > 0) red[h - 1][threadIdx.y][threadIdx.x] = acc;
       __syncthreads();
-      if (h == 0 && inside) A.img[(int64_t)i * I + j] = acc + red[threadIdx.y][threadIdx.x];
+      if (h == 0 && inside) {
+#pragma unroll
+        for (int e = 0; e < kBpSplit - 1; ++e) acc += red[e][threadIdx.y][threadIdx.x];
+        A.img[(int64_t)i * I + j] = acc;
+      }
     } else if (inside) {
       A.img[(int64_t)i * I + j] = acc;
     }
@@ -375,13 +380,13 @@ __host__ __device__ constexpr int bp_threads(int mode) {
 template <int MODE>
 __global__ void __launch_bounds__(bp_threads(MODE))
     backproject_kernel(BpArgs A) {
-  __shared__ float red[kBpBlockY][kBpBlockX];
+  __shared__ float red[kBpSplit - 1][kBpBlockY][kBpBlockX];
   backproject_body<MODE>(A, blockIdx.x, blockIdx.y, red);
 }
 template <int MODE>
 __global__ void __launch_bounds__(bp_threads(MODE))
     backproject_batch(const BpArgs* __restrict__ T, const int* __restrict__ prefix, int n) {
-  __shared__ float red[kBpBlockY][kBpBlockX];
+  __shared__ float red[kBpSplit - 1][kBpBlockY][kBpBlockX];
   const int s = slice_of(prefix, n, blockIdx.x);
   const BpArgs A = T[s];
   const int local = blockIdx.x - prefix[s];
