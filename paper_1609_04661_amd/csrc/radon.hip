@@ -209,15 +209,21 @@ project_batch(const ProjArgs* __restrict__ T, const int* __restrict__ prefix, in
 // the same fraction formula as the projector, hence the same value.
 // Weight of pixel (i, j) on a ray whose cross coordinate at the pixel's
 // major index is p0 + f (p0 = floor): p the pixel's cross index.
+// AX: 0 decides the axis-aligned case (m == 0) per call, 1 / 2 are for a
+// caller that knows m != 0 / m == 0 (a wavefront-uniform branch).
+template <int AX = 0>
 __device__ __forceinline__ float ray_weight_pf(int p0, float f, int p, float m, float inv_r,
                                                float pl) {
   // distance from the line to the pixel's near edge: f for candidate p0,
-  // 1 - f for p0 + 1; any other pixel gets 2, which both forms of
-  // chord_fraction map to 0 (|m| <= 1, so hw <= 1).  Selects, no branches.
-  const float d = (p == p0) ? f : ((p == p0 + 1) ? 1.0f - f : 2.0f);
+  // 1 - f for p0 + 1 (both exactly |(p - p0) - f|); any other pixel gets
+  // |(p - p0) - f| >= 1, which both forms of chord_fraction map to 0
+  // (|m| <= 1, so hw <= 1).  No branches.
+  const float d = fabsf((float)(p - p0) - f);
   const float hw = __fmaf_rn(0.5f, fabsf(m), 0.5f);
   const float g = fminf(fmaxf(__fmul_rn(hw - d, inv_r), 0.0f), 1.0f);
   const float ga = d < 0.5f ? 1.0f : (d == 0.5f ? 0.5f : 0.0f);
+  if (AX == 1) return fabsf(pl) * g;
+  if (AX == 2) return fabsf(pl) * ga;
   return fabsf(pl) * (m == 0.0f ? ga : g);
 }
 __device__ __forceinline__ float ray_weight_parts(int64_t q0_fx, int64_t m_fx, float m, float inv_r,
@@ -279,9 +285,9 @@ __device__ void backproject_body(const BpArgs& A, int bx, int by, float (*red)[k
           const float u = __fmaf_rn(v.a, x, __fmaf_rn(v.b, y, v.c));
           bb[g] = max((int)ceilf(u - v.hw), 0);
           be[g] = (k0 + g < kend) ? min((int)floorf(u + v.hw), A.nb - 1) : -1;
-          const int64_t row = (int64_t)k * A.nb;
+          const float* srow = A.sino + (int64_t)k * A.nb;  // bb >= 0: 32-bit offsets
 #pragma unroll
-          for (int c = 0; c < kBpBinsPar; ++c) sv[g][c] = A.sino[row + min(bb[g] + c, A.nb - 1)];
+          for (int c = 0; c < kBpBinsPar; ++c) sv[g][c] = srow[(unsigned)min(bb[g] + c, A.nb - 1)];
         }
 #pragma unroll
         for (int g = 0; g < kBpViews; ++g) {
@@ -289,17 +295,33 @@ __device__ void backproject_body(const BpArgs& A, int bx, int by, float (*red)[k
           const ViewRay vr = A.vrays[k];
           const bool steep = vr.pl < 0.0f;
           const int p = steep ? j : i;
-          int64_t q = vr.q0_fx + vr.dq_fx * (int64_t)bb[g] + vr.m_fx * (int64_t)(steep ? i : j);
+          // bb, i, j are non-negative: 64 x 32-bit unsigned products
+          int64_t q = vr.q0_fx + vr.dq_fx * (int64_t)(uint32_t)bb[g] +
+                      vr.m_fx * (int64_t)(uint32_t)(steep ? i : j);
+          float wgt[kBpBinsPar];
+          // the axis-aligned views (m == 0) are a wavefront-uniform branch
+          if (vr.m != 0.0f) {
 #pragma unroll
-          for (int c = 0; c < kBpBinsPar; ++c) {
-            int p0;
-            float f;
-            split_fx(q, &p0, &f);
-            const float wgt =
-                (bb[g] + c <= be[g]) ? ray_weight_pf(p0, f, p, vr.m, vr.inv_r, vr.pl) : 0.0f;
-            share = __fmaf_rn(wgt, sv[g][c], share);
-            q += vr.dq_fx;
+            for (int c = 0; c < kBpBinsPar; ++c) {
+              int p0;
+              float f;
+              split_fx(q, &p0, &f);
+              wgt[c] = ray_weight_pf<1>(p0, f, p, vr.m, vr.inv_r, vr.pl);
+              q += vr.dq_fx;
+            }
+          } else {
+#pragma unroll
+            for (int c = 0; c < kBpBinsPar; ++c) {
+              int p0;
+              float f;
+              split_fx(q, &p0, &f);
+              wgt[c] = ray_weight_pf<2>(p0, f, p, vr.m, vr.inv_r, vr.pl);
+              q += vr.dq_fx;
+            }
           }
+#pragma unroll
+          for (int c = 0; c < kBpBinsPar; ++c)
+            share = __fmaf_rn((bb[g] + c <= be[g]) ? wgt[c] : 0.0f, sv[g][c], share);
           if (be[g] - bb[g] + 1 > kBpBinsPar) {
             const int64_t row = (int64_t)(k0 + g) * A.nb;
             for (int b = bb[g] + kBpBinsPar; b <= be[g]; ++b)
