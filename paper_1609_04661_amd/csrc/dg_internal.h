@@ -65,11 +65,13 @@ struct ViewInfo {
   float cx, cy, inv_dg, pad;  // fan: unit vector towards iso, 1/dgamma [1/rad]
 };
 // Parallel beam: the slope terms every ray of a view shares (copies of the
-// view's RayLine fields), so the back-projector reads only q0_fx per ray.
+// view's RayLine fields), so the back-projector needs no per-ray record.
+// The 32.32 fixed-point values are also held as doubles (integers below
+// 2^46, so exact): the cross coordinate of bin b at major index k,
+// q0 + b dq + k m, is then two exact FMAs instead of 64-bit multiplies.
 struct ViewRay {
-  int64_t m_fx;
-  int64_t q0_fx;  // bin 0's cross coordinate; bin b's is q0_fx + b dq_fx exactly
-  int64_t dq_fx;
+  int64_t dq_fx;  // bin b's cross coordinate is bin 0's + b dq_fx exactly
+  double m_d, q0_d, dq_d;  // m_fx, bin 0's q0_fx, dq_fx
   float m, inv_r, pl, pad;
 };
 

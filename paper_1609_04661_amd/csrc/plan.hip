@@ -183,7 +183,7 @@ extern "C" dg_status dg_plan_create(const dg_geom* g, dg_plan** out) {
     for (int k = 0; k < p->nv; ++k) {
       const RayLine& L = rays[(size_t)k * p->nb];
       const int64_t dq = p->nb > 1 ? rays[(size_t)k * p->nb + 1].q0_fx - L.q0_fx : 0;
-      vr[k] = ViewRay{L.m_fx, L.q0_fx, dq, L.m, L.inv_r, L.pl, 0.0f};
+      vr[k] = ViewRay{dq, (double)L.m_fx, (double)L.q0_fx, (double)dq, L.m, L.inv_r, L.pl, 0.0f};
     }
   }
   if ((e = hipMalloc(&p->rays, sizeof(RayLine) * rays.size())) != hipSuccess ||

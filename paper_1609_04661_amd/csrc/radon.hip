@@ -260,6 +260,7 @@ __device__ void backproject_body(const BpArgs& A, int bx, int by, float (*red)[k
   const float y = 0.5f * (float)(I - 1) - (float)i;
   float acc = 0.0f;
   if (MODE == 0 || (MODE == 2 && !A.fan)) {
+    const double di = (double)i, dj = (double)j;
     // parallel beam: a view's rays share their slope terms and their cross
     // coordinates step by dq_fx per bin, so a candidate bin costs one
     // sinogram value.  In the parallel-only kernel kBpSplit threads share a
@@ -276,7 +277,7 @@ __device__ void backproject_body(const BpArgs& A, int bx, int by, float (*red)[k
       const int kbeg = A.nv * hh / kBpSplit, kend = A.nv * (hh + 1) / kBpSplit;
       float share = 0.0f;
       for (int k0 = kbeg; k0 < kend; k0 += kBpViews) {
-        int bb[kBpViews], be[kBpViews];
+        int bb[kBpViews];
         float sv[kBpViews][kBpBinsPar];
 #pragma unroll
         for (int g = 0; g < kBpViews; ++g) {
@@ -284,20 +285,26 @@ __device__ void backproject_body(const BpArgs& A, int bx, int by, float (*red)[k
           const ViewInfo v = A.views[k];
           const float u = __fmaf_rn(v.a, x, __fmaf_rn(v.b, y, v.c));
           bb[g] = max((int)ceilf(u - v.hw), 0);
-          be[g] = (k0 + g < kend) ? min((int)floorf(u + v.hw), A.nb - 1) : -1;
-          const float* srow = A.sino + (int64_t)k * A.nb;  // bb >= 0: 32-bit offsets
+          // wavefront-uniform row base, 32-bit byte offsets (bb >= 0)
+          const char* srow = (const char*)(A.sino + (int64_t)k * A.nb);
 #pragma unroll
-          for (int c = 0; c < kBpBinsPar; ++c) sv[g][c] = srow[(unsigned)min(bb[g] + c, A.nb - 1)];
+          for (int c = 0; c < kBpBinsPar; ++c)
+            sv[g][c] = *(const float*)(srow + (size_t)((unsigned)min(bb[g] + c, A.nb - 1) * 4u));
         }
 #pragma unroll
         for (int g = 0; g < kBpViews; ++g) {
-          const int k = min(k0 + g, kend - 1);
+          if (k0 + g >= kend) continue;  // wavefront-uniform tail of the share
+          const int k = k0 + g;
           const ViewRay vr = A.vrays[k];
           const bool steep = vr.pl < 0.0f;
           const int p = steep ? j : i;
-          // bb, i, j are non-negative: 64 x 32-bit unsigned products
-          int64_t q = vr.q0_fx + vr.dq_fx * (int64_t)(uint32_t)bb[g] +
-                      vr.m_fx * (int64_t)(uint32_t)(steep ? i : j);
+          // q0 + bb dq + k m in 32.32 fixed point, formed exactly in FP64
+          // (every partial result is an integer below 2^53) and split into
+          // its words
+          const double qd = __fma_rn(vr.dq_d, (double)bb[g], __fma_rn(vr.m_d, steep ? di : dj, vr.q0_d));
+          const double qh = floor(qd * 0x1p-32);
+          int64_t q = (int64_t)(((uint64_t)(uint32_t)(int)qh << 32) |
+                                (uint64_t)(uint32_t)__fma_rn(qh, -0x1p32, qd));
           float wgt[kBpBinsPar];
           // the axis-aligned views (m == 0) are a wavefront-uniform branch
           if (vr.m != 0.0f) {
@@ -319,12 +326,20 @@ __device__ void backproject_body(const BpArgs& A, int bx, int by, float (*red)[k
               q += vr.dq_fx;
             }
           }
+          // A candidate bin past the pixel's footprint has weight 0 by the
+          // chord formula itself (its line misses the pixel), so only bins
+          // past the detector's end are masked.
 #pragma unroll
           for (int c = 0; c < kBpBinsPar; ++c)
-            share = __fmaf_rn((bb[g] + c <= be[g]) ? wgt[c] : 0.0f, sv[g][c], share);
-          if (be[g] - bb[g] + 1 > kBpBinsPar) {
-            const int64_t row = (int64_t)(k0 + g) * A.nb;
-            for (int b = bb[g] + kBpBinsPar; b <= be[g]; ++b)
+            share = __fmaf_rn((bb[g] + c < A.nb) ? wgt[c] : 0.0f, sv[g][c], share);
+          // a footprint shorter than 2 bins covers at most 2 of them; only
+          // views with hw >= 1 (bins narrower than 1/sqrt(2) pixel) need more
+          const ViewInfo v = A.views[k];
+          if (v.hw >= 1.0f) {
+            const float u = __fmaf_rn(v.a, x, __fmaf_rn(v.b, y, v.c));
+            const int be = min((int)floorf(u + v.hw), A.nb - 1);
+            const int64_t row = (int64_t)k * A.nb;
+            for (int b = bb[g] + kBpBinsPar; b <= be; ++b)
               share = __fmaf_rn(ray_weight(A.rays[row + b], i, j), A.sino[row + b], share);
           }
         }
