@@ -22,10 +22,21 @@ build's, the paper treats D as a black box):
     approximated by a fixed number K of fast gradient projection steps on
     the dual problem (Beck & Teboulle 2009): the map D is those K steps.
 
+  * prox_tv_w: the same proximal map in the (V^T V)^-1 metric (Sec. 4.3 and
+    Sec. 6 name it for input in the preconditioned domain),
+    x = argmin 1/2 ||x - r||^2_W + lam TV(x), W = (V^T V)^-1 = 1/c on the DFT
+    grid (c the cone symbol), lam = alpha * sqrt(tau_r), approximated by K
+    Chambolle-Pock primal-dual steps (Chambolle & Pock 2011) with K = lam grad,
+    whose primal step is a Fourier-domain division by 1 + tau w.
+
 Parity: haar_soft pinned (orthonormality, exact divergence by brute force);
 prox_tv pinned by special cases (constant images fixed, lam -> 0 identity,
 large lam -> the mean), a one-row image against an exact bounded least
 squares solve of the same dual, and the primal-dual gap of converged runs;
+prox_tv_w pinned by its reduction to prox_tv when W = I (two different
+algorithms), constant images as fixed points, a one-row image with a
+non-trivial circulant W against an exact bounded least squares solve of its
+dual, and the primal-dual gap of converged runs;
 nlm pinned only by special cases (constant images are fixed points; sigma->0
 is the identity; symmetry under image transposition) -- against the paper it
 is unpinned, the paper's BM3D being a different denoiser.
@@ -41,6 +52,7 @@ HAAR = 0
 NLM = 1
 CNN = 2
 TV = 3
+TVW = 4
 
 SQ2 = math.sqrt(2.0)
 
@@ -186,6 +198,52 @@ def prox_tv(r, tau_r, alpha=0.5, iters=50):
     return prox_tv_lam(r, lam, iters)[0]
 
 
+def prox_tv_metric(b, lam, w, K=50):
+    """K Chambolle-Pock steps (theta = 1) on
+    min_x 1/2 (x - b)^T W (x - b) + lam TV(x),  W = F^-1 diag(w) F,
+    w > 0 given on b's 2D DFT grid (numpy ordering), written as
+    min_x G(x) + F(K x) with K = lam grad, F the dual of the unit-disc
+    indicator, and step sizes sigma = tau = 1 / (lam sqrt 8) (||grad||^2 < 8):
+        p    = P(p + sigma K xbar)                      P: pointwise unit disc
+        x'   = argmin G(u) + ||u - (x - tau K^T p)||^2 / (2 tau)
+             = F^-1 [(F(x - tau lam grad^T p) + tau w F b) / (1 + tau w)]
+        xbar = 2 x' - x
+    from x = xbar = b, p = 0.  Returns x_K and p_K."""
+    b = np.asarray(b, dtype=np.float64)
+    w = np.asarray(w, dtype=np.float64)
+    p1 = np.zeros_like(b)
+    p2 = np.zeros_like(b)
+    if not lam > 0.0:
+        return b.copy(), (p1, p2)
+    tau = sigma = 1.0 / (lam * math.sqrt(8.0))
+    x = b.copy()
+    xbar = b.copy()
+    Bh = np.fft.fft2(b)
+    for _ in range(K):
+        g1, g2 = grad_fwd(xbar)
+        q1 = p1 + sigma * lam * g1
+        q2 = p2 + sigma * lam * g2
+        nrm = np.maximum(1.0, np.sqrt(q1 * q1 + q2 * q2))
+        p1, p2 = q1 / nrm, q2 / nrm
+        v = x - tau * lam * grad_adj(p1, p2)
+        xn = np.real(np.fft.ifft2((np.fft.fft2(v) + tau * w * Bh) / (1.0 + tau * w)))
+        xbar = 2.0 * xn - x
+        x = xn
+    return x, (p1, p2)
+
+
+def metric_symbol(I):
+    """w = 1/c: the symbol of (V^T V)^-1 for the cone preconditioner."""
+    from .precond import symbol
+    return 1.0 / symbol(I)
+
+
+def prox_tv_w(r, tau_r, alpha=1.0, iters=50):
+    lam = alpha * math.sqrt(max(tau_r, 0.0))
+    r = np.asarray(r, dtype=np.float64)
+    return prox_tv_metric(r, lam, metric_symbol(r.shape[-1]), iters)[0]
+
+
 def apply(kind, r, tau_r, params):
     if kind == HAAR:
         return haar_soft(r, tau_r, **params)
@@ -196,6 +254,8 @@ def apply(kind, r, tau_r, params):
         return cnn.denoise(r, params["net"])
     if kind == TV:
         return prox_tv(r, tau_r, **params)
+    if kind == TVW:
+        return prox_tv_w(r, tau_r, **params)
     raise ValueError("unknown denoiser kind")
 
 
