@@ -50,7 +50,8 @@ WEIGHTS = os.path.join(ROOT, "paper_1609_04661_amd", "weights", "cnn_c2_x_space.
 
 # configured recursion for these workloads (damping of means and variances)
 CFG = dict(i0=1e5, seed=1002, probe_seed=7, eta=0.15, tau_x0=1.0, fro2_probes=16,
-           nlm=dict(pr=2, sr=10, hfac=0.4), tv=dict(alpha=1.0, iters=50))
+           nlm=dict(pr=2, sr=10, hfac=0.4), tv=dict(alpha=1.0, iters=50),
+           tvw=dict(iters=50, alphas={0: [0.005, 0.01, 0.02, 0.05], 1: [0.25, 1.0, 4.0, 16.0]}))
 # HBM bytes per launch of nlm_kernel<2> at this workload, from two rocprofv3
 # counter passes (FETCH_SIZE, WRITE_SIZE) scaled by a 256 MiB copy kernel
 # (profiles/dgamp_c2_512x512_64views_hbm_traffic.md).  Set to None whenever
@@ -380,31 +381,30 @@ def ablation(api, h, T=50):
     return out
 
 
-def proxtv(api, args, h, T=50):
-    """The proximal-TV plug-in (NEXT rank 2, Sec. 6) on the headline inputs at
-    the configured damping: PSNR after every iteration, ms per iteration from
-    a graph replay of the whole run, and the iteration at which it reaches
-    the plain (NLM) run's final PSNR."""
+def prox_run(api, args, h, kind, params, T=50):
+    """One plug-in run on the headline inputs at the configured damping: PSNR
+    after every iteration, ms per iteration from a graph replay of the whole
+    run, and the iteration at which it reaches the plain (NLM) run's final
+    PSNR."""
     import torch
     plan, y_d, fro2, mu_d, work = h["plan"], h["y_d"], h["fro2"], h["mu_d"], h["work"]
-    params = api.make_params(api.DEN_TV, n_pixels=plan.N, **CFG["tv"])
     kw = dict(probe_seed=CFG["probe_seed"], eta_x=CFG["eta"], eta_s=CFG["eta"])
     mu_out = torch.empty((plan.I, plan.I), dtype=torch.float32, device="cuda")
     st = api.DgampState(plan, CFG["tau_x0"])
     ps = torch.empty(T, dtype=torch.float64, device="cuda")
     for t in range(T):
-        api.dgamp_iterate(plan, y_d, st, 1, fro2, CFG["i0"], api.DEN_TV, params, mu_out=mu_out,
+        api.dgamp_iterate(plan, y_d, st, 1, fro2, CFG["i0"], kind, params, mu_out=mu_out,
                           work=work, **kw)
         api.dg_psnr(mu_out, mu_d, out=ps[t:t + 1])
     curve = [float(v) for v in ps.cpu().numpy()]
     gst = api.DgampState(plan, CFG["tau_x0"])
-    G = api.DgampGraph(plan, y_d, gst, T, fro2, CFG["i0"], api.DEN_TV, params,
+    G = api.DgampGraph(plan, y_d, gst, T, fro2, CFG["i0"], kind, params,
                        tau_x0=CFG["tau_x0"], mu_out=mu_out, work=work, **kw)
     G.launch()
     s = sync_time(G.launch, args.reps)
-    out = dict(iterations=T, alpha=CFG["tv"]["alpha"], dual_steps=CFG["tv"]["iters"],
-               damping=CFG["eta"], ms_per_iter=1e3 * s / T, iter_per_s=T / s,
-               psnr_final=curve[-1], psnr_every_5=[round(v, 3) for v in curve[4::5]],
+    out = dict(iterations=T, damping=CFG["eta"], ms_per_iter=1e3 * s / T, iter_per_s=T / s,
+               psnr_final=curve[-1], psnr_best=max(curve),
+               psnr_every_5=[round(v, 3) for v in curve[4::5]],
                status=float(gst.scal[api.S_STATUS].item()))
     target = h.get("plain_psnr")
     if target is not None:
@@ -413,6 +413,32 @@ def proxtv(api, args, h, T=50):
         out["iters_to_plain_psnr"] = k
         if k is not None:
             out["ms_to_plain_psnr"] = k * out["ms_per_iter"]
+    return out
+
+
+def proxtv(api, args, h, T=50):
+    """The proximal-TV plug-ins (NEXT rank 2, Sec. 6): the l2 map at its
+    configured alpha, and the metric map in both readings of the paper's norm
+    ((V^T V)^-1 as the text writes it, V^T V as its TV figure's subscript),
+    each over a small alpha sweep (no alpha is given for either)."""
+    plan = h["plan"]
+    out = prox_run(api, args, h, api.DEN_TV, api.make_params(api.DEN_TV, n_pixels=plan.N, **CFG["tv"]), T)
+    out.update(alpha=CFG["tv"]["alpha"], dual_steps=CFG["tv"]["iters"])
+    variants = {}
+    for metric, name in ((0, "inv_VtV"), (1, "VtV")):
+        runs = []
+        for a in CFG["tvw"]["alphas"][metric]:
+            prm = api.make_params(api.DEN_TVW, side=plan.I, alpha=a, iters=CFG["tvw"]["iters"],
+                                  metric=metric)
+            r = prox_run(api, args, h, api.DEN_TVW, prm, T)
+            r["alpha"] = a
+            runs.append(r)
+        best = max(runs, key=lambda r: r["psnr_final"] if r["psnr_final"] == r["psnr_final"] else -1e9)
+        variants[name] = dict(metric=metric, primal_dual_steps=CFG["tvw"]["iters"], best=best,
+                              sweep=[dict(alpha=r["alpha"], psnr_final=r["psnr_final"],
+                                          psnr_every_5=r["psnr_every_5"], ms_per_iter=r["ms_per_iter"],
+                                          status=r["status"]) for r in runs])
+    out["metric_variants"] = variants
     return out
 
 

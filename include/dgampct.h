@@ -143,12 +143,25 @@ dg_status gamp_poisson_out(int64_t m, const float* p, const float* y, const doub
  *                the dual (Beck & Teboulle 2009) from a zero dual; the map is
  *                those steps.  work: device, dg_tv_workspace_bytes(I*I) bytes,
  *                owned by the caller, overwritten by every call.
+ *   DG_DEN_TVW : the same map in the (V^T V)^-1 metric (Sec. 4.3 and Sec. 6 name
+ *                it for input in the preconditioned domain): argmin_x 1/2
+ *                (x - r)^T W (x - r) + lam TV(x), W = (V^T V)^-1 the circulant
+ *                with symbol 1/c (c the cone symbol of ct_precondition; with
+ *                metric = 1, W = V^T V, symbol c, the figure's reading), lam =
+ *                alpha sqrt(tau_r), as `iters` Chambolle-Pock primal-dual steps
+ *                (sigma = tau = 1/(lam sqrt 8), theta = 1) from x = r and a zero
+ *                dual, each with a Fourier-domain primal step; the map is those
+ *                steps.  Params: dg_tv_params with work of
+ *                dg_tvw_workspace_bytes(I) bytes (device, caller-owned,
+ *                overwritten by every call).  The side I must be one the FFT
+ *                supports (2^a or 3 * 2^a, <= 1024), else DG_ERR_ARG.
  * r, x_out: I*I floats; tau_r: device double; div_out: device double or NULL
  * (NULL skips the probe evaluation).  work: dg_workspace_bytes(DG_OP_DENOISE). */
 #define DG_DEN_HAAR 0
 #define DG_DEN_NLM 1
 #define DG_DEN_CNN 2
 #define DG_DEN_TV 3
+#define DG_DEN_TVW 4
 typedef struct dg_haar_params { double alpha; int32_t levels; /* 0 = log2 I - 2 */ } dg_haar_params;
 typedef struct dg_nlm_params { int32_t patch_radius; int32_t search_radius; double hfac; } dg_nlm_params;
 typedef struct dg_cnn_params {
@@ -156,11 +169,18 @@ typedef struct dg_cnn_params {
   void* work;           /* device: dg_cnn_workspace_bytes(I*I) bytes (activations) */
 } dg_cnn_params;
 typedef struct dg_tv_params {
-  double alpha;   /* lam = alpha * sqrt(tau_r), >= 0                            */
-  int32_t iters;  /* fast gradient projection steps, 1 .. 10000                 */
-  void* work;     /* device: dg_tv_workspace_bytes(I*I) bytes (dual state)      */
+  double alpha;    /* lam = alpha * sqrt(tau_r), >= 0                            */
+  int32_t iters;   /* TV: fast gradient projection steps; TVW: primal-dual       */
+                   /* steps; 1 .. 10000                                          */
+  int32_t metric;  /* TVW only: 0 = W = (V^T V)^-1 (the norm the text names),    */
+                   /* 1 = W = V^T V (the subscript of the paper's TV figure);    */
+                   /* TV ignores it                                              */
+  void* work;      /* device: dg_tv_workspace_bytes(I*I) bytes for TV,           */
+                   /* dg_tvw_workspace_bytes(I) for TVW                          */
 } dg_tv_params;
 size_t dg_tv_workspace_bytes(int64_t n_pixels);
+/* Work bytes of DG_DEN_TVW for an I x I image (0 for side <= 0). */
+size_t dg_tvw_workspace_bytes(int32_t side);
 dg_status denoise(const dg_plan* plan, int32_t kind, const void* params, const float* r,
                   const double* tau_r, uint64_t probe_seed, int32_t iter, double eps_rel,
                   float* x_out, double* div_out, void* work, void* stream);

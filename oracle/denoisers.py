@@ -232,16 +232,18 @@ def prox_tv_metric(b, lam, w, K=50):
     return x, (p1, p2)
 
 
-def metric_symbol(I):
-    """w = 1/c: the symbol of (V^T V)^-1 for the cone preconditioner."""
+def metric_symbol(I, metric=0):
+    """w = 1/c, the symbol of (V^T V)^-1 for the cone preconditioner (the norm
+    the text names); metric = 1 gives w = c, V^T V itself (the subscript the
+    paper's TV figure prints)."""
     from .precond import symbol
-    return 1.0 / symbol(I)
+    return symbol(I) if metric else 1.0 / symbol(I)
 
 
-def prox_tv_w(r, tau_r, alpha=1.0, iters=50):
+def prox_tv_w(r, tau_r, alpha=1.0, iters=50, metric=0):
     lam = alpha * math.sqrt(max(tau_r, 0.0))
     r = np.asarray(r, dtype=np.float64)
-    return prox_tv_metric(r, lam, metric_symbol(r.shape[-1]), iters)[0]
+    return prox_tv_metric(r, lam, metric_symbol(r.shape[-1], metric), iters)[0]
 
 
 def apply(kind, r, tau_r, params):

@@ -16,7 +16,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libdgampct.so")
 
 PARALLEL, FAN = 0, 1
-DEN_HAAR, DEN_NLM, DEN_CNN, DEN_TV = 0, 1, 2, 3
+DEN_HAAR, DEN_NLM, DEN_CNN, DEN_TV, DEN_TVW = 0, 1, 2, 3, 4
 CHANNEL_LAPLACE, CHANNEL_MODE_ONLY = 0, 1
 OP_PRECOND, OP_DENOISE, OP_DGAMP, OP_FRO2 = 0, 1, 2, 3
 NSCAL = 16
@@ -36,7 +36,7 @@ EXPORTS = ("dg_plan_create", "dg_plan_destroy", "dg_workspace_bytes", "dg_channe
            "dgamp_batch_iterate", "dg_batch_graph_create", "dg_batch_autotune",
            "dg_batch_projector_variant", "dg_plan_autotune", "dg_plan_projector_variant",
            "dg_batch_set_projector_variant", "dg_plan_set_projector_variant",
-           "dg_psnr_workspace_bytes", "dg_psnr", "dg_tv_workspace_bytes")
+           "dg_psnr_workspace_bytes", "dg_psnr", "dg_tv_workspace_bytes", "dg_tvw_workspace_bytes")
 
 
 class DgError(RuntimeError):
@@ -65,7 +65,8 @@ class CnnParams(ctypes.Structure):
 
 
 class TvParams(ctypes.Structure):
-    _fields_ = [("alpha", ctypes.c_double), ("iters", ctypes.c_int32), ("work", ctypes.c_void_p)]
+    _fields_ = [("alpha", ctypes.c_double), ("iters", ctypes.c_int32), ("metric", ctypes.c_int32),
+                ("work", ctypes.c_void_p)]
 
 
 class DgampOpts(ctypes.Structure):
@@ -140,6 +141,7 @@ def load():
         "dg_psnr_workspace_bytes": ([], sz),
         "dg_psnr": ([i64, _VP, _VP, _VP, _VP, _VP], i32),
         "dg_tv_workspace_bytes": ([i64], sz),
+        "dg_tvw_workspace_bytes": ([i32], sz),
     }
     missing = set(EXPORTS) - set(sig)
     if missing:
@@ -286,6 +288,14 @@ def make_params(kind, **kw):
                           device="cuda")
         prm = TvParams(alpha=kw.get("alpha", 0.5), iters=kw.get("iters", 50),
                        work=ctypes.c_void_p(buf.data_ptr()))
+        prm._buf = buf
+        return prm
+    if kind == DEN_TVW:
+        # the solver state (primal, dual, spectra) lives as long as the params object
+        buf = torch.empty(int(load().dg_tvw_workspace_bytes(int(kw["side"]))), dtype=torch.uint8,
+                          device="cuda")
+        prm = TvParams(alpha=kw.get("alpha", 1.0), iters=kw.get("iters", 50),
+                       metric=kw.get("metric", 0), work=ctypes.c_void_p(buf.data_ptr()))
         prm._buf = buf
         return prm
     raise DgError("unknown denoiser kind")

@@ -269,7 +269,7 @@ extern "C" dg_status dg_batch_bind(dg_batch* b, const float* y, const double* i0
     set_error("dg_batch_bind: the CNN denoiser needs slices of one image size");
     return DG_ERR_UNSUPPORTED;
   }
-  if (den_kind == DG_DEN_HAAR || den_kind == DG_DEN_TV) {
+  if (den_kind == DG_DEN_HAAR || den_kind == DG_DEN_TV || den_kind == DG_DEN_TVW) {
     set_error("dg_batch_bind: batched runs support the NLM and CNN denoisers");
     return DG_ERR_UNSUPPORTED;
   }

@@ -337,6 +337,69 @@ def test_prox_tv_identity_at_zero_variance(gpu_lib, plans):
     assert np.array_equal(host(x), r)
 
 
+@pytest.mark.parametrize("I,noise,tau,iters,metric", [(64, 0.05, 2.5e-3, 50, 0), (96, 0.05, 2.5e-3, 20, 0),
+                                                      (256, 0.05, 2.5e-3, 30, 0), (512, 0.05, 2.5e-3, 50, 0),
+                                                      (48, 0.004, 1.6e-5, 1, 0), (64, 0.05, 2.5e-3, 50, 1),
+                                                      (512, 0.05, 2.5e-3, 50, 1)])
+def test_prox_tv_w_matches_oracle(gpu_lib, I, noise, tau, iters, metric):
+    """The metric proximal TV ((V^T V)^-1, and V^T V with metric 1) and its MC
+    divergence against the oracle's same Chambolle-Pock steps in FP64:
+    register-resident transforms (256, 512), LDS-staged ones (64, 48) and a
+    radix-3 side (96)."""
+    g = synth.geometry(synth.PARALLEL, I, 1.0, 4, I + 1, math.pi)
+    P = gpu_lib.Plan(g)
+    r = synth.ellipse_phantom(I, 8) + noise * np.random.default_rng(3).standard_normal((I, I))
+    r32 = r.astype(np.float32).astype(np.float64)
+    prm = gpu_lib.make_params(gpu_lib.DEN_TVW, alpha=1.0, iters=iters, side=I, metric=metric)
+    x, div = gpu_lib.denoise(P, gpu_lib.DEN_TVW, prm, cu(r32), cu([tau], torch.float64),
+                             probe_seed=9, iteration=2)
+    params = dict(alpha=1.0, iters=iters, metric=metric)
+    x_ref = oden.prox_tv_w(r32, tau, **params)
+    assert rel_l2(host(x), x_ref) <= 2e-5, rel_l2(host(x), x_ref)
+    div_ref, _ = oden.mc_divergence(oden.TVW, r32, tau, params, x_ref, 9, 2)
+    assert abs(float(host(div)[0]) - div_ref) <= 2e-3, (float(host(div)[0]), div_ref)
+
+
+def test_prox_tv_w_identity_at_zero_variance(gpu_lib, plans):
+    I = 64
+    g = synth.geometry(synth.PARALLEL, I, 1.0, 4, I + 1, math.pi)
+    P = gpu_lib.Plan(g)
+    r = np.random.default_rng(4).standard_normal((I, I)).astype(np.float32)
+    prm = gpu_lib.make_params(gpu_lib.DEN_TVW, alpha=1.0, iters=3, side=I)
+    x, _ = gpu_lib.denoise(P, gpu_lib.DEN_TVW, prm, cu(r), cu([0.0], torch.float64), with_div=False)
+    assert np.array_equal(host(x), r)
+
+
+def test_prox_tv_w_rejects_sides_the_fft_cannot_take(gpu_lib, plans):
+    I = 40  # 5 * 2^3
+    g = synth.geometry(synth.PARALLEL, I, 1.0, 4, I + 1, math.pi)
+    P = gpu_lib.Plan(g)
+    prm = gpu_lib.make_params(gpu_lib.DEN_TVW, alpha=1.0, iters=3, side=I)
+    with pytest.raises(gpu_lib.DgError):
+        gpu_lib.denoise(P, gpu_lib.DEN_TVW, prm, cu(np.zeros((I, I), np.float32)),
+                        cu([1e-3], torch.float64), with_div=False)
+
+
+@pytest.mark.parametrize("metric,alpha", [(0, 0.02), (1, 1.0)])
+def test_dgamp_c1_prox_tv_w_matches_oracle(gpu_lib, plans, metric, alpha):
+    """D-GAMP-CT with the metric proximal TV (C1 inputs, 20 iterations).  The
+    weights keep the first divergence estimate away from zero: a denoiser
+    whose output barely moves with r (div ~ 0 at t = 0, as the (V^T V)^-1
+    metric gives with alpha >= 0.25 at tau_r = 1.5) clamps tau_x to ~0, and
+    the channel with tau_p ~ 1e-11 then amplifies FP32 rounding."""
+    g, R, mu, y, fro2 = c1_inputs()
+    T, eta, seed = 20, 0.5, 13
+    params = dict(alpha=alpha, iters=30, metric=metric)
+    ref_mu, ref_log, _ = ogamp.dgamp_ct(R, y, 1e4, fro2, T, oden.TVW, params, seed,
+                                        eta_x=eta, eta_s=eta)
+    out_mu, log, st = run_gpu_dgamp(gpu_lib, plans["c1"], y, fro2, 1e4, T, gpu_lib.DEN_TVW,
+                                    gpu_lib.make_params(gpu_lib.DEN_TVW, side=64, **params),
+                                    seed, eta)
+    assert float(host(st.scal)[gpu_lib.S_STATUS]) == 0.0
+    p_ref, p_gpu = metrics.psnr(ref_mu, mu), metrics.psnr(out_mu, mu)
+    assert abs(p_gpu - p_ref) <= 0.1, (p_gpu, p_ref)
+
+
 def test_dgamp_c1_prox_tv_matches_oracle(gpu_lib, plans):
     """D-GAMP-CT with the proximal-TV plug-in (C1 inputs, 20 iterations)."""
     g, R, mu, y, fro2 = c1_inputs()

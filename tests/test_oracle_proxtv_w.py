@@ -27,6 +27,8 @@ def test_metric_symbol_is_the_inverse_cone_symbol():
     assert abs(w[0, 0] - 1.0 / (4.0 * math.log(1.0 + math.sqrt(2.0)) * I)) < 1e-15
     assert abs(w[0, 1] - 1.0 / I) < 1e-15 and abs(w[3, 4] - 5.0 / I) < 1e-15
     assert np.all(w > 0.0)
+    # the figure's reading V^T V: the cone symbol itself
+    assert np.array_equal(den.metric_symbol(I, 1), precond.symbol(I))
 
 
 def test_identity_metric_reaches_the_l2_prox():
