@@ -51,7 +51,7 @@ WEIGHTS = os.path.join(ROOT, "paper_1609_04661_amd", "weights", "cnn_c2_x_space.
 # configured recursion for these workloads (damping of means and variances)
 CFG = dict(i0=1e5, seed=1002, probe_seed=7, eta=0.15, tau_x0=1.0, fro2_probes=16,
            nlm=dict(pr=2, sr=10, hfac=0.4), tv=dict(alpha=1.0, iters=50),
-           tvw=dict(iters=50, alphas={0: [0.005, 0.01, 0.02, 0.05], 1: [0.25, 1.0, 4.0, 16.0]}))
+           tvw=dict(iters=50, alphas={0: [0.02, 0.05, 0.1, 0.2], 1: [64.0, 256.0, 1024.0, 4096.0]}))
 # HBM bytes per launch of nlm_kernel<2> at this workload, from two rocprofv3
 # counter passes (FETCH_SIZE, WRITE_SIZE) scaled by a 256 MiB copy kernel
 # (profiles/dgamp_c2_512x512_64views_hbm_traffic.md).  Set to None whenever
