@@ -14,13 +14,17 @@
 //   v    = x - grad^T(p) / sqrt 8                     (tau lam = 1/sqrt 8)
 //   x'   = F^-1 [(F v + tau w F r) / (1 + tau w)]     (the primal prox of G)
 //   xbar = 2 x' - x
-// from x = xbar = r, p = 0; the map is those K steps.  Each step is four
-// launches over both images (r and the probe's r + eps b): the dual update,
-// then the three passes of a 2D FFT solve (row transforms of v, column
-// transforms with the Fourier-domain division, inverse row transforms with
-// the extrapolation).  F r is computed once per call.  The FFT passes share
-// the wavefront transforms of the cone preconditioner.
+// from x = xbar = r, p = 0; the map is those K steps.  Each step is three
+// launches over both images (r and the probe's r + eps b), the passes of a
+// 2D FFT solve: row transforms of v, with the dual update fused in front
+// (a row pair's v needs the new dual on its rows and on the row above; the
+// dual is ping-ponged between two buffers so that the rows recomputed by a
+// neighbouring workgroup still read the old one), column transforms with the
+// Fourier-domain division, inverse row transforms with the extrapolation.
+// F r is computed once per call.  The FFT passes share the wavefront
+// transforms of the cone preconditioner.
 #include <cmath>
+#include <utility>
 
 #include "dg_internal.h"
 #include "fft_wave.h"
@@ -32,7 +36,8 @@ struct TvwArgs {
   float* b1;            // image 1 input r + eps b (written by tvw_prep)
   float* x;             // primal, [img][N]
   float* xb;            // extrapolated primal, [img][N]
-  float* p;             // dual, [img][2][N]
+  float* p;             // dual read by a step, [img][2][N]
+  float* pn;            // dual written by a step, [img][2][N] (swapped with p per step)
   float2* spec;         // [img][spec_n]: row-transformed / solved spectrum, spec[k][row]
   float2* rspec;        // [img][spec_n]: F r, after the column transforms
   const float2* tw;     // plan twiddles, I entries
@@ -79,45 +84,27 @@ __global__ void __launch_bounds__(256) tvw_prep(TvwArgs A, uint64_t seed, int it
   }
 }
 
-// p = P(p + grad(xbar) / sqrt 8), forward differences, zero past the last
-// row / column; P the pointwise projection onto the unit disc.
-__global__ void __launch_bounds__(256) tvw_dual(TvwArgs A) {
-  const int I = A.I;
-  const int img = blockIdx.y;
-  const float sl = tvw_tau(A) > 0.0f ? kInvSqrt8 : 0.0f;  // sigma lam (0: the identity map)
-  const float* xb = A.xb + img * A.N;
-  float* p1 = A.p + (2 * img) * A.N;
-  float* p2 = p1 + A.N;
-  for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < A.npix;
-       k += (int64_t)gridDim.x * blockDim.x) {
-    const int i = (int)(k / I), j = (int)(k % I);
-    const float c = xb[k];
-    const float g1 = i < I - 1 ? xb[k + I] - c : 0.0f;
-    const float g2 = j < I - 1 ? xb[k + 1] - c : 0.0f;
-    const float q1 = __fmaf_rn(sl, g1, p1[k]);
-    const float q2 = __fmaf_rn(sl, g2, p2[k]);
-    const float nrm = fmaxf(1.0f, sqrtf(__fmaf_rn(q1, q1, q2 * q2)));
-    p1[k] = q1 / nrm;
-    p2[k] = q2 / nrm;
-  }
-}
-
-// (grad^T p)(i, j): the adjoint of the forward differences.
-__device__ __forceinline__ float tvw_adj(const float* __restrict__ p1, const float* __restrict__ p2,
-                                         int i, int j, int I) {
-  const int64_t k = (int64_t)i * I + j;
-  float a = 0.0f;
-  if (i > 0) a += p1[k - I];
-  if (i < I - 1) a -= p1[k];
-  if (j > 0) a += p2[k - 1];
-  if (j < I - 1) a -= p2[k];
-  return a;
+// The new dual at (a, b): P(p + sl grad(xbar)), forward differences with
+// zero past the last row / column, P the projection onto the unit disc.
+__device__ __forceinline__ float2 tvw_pnew(const float* __restrict__ xb, const float* __restrict__ p1,
+                                           const float* __restrict__ p2, int a, int b, int I,
+                                           float sl) {
+  const int64_t k = (int64_t)a * I + b;
+  const float c = xb[k];
+  const float g1 = a < I - 1 ? xb[k + I] - c : 0.0f;
+  const float g2 = b < I - 1 ? xb[k + 1] - c : 0.0f;
+  const float q1 = __fmaf_rn(sl, g1, p1[k]);
+  const float q2 = __fmaf_rn(sl, g2, p2[k]);
+  const float nrm = fmaxf(1.0f, sqrtf(__fmaf_rn(q1, q1, q2 * q2)));
+  return make_float2(q1 / nrm, q2 / nrm);
 }
 
 // Row pass: workgroup blockIdx.x owns real rows kRowsPerBlock blk onwards of
-// image blockIdx.y; mode 0 transforms the input, mode 1 transforms
-// v = x - grad^T(p) / sqrt 8.  Output spec[k][row], k = 0..I/2, as the cone
-// preconditioner's row pass.
+// image blockIdx.y; mode 0 transforms the input, mode 1 first takes the
+// dual step p' = P(p + grad(xbar) / sqrt 8) on its rows (written to pn) and
+// transforms v = x - grad^T(p') / sqrt 8, recomputing p' on the row above
+// and one column to the left where the adjoint needs it.  Output
+// spec[k][row], k = 0..I/2, as the cone preconditioner's row pass.
 __global__ void __launch_bounds__(kFftThreads) tvw_rows(TvwArgs A, int mode) {
   __shared__ FftShared S;
   const int I = A.I, lane = threadIdx.x & 63, w = threadIdx.x >> 6;
@@ -126,21 +113,43 @@ __global__ void __launch_bounds__(kFftThreads) tvw_rows(TvwArgs A, int mode) {
   const int m = blk * kFftWaves + w;
   const bool live = 2 * m < I;
   const float* src = mode ? A.x + img * A.N : tvw_input(A, img);
+  const float* xbar = A.xb + img * A.N;
   const float* p1 = A.p + (2 * img) * A.N;
   const float* p2 = p1 + A.N;
+  float* q1 = A.pn + (2 * img) * A.N;
+  float* q2 = q1 + A.N;
   float2* spec = A.spec + img * A.spec_n;
-  const float tl = tvw_tau(A) > 0.0f ? kInvSqrt8 : 0.0f;  // tau lam
+  // sigma lam = tau lam = 1/sqrt 8; 0 when lam = 0 (the identity map)
+  const float sl = tvw_tau(A) > 0.0f ? kInvSqrt8 : 0.0f;
   float ra[kPerLane], rb[kPerLane];
   if (live) {
+    const int ia = 2 * m, ib = 2 * m + 1;
 #pragma unroll
     for (int q = 0; q < kPerLane; ++q) {
       const int t = lane + 64 * q;
       if (t < I) {
-        float va = src[(int64_t)(2 * m) * I + t];
-        float vb = src[(int64_t)(2 * m + 1) * I + t];
+        float va = src[(int64_t)ia * I + t];
+        float vb = src[(int64_t)ib * I + t];
         if (mode) {
-          va = __fmaf_rn(-tl, tvw_adj(p1, p2, 2 * m, t, I), va);
-          vb = __fmaf_rn(-tl, tvw_adj(p1, p2, 2 * m + 1, t, I), vb);
+          const float2 na = tvw_pnew(xbar, p1, p2, ia, t, I, sl);
+          const float2 nb = tvw_pnew(xbar, p1, p2, ib, t, I, sl);
+          q1[(int64_t)ia * I + t] = na.x;
+          q2[(int64_t)ia * I + t] = na.y;
+          q1[(int64_t)ib * I + t] = nb.x;
+          q2[(int64_t)ib * I + t] = nb.y;
+          // grad^T p' in the order of the adjoint's terms: +p1(i-1), -p1(i),
+          // +p2(j-1), -p2(j)
+          float aa = 0.0f, ab = 0.0f;
+          if (ia > 0) aa += tvw_pnew(xbar, p1, p2, ia - 1, t, I, sl).x;
+          aa -= na.x;  // ia < I - 1 always (ib = ia + 1 exists)
+          if (t > 0) aa += tvw_pnew(xbar, p1, p2, ia, t - 1, I, sl).y;
+          if (t < I - 1) aa -= na.y;
+          ab += na.x;  // ib > 0
+          if (ib < I - 1) ab -= nb.x;
+          if (t > 0) ab += tvw_pnew(xbar, p1, p2, ib, t - 1, I, sl).y;
+          if (t < I - 1) ab -= nb.y;
+          va = __fmaf_rn(-sl, aa, va);
+          vb = __fmaf_rn(-sl, ab, vb);
         }
         ra[q] = va;
         rb[q] = vb;
@@ -363,11 +372,11 @@ __global__ void __launch_bounds__(kFftThreads) tvw_rows_inv(TvwArgs A, int last)
 static size_t tvw_align(size_t n) { return (n + 255) & ~(size_t)255; }
 
 size_t tvw_work_bytes(int64_t npix, int I) {
-  // b1; x, xb for two images; p (2 components) for two images; spec and
-  // rspec for two images
+  // b1; x, xb for two images; p and pn (2 components each) for two images;
+  // spec and rspec for two images
   const size_t f = tvw_align(sizeof(float) * (size_t)npix);
   const size_t sp = tvw_align(sizeof(float2) * (size_t)(I / 2 + 1) * (size_t)I);
-  return f + 2 * 2 * f + 2 * 2 * f + 2 * 2 * sp;
+  return f + 2 * 2 * f + 2 * 2 * 2 * f + 2 * 2 * sp;
 }
 
 dg_status tvw_check_params(const dg_plan* p, const void* params) {
@@ -397,8 +406,9 @@ dg_status tvw_launch_denoise(const dg_plan* p, const void* params, const float* 
   A.x = (float*)(c + f);        // 2 planes, f apart
   A.xb = (float*)(c + 3 * f);   // 2 planes
   A.p = (float*)(c + 5 * f);    // 4 planes
-  A.spec = (float2*)(c + 9 * f);          // 2 spectra, sp apart
-  A.rspec = (float2*)(c + 9 * f + 2 * sp);
+  A.pn = (float*)(c + 9 * f);   // 4 planes
+  A.spec = (float2*)(c + 13 * f);          // 2 spectra, sp apart
+  A.rspec = (float2*)(c + 13 * f + 2 * sp);
   A.tw = p->twiddle;
   A.I = I;
   A.nimg = x_pert ? 2 : 1;
@@ -414,7 +424,7 @@ dg_status tvw_launch_denoise(const dg_plan* p, const void* params, const float* 
   A.spec_n = (int64_t)(sp / sizeof(float2));
   const unsigned int g = (unsigned int)((N + 255) / 256 < 2048 ? (N + 255) / 256 : 2048);
   // the kernels index planes A.N floats apart and touch only the first I*I of each
-  const TvwArgs K = A;
+  TvwArgs K = A;
   hipLaunchKernelGGL(tvw_prep, dim3(g), dim3(256), 0, st, K, seed, iter);
   DG_LAUNCH_CHECK("tvw_prep");
   const dim3 rgrid((I + kRowsPerBlock - 1) / kRowsPerBlock, A.nimg);
@@ -424,8 +434,7 @@ dg_status tvw_launch_denoise(const dg_plan* p, const void* params, const float* 
   hipLaunchKernelGGL(tvw_cols, cgrid, dim3(kFftThreads), 0, st, K, 0);
   DG_LAUNCH_CHECK("tvw_cols");
   for (int k = 0; k < tp->iters; ++k) {
-    hipLaunchKernelGGL(tvw_dual, dim3(g, A.nimg), dim3(256), 0, st, K);
-    DG_LAUNCH_CHECK("tvw_dual");
+    if (k > 0) std::swap(K.p, K.pn);  // this step reads the dual the last one wrote
     hipLaunchKernelGGL(tvw_rows, rgrid, dim3(kFftThreads), 0, st, K, 1);
     DG_LAUNCH_CHECK("tvw_rows");
     hipLaunchKernelGGL(tvw_cols, cgrid, dim3(kFftThreads), 0, st, K, 1);

@@ -73,14 +73,15 @@ def test_tv_workspace_size():
 
 
 def test_tvw_workspace_size():
-    """The metric proximal TV's state: the perturbed input, x, xbar and the two
-    dual components per image (9 planes), and two half spectra of (I/2+1) x I
-    complex floats per image (F v and F r), each region 256-byte aligned."""
+    """The metric proximal TV's state: the perturbed input, x, xbar and two
+    ping-pong copies of the two dual components per image (13 planes), and
+    two half spectra of (I/2+1) x I complex floats per image (F v and F r),
+    each region 256-byte aligned."""
     L = api.load()
     assert L.dg_tvw_workspace_bytes(0) == 0
-    assert L.dg_tvw_workspace_bytes(512) == 9 * 512 * 512 * 4 + 4 * 257 * 512 * 8
+    assert L.dg_tvw_workspace_bytes(512) == 13 * 512 * 512 * 4 + 4 * 257 * 512 * 8
     # side 12: 144 floats -> 768 bytes per plane; 7 x 12 complex -> 768 bytes per spectrum
-    assert L.dg_tvw_workspace_bytes(12) == 9 * 768 + 4 * 768
+    assert L.dg_tvw_workspace_bytes(12) == 13 * 768 + 4 * 768
 
 
 def test_product_path_has_no_cpu_fallback():
