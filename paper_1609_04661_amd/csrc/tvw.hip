@@ -95,15 +95,16 @@ __device__ __forceinline__ float2 tvw_pnew(const float* __restrict__ xb, const f
   const float g2 = b < I - 1 ? xb[k + 1] - c : 0.0f;
   const float q1 = __fmaf_rn(sl, g1, p1[k]);
   const float q2 = __fmaf_rn(sl, g2, p2[k]);
-  const float nrm = fmaxf(1.0f, sqrtf(__fmaf_rn(q1, q1, q2 * q2)));
-  return make_float2(q1 / nrm, q2 / nrm);
+  const float inv = 1.0f / fmaxf(1.0f, sqrtf(__fmaf_rn(q1, q1, q2 * q2)));
+  return make_float2(q1 * inv, q2 * inv);
 }
 
 // Row pass: workgroup blockIdx.x owns real rows kRowsPerBlock blk onwards of
 // image blockIdx.y; mode 0 transforms the input, mode 1 first takes the
 // dual step p' = P(p + grad(xbar) / sqrt 8) on its rows (written to pn) and
-// transforms v = x - grad^T(p') / sqrt 8, recomputing p' on the row above
-// and one column to the left where the adjoint needs it.  Output
+// transforms v = x - grad^T(p') / sqrt 8; the adjoint's p' on the row above
+// is recomputed, the one a column to the left is taken from the neighbouring
+// lane.  Output
 // spec[k][row], k = 0..I/2, as the cone preconditioner's row pass.
 __global__ void __launch_bounds__(kFftThreads) tvw_rows(TvwArgs A, int mode) {
   __shared__ FftShared S;
@@ -124,29 +125,44 @@ __global__ void __launch_bounds__(kFftThreads) tvw_rows(TvwArgs A, int mode) {
   float ra[kPerLane], rb[kPerLane];
   if (live) {
     const int ia = 2 * m, ib = 2 * m + 1;
+    // p2' one column to the left comes from the neighbouring lane, and for
+    // lane 0 from lane 63 of the previous group of 64 columns
+    float carry_a = 0.0f, carry_b = 0.0f;
 #pragma unroll
     for (int q = 0; q < kPerLane; ++q) {
       const int t = lane + 64 * q;
-      if (t < I) {
-        float va = src[(int64_t)ia * I + t];
-        float vb = src[(int64_t)ib * I + t];
+      if (64 * q < I) {  // wavefront-uniform: the shuffles need every lane
+        const bool in = t < I;
+        float va = in ? src[(int64_t)ia * I + t] : 0.0f;
+        float vb = in ? src[(int64_t)ib * I + t] : 0.0f;
         if (mode) {
-          const float2 na = tvw_pnew(xbar, p1, p2, ia, t, I, sl);
-          const float2 nb = tvw_pnew(xbar, p1, p2, ib, t, I, sl);
-          q1[(int64_t)ia * I + t] = na.x;
-          q2[(int64_t)ia * I + t] = na.y;
-          q1[(int64_t)ib * I + t] = nb.x;
-          q2[(int64_t)ib * I + t] = nb.y;
+          float2 na = make_float2(0.0f, 0.0f), nb = na, nu = na;
+          if (in) {
+            na = tvw_pnew(xbar, p1, p2, ia, t, I, sl);
+            nb = tvw_pnew(xbar, p1, p2, ib, t, I, sl);
+            if (ia > 0) nu = tvw_pnew(xbar, p1, p2, ia - 1, t, I, sl);  // the row above
+            q1[(int64_t)ia * I + t] = na.x;
+            q2[(int64_t)ia * I + t] = na.y;
+            q1[(int64_t)ib * I + t] = nb.x;
+            q2[(int64_t)ib * I + t] = nb.y;
+          }
+          float la = __shfl_up(na.y, 1, 64), lb = __shfl_up(nb.y, 1, 64);
+          if (lane == 0) {
+            la = carry_a;
+            lb = carry_b;
+          }
+          carry_a = __shfl(na.y, 63, 64);
+          carry_b = __shfl(nb.y, 63, 64);
           // grad^T p' in the order of the adjoint's terms: +p1(i-1), -p1(i),
           // +p2(j-1), -p2(j)
           float aa = 0.0f, ab = 0.0f;
-          if (ia > 0) aa += tvw_pnew(xbar, p1, p2, ia - 1, t, I, sl).x;
+          if (ia > 0) aa += nu.x;
           aa -= na.x;  // ia < I - 1 always (ib = ia + 1 exists)
-          if (t > 0) aa += tvw_pnew(xbar, p1, p2, ia, t - 1, I, sl).y;
+          if (t > 0) aa += la;
           if (t < I - 1) aa -= na.y;
           ab += na.x;  // ib > 0
           if (ib < I - 1) ab -= nb.x;
-          if (t > 0) ab += tvw_pnew(xbar, p1, p2, ib, t - 1, I, sl).y;
+          if (t > 0) ab += lb;
           if (t < I - 1) ab -= nb.y;
           va = __fmaf_rn(-sl, aa, va);
           vb = __fmaf_rn(-sl, ab, vb);
