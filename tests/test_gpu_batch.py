@@ -171,13 +171,18 @@ def test_batch_cnn_equals_single_slices(gpu_lib):
     check_slices_equal(api, B, data, mu_out, singles)
 
 
-def test_batch_rejects_haar_and_mixed_cnn(gpu_lib, data):
+def test_batch_rejects_haar_tv_and_mixed_cnn(gpu_lib, data):
     api = gpu_lib
     B, y = make_batch(api, data)
     i0 = [d["i0"] for d in data]
     fro2 = [d["fro2"] for d in data]
     with pytest.raises(api.DgError, match="status -4"):
         B.bind(y, i0, fro2, api.DEN_HAAR, api.make_params(api.DEN_HAAR))
+    # the proximal-TV plug-ins run per slice only (their state is per image)
+    with pytest.raises(api.DgError, match="status -4"):
+        B.bind(y, i0, fro2, api.DEN_TV, api.make_params(api.DEN_TV, n_pixels=128 * 128))
+    with pytest.raises(api.DgError, match="status -4"):
+        B.bind(y, i0, fro2, api.DEN_TVW, api.make_params(api.DEN_TVW, side=128))
     net = api.CnnNet(seed=1)
     with pytest.raises(api.DgError, match="status -4"):
         B.bind(y, i0, fro2, api.DEN_CNN, api.make_params(api.DEN_CNN, net=net, n_pixels=B.totN))

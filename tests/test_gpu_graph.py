@@ -10,7 +10,19 @@ from paper_1609_04661_amd import synth
 pytestmark = pytest.mark.gpu
 
 
-@pytest.mark.parametrize("kind", ["haar", "nlm"])
+def den_params(gpu_lib, kind):
+    """Denoiser kind and parameters at the 64 x 64 C1 side."""
+    if kind == "haar":
+        return gpu_lib.DEN_HAAR, gpu_lib.make_params(gpu_lib.DEN_HAAR)
+    if kind == "nlm":
+        return gpu_lib.DEN_NLM, gpu_lib.make_params(gpu_lib.DEN_NLM)
+    if kind == "tv":
+        return gpu_lib.DEN_TV, gpu_lib.make_params(gpu_lib.DEN_TV, n_pixels=64 * 64)
+    return gpu_lib.DEN_TVW, gpu_lib.make_params(gpu_lib.DEN_TVW, side=64, alpha=1.0, iters=20,
+                                                metric=1)
+
+
+@pytest.mark.parametrize("kind", ["haar", "nlm", "tv", "tvw"])
 def test_graph_replay_equals_eager(gpu_lib, kind):
     g = synth.c1_geometry()
     R = radon.Radon(g)
@@ -18,8 +30,7 @@ def test_graph_replay_equals_eager(gpu_lib, kind):
     y = torch.as_tensor(synth.poisson_counts(R.project(mu), 1e4, 1001), dtype=torch.float32).cuda()
     fro2 = ogamp.fro2_hutchinson(R, 8, 5)
     plan = gpu_lib.Plan(g)
-    den = gpu_lib.DEN_HAAR if kind == "haar" else gpu_lib.DEN_NLM
-    params = gpu_lib.make_params(den)
+    den, params = den_params(gpu_lib, kind)
     T = 6
     # eager reference
     st = gpu_lib.DgampState(plan, 1.0)
@@ -43,7 +54,7 @@ def test_graph_replay_equals_eager(gpu_lib, kind):
         del junk
 
 
-@pytest.mark.parametrize("kind", ["nlm", "tv"])
+@pytest.mark.parametrize("kind", ["nlm", "tv", "tvw"])
 def test_split_calls_equal_one_call(gpu_lib, kind):
     """T iterations in one dgamp_iterate call against T calls of one iteration
     (with and without mu_out): with NLM the divergence step's scalar finish
@@ -55,8 +66,7 @@ def test_split_calls_equal_one_call(gpu_lib, kind):
     y = torch.as_tensor(synth.poisson_counts(R.project(mu), 1e4, 1001), dtype=torch.float32).cuda()
     fro2 = ogamp.fro2_hutchinson(R, 8, 5)
     plan = gpu_lib.Plan(g)
-    den = gpu_lib.DEN_NLM if kind == "nlm" else gpu_lib.DEN_TV
-    params = gpu_lib.make_params(den) if kind == "nlm" else gpu_lib.make_params(den, n_pixels=64 * 64)
+    den, params = den_params(gpu_lib, kind)
     T = 5
     kw = dict(probe_seed=3, eta_x=0.5, eta_s=0.5)
     st1 = gpu_lib.DgampState(plan, 1.0)
