@@ -51,8 +51,11 @@ __device__ __forceinline__ int reflect_idx(int k, int I) {
 
 // Non-local means, register-blocked.  A workgroup owns a 32 x 32 output
 // tile and stages the tile plus its search and patch halos in LDS.  Its
-// kNlmWaves wavefronts split the rows oi of the search window (more, shorter
-// wavefronts hide LDS and exp latency better than few long ones); each thread
+// kNlmWaves wavefronts split the offsets of the search window evenly, taken in
+// row-major order (a wavefront's share may start and end inside a row: the
+// 441 offsets of S = 10 give 55 or 56 per wavefront, where whole rows
+// gave 3 rows = 63 to each of 7 wavefronts and left an eighth of the wave
+// slots idle); each thread
 // owns a 2-wide, 8-tall block of outputs and keeps the (8 + 2P) x (2 + 2P)
 // input pixels its patches cover in registers (own).  Along a row of the
 // search window (oj = -S .. S) the shifted region slides right by one
@@ -66,7 +69,7 @@ __device__ __forceinline__ int reflect_idx(int k, int I) {
 // sums are added in a fixed order at the end.
 static constexpr int kNlmBX = 2, kNlmBY = 8;
 static_assert(kNlmBX == 2, "the row sums below are written for two outputs per row");
-static constexpr int kNlmWaves = 7;  // 21 search rows (S = 10): 3 per wavefront
+static constexpr int kNlmWaves = 8;  // the (2S+1)^2 offsets split evenly, row-major
 static constexpr int kNlmThreads = 64 * kNlmWaves;
 // The search loop and the per-output normalisation of nlm_body.
 template <int P, class Emit>
@@ -95,21 +98,32 @@ __device__ __forceinline__ void nlm_search(const NlmArgs& Ar, const float* R,
   for (int a = 0; a < BY; ++a)
 #pragma unroll
     for (int c = 0; c < BX; ++c) wsum[a][c] = acc[a][c] = 0.0f;
-  const int nside = 2 * S + 1;
-  for (int oi = g - S; oi <= S; oi += kNlmWaves) {
+  const int nside = 2 * S + 1, n2 = nside * nside;
+  // this wavefront's offsets e = (oi + S) nside + (oj + S), e0 <= e < e1
+  const int e0 = g * n2 / kNlmWaves, e1 = (g + 1) * n2 / kNlmWaves;
+  for (int row = e0 / nside; row * nside < e1; ++row) {
+    const int oi = row - S;
+    const int ja = max(e0 - row * nside, 0), jb = min(e1 - row * nside, nside) - 1;
+    if (ja > jb) continue;  // wavefront-uniform
     // shifted region of step t = oj + S: column c of it is LDS column
-    // ox0 + t + c of row S + oy0 + a + oi, held in ring slot (t + c) % WX
+    // ox0 + t + c of row S + oy0 + a + oi, held in ring slot (t + c) % WX;
+    // before step ja the slots hold columns ja .. ja + WX - 2
     const float* rowbase = R + (S + oy0 + oi) * kNlmPitch + ox0;
     float win[WY][WX];
+    const int jr = ja % WX;
 #pragma unroll
-    for (int a = 0; a < WY; ++a)
+    for (int sl = 0; sl < WX; ++sl) {
+      const int pc = ja + (sl - jr + WX) % WX;  // the column of ring slot sl
+      if (pc < ja + WX - 1) {
 #pragma unroll
-      for (int c = 0; c < WX - 1; ++c) win[a][c] = rowbase[a * kNlmPitch + c];
-    for (int t0 = 0; t0 < nside; t0 += WX) {
+        for (int a = 0; a < WY; ++a) win[a][sl] = rowbase[a * kNlmPitch + pc];
+      }
+    }
+    for (int t0 = ja - jr; t0 <= jb; t0 += WX) {
 #pragma unroll
       for (int tau = 0; tau < WX; ++tau) {
         const int t = t0 + tau;
-        if (t < nside) {  // wavefront-uniform
+        if (t >= ja && t <= jb) {  // wavefront-uniform
 #pragma unroll
           for (int a = 0; a < WY; ++a)
             win[a][(tau + WX - 1) % WX] = rowbase[a * kNlmPitch + t + WX - 1];
