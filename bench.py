@@ -56,7 +56,7 @@ CFG = dict(i0=1e5, seed=1002, probe_seed=7, eta=0.15, tau_x0=1.0, fro2_probes=16
 # counter passes (FETCH_SIZE, WRITE_SIZE) scaled by a 256 MiB copy kernel
 # (profiles/dgamp_c2_512x512_64views_hbm_traffic.md).  Set to None whenever
 # that kernel changes until the counters are taken again.
-NLM_TRAFFIC_BYTES = 7.215e6
+NLM_TRAFFIC_BYTES = 7.250e6
 # dampings tried per denoiser for the time-to-equal-PSNR comparison (above
 # 0.35 both recursions diverge on these inputs)
 DAMPING_SWEEP = (0.15, 0.25, 0.35)
