@@ -51,7 +51,8 @@ WEIGHTS = os.path.join(ROOT, "paper_1609_04661_amd", "weights", "cnn_c2_x_space.
 # configured recursion for these workloads (damping of means and variances)
 CFG = dict(i0=1e5, seed=1002, probe_seed=7, eta=0.15, tau_x0=1.0, fro2_probes=16,
            nlm=dict(pr=2, sr=10, hfac=0.4), tv=dict(alpha=1.0, iters=50),
-           tvw=dict(iters=50, alphas={0: [0.02, 0.05, 0.1, 0.2], 1: [64.0, 256.0, 1024.0, 4096.0]}))
+           tvw=dict(iters=50, alphas={0: [0.02, 0.05, 0.1, 0.2], 1: [64.0, 256.0, 1024.0, 4096.0]},
+                    fewer_steps=[10, 20]))
 # HBM bytes per launch of nlm_kernel<2> at this workload, from two rocprofv3
 # counter passes (FETCH_SIZE, WRITE_SIZE) scaled by a 256 MiB copy kernel
 # (profiles/dgamp_c2_512x512_64views_hbm_traffic.md).  Set to None whenever
@@ -434,10 +435,19 @@ def proxtv(api, args, h, T=50):
             r["alpha"] = a
             runs.append(r)
         best = max(runs, key=lambda r: r["psnr_final"] if r["psnr_final"] == r["psnr_final"] else -1e9)
+        # fewer primal-dual steps per call at the best alpha (K is not given either)
+        steps = []
+        for K in CFG["tvw"]["fewer_steps"]:
+            prm = api.make_params(api.DEN_TVW, side=plan.I, alpha=best["alpha"], iters=K, metric=metric)
+            r = prox_run(api, args, h, api.DEN_TVW, prm, T)
+            steps.append(dict(primal_dual_steps=K, psnr_final=r["psnr_final"], ms_per_iter=r["ms_per_iter"],
+                              iters_to_plain_psnr=r.get("iters_to_plain_psnr"),
+                              ms_to_plain_psnr=r.get("ms_to_plain_psnr"), status=r["status"]))
         variants[name] = dict(metric=metric, primal_dual_steps=CFG["tvw"]["iters"], best=best,
                               sweep=[dict(alpha=r["alpha"], psnr_final=r["psnr_final"],
                                           psnr_every_5=r["psnr_every_5"], ms_per_iter=r["ms_per_iter"],
-                                          status=r["status"]) for r in runs])
+                                          status=r["status"]) for r in runs],
+                              fewer_steps_at_best_alpha=steps)
     out["metric_variants"] = variants
     return out
 
