@@ -27,8 +27,10 @@ namespace dg {
 // row.  The two real spectra are separated by conjugate symmetry and stored
 // column-major as spec[k][row], k = 0..I/2; the workgroup writes its rows of
 // every k as one contiguous run.
+// fin_blk: the workgroup that runs the scalar finish; a workgroup past the
+// row blocks (blk >= prec_row_blocks(I)) runs only that.
 __device__ void rows_fwd_body(const RowsFwdArgs& A, int blk, FftShared& S, int fin_t,
-                              double fin_eta) {
+                              double fin_eta, int fin_blk) {
   const int I = A.I, lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int half = I / 2 + 1;
   const int m = blk * kFftWaves + w;
@@ -50,12 +52,13 @@ __device__ void rows_fwd_body(const RowsFwdArgs& A, int blk, FftShared& S, int f
   }
   // the output channel's finish (tau_s, tau_r), or a pending divergence
   // step's, saving it a launch of its own
-  if (blk == 0) {
+  if (blk == fin_blk) {
     if (A.fin)
       channel_finish_body<true>(A.chan, fin_eta, fin_t, S.dred);
     else if (A.dv.part && fin_t >= 0)
       div_finish_pending(A.dv, fin_eta, fin_t, S.dred);
   }
+  if (2 * blk * kFftWaves >= I) return;  // the finish-only workgroup
   float2* a = S.buf[w][0];
   float2* b = S.buf[w][1];
   if (I == 512 || I == 256) {
@@ -284,14 +287,14 @@ __device__ void eps_body(const EpsArgs& A, float* red) {
 __global__ void __launch_bounds__(kFftThreads)
 prec_rows_fwd(RowsFwdArgs A, int fin_t, double fin_eta) {
   __shared__ FftShared S;
-  rows_fwd_body(A, blockIdx.x, S, fin_t, fin_eta);
+  rows_fwd_body(A, blockIdx.x, S, fin_t, fin_eta, (int)gridDim.x - 1);
 }
 __global__ void __launch_bounds__(kFftThreads)
 prec_rows_fwd_batch(const RowsFwdArgs* __restrict__ T, const int* __restrict__ prefix, int n,
                     int fin_t, double fin_eta) {
   __shared__ FftShared S;
   const int s = slice_of(prefix, n, blockIdx.x);
-  rows_fwd_body(T[s], blockIdx.x - prefix[s], S, fin_t, fin_eta);
+  rows_fwd_body(T[s], blockIdx.x - prefix[s], S, fin_t, fin_eta, 0);
 }
 __global__ void __launch_bounds__(kFftThreads) prec_cols(ColsArgs A) {
   __shared__ FftShared S;
@@ -364,8 +367,10 @@ dg_status launch_precondition(const dg_plan* p, const PrecArgs& a, hipStream_t s
   }
   const int I = p->I;
   RowsFwdArgs f{a.in, a.spec, p->twiddle, I, a.fin, a.chan, a.dv};
-  hipLaunchKernelGGL(prec_rows_fwd, dim3(prec_row_blocks(I)), dim3(kFftThreads), 0, s, f, a.fin_t,
-                     a.fin_eta);
+  // one workgroup more than the rows need, for the scalar finish, so that it
+  // runs beside the transforms instead of in front of one of them
+  hipLaunchKernelGGL(prec_rows_fwd, dim3(prec_row_blocks(I) + 1), dim3(kFftThreads), 0, s, f,
+                     a.fin_t, a.fin_eta);
   DG_LAUNCH_CHECK("prec_rows_fwd");
   ColsArgs c{a.spec, p->twiddle, I, a.dir};
   hipLaunchKernelGGL(prec_cols, dim3(prec_col_blocks(I)), dim3(kFftThreads), 0, s, c);
