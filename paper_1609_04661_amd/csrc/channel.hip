@@ -28,8 +28,9 @@ static constexpr int kChanMaxBlocks = 1024;
 // tau_s by channel_finish.  Inside the iteration the same per-ray math runs
 // in the projector's epilogue (fused form: tau_p = fro2 tau_x / M,
 // p = z - tau_p s_prev, s damped towards s_prev), and the finish (tau_s
-// damped likewise, tau_r = N / (fro2 tau_s)) in the first row workgroup of
-// the next preconditioner application.
+// damped likewise, tau_r = N / (fro2 tau_s)) in the row pass of the next
+// preconditioner application (a workgroup of its own beside the transforms;
+// a slice's first row workgroup in batches).
 __device__ void channel_body(const ChanArgs& A, int blk, int mode, double* red) {
   const float tau_p = (float)(*A.tau_p_ptr);
   const float ln_i0 = (float)log(A.i0);

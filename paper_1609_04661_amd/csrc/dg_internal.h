@@ -442,7 +442,7 @@ struct RowsFwdArgs {
   float2* spec;
   const float2* tw;
   int I;
-  int fin;        // 1: the first workgroup also finishes the output channel
+  int fin;        // 1: the row pass also finishes the output channel
   ChanArgs chan;  // (tau_s, tau_r from the channel's partial sums)
   DivFinish dv;   // else, with fin_t >= 0: it finishes a pending divergence step
 };
@@ -482,7 +482,7 @@ struct PrecArgs {
   double* scal_out;      // PREC_UPDATE_R: eps written to scal_out[DG_S_EPS]
   double eps_rel;
   int eps_elsewhere;     // PREC_UPDATE_R: leave the eps finish to the denoiser
-  int fin;               // 1: finish the output channel in the first row workgroup
+  int fin;               // 1: finish the output channel in the row pass
   ChanArgs chan;
   DivFinish dv;          // fin == 0, fin_t >= 0: finish a pending divergence step there
   double fin_eta;        // eta_s (channel) or eta_x (divergence)

@@ -196,8 +196,8 @@ extern "C" dg_status dgamp_iterate(const dg_plan* p, const float* y, const dgamp
   };
   const bool nlm = o->den_kind == DG_DEN_NLM;
   // with NLM the divergence step's scalar finish of iteration t runs in the
-  // first row workgroup of the next V^-1 x (or of the final V^-1 x for
-  // mu_out, or in a finish launch of its own after the last iteration)
+  // finish workgroup of the next V^-1 x's row pass (or of the final V^-1 x
+  // for mu_out, or in a finish launch of its own after the last iteration)
   const DivFinish pending{w.npart, (int)nlm_blocks(p->I), N, st->scal + DG_S_EPS, st->scal};
   auto log_it = [&](int it) -> dg_status {
     if (log) {
@@ -227,8 +227,8 @@ extern "C" dg_status dgamp_iterate(const dg_plan* p, const float* y, const dgamp
     if (nlm && it > 0 && (rc = log_it(it - 1)) != DG_OK) return rc;
     if ((rc = mark(it, 1)) != DG_OK) return rc;
     // A with the output channel applied to every ray in the same launch; the
-    // channel's finish (tau_s, tau_r) runs in the first row workgroup of the
-    // next preconditioner application, and NLM finishes the MC step
+    // channel's finish (tau_s, tau_r) runs in the finish workgroup of the
+    // next preconditioner application's row pass, and NLM finishes the MC step
     const ChanArgs chan{p->M, nullptr, y,      st->s,   nullptr, nullptr, st->scal,
                         nullptr, o->i0, o->fro2, N, w.dpart, (int)project_blocks(p->M)};
     const ProjArgs pa{p->rays, w.mu, w.mu_t, w.z, p->I, p->M, 1, chan};
