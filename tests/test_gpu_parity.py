@@ -340,12 +340,12 @@ def test_prox_tv_identity_at_zero_variance(gpu_lib, plans):
 @pytest.mark.parametrize("I,noise,tau,iters,metric", [(64, 0.05, 2.5e-3, 50, 0), (96, 0.05, 2.5e-3, 20, 0),
                                                       (256, 0.05, 2.5e-3, 30, 0), (512, 0.05, 2.5e-3, 50, 0),
                                                       (48, 0.004, 1.6e-5, 1, 0), (64, 0.05, 2.5e-3, 50, 1),
-                                                      (512, 0.05, 2.5e-3, 50, 1)])
+                                                      (512, 0.05, 2.5e-3, 50, 1), (1024, 0.05, 2.5e-3, 5, 1)])
 def test_prox_tv_w_matches_oracle(gpu_lib, I, noise, tau, iters, metric):
     """The metric proximal TV ((V^T V)^-1, and V^T V with metric 1) and its MC
     divergence against the oracle's same Chambolle-Pock steps in FP64:
-    register-resident transforms (256, 512), LDS-staged ones (64, 48) and a
-    radix-3 side (96)."""
+    register-resident transforms (256, 512), LDS-staged ones (64, 48, 1024)
+    and a radix-3 side (96)."""
     g = synth.geometry(synth.PARALLEL, I, 1.0, 4, I + 1, math.pi)
     P = gpu_lib.Plan(g)
     r = synth.ellipse_phantom(I, 8) + noise * np.random.default_rng(3).standard_normal((I, I))
