@@ -241,13 +241,16 @@ __device__ __forceinline__ float ray_weight(const RayLine& L, int i, int j) {
 // bx, by: block coordinates of a (kBpBlockX x kBpBlockY) pixel block.
 // Views are taken kBpViews at a time: the footprint of the pixel in every
 // view of the group is found first and the ray records and sinogram values
-// of the first kBpBins (fan) or kBpBinsPar (parallel) bins per view are
+// of the first kBpBinsFan (fan) or kBpBinsPar (parallel) bins per view are
 // requested together (clamped in-bounds index, weight 0 when the bin is
 // outside the footprint), then accumulated in the order view, bin; a longer
 // footprint finishes in a plain loop.  A parallel-beam pixel's footprint is
 // (|cos| + |sin|) pixel widths long, so two bins cover it whenever a bin is
-// wider than 1/sqrt(2) pixel; the fan beam magnifies it, hence three.
-static constexpr int kBpViewsPar = 2, kBpViewsFan = 4, kBpBins = 3, kBpBinsPar = 2, kBpSplit = 4;
+// wider than 1/sqrt(2) pixel.  The fan kernel is bound by its address unit
+// (one 32-byte ray record per bin), so a requested bin that falls outside a
+// short footprint is pure cost: it requests one bin per view and loops over
+// the rest.
+static constexpr int kBpViewsPar = 2, kBpViewsFan = 4, kBpBinsFan = 1, kBpBinsPar = 2, kBpSplit = 4;
 
 // MODE 0: parallel beam, 1: fan beam, 2: either (decided per slice).
 template <int MODE>
@@ -364,8 +367,8 @@ __device__ void backproject_body(const BpArgs& A, int bx, int by, float (*red)[k
   constexpr int kBpViews = kBpViewsFan;
   for (int k0 = 0; k0 < A.nv; k0 += kBpViews) {
     int bb[kBpViews], be[kBpViews];
-    RayLine L[kBpViews][kBpBins];
-    float sv[kBpViews][kBpBins];
+    RayLine L[kBpViews][kBpBinsFan];
+    float sv[kBpViews][kBpBinsFan];
 #pragma unroll
     for (int g = 0; g < kBpViews; ++g) {
       const int k = k0 + g;
@@ -386,7 +389,7 @@ __device__ void backproject_body(const BpArgs& A, int bx, int by, float (*red)[k
       const int kc = min(k, A.nv - 1);
       const int64_t row = (int64_t)kc * A.nb;
 #pragma unroll
-      for (int c = 0; c < kBpBins; ++c) {
+      for (int c = 0; c < kBpBinsFan; ++c) {
         const int b = min(max(bb[g] + c, 0), A.nb - 1);
         L[g][c] = A.rays[row + b];
         sv[g][c] = A.sino[row + b];
@@ -395,13 +398,13 @@ __device__ void backproject_body(const BpArgs& A, int bx, int by, float (*red)[k
 #pragma unroll
     for (int g = 0; g < kBpViews; ++g) {
 #pragma unroll
-      for (int c = 0; c < kBpBins; ++c) {
+      for (int c = 0; c < kBpBinsFan; ++c) {
         const float wgt = (bb[g] + c <= be[g]) ? ray_weight(L[g][c], i, j) : 0.0f;
         acc = __fmaf_rn(wgt, sv[g][c], acc);
       }
-      if (be[g] - bb[g] + 1 > kBpBins) {
+      if (be[g] - bb[g] + 1 > kBpBinsFan) {
         const int64_t row = (int64_t)(k0 + g) * A.nb;
-        for (int b = bb[g] + kBpBins; b <= be[g]; ++b)
+        for (int b = bb[g] + kBpBinsFan; b <= be[g]; ++b)
           acc = __fmaf_rn(ray_weight(A.rays[row + b], i, j), A.sino[row + b], acc);
       }
     }
