@@ -8,10 +8,12 @@
 // consecutive columns of one image row.  Flat rays read the transposed copy
 // of the image when one is supplied, which makes their reads consecutive too.
 //
-// Back-projector: one thread per pixel.  For every view it finds the (one to
-// three) bins whose footprint covers the pixel and adds weight * s for each,
-// recomputing the weight with the very same formula and operands as the
-// projector; no atomics, so the result is deterministic.
+// Back-projector: pixel-driven (fan beam: one thread per pixel; parallel
+// beam: four, each over a quarter of the views, their sums added in a fixed
+// order).  For every view it finds the few bins whose footprint covers the
+// pixel and adds weight * s for each, recomputing the weight with the very
+// same formula and operands as the projector; no atomics, so the result is
+// deterministic.
 #include "dg_internal.h"
 
 namespace dg {
