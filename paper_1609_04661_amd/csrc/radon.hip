@@ -32,8 +32,11 @@ static constexpr int kBpBlockX = 64, kBpBlockY = 4;
 // before the first multiply-add.  Out-of-range candidates get an offset past
 // the end of the buffer, which a raw buffer load returns as 0.  The accumulation order (k ascending,
 // candidate p0 before p0 + 1) and every weight are those of ray_weight, so
-// A and A^T stay exact transposes of one another.
-static constexpr int kMarch = 16;
+// A and A^T stay exact transposes of one another.  Each segment's last
+// group of kMarch steps runs whole, with dead loads past its end; 8 steps
+// keep enough loads in flight while wasting less there than 16 when a
+// variant splits the march into many short segments.
+static constexpr int kMarch = 8;
 
 template <int SEGS>
 __device__ void project_body(const ProjArgs& A, int blk, float (*part)[kRaysPerBlock],
