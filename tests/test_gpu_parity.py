@@ -50,6 +50,11 @@ GEOMS = {
                                       bin_mm=1.1),
     "fan_small": synth.geometry(synth.FAN, 128, 0.5, 64, 200, 2 * math.pi, dso_mm=120.0,
                                 ddo_mm=100.0),
+    # ragged fan: odd side, a view count that is no multiple of the
+    # back-projector's view group, and bins narrow enough that most
+    # footprints span several of them
+    "ragged_fan": synth.geometry(synth.FAN, 77, 0.9, 29, 311, 1.3 * math.pi, angle0_rad=0.7,
+                                 dso_mm=90.0, ddo_mm=80.0),
     "c5": synth.c5_geometry(),
 }
 
@@ -92,7 +97,7 @@ def test_backproject_matches_oracle(gpu_lib, plans, name):
     assert np.max(np.abs(out - ref)) <= 1e-4 * np.max(np.abs(ref))
 
 
-@pytest.mark.parametrize("name", ["c1", "c2", "fan_small"])
+@pytest.mark.parametrize("name", ["c1", "c2", "fan_small", "ragged_fan"])
 def test_gpu_adjoint_identity(gpu_lib, plans, name):
     g = GEOMS[name]
     rng = np.random.default_rng(9)
