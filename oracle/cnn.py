@@ -11,8 +11,21 @@ Parameters are a list of (w, b) per layer with w of shape (co, ci, 3, 3).
 The divergence follows eq. MC_SURE with the finite difference
 b^T (D(r + eps b) - D(r)) / (N eps).
 
+BF16 storage (``bf16=True``): the learned denoiser keeps its activations in
+BF16 (the configured network: BF16 weights and activations, FP32
+accumulation).  With ``bf16=True`` the oracle rounds, in FP64 otherwise,
+at exactly the points where such a network stores BF16 values: every hidden
+layer's post-ReLU activation (and its tangent) in the forward pass, and the
+back-propagated gradient after each ReLU mask in the backward pass.  The
+rounding is IEEE round-to-nearest-even to 8 significant bits of the FP32
+value.  This separates the error BF16 storage itself causes (amplified
+through cancelling sums over pixels in the weight gradients) from any
+error of an implementation that stores BF16 at those points.
+
 Parity: forward/backward pinned by central finite differences of the loss
-and by linearity checks; against the paper unpinned (the paper has no CNN).
+and by linearity checks; bf16 rounding pinned by exact binary cases and by
+the bf16 mode equalling the FP64 mode where every stored value is exactly
+representable; against the paper unpinned (the paper has no CNN).
 """
 import numpy as np
 
@@ -81,13 +94,29 @@ def conv3x3_weight_grad(g, x):
     return dw, g2.sum(axis=1)
 
 
-def forward(r, params):
-    """f(r) and the post-ReLU activations of every hidden layer."""
+def bf16_round(a):
+    """Round to the nearest BF16 value (ties to even) of the FP32 value of a;
+    returned as float64."""
+    a32 = np.asarray(a, dtype=np.float64).astype(np.float32)
+    u = a32.view(np.uint32).astype(np.uint64)
+    lsb = (u >> 16) & 1
+    u = ((u + 0x7FFF + lsb) >> 16) << 16
+    return u.astype(np.uint32).view(np.float32).astype(np.float64)
+
+
+def forward(r, params, bf16=False):
+    """f(r) and the post-ReLU activations of every hidden layer (BF16-rounded
+    when bf16)."""
     a = np.asarray(r, dtype=np.float64)[None]
     acts = [a]
     for l, (w, b) in enumerate(params):
         z = conv3x3(a, w, b)
-        a = np.maximum(z, 0.0) if l < len(params) - 1 else z
+        if l < len(params) - 1:
+            a = np.maximum(z, 0.0)
+            if bf16:
+                a = bf16_round(a)
+        else:
+            a = z
         acts.append(a)
     return a[0], acts
 
@@ -97,27 +126,30 @@ def denoise(r, params):
     return np.asarray(r, dtype=np.float64) - f
 
 
-def backward(acts, params, g_f):
-    """Gradients of sum(g_f * f) w.r.t. every (w, b) and w.r.t. the input r."""
+def backward(acts, params, g_f, bf16=False):
+    """Gradients of sum(g_f * f) w.r.t. every (w, b) and w.r.t. the input r
+    (the masked gradient BF16-rounded at every hidden layer when bf16)."""
     g = np.asarray(g_f, dtype=np.float64)[None]
     grads = [None] * len(params)
     for l in range(len(params) - 1, -1, -1):
         w, b = params[l]
         if l < len(params) - 1:
             g = g * (acts[l + 1] > 0)
+            if bf16:
+                g = bf16_round(g)
         grads[l] = conv3x3_weight_grad(g, acts[l])
         g = conv3x3_input_grad(g, w)
     return grads, g[0]
 
 
-def mse_loss_and_grads(noisy, clean, params):
+def mse_loss_and_grads(noisy, clean, params, bf16=False):
     """L = mean((D(noisy) - clean)^2) for one image; gradients w.r.t. params."""
-    f, acts = forward(noisy, params)
+    f, acts = forward(noisy, params, bf16)
     res = noisy - f - clean
     n = res.size
     loss = float(np.sum(res * res) / n)
     g_f = -2.0 * res / n
-    grads, _ = backward(acts, params, g_f)
+    grads, _ = backward(acts, params, g_f, bf16)
     return loss, grads
 
 
@@ -128,12 +160,15 @@ def fd_divergence(r, params, b, eps):
     return float(np.sum(b * (d1 - d0)) / (r.size * eps))
 
 
-def tangent_divergence(r, params, b):
-    """b^T J_D(r) b / N with the ReLU pattern of r (the eps -> 0 limit)."""
-    _, acts = forward(r, params)
+def tangent_divergence(r, params, b, bf16=False):
+    """b^T J_D(r) b / N with the ReLU pattern of r (the eps -> 0 limit); with
+    bf16 the activations and the tangent are BF16-rounded per hidden layer."""
+    _, acts = forward(r, params, bf16)
     t = np.asarray(b, dtype=np.float64)[None]
     for l, (w, _) in enumerate(params):
         t = conv3x3(t, w)
         if l < len(params) - 1:
             t = t * (acts[l + 1] > 0)
+            if bf16:
+                t = bf16_round(t)
     return float(np.sum(b * (b - t[0])) / r.size)

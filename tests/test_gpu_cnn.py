@@ -1,11 +1,19 @@
 """Residual CNN denoiser on MFMA against the FP64 oracle (same BF16-rounded weights).
 
-Tolerances (BF16 activations between layers, FP32 accumulation): the network
-output f has relative L2 error <= 2e-2 and cosine >= 0.999 against FP64;
-a layer's weight gradient, d layers from the output, relative L2 error
-<= 1.5e-2 d + 5e-3 and cosine >= 0.99 (BF16 gradients lose ~1% per layer
-they travel back through); the tangent divergence b^T J_D b / N within 0.02
-of the oracle's tangent divergence for the same probe.
+Two oracle references:
+  * the oracle in BF16-storage mode, which rounds to BF16 exactly where the
+    kernels store BF16 (hidden activations, their tangents, the masked
+    back-propagated gradients) and computes in FP64 otherwise.  What is left
+    between it and the GPU is FP32 accumulation order, which moves a stored
+    value across a BF16 rounding boundary only rarely (a relative FP32 error
+    of ~1e-6 against BF16's 2^-9 spacing); the bounds are cosine >= 0.9999
+    and relative L2 <= 5e-3 for f, the tangent divergence and every weight
+    gradient (the gradient of the first layer is a sum over pixels that
+    cancels to ~1/50 of its terms, so the same per-element disagreement
+    weighs ~50x more there);
+  * the plain FP64 oracle, which shows what BF16 storage itself costs: the
+    GPU may differ from it by no more than 1.5x the distance of the BF16-mode
+    oracle from it (plus 1e-3 relative), layer by layer.
 """
 import math
 
@@ -36,6 +44,17 @@ def cos(a, b):
     return float(a @ b / (np.linalg.norm(a) * np.linalg.norm(b)))
 
 
+def rel(a, b):
+    return float(np.linalg.norm(np.ravel(a) - np.ravel(b)) / np.linalg.norm(np.ravel(b)))
+
+
+def check_vs_oracles(got, ref16, ref64, what, tol=5e-3):
+    """got against the BF16-storage oracle (tight), and no further from the FP64
+    oracle than BF16 storage itself moves it."""
+    assert cos(got, ref16) >= 0.9999 and rel(got, ref16) <= tol, (what, cos(got, ref16), rel(got, ref16))
+    assert rel(got, ref64) <= 1.5 * rel(ref16, ref64) + 1e-3, (what, rel(got, ref64), rel(ref16, ref64))
+
+
 def test_cnn_forward_matches_oracle(gpu_lib):
     net = gpu_lib.CnnNet(seed=3)
     params = oracle_params(net)
@@ -45,10 +64,11 @@ def test_cnn_forward_matches_oracle(gpu_lib):
     torch.cuda.synchronize()
     out = out.cpu().double().numpy()
     for k in range(2):
-        f_ref, _ = ocnn.forward(imgs[k].astype(np.float32).astype(np.float64), params)
-        f_gpu = imgs[k].astype(np.float32) - out[k]
-        assert cos(f_gpu, f_ref) >= 0.999
-        assert np.linalg.norm(f_gpu - f_ref) <= 2e-2 * np.linalg.norm(f_ref)
+        r = imgs[k].astype(np.float32).astype(np.float64)
+        f64, _ = ocnn.forward(r, params)
+        f16, _ = ocnn.forward(r, params, bf16=True)
+        f_gpu = r - out[k]
+        check_vs_oracles(f_gpu, f16, f64, "f")
 
 
 def test_cnn_gradients_match_oracle(gpu_lib):
@@ -61,34 +81,36 @@ def test_cnn_gradients_match_oracle(gpu_lib):
                           torch.as_tensor(clean, dtype=torch.float32).cuda(), lr=1e-30)
     torch.cuda.synchronize()
     g_gpu = net.grad.cpu().double().numpy()
-    ref_loss, ref_grads = 0.0, None
-    for k in range(2):
-        l, g = ocnn.mse_loss_and_grads(noisy[k], clean[k], params)
-        ref_loss += 0.5 * l
-        g = [(0.5 * dw, 0.5 * db) for dw, db in g]
-        ref_grads = g if ref_grads is None else [(a + c, b + d) for (a, b), (c, d) in zip(ref_grads, g)]
-    assert abs(float(loss.item()) - ref_loss) <= 2e-2 * ref_loss
+    refs = {}
+    for bf in (False, True):
+        ref_loss, ref_grads = 0.0, None
+        for k in range(2):
+            l, g = ocnn.mse_loss_and_grads(noisy[k], clean[k], params, bf16=bf)
+            ref_loss += 0.5 * l
+            g = [(0.5 * dw, 0.5 * db) for dw, db in g]
+            ref_grads = g if ref_grads is None else [(a + c, b + d) for (a, b), (c, d) in zip(ref_grads, g)]
+        refs[bf] = (ref_loss, ref_grads)
+    assert abs(float(loss.item()) - refs[True][0]) <= 1e-4 * refs[True][0]
     off = 0
     stats = []
-    for l, (dw, db) in enumerate(ref_grads):
-        gw = g_gpu[off:off + dw.size].reshape(dw.shape)
-        gb = g_gpu[off + dw.size:off + dw.size + db.size]
-        off += dw.size + db.size
-        stats.append((l, round(cos(gw, dw), 5), round(float(np.linalg.norm(gw - dw) / np.linalg.norm(dw)), 4),
-                      round(cos(gb, db), 5)))
+    for l, ((dw64, db64), (dw16, db16)) in enumerate(zip(refs[False][1], refs[True][1])):
+        gw = g_gpu[off:off + dw64.size].reshape(dw64.shape)
+        gb = g_gpu[off + dw64.size:off + dw64.size + db64.size]
+        off += dw64.size + db64.size
+        stats.append((l, round(cos(gw, dw16), 6), round(rel(gw, dw16), 5), round(rel(gw, dw64), 4),
+                      round(rel(dw16, dw64), 4)))
+        check_vs_oracles(gw, dw16, dw64, ("dW", l))
+        check_vs_oracles(gb, db16, db64, ("db", l))
     print(stats)
-    # BF16 rounding of activations and gradients adds ~1% relative error per layer the
-    # gradient travels back through (measured: 0.2% at the last layer, ~10% at the first)
-    for l, cw, rw, cb in stats:
-        depth = len(stats) - l
-        assert rw <= 0.015 * depth + 0.005 and cw >= 0.99 and cb >= 0.99, stats
 
 
-@pytest.mark.parametrize("I", [48, 70])
+@pytest.mark.parametrize("I", [48, 70, 288])
 def test_cnn_denoise_and_tangent_divergence(gpu_lib, I):
     """The fused forward + tangent passes of the denoiser (a ragged tile tail
-    at 70): D(r) bitwise equal to the forward-only kernels, f and the tangent
-    divergence against the oracle."""
+    at 70; at 288, 324 tiles of 16 x 16, more than the 256 workgroups a layer
+    launches, so every workgroup walks several tiles): D(r) bitwise equal to
+    the forward-only kernels, f and the tangent divergence against the
+    oracle."""
     g = synth.geometry(synth.PARALLEL, I, 1.0, 4, I + 1, math.pi)
     plan = gpu_lib.Plan(g)
     net = gpu_lib.CnnNet(seed=7)
@@ -102,13 +124,17 @@ def test_cnn_denoise_and_tangent_divergence(gpu_lib, I):
     x_fwd = net.forward(torch.as_tensor(r, dtype=torch.float32).cuda()[None])[0]
     torch.cuda.synchronize()
     assert torch.equal(x, x_fwd.reshape(x.shape))
-    x_ref = ocnn.denoise(r, params)
-    f_ref = r - x_ref
+    f64, _ = ocnn.forward(r, params)
+    f16, _ = ocnn.forward(r, params, bf16=True)
     f_gpu = r - x.cpu().double().numpy()
-    assert cos(f_gpu, f_ref) >= 0.999
+    check_vs_oracles(f_gpu, f16, f64, "f")
     b = rademacher(11, 2, I * I).reshape(I, I)
-    d_ref = ocnn.tangent_divergence(r, params, b)
-    assert abs(float(div.item()) - d_ref) <= 0.02, (float(div.item()), d_ref)
+    d16 = ocnn.tangent_divergence(r, params, b, bf16=True)
+    d64 = ocnn.tangent_divergence(r, params, b)
+    got = float(div.item())
+    # 1 - div is b^T J_f b / N, the part the network contributes
+    assert abs(got - d16) <= 5e-3 * abs(1.0 - d16) + 1e-6, (got, d16, d64)
+    assert abs(got - d64) <= 1.5 * abs(d16 - d64) + 1e-3 * abs(1.0 - d64), (got, d16, d64)
 
 
 def test_cnn_training_reduces_loss(gpu_lib):

@@ -67,3 +67,50 @@ def test_tangent_divergence_is_the_small_eps_limit():
     # a linear network (no ReLU active flips) has the exact trace; identity check:
     zero = [(np.zeros_like(w), np.zeros_like(bb)) for w, bb in params]
     assert abs(cnn.tangent_divergence(r, zero, b) - 1.0) < 1e-15
+
+
+def test_bf16_round_exact_binary_cases():
+    # BF16 keeps 7 fraction bits: near 1 the grid is 1 + k 2^-7; halfway cases go to even k
+    e = 2.0 ** -8
+    vals = np.array([1.0, 1 + e, 1 + 3 * e, 1 + e + 2.0 ** -20, -(1 + 3 * e), 3.0 * 2.0 ** -130,
+                     65535.0, 0.0])
+    ref = np.array([1.0, 1.0, 1 + 2.0 ** -6, 1 + 2.0 ** -7, -(1 + 2.0 ** -6), 3.0 * 2.0 ** -130,
+                    65536.0, 0.0])
+    assert np.array_equal(cnn.bf16_round(vals), ref)
+
+
+def _identity_net():
+    """Every stored value of this network is a small integer times a power of
+    two: BF16 storage must then change nothing."""
+    params = []
+    w = np.zeros((64, 1, 3, 3)); w[:, 0, 1, 1] = 1.0
+    params.append((w, np.zeros(64)))
+    for _ in range(8):
+        w = np.zeros((64, 64, 3, 3))
+        w[np.arange(64), np.arange(64), 1, 1] = 1.0
+        params.append((w, np.zeros(64)))
+    w = np.zeros((1, 64, 3, 3)); w[0, :, 1, 1] = 1.0 / 64
+    params.append((w, np.zeros(1)))
+    return params
+
+
+def test_bf16_mode_rounds_only_where_values_are_stored():
+    params = _identity_net()
+    rng = np.random.default_rng(8)
+    r = rng.integers(-8, 9, (8, 8)).astype(np.float64)
+    clean = rng.integers(-8, 9, (8, 8)).astype(np.float64)
+    f64, _ = cnn.forward(r, params)
+    f16, _ = cnn.forward(r, params, bf16=True)
+    assert np.array_equal(f64, np.maximum(r, 0)) and np.array_equal(f16, f64)
+    l64, g64 = cnn.mse_loss_and_grads(r, clean, params)
+    l16, g16 = cnn.mse_loss_and_grads(r, clean, params, bf16=True)
+    assert l16 == l64
+    for (a, b), (c, d) in zip(g64, g16):
+        assert np.array_equal(a, c) and np.array_equal(b, d)
+    # a generic network does differ, by about BF16's unit roundoff per layer
+    params = cnn.init_params(3)
+    r = rng.standard_normal((10, 10))
+    f64, _ = cnn.forward(r, params)
+    f16, _ = cnn.forward(r, params, bf16=True)
+    rel = np.linalg.norm(f16 - f64) / np.linalg.norm(f64)
+    assert 1e-4 < rel < 3e-2, rel
