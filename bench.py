@@ -58,21 +58,66 @@ CFG = dict(i0=1e5, seed=1002, probe_seed=7, eta=0.15, tau_x0=1.0, fro2_probes=16
 # (profiles/dgamp_c2_512x512_64views_hbm_traffic.md).  Set to None whenever
 # that kernel changes until the counters are taken again.
 NLM_TRAFFIC_BYTES = 7.250e6
+# Counters of the two operators at this workload (per launch, rocprofv3 --pmc
+# passes; profiles/radon_c2_512x512_64views_counters.md).  Set to None when
+# either kernel changes until the counters are taken again.
+A_AT_COUNTERS = None
 # dampings tried per denoiser for the time-to-equal-PSNR comparison (above
 # 0.35 both recursions diverge on these inputs)
 DAMPING_SWEEP = (0.15, 0.25, 0.35)
 C3 = dict(seed=1003, slices=64, iters=30)
+# timed runs of the headline (each K iterations from a fresh state); the
+# reported value is the median
+TIMED_RUNS = 5
 C5 = dict(seed=1005, slices=16, iters=50)
 
 
 def nlm_flops_per_pixel(pr, sr):
-    """Algorithmic FP32 operations of the non-local-means kernel per output
-    pixel: per search offset, one difference and one square per pixel of the
-    (tile + patch halo) region (amortised 2), a separable box sum of
-    2 (2 pr + 1) additions, and the weight: subtract, max, multiply, exp,
-    weight sum, weighted accumulate (6)."""
-    per_offset = 2 + 2 * (2 * pr + 1) + 6
-    return (2 * sr + 1) ** 2 * per_offset
+    """Algorithmic FP32 operations of non-local means per output pixel, as the
+    cost model of the patch-based denoiser counts them: 12 per search offset
+    (the squared difference and its separable box sum amortised over the
+    patch, the weight and the two running sums), over (2 sr + 1)^2 offsets."""
+    del pr
+    return (2 * sr + 1) ** 2 * 12
+
+
+def ray_pixel_interactions(geom):
+    """Number of (ray, pixel) pairs with a non-zero chord: for every ray, the
+    pixels a line crosses inside the I x I square, counted as its clipped
+    length times (|cos| + |sin|) / h (one pixel per grid-line crossing) plus
+    one.  Geometry only; this is the work count of one A or A^T."""
+    import numpy as np
+    I, h = geom["n"], geom["pixel_mm"]
+    half = 0.5 * I * h
+    nv, nb = geom["n_views"], geom["n_bins"]
+    b = np.arange(nb) - 0.5 * (nb - 1)
+    total = 0.0
+    for k in range(nv):
+        if geom["kind"] == 0:
+            th = geom["angle0_rad"] + k * geom["span_rad"] / nv
+            nx = np.full(nb, math.cos(th))
+            ny = np.full(nb, math.sin(th))
+            s = b * geom["bin_mm"]
+        else:
+            R = I * h / math.sqrt(2.0)
+            dg = geom["dgamma_rad"] or 2.0 * math.asin(R / geom["dso_mm"]) / nb
+            beta = geom["angle0_rad"] + k * geom["span_rad"] / nv
+            ang = beta + b * dg + 0.5 * math.pi
+            nx, ny = np.cos(ang), np.sin(ang)
+            s = -geom["dso_mm"] * np.sin(b * dg)
+        # clip the line {<u, n> = s} to the square: parametrise u = s n + t (-ny, nx)
+        px, py, dx, dy = s * nx, s * ny, -ny, nx
+        with np.errstate(divide="ignore", invalid="ignore"):
+            tx0, tx1 = (-half - px) / dx, (half - px) / dx
+            ty0, ty1 = (-half - py) / dy, (half - py) / dy
+            lo = np.maximum(np.where(dx != 0, np.minimum(tx0, tx1), -np.inf),
+                            np.where(dy != 0, np.minimum(ty0, ty1), -np.inf))
+            hi = np.minimum(np.where(dx != 0, np.maximum(tx0, tx1), np.inf),
+                            np.where(dy != 0, np.maximum(ty0, ty1), np.inf))
+        inside = (np.abs(np.where(dx == 0, px, 0)) <= half) & (np.abs(np.where(dy == 0, py, 0)) <= half)
+        ln = np.where(inside, np.maximum(hi - lo, 0.0), 0.0)
+        total += float(np.sum(np.where(ln > 0, ln * (np.abs(nx) + np.abs(ny)) / h + 1.0, 0.0)))
+    return total
 
 
 def cnn_flops_per_pixel():
@@ -117,12 +162,28 @@ def _phantom_job(a):
     return synth.ellipse_phantom(n, seed, pixel_mm=pixel_mm, inserts=inserts).astype("float32")
 
 
+def _gpu_may_be_initialised():
+    """True when a profiler's preloaded library may already have set up the
+    GPU in this process (rocprofv3 --pmc does so before the program starts):
+    then no worker may be forked."""
+    pre = os.environ.get("LD_PRELOAD", "")
+    return "rocprof" in pre or any(k.startswith("ROCPROF") for k in os.environ)
+
+
 def make_phantoms(jobs):
-    """Phantoms on host cores, in a worker pool forked before this process
-    touches the GPU."""
+    """Phantoms on host cores: in a worker pool forked before this process
+    touches the GPU, or in this process when the GPU may already be set up.
+    The pool is closed and joined, so its workers exit normally."""
     procs = max(1, min(16, os.cpu_count() or 1, len(jobs)))
-    with mp.get_context("fork").Pool(procs) as pool:
-        return pool.map(_phantom_job, jobs)
+    if procs == 1 or _gpu_may_be_initialised():
+        return [_phantom_job(a) for a in jobs]
+    pool = mp.get_context("fork").Pool(procs)
+    try:
+        out = pool.map(_phantom_job, jobs)
+    finally:
+        pool.close()
+        pool.join()
+    return out
 
 
 def cpu_baseline(geom, mu, y, fro2, iters):
@@ -207,18 +268,22 @@ def headline(api, synth, args, mu, results):
     torch.cuda.synchronize()
     wev.close()
 
-    # timed: K iterations; HIP events on the library's stream bracket the
-    # denoiser (the dominant kernel) in every timed iteration
+    # timed: RUNS runs of K iterations from a fresh state each; HIP events on
+    # the library's stream bracket the denoiser (the dominant kernel) in every
+    # timed iteration; `value` is from the median run
     ev = HipEvents(K * (api.NPHASES + 1))
     log = torch.zeros(K * api.LOG_STRIDE, dtype=torch.float64, device="cuda")
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    st = run(K, events=ev.arr, log=log, mask=den_mask)
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
+    elapsed_runs, den_ms = [], []
+    for _ in range(TIMED_RUNS):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        st = run(K, events=ev.arr, log=log, mask=den_mask)
+        torch.cuda.synchronize()
+        elapsed_runs.append(time.perf_counter() - t0)
+        den_ms += [ev.ms(it * (api.NPHASES + 1) + den, it * (api.NPHASES + 1) + den + 1)
+                   for it in range(K)]
+    elapsed = statistics.median(elapsed_runs)
     status = float(st.scal[api.S_STATUS].item())
-    den_ms = [ev.ms(it * (api.NPHASES + 1) + den, it * (api.NPHASES + 1) + den + 1)
-              for it in range(K)]
     # untimed: the same iterations with every phase boundary marked
     phase_ms = {name: [] for name in api.PHASES}
     run(K, events=ev.arr)
@@ -245,9 +310,11 @@ def headline(api, synth, args, mu, results):
     nlm_flops = nlm_flops_per_pixel(CFG["nlm"]["pr"], CFG["nlm"]["sr"]) * N * 2  # r, r + eps b
     achieved_tflops = nlm_flops / (nlm_ms * 1e-3) / 1e12
     a_bytes = 4.0 * (N + M)
+    nnz = ray_pixel_interactions(geom)
     results.update({
         "value": K / elapsed,
         "ms_per_step": 1e3 * elapsed / K,
+        "timed_runs_iter_per_s": [K / e for e in elapsed_runs],
         "roofline": {"bound": "alu", "kernel": "nlm_kernel<2>", "kernel_ms": nlm_ms,
                      "achieved": achieved_tflops, "peak": FP32_VECTOR_TFLOPS,
                      "unit": "TFLOP/s", "frac": achieved_tflops / FP32_VECTOR_TFLOPS,
@@ -260,6 +327,10 @@ def headline(api, synth, args, mu, results):
         "At_GBps_algorithmic": a_bytes / (avg["backproject"] * 1e-3) / 1e9,
         "A_At_frac_of_hbm_peak": (2 * a_bytes / ((avg["project"] + avg["backproject"]) * 1e-3)
                                   / 1e9) / HBM_PEAK_GBS,
+        "ray_pixel_interactions": nnz,
+        "A_interactions_per_s": nnz / (avg["project"] * 1e-3),
+        "At_interactions_per_s": nnz / (avg["backproject"] * 1e-3),
+        "A_At_counters": A_AT_COUNTERS,
         "psnr_db_after_steps": psnr,
         "nonfinite_pixels": int((~np.isfinite(mu_hat)).sum()),
         "final_log": dict(zip(api.LOG_FIELDS, [float(v) for v in
@@ -512,8 +583,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--only-headline", action="store_true",
                     help="skip the learned, batched and fan-beam figures")
-    ap.add_argument("--parts", default="headline,learned,batch,fan,ablation,proxtv",
-                    help="comma-separated subset of headline,learned,batch,fan,ablation,proxtv")
+    ap.add_argument("--parts", default="headline,learned,batch,fan,ablation",
+                    help="comma-separated subset of headline,learned,batch,fan,ablation,proxtv "
+                         "(proxtv, the proximal-TV plug-ins with their alpha sweeps, is opt-in)")
     ap.add_argument("--learned-iters", type=int, default=50)
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="first copy this many MiB device-to-device 3 times (a kernel of known "

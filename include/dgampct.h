@@ -36,6 +36,9 @@ typedef int32_t dg_status;
 #define DG_ERR_ARG (-1)         /* invalid argument: nothing launched          */
 #define DG_ERR_HIP (-2)         /* HIP runtime error (message in dg_last_error)*/
 #define DG_ERR_NUMERIC (-3)     /* a GAMP variance became non-finite or <= 0   */
+                                /* (reported by dg_check_status: the iteration */
+                                /* calls are asynchronous and record it in the */
+                                /* device status word scal[DG_S_STATUS])       */
 #define DG_ERR_UNSUPPORTED (-4) /* size or option not implemented              */
 #define DG_ERR_NOMEM (-5)       /* device allocation failed (plan tables only)  */
 
@@ -79,6 +82,7 @@ dg_status dg_plan_destroy(dg_plan* plan);
 #define DG_OP_DENOISE 1
 #define DG_OP_DGAMP 2
 #define DG_OP_FRO2 3
+#define DG_OP_SE 4
 size_t dg_workspace_bytes(const dg_plan* plan, int32_t op);
 /* Workspace of gamp_poisson_out for m rays.                                 */
 size_t dg_channel_workspace_bytes(int64_t m);
@@ -268,6 +272,44 @@ dg_status dgamp_state_init(const dg_plan* plan, dgamp_state* st, double tau_x0, 
 dg_status dgamp_iterate(const dg_plan* plan, const float* y, const dgamp_opts* opts,
                         dgamp_state* st, float* mu_out, double* log, void* work,
                         void* stream);
+
+/* Synchronous status check of the asynchronous iteration calls (Algorithm 1
+ * stops being meaningful once a variance tau is non-finite or <= 0).
+ * Synchronises `stream`, reads the status word of n_slices consecutive
+ * scalar blocks (scal: device, n_slices * DG_NSCAL doubles, as dgamp_state
+ * or a batch holds them) and returns DG_ERR_NUMERIC for the first slice whose
+ * status is set, with that slice and its failing iteration in *failed_slice
+ * and *failed_iter (both nullable; -1 when every slice is fine) and in
+ * dg_last_error(); DG_OK otherwise.                                          */
+dg_status dg_check_status(const double* scal, int32_t n_slices, int32_t* failed_slice,
+                          int32_t* failed_iter, void* stream);
+
+/* Scalar state evolution of D-GAMP-CT (Sec. 4.4, eqs. SEasym and SE_matches;
+ * the error function E_in and the sensitivity function A_in), evaluated on a
+ * known phantom with the iteration's own channel and denoiser kernels.  For
+ * t = 0 .. opts->n_iter - 1, from tau_x = tau_x0:
+ *   tau_p = fro2 tau_x / M;  P = z + sqrt(tau_p) n;
+ *   tau_s = sum_i (1 - Var[z_i | P_i, y_i, tau_p] / tau_p) / (M tau_p)
+ *           (-E[d g_out / dp] of the matched channel), damped by eta_s from t = 1;
+ *   tau_r = N / (fro2 tau_s) = xi_r;  R = x + sqrt(tau_r) v;
+ *   D(R) and div (one probe, eq. MC_SURE, iteration index t);
+ *   E_in = ||D(R) - x||^2 / N  (the predicted MSE of the denoiser's output);
+ *   tau_x = tau_r div (A_in; div <= 0 gives 1e-12 tau_r), damped by eta_x.
+ * z: M floats, the true line integrals A mu; x: N floats, V mu (the
+ * preconditioned-domain signal); y: M counts; n: M and v: N floats, standard
+ * normal fields supplied by the caller (all device).  Denoiser, i0, fro2,
+ * probe seed, eps_rel, damping and channel mode from opts (phase_events must
+ * be NULL; onsager is unused).  se_log (device, nullable): n_iter *
+ * DG_LOG_STRIDE doubles per iteration (tau_p, tau_s, tau_r, div, tau_x,
+ * E_in at DG_SE_LOG_MSE, status, clamps).  scal_out (device, nullable):
+ * the final DG_NSCAL scalars.  A non-finite or non-positive variance sets
+ * the status word to 1 + t and freezes the scalars.
+ * work: dg_workspace_bytes(plan, DG_OP_SE).                                 */
+#define DG_SE_LOG_MSE 5
+dg_status dgamp_state_evolution(const dg_plan* plan, const float* z, const float* x,
+                                const float* y, const float* n, const float* v,
+                                const dgamp_opts* opts, double tau_x0, double* se_log,
+                                double* scal_out, void* work, void* stream);
 
 /* A whole reconstruction as one replayable HIP graph: optional state reset
  * (dgamp_state_init with tau_x0 when tau_x0 > 0), then opts->n_iter

@@ -18,7 +18,9 @@ LIB_PATH = os.path.join(_HERE, "libdgampct.so")
 PARALLEL, FAN = 0, 1
 DEN_HAAR, DEN_NLM, DEN_CNN, DEN_TV, DEN_TVW = 0, 1, 2, 3, 4
 CHANNEL_LAPLACE, CHANNEL_MODE_ONLY = 0, 1
-OP_PRECOND, OP_DENOISE, OP_DGAMP, OP_FRO2 = 0, 1, 2, 3
+OP_PRECOND, OP_DENOISE, OP_DGAMP, OP_FRO2, OP_SE = 0, 1, 2, 3, 4
+SE_LOG_MSE = 5
+ERR_ARG, ERR_HIP, ERR_NUMERIC, ERR_UNSUPPORTED, ERR_NOMEM = -1, -2, -3, -4, -5
 NSCAL = 16
 S_TAU_X, S_TAU_P, S_TAU_S, S_TAU_R, S_DIV, S_EPS, S_STATUS, S_CLAMPS = range(8)
 LOG_STRIDE = 8
@@ -36,7 +38,8 @@ EXPORTS = ("dg_plan_create", "dg_plan_destroy", "dg_workspace_bytes", "dg_channe
            "dgamp_batch_iterate", "dg_batch_graph_create", "dg_batch_autotune",
            "dg_batch_projector_variant", "dg_plan_autotune", "dg_plan_projector_variant",
            "dg_batch_set_projector_variant", "dg_plan_set_projector_variant",
-           "dg_psnr_workspace_bytes", "dg_psnr", "dg_tv_workspace_bytes", "dg_tvw_workspace_bytes")
+           "dg_psnr_workspace_bytes", "dg_psnr", "dg_tv_workspace_bytes", "dg_tvw_workspace_bytes",
+           "dg_check_status", "dgamp_state_evolution")
 
 
 class DgError(RuntimeError):
@@ -142,6 +145,9 @@ def load():
         "dg_psnr": ([i64, _VP, _VP, _VP, _VP, _VP], i32),
         "dg_tv_workspace_bytes": ([i64], sz),
         "dg_tvw_workspace_bytes": ([i32], sz),
+        "dg_check_status": ([_VP, i32, ctypes.POINTER(i32), ctypes.POINTER(i32), _VP], i32),
+        "dgamp_state_evolution": ([_VP, _VP, _VP, _VP, _VP, _VP, ctypes.POINTER(DgampOpts), dbl,
+                                   _VP, _VP, _VP, _VP], i32),
     }
     missing = set(EXPORTS) - set(sig)
     if missing:
@@ -362,6 +368,42 @@ def dgamp_iterate(plan, y, state, n_iter, fro2, i0, den_kind, den_params, probe_
                               _ptr(log, torch.float64, None, "log"),
                               _ptr(work, torch.uint8, None, "work"), _stream()))
     return mu_out
+
+
+def dgamp_state_evolution(plan, z, x, y, n, v, n_iter, fro2, i0, den_kind, den_params,
+                          probe_seed=0, eps_rel=1e-3, eta_x=1.0, eta_s=1.0,
+                          channel_mode=CHANNEL_LAPLACE, tau_x0=1.0, log=None, scal_out=None,
+                          work=None):
+    """Scalar state evolution on a known phantom: z = A mu (M), x = V mu (N),
+    y the counts, n (M) and v (N) standard-normal fields.  Returns the
+    per-iteration log (n_iter x LOG_STRIDE, E_in at SE_LOG_MSE)."""
+    opts = make_opts(n_iter, fro2, i0, den_kind, den_params, probe_seed, eps_rel, eta_x, eta_s,
+                     True, channel_mode)
+    if log is None:
+        log = torch.zeros(max(n_iter, 1) * LOG_STRIDE, dtype=torch.float64, device="cuda")
+    if work is None:
+        work = plan.workspace(OP_SE)
+    _check(_lib.dgamp_state_evolution(plan.handle, _ptr(z, torch.float32, plan.M, "z"),
+                                      _ptr(x, torch.float32, plan.N, "x"),
+                                      _ptr(y, torch.float32, plan.M, "y"),
+                                      _ptr(n, torch.float32, plan.M, "n"),
+                                      _ptr(v, torch.float32, plan.N, "v"), ctypes.byref(opts),
+                                      float(tau_x0), _ptr(log, torch.float64, None, "log"),
+                                      _ptr(scal_out, torch.float64, NSCAL, "scal_out"),
+                                      _ptr(work, torch.uint8, None, "work"), _stream()))
+    return log
+
+
+def dg_check_status(scal, n_slices=1):
+    """Synchronise the current stream and read the status words: returns
+    (status, failed_slice, failed_iter) with status 0 or ERR_NUMERIC (not
+    raised), the indices -1 when every slice is fine."""
+    fs, fi = ctypes.c_int32(), ctypes.c_int32()
+    rc = _lib.dg_check_status(_ptr(scal, torch.float64, n_slices * NSCAL, "scal"), int(n_slices),
+                              ctypes.byref(fs), ctypes.byref(fi), _stream())
+    if rc not in (0, ERR_NUMERIC):
+        _check(rc)
+    return rc, fs.value, fi.value
 
 
 def dg_fro2_hutchinson(plan, n_probes, seed, out=None, work=None):

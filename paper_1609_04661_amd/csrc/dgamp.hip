@@ -8,6 +8,7 @@
 // All scalars stay on the device, so a whole run is host-sync free and can be
 // captured into a graph by the caller.
 #include <cmath>
+#include <vector>
 
 #include "dg_internal.h"
 
@@ -129,6 +130,7 @@ dg_status launch_fill(float* p, int64_t n, float v, hipStream_t st) {
 }
 
 size_t iter_work_bytes(const dg_plan* p) { return iter_work_layout(p, nullptr, nullptr); }
+size_t se_work_bytes(const dg_plan* p);
 
 }  // namespace dg
 
@@ -144,6 +146,8 @@ extern "C" size_t dg_workspace_bytes(const dg_plan* p, int32_t op) {
     case DG_OP_DGAMP:
     case DG_OP_FRO2:
       return iter_work_bytes(p);
+    case DG_OP_SE:
+      return se_work_bytes(p);
     default:
       return 0;
   }
@@ -301,6 +305,29 @@ extern "C" dg_status dgamp_iterate(const dg_plan* p, const float* y, const dgamp
     if ((rc = launch_div_finish(A, o->eta_x, t_last, s)) != DG_OK) return rc;
   }
   if (finish && (rc = log_it(o->n_iter - 1)) != DG_OK) return rc;
+  return DG_OK;
+}
+
+extern "C" dg_status dg_check_status(const double* scal, int32_t n_slices, int32_t* failed_slice,
+                                     int32_t* failed_iter, void* stream) {
+  DG_ARG_CHECK(scal && n_slices >= 1, "dg_check_status: null scalars or no slices");
+  DG_HIP(hipStreamSynchronize((hipStream_t)stream));
+  std::vector<double> h((size_t)n_slices * DG_NSCAL);
+  DG_HIP(hipMemcpy(h.data(), scal, sizeof(double) * h.size(), hipMemcpyDeviceToHost));
+  if (failed_slice) *failed_slice = -1;
+  if (failed_iter) *failed_iter = -1;
+  for (int32_t k = 0; k < n_slices; ++k) {
+    const double v = h[(size_t)k * DG_NSCAL + DG_S_STATUS];
+    if (v != 0.0) {
+      const int32_t it = (int32_t)v - 1;
+      if (failed_slice) *failed_slice = k;
+      if (failed_iter) *failed_iter = it;
+      set_error("slice " + std::to_string(k) + ": a GAMP variance became non-finite or "
+                "non-positive at iteration " + std::to_string(it) +
+                "; later iterations left its state unchanged");
+      return DG_ERR_NUMERIC;
+    }
+  }
   return DG_OK;
 }
 

@@ -9,8 +9,9 @@ Tolerances:
     + |p|) / tau_p): FP32 rounding of the terms of the mode equation (each
     of those sizes) divided by its slope; tau_s relative 1e-5.
   * denoisers: relative L2 <= 1e-5 (Haar), <= 2e-5 (NLM: FP32 exp and sums
-    over 441 offsets); divergence absolute 2e-3 (the difference quotient
-    divides FP32 rounding of D by eps = 1e-3 max|r|).
+    over 441 offsets); divergence: ``div_tol`` (FP32 error of the two
+    denoiser outputs divided by eps and summed with the probe's random
+    signs; see there).
   * D-GAMP-CT: PSNR within 0.1 dB of the oracle's on identical inputs.
 """
 import math
@@ -41,6 +42,22 @@ def host(t):
 
 def rel_l2(a, b):
     return float(np.linalg.norm((a - b).ravel()) / max(np.linalg.norm(b.ravel()), 1e-300))
+
+
+def div_tol(div_ref, x_ref, r, rho):
+    """Bound on |div_gpu - div_ref| for eq. MC_SURE with one Rademacher probe,
+    div = sum_i b_i (D(r + eps b)_i - D(r)_i) / (N eps), eps = 1e-3 max|r|.
+    The FP32 outputs D(r) and D(r + eps b) each differ from FP64 by an error
+    field e with ||e||_2 <= rho ||D||_2 (rho: the output's own relative-L2
+    parity bound).  A step of 1e-3 max|r| is ~1e4 FP32 ulps, so the two
+    fields' rounding patterns are unrelated, and the probe signs b_i make
+    sum_i b_i e_i a random walk of standard deviation ||e||_2: at four
+    standard deviations 4 sqrt(2) rho ||D||_2 / (N eps).  FP32 rounding of
+    r + eps b moves each pixel's step by u |r_i| / eps <= 6e-5 of eps,
+    i.e. at most 1e-4 |div|."""
+    N = r.size
+    eps = max(1e-3 * float(np.max(np.abs(r))), 1e-12)
+    return 1e-4 * abs(div_ref) + 4 * math.sqrt(2) * rho * float(np.linalg.norm(x_ref)) / (N * eps)
 
 
 GEOMS = {
@@ -150,23 +167,35 @@ def channel_cases(n=20000, seed=3):
     return out
 
 
+def channel_bound(p, y, tau_p, i0, s_ref):
+    """Per-ray bound on |s_gpu - s_ref|: the FP32 mode solve rounds each term
+    of its equation (delta, ln w, ln tau_p, ln I0, p) at u = eps32 of its
+    size, which moves the root by that over the slope (~1 in delta, then / tau_p
+    in s); 64 u covers the few roundings per term and the Laplace terms."""
+    z0 = och.mode(p, y, tau_p, i0)
+    delta = z0 - p
+    w = tau_p * i0 * np.exp(-z0)
+    scale = np.abs(s_ref) + (np.abs(delta) + np.abs(np.log(w)) + abs(math.log(tau_p)) +
+                             math.log(i0) + np.abs(p)) / tau_p
+    return 64 * EPS32 * scale
+
+
 @pytest.mark.parametrize("mode", [0, 1])
 def test_channel_matches_oracle(gpu_lib, mode):
     for p, y, tau_p, i0 in channel_cases():
         s_ref, ts_ref = och.poisson_out(p, y, tau_p, i0, kind=mode)
         s, ts = gpu_lib.gamp_poisson_out(cu(p), cu(y), cu([tau_p], torch.float64), i0, mode)
         s, ts = host(s), float(host(ts)[0])
-        z0 = och.mode(p, y, tau_p, i0)
-        delta = z0 - p
-        w = tau_p * i0 * np.exp(-z0)
-        scale = np.abs(s_ref) + (np.abs(delta) + np.abs(np.log(w)) + abs(math.log(tau_p)) +
-                                 math.log(i0) + np.abs(p)) / tau_p
-        bad = np.abs(s - s_ref) > 64 * EPS32 * scale
-        assert not bad.any(), (tau_p, i0, np.max(np.abs(s - s_ref) / scale))
+        bound = channel_bound(p, y, tau_p, i0, s_ref)
+        bad = np.abs(s - s_ref) > bound
+        assert not bad.any(), (tau_p, i0, np.max(np.abs(s - s_ref) / bound))
         assert abs(ts - ts_ref) <= 1e-5 * abs(ts_ref), (tau_p, i0, ts, ts_ref)
 
 
 def test_channel_ragged_and_single(gpu_lib):
+    """Ray counts around the 256-ray workgroup and the grid-stride step, one
+    ray alone, and 100003 rays; every ray within the same per-ray bound as the
+    main channel test."""
     for m in (1, 255, 257, 100003):
         rng = np.random.default_rng(m)
         zt = rng.uniform(0, 5, m)
@@ -175,7 +204,7 @@ def test_channel_ragged_and_single(gpu_lib):
         s_ref, ts_ref = och.poisson_out(p, y, 0.3, 1e4)
         s, ts = gpu_lib.gamp_poisson_out(cu(p), cu(y), cu([0.3], torch.float64), 1e4)
         assert abs(float(host(ts)[0]) - ts_ref) <= 1e-5 * ts_ref
-        assert rel_l2(host(s), s_ref) <= 3e-5
+        assert np.all(np.abs(host(s) - s_ref) <= channel_bound(p, y, 0.3, 1e4, s_ref)), m
 
 
 @pytest.mark.parametrize("I", [64, 512])
@@ -190,24 +219,34 @@ def test_haar_matches_oracle(gpu_lib, I):
     x_ref = oden.haar_soft(r32, tau, 1.5)
     assert rel_l2(host(x), x_ref) <= 1e-5
     div_ref, _ = oden.mc_divergence(oden.HAAR, r32, tau, dict(alpha=1.5), x_ref, 77, 3)
-    assert abs(float(host(div)[0]) - div_ref) <= 2e-3
+    got = float(host(div)[0])
+    print("haar div gpu %.9f oracle %.9f tol %.2e" % (got, div_ref, div_tol(div_ref, x_ref, r32, 1e-5)))
+    assert abs(got - div_ref) <= div_tol(div_ref, x_ref, r32, 1e-5)
 
 
-@pytest.mark.parametrize("I,noise,tau", [(64, 0.004, 1.6e-5), (100, 0.004, 1.6e-5),
-                                         (256, 3.0, 9.0), (1024, 0.05, 2.5e-3)])
-def test_nlm_matches_oracle(gpu_lib, I, noise, tau):
+@pytest.mark.parametrize("I,noise,tau,xspace", [(64, 0.004, 1.6e-5, False), (100, 0.004, 1.6e-5, False),
+                                                (256, 3.0, 9.0, False), (1024, 0.05, 2.5e-3, False),
+                                                (512, 0.15, 0.0225, True)])
+def test_nlm_matches_oracle(gpu_lib, I, noise, tau, xspace):
     """Small and large sides (tile tails, 1024 x 1024) and both noise regimes
-    (weights near 1 everywhere at sigma^2 = tau = 9)."""
+    (weights near 1 everywhere at sigma^2 = tau = 9); and the headline's
+    operating point: r = V mu + noise in the preconditioned domain at 512 x 512
+    with tau_r = 0.0225, where the divergence is ~1e-2."""
     g = synth.geometry(synth.PARALLEL, I, 1.0, 4, I + 1, math.pi)
     P = gpu_lib.Plan(g)
-    r = synth.ellipse_phantom(I, 6) + noise * np.random.default_rng(2).standard_normal((I, I))
+    base = synth.ellipse_phantom(I, 6)
+    if xspace:
+        base = precond.apply_V(base)
+    r = base + noise * np.random.default_rng(2).standard_normal((I, I))
     r32 = r.astype(np.float32).astype(np.float64)
     x, div = gpu_lib.denoise(P, gpu_lib.DEN_NLM, gpu_lib.make_params(gpu_lib.DEN_NLM),
                              cu(r32), cu([tau], torch.float64), probe_seed=5, iteration=1)
     x_ref = oden.nlm(r32, tau)
     assert rel_l2(host(x), x_ref) <= 2e-5, rel_l2(host(x), x_ref)
     div_ref, _ = oden.mc_divergence(oden.NLM, r32, tau, {}, x_ref, 5, 1)
-    assert abs(float(host(div)[0]) - div_ref) <= 2e-3, (float(host(div)[0]), div_ref)
+    got, tol = float(host(div)[0]), div_tol(div_ref, x_ref, r32, 2e-5)
+    print("nlm %d div gpu %.9f oracle %.9f tol %.2e" % (I, got, div_ref, tol))
+    assert abs(got - div_ref) <= tol, (got, div_ref, tol)
 
 
 def test_fro2_hutchinson_matches_oracle(gpu_lib, plans):
@@ -329,7 +368,9 @@ def test_prox_tv_matches_oracle(gpu_lib, I, noise, tau, iters):
     # FP32 over 50 steps of a non-expansive map: errors stay near a few ulps of |x|
     assert rel_l2(host(x), x_ref) <= 1e-5, rel_l2(host(x), x_ref)
     div_ref, _ = oden.mc_divergence(oden.TV, r32, tau, dict(alpha=0.5, iters=iters), x_ref, 9, 2)
-    assert abs(float(host(div)[0]) - div_ref) <= 2e-3, (float(host(div)[0]), div_ref)
+    got, tol = float(host(div)[0]), div_tol(div_ref, x_ref, r32, 1e-5)
+    print("tv %d div gpu %.9f oracle %.9f tol %.2e" % (I, got, div_ref, tol))
+    assert abs(got - div_ref) <= tol, (got, div_ref, tol)
 
 
 def test_prox_tv_identity_at_zero_variance(gpu_lib, plans):
@@ -362,7 +403,9 @@ def test_prox_tv_w_matches_oracle(gpu_lib, I, noise, tau, iters, metric):
     x_ref = oden.prox_tv_w(r32, tau, **params)
     assert rel_l2(host(x), x_ref) <= 2e-5, rel_l2(host(x), x_ref)
     div_ref, _ = oden.mc_divergence(oden.TVW, r32, tau, params, x_ref, 9, 2)
-    assert abs(float(host(div)[0]) - div_ref) <= 2e-3, (float(host(div)[0]), div_ref)
+    got, tol = float(host(div)[0]), div_tol(div_ref, x_ref, r32, 2e-5)
+    print("tvw %d div gpu %.9f oracle %.9f tol %.2e" % (I, got, div_ref, tol))
+    assert abs(got - div_ref) <= tol, (got, div_ref, tol)
 
 
 def test_prox_tv_w_identity_at_zero_variance(gpu_lib, plans):
