@@ -61,7 +61,9 @@ def conv3x3(x, w, b=None):
     for ty in range(3):
         for tx in range(3):
             patch = xp[:, ty:ty + H, tx:tx + W].reshape(ci, -1)
-            out += (w[:, :, ty, tx] @ patch).reshape(-1, H, W)
+            # (a contiguous copy of the tap's weight matrix keeps the product on
+            # the library's fast path; the arithmetic is unchanged)
+            out += (np.ascontiguousarray(w[:, :, ty, tx]) @ patch).reshape(-1, H, W)
     if b is not None:
         out += b[:, None, None]
     return out
@@ -77,7 +79,7 @@ def conv3x3_input_grad(g, w):
         for tx in range(3):
             # x[y', x'] feeds out[y' - ty + 1, x' - tx + 1]
             patch = gp[:, 2 - ty:2 - ty + H, 2 - tx:2 - tx + W].reshape(co, -1)
-            out += (w[:, :, ty, tx].T @ patch).reshape(-1, H, W)
+            out += (np.ascontiguousarray(w[:, :, ty, tx].T) @ patch).reshape(-1, H, W)
     return out
 
 

@@ -3,17 +3,21 @@
 Two oracle references:
   * the oracle in BF16-storage mode, which rounds to BF16 exactly where the
     kernels store BF16 (hidden activations, their tangents, the masked
-    back-propagated gradients) and computes in FP64 otherwise.  What is left
-    between it and the GPU is FP32 accumulation order, which moves a stored
-    value across a BF16 rounding boundary only rarely (a relative FP32 error
-    of ~1e-6 against BF16's 2^-9 spacing); the bounds are cosine >= 0.9999
-    and relative L2 <= 5e-3 for f, the tangent divergence and every weight
-    gradient (the gradient of the first layer is a sum over pixels that
-    cancels to ~1/50 of its terms, so the same per-element disagreement
-    weighs ~50x more there);
-  * the plain FP64 oracle, which shows what BF16 storage itself costs: the
-    GPU may differ from it by no more than 1.5x the distance of the BF16-mode
-    oracle from it (plus 1e-3 relative), layer by layer.
+    back-propagated gradients) and computes in FP64 otherwise;
+  * the plain FP64 oracle.
+The GPU differs from the BF16-mode oracle only in FP32 accumulation order,
+but that does not keep two BF16 pipelines close: a stored value within an
+FP32 rounding of a BF16 rounding boundary rounds the other way, each such
+flip changes the next layer's sums over a 3x3x64 window, more values then
+cross boundaries, and layer by layer the two pipelines drift apart to a
+distance of the order of BF16's own rounding, the same order as either's
+distance from FP64 (and the first layer's weight gradient, a sum over
+pixels that cancels to a small fraction of its terms, magnifies both
+alike).  So, with d16 = the BF16-mode oracle's distance from FP64 (what BF16
+storage itself costs), every compared quantity must satisfy:
+cosine with the BF16-mode oracle >= 0.999, distance from it <= 2 d16, and
+distance from FP64 <= 3 d16 (plus a floor of 1e-4 relative).  A kernel error
+larger than BF16 storage itself fails these.
 """
 import math
 
@@ -48,11 +52,15 @@ def rel(a, b):
     return float(np.linalg.norm(np.ravel(a) - np.ravel(b)) / np.linalg.norm(np.ravel(b)))
 
 
-def check_vs_oracles(got, ref16, ref64, what, tol=5e-3):
-    """got against the BF16-storage oracle (tight), and no further from the FP64
-    oracle than BF16 storage itself moves it."""
-    assert cos(got, ref16) >= 0.9999 and rel(got, ref16) <= tol, (what, cos(got, ref16), rel(got, ref16))
-    assert rel(got, ref64) <= 1.5 * rel(ref16, ref64) + 1e-3, (what, rel(got, ref64), rel(ref16, ref64))
+def check_vs_oracles(got, ref16, ref64, what):
+    """got against the BF16-storage oracle and the FP64 oracle, in units of
+    the distance BF16 storage itself puts between the two oracles."""
+    d16 = rel(ref16, ref64)
+    c = cos(got, ref16)
+    r16, r64 = rel(got, ref16), rel(got, ref64)
+    print(what, "cos %.6f  rel16 %.2e  rel64 %.2e  d16 %.2e" % (c, r16, r64, d16))
+    assert c >= 0.999 and r16 <= 2.0 * d16 + 1e-4 and r64 <= 3.0 * d16 + 1e-4, \
+        (what, c, r16, r64, d16)
 
 
 def test_cnn_forward_matches_oracle(gpu_lib):
@@ -132,9 +140,11 @@ def test_cnn_denoise_and_tangent_divergence(gpu_lib, I):
     d16 = ocnn.tangent_divergence(r, params, b, bf16=True)
     d64 = ocnn.tangent_divergence(r, params, b)
     got = float(div.item())
-    # 1 - div is b^T J_f b / N, the part the network contributes
-    assert abs(got - d16) <= 5e-3 * abs(1.0 - d16) + 1e-6, (got, d16, d64)
-    assert abs(got - d64) <= 1.5 * abs(d16 - d64) + 1e-3 * abs(1.0 - d64), (got, d16, d64)
+    # 1 - div = b^T J_f b / N is the part the network contributes
+    floor = 1e-4 * abs(1.0 - d64)
+    print("tangent div gpu %.6f bf16-oracle %.6f fp64-oracle %.6f" % (got, d16, d64))
+    assert abs(got - d16) <= 2.0 * abs(d16 - d64) + floor, (got, d16, d64)
+    assert abs(got - d64) <= 3.0 * abs(d16 - d64) + floor, (got, d16, d64)
 
 
 def test_cnn_training_reduces_loss(gpu_lib):
