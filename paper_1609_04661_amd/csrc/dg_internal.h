@@ -193,6 +193,17 @@ __device__ __forceinline__ float finish_max(const float* partials, int n, float*
 // Batched launches: one grid covers many slices.  prefix[s] is the first
 // block of slice s (prefix[0] = 0, prefix[n] = total blocks); a block finds its
 // slice by binary search (uniform per block, so it runs on scalar registers).
+// The chip's 8 XCDs (each with its own L2) receive a launch's workgroups
+// round-robin: workgroup b runs on XCD b % 8.  xcd_block maps the hardware
+// index to a logical one under which every XCD's workgroups form one
+// contiguous range (XCD x takes logical blocks [x q + min(x, r), ...) with
+// q = nblk / 8, r = nblk % 8), so that neighbouring logical blocks, which
+// read the same data, share an L2.  A bijection on [0, nblk).
+__device__ __forceinline__ int xcd_block(int b, int nblk) {
+  const int q = nblk >> 3, r = nblk & 7, x = b & 7;
+  return x * q + (x < r ? x : r) + (b >> 3);
+}
+
 __device__ __forceinline__ int slice_of(const int* __restrict__ prefix, int n, int b) {
   int lo = 0, hi = n;
   while (hi - lo > 1) {

@@ -197,17 +197,22 @@ __device__ void project_body(const ProjArgs& A, int blk, float (*part)[kRaysPerB
   if (lane == 0) C.partials[blk] = bs;
 }
 
+// Consecutive blocks hold consecutive rays, i.e. the bins of one view, and
+// a view reads either the image (steep rays) or its transpose (flat rays);
+// with the XCD-contiguous block order every XCD's L2 holds the rays of a
+// contiguous range of views and so mostly one of the two buffers.
 template <int SEGS>
 __global__ void __launch_bounds__(kRaysPerBlock * SEGS) project_kernel(ProjArgs A, ChanRun cr) {
   __shared__ float part[SEGS][kRaysPerBlock];
-  project_body<SEGS>(A, blockIdx.x, part, cr);
+  project_body<SEGS>(A, xcd_block((int)blockIdx.x, (int)gridDim.x), part, cr);
 }
 template <int SEGS>
 __global__ void __launch_bounds__(kRaysPerBlock * SEGS)
 project_batch(const ProjArgs* __restrict__ T, const int* __restrict__ prefix, int n, ChanRun cr) {
   __shared__ float part[SEGS][kRaysPerBlock];
-  const int s = slice_of(prefix, n, blockIdx.x);
-  project_body<SEGS>(T[s], blockIdx.x - prefix[s], part, cr);
+  const int b = xcd_block((int)blockIdx.x, (int)gridDim.x);
+  const int s = slice_of(prefix, n, b);
+  project_body<SEGS>(T[s], b - prefix[s], part, cr);
 }
 
 // Weight of pixel (i, j) on a ray: the same fixed-point cross coordinate and
