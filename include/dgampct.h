@@ -284,6 +284,23 @@ dg_status dgamp_iterate(const dg_plan* plan, const float* y, const dgamp_opts* o
 dg_status dg_check_status(const double* scal, int32_t n_slices, int32_t* failed_slice,
                           int32_t* failed_iter, void* stream);
 
+/* dgamp_iterate without a workspace argument and without any device
+ * allocation, for callers that cannot allocate (code under stream capture,
+ * serving loops, harnesses that forbid hipMalloc).  Same arguments, kernels
+ * and results as dgamp_iterate; the iteration workspace is a fixed device
+ * array inside the library, dg_noalloc_scratch_bytes() = 48 MiB on every
+ * GPU the library runs on, held until the process ends.  A plan whose
+ * dg_workspace_bytes(plan, DG_OP_DGAMP) exceeds it returns DG_ERR_ARG with
+ * nothing launched (every image side up to 1024 with up to ~10^6 rays fits).
+ * The first call on a device looks up the array's device address (no
+ * allocation).  All calls on one GPU share the array: calls that overlap on
+ * one GPU (different streams or threads) race.  Buffers a denoiser takes
+ * through den_params (CNN activations, the TV kinds' state) stay the
+ * caller's, as with dgamp_iterate.                                          */
+size_t dg_noalloc_scratch_bytes(void);
+dg_status dgamp_iterate_noalloc(const dg_plan* plan, const float* y, const dgamp_opts* opts,
+                                dgamp_state* st, float* mu_out, double* log, void* stream);
+
 /* Scalar state evolution of D-GAMP-CT (Sec. 4.4, eqs. SEasym and SE_matches;
  * the error function E_in and the sensitivity function A_in), evaluated on a
  * known phantom with the iteration's own channel and denoiser kernels.  For

@@ -39,7 +39,8 @@ EXPORTS = ("dg_plan_create", "dg_plan_destroy", "dg_workspace_bytes", "dg_channe
            "dg_batch_projector_variant", "dg_plan_autotune", "dg_plan_projector_variant",
            "dg_batch_set_projector_variant", "dg_plan_set_projector_variant",
            "dg_psnr_workspace_bytes", "dg_psnr", "dg_tv_workspace_bytes", "dg_tvw_workspace_bytes",
-           "dg_check_status", "dgamp_state_evolution")
+           "dg_check_status", "dg_noalloc_scratch_bytes", "dgamp_iterate_noalloc",
+           "dgamp_state_evolution")
 
 
 class DgError(RuntimeError):
@@ -146,8 +147,11 @@ def load():
         "dg_tv_workspace_bytes": ([i64], sz),
         "dg_tvw_workspace_bytes": ([i32], sz),
         "dg_check_status": ([_VP, i32, ctypes.POINTER(i32), ctypes.POINTER(i32), _VP], i32),
+        "dg_noalloc_scratch_bytes": ([], sz),
         "dgamp_state_evolution": ([_VP, _VP, _VP, _VP, _VP, _VP, ctypes.POINTER(DgampOpts), dbl,
                                    _VP, _VP, _VP, _VP], i32),
+        "dgamp_iterate_noalloc": ([_VP, _VP, ctypes.POINTER(DgampOpts), ctypes.POINTER(DgampStateC),
+                                   _VP, _VP, _VP], i32),
     }
     missing = set(EXPORTS) - set(sig)
     if missing:
@@ -392,6 +396,25 @@ def dgamp_state_evolution(plan, z, x, y, n, v, n_iter, fro2, i0, den_kind, den_p
                                       _ptr(scal_out, torch.float64, NSCAL, "scal_out"),
                                       _ptr(work, torch.uint8, None, "work"), _stream()))
     return log
+
+
+def dgamp_iterate_noalloc(plan, y, state, n_iter, fro2, i0, den_kind, den_params, probe_seed=0,
+                          eps_rel=1e-3, eta_x=1.0, eta_s=1.0, onsager=True,
+                          channel_mode=CHANNEL_LAPLACE, mu_out=None, log=None):
+    """dgamp_iterate with the library's fixed scratch array as its workspace."""
+    opts = make_opts(n_iter, fro2, i0, den_kind, den_params, probe_seed, eps_rel, eta_x, eta_s,
+                     onsager, channel_mode)
+    if log is not None and log.numel() < n_iter * LOG_STRIDE:
+        raise DgError("log needs n_iter * %d doubles" % LOG_STRIDE)
+    _check(_lib.dgamp_iterate_noalloc(plan.handle, _ptr(y, torch.float32, plan.M, "y"),
+                                      ctypes.byref(opts), ctypes.byref(state.c),
+                                      _ptr(mu_out, torch.float32, plan.N, "mu_out"),
+                                      _ptr(log, torch.float64, None, "log"), _stream()))
+    return mu_out
+
+
+def dg_noalloc_scratch_bytes():
+    return int(_lib.dg_noalloc_scratch_bytes())
 
 
 def dg_check_status(scal, n_slices=1):

@@ -119,7 +119,9 @@ def test_psnr_rejects_bad_arguments():
     assert L.dg_psnr(10, None, None, None, None, None) == -1
 
 
-def test_check_status_rejects_null_arguments():
+def test_check_status_and_noalloc_reject_null_arguments():
     L = api.load()
     assert L.dg_check_status(None, 1, None, None, None) == -1
     assert L.dg_check_status(ctypes.c_void_p(8), 0, None, None, None) == -1
+    assert L.dgamp_iterate_noalloc(None, None, None, None, None, None, None) == -1
+    assert L.dg_noalloc_scratch_bytes() == 48 << 20
