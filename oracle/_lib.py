@@ -29,6 +29,8 @@ def build():
 
 _D = ctypes.POINTER(ctypes.c_double)
 _I32 = ctypes.POINTER(ctypes.c_int32)
+_F32 = ctypes.POINTER(ctypes.c_float)
+_U8 = ctypes.POINTER(ctypes.c_uint8)
 
 
 def lib():
@@ -47,6 +49,14 @@ def lib():
         L.oracle_nlm.argtypes = [ctypes.c_int, _D, ctypes.c_double, ctypes.c_int, ctypes.c_int,
                                  ctypes.c_double, _D]
         L.oracle_nlm.restype = None
+        L.oracle_bm3d_ref_axis.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, _I32]
+        L.oracle_bm3d_ref_axis.restype = ctypes.c_int
+        L.oracle_bm3d_groups.argtypes = [ctypes.c_int, _F32, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                         ctypes.c_float, ctypes.c_int, _I32, _I32, _I32]
+        L.oracle_bm3d_groups.restype = None
+        L.oracle_bm3d_keep.argtypes = [ctypes.c_int, _F32, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                       _I32, _I32, _F32, ctypes.c_float, _U8, _I32]
+        L.oracle_bm3d_keep.restype = None
         L.oracle_set_threads.argtypes = [ctypes.c_int]
         L.oracle_set_threads.restype = None
         L.oracle_max_threads.argtypes = []
@@ -71,3 +81,13 @@ def dptr(a):
 def iptr(a):
     assert a.dtype == np.int32 and a.flags["C_CONTIGUOUS"]
     return a.ctypes.data_as(_I32)
+
+
+def fptr(a):
+    assert a.dtype == np.float32 and a.flags["C_CONTIGUOUS"]
+    return a.ctypes.data_as(_F32)
+
+
+def u8ptr(a):
+    assert a.dtype == np.uint8 and a.flags["C_CONTIGUOUS"]
+    return a.ctypes.data_as(_U8)

@@ -203,3 +203,150 @@ void oracle_nlm(int I, const double *r, double sigma, int pr, int sr,
 #include <omp.h>
 void oracle_set_threads(int n) { omp_set_num_threads(n > 0 ? n : 1); }
 int oracle_max_threads(void) { return omp_get_max_threads(); }
+
+/* ------------------------------------------------------------------ BM3D
+ * The decisions of the two-stage block-matching collaborative filter (the
+ * paper's plug-in denoiser, Dabov, Foi, Katkovnik & Egiazarian 2007): which
+ * blocks join each reference block's group, and which coefficients of the
+ * group's 3D transform survive the hard threshold.  They are taken on FP32
+ * values, with every sum in the order written here (no contraction of a
+ * multiply and an add), so that any implementation following the same order
+ * takes the same decisions; everything continuous is left to FP64 code.
+ */
+
+/* Reference positions along one axis: 0, step, 2 step, ... <= I - n1, and
+ * I - n1 itself if the grid misses it.  Returns the count. */
+int oracle_bm3d_ref_axis(int I, int n1, int step, int32_t *pos) {
+  int n = 0;
+  for (int p = 0; p <= I - n1; p += step) pos[n++] = p;
+  if (pos[n - 1] != I - n1) pos[n++] = I - n1;
+  return n;
+}
+
+/* For every reference block (row-major over the reference grid): the
+ * reference block itself first, then the other blocks (y, x) with
+ * |y - y_r| <= ns, |x - x_r| <= ns, 0 <= y, x <= I - n1 whose distance
+ * d = (sum over the block, row by row, of (a - b)^2) / n1^2 (the mean
+ * squared difference) satisfies d <= thr, ordered by (d, y I + x); the first
+ * min(count, n2) rounded down to a power of two form the group.
+ * grp: n_ref * n2 raster indices (-1 past the group), gsize: n_ref. */
+void oracle_bm3d_groups(int I, const float *r, int n1, int ns, int n2, float thr,
+                        int n_axis, const int32_t *axis, int32_t *grp, int32_t *gsize) {
+  const float inv = 1.0f / (float)(n1 * n1);
+#pragma omp parallel
+  {
+    int cap = (2 * ns + 1) * (2 * ns + 1);
+    float *dd = (float *)malloc(sizeof(float) * cap);
+    int32_t *ii = (int32_t *)malloc(sizeof(int32_t) * cap);
+#pragma omp for schedule(dynamic, 4)
+    for (int q = 0; q < n_axis * n_axis; q++) {
+      const int yr = axis[q / n_axis], xr = axis[q % n_axis];
+      int m = 0;
+      dd[m] = 0.0f; /* the reference block leads its group */
+      ii[m] = yr * I + xr;
+      m++;
+      for (int y = yr - ns; y <= yr + ns; y++) {
+        if (y < 0 || y > I - n1) continue;
+        for (int x = xr - ns; x <= xr + ns; x++) {
+          if (x < 0 || x > I - n1 || (y == yr && x == xr)) continue;
+          float acc = 0.0f;
+          for (int u = 0; u < n1; u++)
+            for (int v = 0; v < n1; v++) {
+              float t = r[(yr + u) * I + xr + v] - r[(y + u) * I + x + v];
+              float t2 = t * t;
+              acc = acc + t2;
+            }
+          float d = acc * inv;
+          if (d <= thr) {
+            dd[m] = d;
+            ii[m] = y * I + x;
+            m++;
+          }
+        }
+      }
+      /* the n2 smallest by (d, index), selection in order */
+      int take = m < n2 ? m : n2;
+      for (int k = 1; k < take; k++) {
+        int best = k;
+        for (int e = k + 1; e < m; e++)
+          if (dd[e] < dd[best] || (dd[e] == dd[best] && ii[e] < ii[best])) best = e;
+        float td = dd[k]; dd[k] = dd[best]; dd[best] = td;
+        int32_t ti = ii[k]; ii[k] = ii[best]; ii[best] = ti;
+      }
+      int g = 1;
+      while (2 * g <= take) g *= 2;
+      gsize[q] = g;
+      for (int k = 0; k < n2; k++) grp[(int64_t)q * n2 + k] = k < g ? ii[k] : -1;
+    }
+    free(dd);
+    free(ii);
+  }
+}
+
+/* Forward 3D transform of every group in FP32 -- per block the separable
+ * 2D transform T1[u][v] = sum_k D[u][k] B[k][v], C[u][v] = sum_k T1[u][k]
+ * D[v][k] (k ascending, each product rounded, then added), then along the
+ * group the orthonormal Haar pyramid: at each level of length L the pairs
+ * (2i, 2i+1) give ((a + b) c, (a - b) c), c = FP32(1/sqrt 2), sums first
+ * then differences -- and the hard-threshold decision |coefficient| > thr.
+ * keep: n_ref * n2 * n1 * n1 bytes (the group's first gsize blocks used),
+ * nkeep: per group the number of surviving coefficients. */
+void oracle_bm3d_keep(int I, const float *r, int n1, int n2, int n_ref, const int32_t *grp,
+                      const int32_t *gsize, const float *D, float thr, uint8_t *keep,
+                      int32_t *nkeep) {
+  const float c = (float)0.70710678118654752440;
+  const int bs = n1 * n1;
+#pragma omp parallel
+  {
+    float *G = (float *)malloc(sizeof(float) * n2 * bs);
+    float *T = (float *)malloc(sizeof(float) * n2 * bs);
+    float *T1 = (float *)malloc(sizeof(float) * bs);
+#pragma omp for schedule(dynamic, 4)
+    for (int q = 0; q < n_ref; q++) {
+      const int n = gsize[q];
+      for (int b = 0; b < n; b++) {
+        const int p = grp[(int64_t)q * n2 + b], y0 = p / I, x0 = p % I;
+        for (int u = 0; u < n1; u++)
+          for (int v = 0; v < n1; v++) {
+            float acc = 0.0f;
+            for (int k = 0; k < n1; k++) {
+              float t = D[u * n1 + k] * r[(y0 + k) * I + x0 + v];
+              acc = acc + t;
+            }
+            T1[u * n1 + v] = acc;
+          }
+        for (int u = 0; u < n1; u++)
+          for (int v = 0; v < n1; v++) {
+            float acc = 0.0f;
+            for (int k = 0; k < n1; k++) {
+              float t = T1[u * n1 + k] * D[v * n1 + k];
+              acc = acc + t;
+            }
+            G[b * bs + u * n1 + v] = acc;
+          }
+      }
+      for (int L = n; L > 1; L /= 2) {
+        for (int i = 0; i < L / 2; i++)
+          for (int e = 0; e < bs; e++) {
+            float a = G[(2 * i) * bs + e], b = G[(2 * i + 1) * bs + e];
+            float s = a + b, d = a - b;
+            T[i * bs + e] = s * c;
+            T[(L / 2 + i) * bs + e] = d * c;
+          }
+        memcpy(G, T, sizeof(float) * L * bs);
+      }
+      int cnt = 0;
+      uint8_t *kq = keep + (int64_t)q * n2 * bs;
+      for (int e = 0; e < n2 * bs; e++) kq[e] = 0;
+      for (int e = 0; e < n * bs; e++) {
+        uint8_t k = fabsf(G[e]) > thr;
+        kq[e] = k;
+        cnt += k;
+      }
+      nkeep[q] = cnt;
+    }
+    free(G);
+    free(T);
+    free(T1);
+  }
+}
