@@ -105,7 +105,35 @@ dg_status ct_project(const dg_plan* plan, const float* img, const float* img_t,
 dg_status ct_backproject(const dg_plan* plan, const float* sino, float* img,
                          void* stream);
 
-/* Cone preconditioner (Sec. 2.3, eq. PPFT preconditioner; eq. Aprecon):
+/* Fourier-slice Radon operator (Sec. 2.4, eq. Radon_op: A = F_gamma^-1
+ * Omega F), the paper's O(N log N) operator model, for parallel-beam
+ * geometries: the image as point masses h^2 mu_ij at the pixel centres of
+ * the ray-driven grid; view k samples its 2D Fourier transform along
+ * rho (cos theta_k, sin theta_k) at rho_m = (m - floor(n_bins/2)) /
+ * (n_bins bin_mm), m < n_bins, and the radial inverse DFT returns
+ *   sino_k(b) = Re (1/(n_bins bin_mm)) sum_m P_k(m) exp(2 pi i rho_m s_b),
+ *   s_b = (b - (n_bins - 1)/2) bin_mm
+ * (line integrals of the band-limited image; a unit pixel at the origin
+ * gives h at the central bin when bin_mm = h).  Computed as a non-uniform
+ * FFT: deapodised image on a 2I x 2I grid, 2D FFT, Kaiser-Bessel
+ * interpolation of width 8 at the polar samples (relative error ~1e-8
+ * before FP32 rounding), direct radial DFT.  ct_backproject_fourier is its
+ * exact adjoint (the transposed steps; a deterministic gather onto the grid).
+ * The operator object holds the interpolation weights and the adjoint's
+ * sparse table (about 8 * 81 * n_views * n_bins bytes) on the current device.
+ * Image side: a power of two in [8, 512]; n_bins >= 2, n_views * n_bins
+ * <= 2^22 (else DG_ERR_ARG).  img: I*I floats, sino:
+ * n_views*n_bins floats (view-major), work: dg_fourier_workspace_bytes.    */
+typedef struct dg_fourier dg_fourier;
+dg_status dg_fourier_create(const dg_geom* g, dg_fourier** out);
+dg_status dg_fourier_destroy(dg_fourier* f);
+size_t dg_fourier_workspace_bytes(const dg_fourier* f);
+dg_status ct_project_fourier(const dg_fourier* f, const float* img, float* sino, void* work,
+                             void* stream);
+dg_status ct_backproject_fourier(const dg_fourier* f, const float* sino, float* img, void* work,
+                                 void* stream);
+
+/* Cone preconditioner (Sec. 2.4, eq. PPFT preconditioner; eq. Aprecon):
  * V = F^-1 C^(1/2) F with C = diag(1/|rho|) on the unpadded I x I DFT grid,
  * |rho| in cycles per pixel, DC value 4 ln(1+sqrt 2) I (the mean of 1/|rho|
  * over the central DFT cell).
@@ -159,6 +187,20 @@ dg_status gamp_poisson_out(int64_t m, const float* p, const float* y, const doub
  *                dg_tvw_workspace_bytes(I) bytes (device, caller-owned,
  *                overwritten by every call).  The side I must be one the FFT
  *                supports (2^a or 3 * 2^a, <= 1024), else DG_ERR_ARG.
+ *   DG_DEN_BM3D: two-stage block-matching 3D filter (the paper's denoiser,
+ *                Dabov et al. 2007): 8x8 blocks on a step-3 grid, groups of
+ *                the reference block and up to 15 others within +-19 pixels
+ *                with mean squared difference <= 4.8 sigma^2 (by distance,
+ *                then raster position; a power of two), 8x8 DCT + Haar along
+ *                the group, hard threshold 2.7 sigma with 1/(sigma^2 N_har)
+ *                weights, then the Wiener stage on the same groups with
+ *                1/(sigma^2 ||W||^2) weights, Kaiser-window (beta 2)
+ *                aggregation; sigma = sqrt(tau_r).  The decisions (distances,
+ *                threshold tests) are FP32 in a fixed order; the aggregation
+ *                sums by FP32 atomics (reproducible to rounding, not bit for
+ *                bit).  Params: dg_bm3d_params with work of
+ *                dg_bm3d_workspace_bytes(I) bytes (device, caller-owned,
+ *                overwritten by every call); 16 <= I <= 4096.
  * r, x_out: I*I floats; tau_r: device double; div_out: device double or NULL
  * (NULL skips the probe evaluation).  work: dg_workspace_bytes(DG_OP_DENOISE). */
 #define DG_DEN_HAAR 0
@@ -166,6 +208,7 @@ dg_status gamp_poisson_out(int64_t m, const float* p, const float* y, const doub
 #define DG_DEN_CNN 2
 #define DG_DEN_TV 3
 #define DG_DEN_TVW 4
+#define DG_DEN_BM3D 5
 typedef struct dg_haar_params { double alpha; int32_t levels; /* 0 = log2 I - 2 */ } dg_haar_params;
 typedef struct dg_nlm_params { int32_t patch_radius; int32_t search_radius; double hfac; } dg_nlm_params;
 typedef struct dg_cnn_params {
@@ -182,6 +225,11 @@ typedef struct dg_tv_params {
   void* work;      /* device: dg_tv_workspace_bytes(I*I) bytes for TV,           */
                    /* dg_tvw_workspace_bytes(I) for TVW                          */
 } dg_tv_params;
+typedef struct dg_bm3d_params {
+  void* work;      /* device: dg_bm3d_workspace_bytes(I) bytes                  */
+} dg_bm3d_params;
+/* Work bytes of DG_DEN_BM3D for an I x I image (0 for side < 8). */
+size_t dg_bm3d_workspace_bytes(int32_t side);
 size_t dg_tv_workspace_bytes(int64_t n_pixels);
 /* Work bytes of DG_DEN_TVW for an I x I image (0 for side <= 0). */
 size_t dg_tvw_workspace_bytes(int32_t side);

@@ -16,7 +16,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libdgampct.so")
 
 PARALLEL, FAN = 0, 1
-DEN_HAAR, DEN_NLM, DEN_CNN, DEN_TV, DEN_TVW = 0, 1, 2, 3, 4
+DEN_HAAR, DEN_NLM, DEN_CNN, DEN_TV, DEN_TVW, DEN_BM3D = 0, 1, 2, 3, 4, 5
 CHANNEL_LAPLACE, CHANNEL_MODE_ONLY = 0, 1
 OP_PRECOND, OP_DENOISE, OP_DGAMP, OP_FRO2, OP_SE = 0, 1, 2, 3, 4
 SE_LOG_MSE = 5
@@ -40,7 +40,8 @@ EXPORTS = ("dg_plan_create", "dg_plan_destroy", "dg_workspace_bytes", "dg_channe
            "dg_batch_set_projector_variant", "dg_plan_set_projector_variant",
            "dg_psnr_workspace_bytes", "dg_psnr", "dg_tv_workspace_bytes", "dg_tvw_workspace_bytes",
            "dg_check_status", "dg_noalloc_scratch_bytes", "dgamp_iterate_noalloc",
-           "dgamp_state_evolution")
+           "dgamp_state_evolution", "dg_bm3d_workspace_bytes", "dg_fourier_create", "dg_fourier_destroy",
+           "dg_fourier_workspace_bytes", "ct_project_fourier", "ct_backproject_fourier")
 
 
 class DgError(RuntimeError):
@@ -71,6 +72,10 @@ class CnnParams(ctypes.Structure):
 class TvParams(ctypes.Structure):
     _fields_ = [("alpha", ctypes.c_double), ("iters", ctypes.c_int32), ("metric", ctypes.c_int32),
                 ("work", ctypes.c_void_p)]
+
+
+class Bm3dParams(ctypes.Structure):
+    _fields_ = [("work", ctypes.c_void_p)]
 
 
 class DgampOpts(ctypes.Structure):
@@ -148,6 +153,12 @@ def load():
         "dg_tvw_workspace_bytes": ([i32], sz),
         "dg_check_status": ([_VP, i32, ctypes.POINTER(i32), ctypes.POINTER(i32), _VP], i32),
         "dg_noalloc_scratch_bytes": ([], sz),
+        "dg_bm3d_workspace_bytes": ([i32], sz),
+        "dg_fourier_create": ([ctypes.POINTER(Geom), ctypes.POINTER(_VP)], i32),
+        "dg_fourier_destroy": ([_VP], i32),
+        "dg_fourier_workspace_bytes": ([_VP], sz),
+        "ct_project_fourier": ([_VP, _VP, _VP, _VP, _VP], i32),
+        "ct_backproject_fourier": ([_VP, _VP, _VP, _VP, _VP], i32),
         "dgamp_state_evolution": ([_VP, _VP, _VP, _VP, _VP, _VP, ctypes.POINTER(DgampOpts), dbl,
                                    _VP, _VP, _VP, _VP], i32),
         "dgamp_iterate_noalloc": ([_VP, _VP, ctypes.POINTER(DgampOpts), ctypes.POINTER(DgampStateC),
@@ -308,6 +319,13 @@ def make_params(kind, **kw):
                        metric=kw.get("metric", 0), work=ctypes.c_void_p(buf.data_ptr()))
         prm._buf = buf
         return prm
+    if kind == DEN_BM3D:
+        # groups, accumulators and the basic estimate live as long as the params object
+        buf = torch.empty(max(int(load().dg_bm3d_workspace_bytes(int(kw["side"]))), 256),
+                          dtype=torch.uint8, device="cuda")
+        prm = Bm3dParams(work=ctypes.c_void_p(buf.data_ptr()))
+        prm._buf = buf
+        return prm
     raise DgError("unknown denoiser kind")
 
 
@@ -372,6 +390,45 @@ def dgamp_iterate(plan, y, state, n_iter, fro2, i0, den_kind, den_params, probe_
                               _ptr(log, torch.float64, None, "log"),
                               _ptr(work, torch.uint8, None, "work"), _stream()))
     return mu_out
+
+
+class FourierOp:
+    """The Fourier-slice Radon operator of a parallel-beam geometry (device tables)."""
+
+    def __init__(self, geom):
+        g = Geom(**{k: geom[k] for k, _ in Geom._fields_})
+        h = _VP()
+        _check(_lib.dg_fourier_create(ctypes.byref(g), ctypes.byref(h)))
+        self._h = h
+        self.I, self.nv, self.nb = geom["n"], geom["n_views"], geom["n_bins"]
+        self.work = torch.empty(max(int(_lib.dg_fourier_workspace_bytes(h)), 256), dtype=torch.uint8,
+                                device="cuda")
+
+    def __del__(self):
+        try:
+            if getattr(self, "_h", None) and _lib is not None:
+                _lib.dg_fourier_destroy(self._h)
+                self._h = None
+        except Exception:
+            pass
+
+
+def ct_project_fourier(op, img, sino=None):
+    if sino is None:
+        sino = torch.empty((op.nv, op.nb), dtype=torch.float32, device="cuda")
+    _check(_lib.ct_project_fourier(op._h, _ptr(img, torch.float32, op.I * op.I, "img"),
+                                   _ptr(sino, torch.float32, op.nv * op.nb, "sino"),
+                                   _ptr(op.work, torch.uint8, None, "work"), _stream()))
+    return sino
+
+
+def ct_backproject_fourier(op, sino, img=None):
+    if img is None:
+        img = torch.empty((op.I, op.I), dtype=torch.float32, device="cuda")
+    _check(_lib.ct_backproject_fourier(op._h, _ptr(sino, torch.float32, op.nv * op.nb, "sino"),
+                                       _ptr(img, torch.float32, op.I * op.I, "img"),
+                                       _ptr(op.work, torch.uint8, None, "work"), _stream()))
+    return img
 
 
 def dgamp_state_evolution(plan, z, x, y, n, v, n_iter, fro2, i0, den_kind, den_params,
