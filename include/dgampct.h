@@ -194,7 +194,8 @@ dg_status gamp_poisson_out(int64_t m, const float* p, const float* y, const doub
  *                then raster position; a power of two), 8x8 DCT + Haar along
  *                the group, hard threshold 2.7 sigma with 1/(sigma^2 N_har)
  *                weights, then the Wiener stage on the same groups with
- *                1/(sigma^2 ||W||^2) weights, Kaiser-window (beta 2)
+ *                1/(sigma^2 ||W||^2) weights (1 where every factor vanishes),
+ *                Kaiser-window (beta 2)
  *                aggregation; sigma = sqrt(tau_r).  The decisions (distances,
  *                threshold tests) are FP32 in a fixed order; the aggregation
  *                sums by FP32 atomics (reproducible to rounding, not bit for

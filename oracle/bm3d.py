@@ -20,7 +20,10 @@ input r and noise level sigma = sqrt(tau_r):
   Stage 2 (Wiener).  The same groups; the 3D transforms of the noisy blocks
   T_n and of the basic estimate's blocks T_b give the empirical Wiener
   shrinkage W = T_b^2 / (T_b^2 + sigma^2) applied to T_n; weight
-  1 / (sigma^2 ||W||^2) times the Kaiser window; the result is D(r).
+  1 / (sigma^2 ||W||^2) (1 when every factor vanishes, the basic estimate
+  being zero on the whole group -- the first stage's rule for a group
+  without surviving coefficients) times the Kaiser window; the result is
+  D(r).
 
 Readings (the paper names BM3D only; the values are the normal profile of
 Dabov et al. for sigma up to 40 on the 8-bit scale):
@@ -178,7 +181,8 @@ def bm3d(r, tau_r):
         Tn = transform3d(_blocks(r, grp[q, :n], I), D)
         Tb = transform3d(_blocks(yb, grp[q, :n], I), D)
         W = Tb * Tb / (Tb * Tb + sigma2)
-        w = 1.0 / (sigma2 * float(np.sum(W * W)))
+        wsq = float(np.sum(W * W))
+        w = 1.0 / (sigma2 * wsq) if wsq > 0.0 else 1.0
         est2.append((inverse3d(W * Tn, D), w))
     return _aggregate(I, grp, gsize, est2)
 

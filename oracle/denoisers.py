@@ -22,6 +22,9 @@ build's, the paper treats D as a black box):
     approximated by a fixed number K of fast gradient projection steps on
     the dual problem (Beck & Teboulle 2009): the map D is those K steps.
 
+  * bm3d: the two-stage block-matching 3D filter (module ``bm3d``), the
+    paper's own denoiser; its decisions are taken on the FP32 input.
+
   * prox_tv_w: the same proximal map in the (V^T V)^-1 metric (Sec. 4.3 and
     Sec. 6 name it for input in the preconditioned domain),
     x = argmin 1/2 ||x - r||^2_W + lam TV(x), W = (V^T V)^-1 = 1/c on the DFT
@@ -53,6 +56,7 @@ NLM = 1
 CNN = 2
 TV = 3
 TVW = 4
+BM3D = 5
 
 SQ2 = math.sqrt(2.0)
 
@@ -258,11 +262,18 @@ def apply(kind, r, tau_r, params):
         return prox_tv(r, tau_r, **params)
     if kind == TVW:
         return prox_tv_w(r, tau_r, **params)
+    if kind == BM3D:
+        from . import bm3d
+        return bm3d.bm3d(np.asarray(r, dtype=np.float32), tau_r)
     raise ValueError("unknown denoiser kind")
 
 
 def mc_divergence(kind, r, tau_r, params, x_out, seed, t, eps_rel=1e-3):
     """eq. MC_SURE with K = 1 Rademacher probe; eps = eps_rel * max|r|."""
+    if kind == BM3D:
+        # BM3D takes its decisions on the FP32 input: the perturbed input is formed in FP32
+        from . import bm3d
+        return bm3d.mc_divergence(r, tau_r, x_out, seed, t, eps_rel)
     r = np.asarray(r, dtype=np.float64)
     N = r.size
     b = rademacher(seed, t, N).reshape(r.shape)

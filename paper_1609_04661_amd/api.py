@@ -25,6 +25,8 @@ NSCAL = 16
 S_TAU_X, S_TAU_P, S_TAU_S, S_TAU_R, S_DIV, S_EPS, S_STATUS, S_CLAMPS = range(8)
 LOG_STRIDE = 8
 LOG_FIELDS = ("tau_p", "tau_s", "tau_r", "div", "tau_x", "eps", "status", "clamps")
+# column of each field in a per-iteration log record (not the scalar-block indices S_*)
+LOG_TAU_P, LOG_TAU_S, LOG_TAU_R, LOG_DIV, LOG_TAU_X, LOG_EPS, LOG_STATUS = range(7)
 NPHASES = 7
 PHASES = ("precond_x", "project", "channel", "backproject", "precond_g_update", "denoise", "div")
 

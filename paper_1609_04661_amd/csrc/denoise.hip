@@ -27,6 +27,10 @@ dg_status tv_launch_denoise(const dg_plan* p, const void* params, const float* r
                             float* x_den, float* x_pert, hipStream_t st);
 // proximal TV in the (V^T V)^-1 metric (tvw.hip)
 dg_status tvw_check_params(const dg_plan* p, const void* params);
+dg_status bm3d_check_params(const dg_plan* p, const void* params);
+dg_status bm3d_launch_denoise(const dg_plan* p, const void* params, const float* r,
+                              const double* tau_r, const double* eps, uint64_t seed, int iter,
+                              float* x_den, float* x_pert, hipStream_t st);
 dg_status tvw_launch_denoise(const dg_plan* p, const void* params, const float* r,
                              const double* tau_r, const double* eps, uint64_t seed, int iter,
                              float* x_den, float* x_pert, hipStream_t st);
@@ -531,6 +535,8 @@ dg_status check_denoise_params(const dg_plan* p, int kind, const void* params) {
     return tv_check_params(p, params);
   } else if (kind == DG_DEN_TVW) {
     return tvw_check_params(p, params);
+  } else if (kind == DG_DEN_BM3D) {
+    return bm3d_check_params(p, params);
   } else if (kind == DG_DEN_CNN) {
     set_error("denoise: CNN kind is dispatched by the CNN module");
     return DG_ERR_UNSUPPORTED;
@@ -586,6 +592,8 @@ dg_status launch_denoiser(const dg_plan* p, int kind, const void* params, const 
     return tv_launch_denoise(p, params, r, tau_r, eps, seed, iter, x_den, x_pert, st);
   if (kind == DG_DEN_TVW)
     return tvw_launch_denoise(p, params, r, tau_r, eps, seed, iter, x_den, x_pert, st);
+  if (kind == DG_DEN_BM3D)
+    return bm3d_launch_denoise(p, params, r, tau_r, eps, seed, iter, x_den, x_pert, st);
   if (kind == DG_DEN_HAAR) {
     const dg_haar_params* hp = (const dg_haar_params*)params;
     const int J = haar_levels(p, hp);

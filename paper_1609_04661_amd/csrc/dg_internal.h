@@ -94,6 +94,8 @@ struct dg_plan {
   int fft_ok;            // I supported by the FFT kernels
   double half_diag_px;   // sqrt(2)/2 (fan candidate search)
   int proj_variant;      // index into kProjSegVariants (autotuned; default 1)
+  float* bm3d_tab;       // device, 72: the orthonormal 8-point DCT-II matrix D[u][k]
+                         // (FP64 cosines rounded to FP32) then the 8-point Kaiser window
 };
 
 namespace dg {

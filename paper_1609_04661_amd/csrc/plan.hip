@@ -171,11 +171,33 @@ extern "C" dg_status dg_plan_create(const dg_geom* g, dg_plan** out) {
     tw[t] = make_float2((float)std::cos(a), (float)std::sin(a));
   }
 
+  // block-matching denoiser tables: orthonormal DCT-II of length 8,
+  // D[u][k] = a_u cos(pi (2k + 1) u / 16), then the Kaiser window of beta 2,
+  // K[n] = I0(beta sqrt(1 - (2n/7 - 1)^2)) / I0(beta)
+  std::vector<float> bt(72);
+  for (int u = 0; u < 8; ++u)
+    for (int k = 0; k < 8; ++k)
+      bt[u * 8 + k] = (float)((u == 0 ? std::sqrt(1.0 / 8.0) : std::sqrt(2.0 / 8.0)) *
+                              std::cos(M_PI * (2 * k + 1) * u / 16.0));
+  auto i0 = [](double x) {
+    double sum = 1.0, t = 1.0, q = 0.25 * x * x;
+    for (int k = 1; k < 100; ++k) {
+      t *= q / ((double)k * k);
+      sum += t;
+    }
+    return sum;
+  };
+  for (int n = 0; n < 8; ++n) {
+    const double a = 2.0 * n / 7.0 - 1.0;
+    bt[64 + n] = (float)(i0(2.0 * std::sqrt(1.0 - a * a)) / i0(2.0));
+  }
+
   hipError_t e;
   p->rays = nullptr;
   p->views = nullptr;
   p->twiddle = nullptr;
   p->vrays = nullptr;
+  p->bm3d_tab = nullptr;
   // parallel beam: per-view slope terms and bin progression for the back-projector
   std::vector<ViewRay> vr;
   if (g->kind == DG_GEOM_PARALLEL) {
@@ -189,6 +211,7 @@ extern "C" dg_status dg_plan_create(const dg_geom* g, dg_plan** out) {
   if ((e = hipMalloc(&p->rays, sizeof(RayLine) * rays.size())) != hipSuccess ||
       (e = hipMalloc(&p->views, sizeof(ViewInfo) * views.size())) != hipSuccess ||
       (e = hipMalloc(&p->twiddle, sizeof(float2) * tw.size())) != hipSuccess ||
+      (e = hipMalloc(&p->bm3d_tab, sizeof(float) * bt.size())) != hipSuccess ||
       (!vr.empty() && (e = hipMalloc(&p->vrays, sizeof(ViewRay) * vr.size())) != hipSuccess)) {
     dg_plan_destroy(p);
     hip_fail(e, "dg_plan_create: hipMalloc");
@@ -199,6 +222,8 @@ extern "C" dg_status dg_plan_create(const dg_geom* g, dg_plan** out) {
       (e = hipMemcpy(p->views, views.data(), sizeof(ViewInfo) * views.size(),
                      hipMemcpyHostToDevice)) != hipSuccess ||
       (e = hipMemcpy(p->twiddle, tw.data(), sizeof(float2) * tw.size(), hipMemcpyHostToDevice)) !=
+          hipSuccess ||
+      (e = hipMemcpy(p->bm3d_tab, bt.data(), sizeof(float) * bt.size(), hipMemcpyHostToDevice)) !=
           hipSuccess ||
       (!vr.empty() && (e = hipMemcpy(p->vrays, vr.data(), sizeof(ViewRay) * vr.size(),
                                      hipMemcpyHostToDevice)) != hipSuccess)) {
@@ -213,6 +238,7 @@ extern "C" dg_status dg_plan_destroy(dg_plan* p) {
   if (!p) return DG_OK;
   if (p->rays) (void)hipFree(p->rays);
   if (p->views) (void)hipFree(p->views);
+  if (p->bm3d_tab) (void)hipFree(p->bm3d_tab);
   if (p->twiddle) (void)hipFree(p->twiddle);
   if (p->vrays) (void)hipFree(p->vrays);
   delete p;

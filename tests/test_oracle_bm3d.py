@@ -95,3 +95,10 @@ def test_bm3d_denoises_and_its_divergence_is_unbiased_in_the_mean():
     assert np.mean((x - clean) ** 2) < 0.4 * np.mean((r - clean) ** 2)
     div, eps = bm3d.mc_divergence(r, s2, x, 5, 0)
     assert 0.0 < div < 1.0
+
+
+def test_group_with_vanishing_basic_estimate_gets_unit_weight():
+    # zero input: every stage-1 coefficient is cut, the basic estimate is zero, every Wiener
+    # factor vanishes; the defined weight keeps the output finite (and zero)
+    out = bm3d.bm3d(np.zeros((24, 24), dtype=np.float32), 0.5)
+    assert np.all(np.isfinite(out)) and np.max(np.abs(out)) == 0.0
