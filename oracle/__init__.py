@@ -11,7 +11,7 @@ Passing" (arXiv 1609.04661), cited by section / equation / algorithm:
 
   geometry   ray lines of the parallel and fan acquisitions (Sec. 2.1)
   radon      exact-chord system matrix A and A^T (Sec. 2.1, eq. linCT)
-  precond    cone preconditioner V, V^-1 (Sec. 2.3, eqs. PPFT preconditioner,
+  precond    cone preconditioner V, V^-1 (Sec. 2.4, eqs. PPFT preconditioner,
              Aprecon, GramATA)
   channel    Poisson output channel of GAMP: mode, Laplace moments, s, tau_s
              (Sec. 4.2, eqs. MMSEmm / post_exp, Appendix A)

@@ -1,6 +1,6 @@
 """Cone preconditioner V = F^-1 C^(1/2) F and its inverse, FP64 (test infrastructure).
 
-Sec. 2.3, eq. PPFT preconditioner: C = diag(1/|rho|) on the 2D DFT grid,
+Sec. 2.4, eq. PPFT preconditioner: C = diag(1/|rho|) on the 2D DFT grid,
 |rho| = sqrt(a^2 + b^2); eq. Aprecon: A~ = A V^-1 = ... C^(-1/2) F, so V^-1
 multiplies the spectrum by |rho|^(1/2) (the "cone" high-pass) and V by
 |rho|^(-1/2).  eq. GramATA: A~^T A~ is (approximately) the identity.

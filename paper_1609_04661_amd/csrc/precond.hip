@@ -1,4 +1,4 @@
-// Cone preconditioner V^-1 / V (Sec. 2.3, eq. PPFT preconditioner and eq.
+// Cone preconditioner V^-1 / V (Sec. 2.4, eq. PPFT preconditioner and eq.
 // Aprecon): a circulant filter on the I x I grid, applied as
 //   rows  : real-to-complex row transforms, two rows per complex FFT
 //   cols  : for each of the I/2+1 retained column frequencies, FFT down the

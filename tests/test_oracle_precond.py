@@ -1,4 +1,4 @@
-"""Pins of the oracle's cone preconditioner (Sec. 2.3, eqs. PPFT preconditioner, Aprecon, GramATA)."""
+"""Pins of the oracle's cone preconditioner (Sec. 2.4, eqs. PPFT preconditioner, Aprecon, GramATA)."""
 import math
 
 import numpy as np
