@@ -4,13 +4,25 @@ Training pairs are (x + sigma psi, x) with x = V mu the preconditioned image
 of a synthetic ellipse + texture phantom (the space the plug-in denoiser of
 Sec. 4.3 works in), psi white Gaussian noise and sigma drawn log-uniformly
 from the range of sqrt(tau_r) that plain D-GAMP-CT runs produce on the same
-workload.  Every forward, backward and Adam step runs in the HIP kernels
-(dg_cnn_train_step); phantoms come from ``synth`` on host cores and are
-preconditioned on the GPU (ct_precondition).
+workload: the 512 x 512, 64-view, I0 = 1e5 run with the patch-based
+denoiser (damping 0.15, 50 iterations; its per-iteration log is stored in
+tests/golden/c2.npz, column tau_r) has sqrt(tau_r) from 2.47 at its first
+iteration down to 0.027 at its 50th, and [0.02, 2.5] covers it.
+Every forward, backward and Adam step runs in the HIP kernels
+(dg_cnn_train_step); phantoms come from ``synth`` on host cores (a worker
+pool forked before the GPU is touched, streamed in chunks) and are
+preconditioned on the GPU (ct_precondition) as they arrive.
 
-    python -m paper_1609_04661_amd.train --phantoms 256 --steps 2000 --out weights.safetensors
+The shipped weights were made by
+
+    python -m paper_1609_04661_amd.train --phantoms 20000 --steps 4000
+
+(20000 phantoms from seed 1004 * 10^6 + k, batches of 16 random 128 x 128
+crops with flips, Adam with cosine decay from 1e-3); the run's record is
+weights/cnn_c2_x_space.json.
 """
 import argparse
+import json
 import math
 import multiprocessing as mp
 import os
@@ -35,25 +47,29 @@ def _phantom(args):
     return synth.ellipse_phantom(n, seed).astype(np.float32)
 
 
-def make_phantoms(n_phantoms, side=512, procs=None):
-    """Phantoms on host cores.  Call before the process touches the GPU: the
-    worker pool is forked, and a forked child must not inherit a live GPU
-    context."""
+def make_dataset(n_phantoms, side=512, procs=None, chunk=256):
+    """x = V mu for every phantom, as a (n, side, side) CUDA tensor.  The
+    phantoms are drawn on host cores by a worker pool that is forked before
+    this process touches the GPU; chunks of them are preconditioned on the
+    GPU as they arrive, so the host holds at most a chunk at a time."""
     procs = procs or min(16, os.cpu_count() or 1)
-    with mp.get_context("fork").Pool(procs) as pool:
-        return pool.map(_phantom, [(side, TRAIN_SEED_BASE + k) for k in range(n_phantoms)])
-
-
-def make_dataset(mus):
-    """x = V mu for every phantom, as a (n, side, side) CUDA tensor."""
-    n_phantoms, side = len(mus), mus[0].shape[0]
-    g = synth.geometry(synth.PARALLEL, side, 1.0, 1, side + 1, math.pi)
-    plan = api.Plan(g)
-    work = plan.workspace(api.OP_PRECOND)
-    xs = torch.empty((n_phantoms, side, side), dtype=torch.float32, device="cuda")
-    for k, mu in enumerate(mus):
-        api.ct_precondition(plan, -1, torch.from_numpy(mu).cuda(), out=xs[k], work=work)
-    torch.cuda.synchronize()
+    jobs = [(side, TRAIN_SEED_BASE + k) for k in range(n_phantoms)]
+    pool = mp.get_context("fork").Pool(procs)
+    try:
+        torch.cuda.set_device(0)
+        api.load()
+        g = synth.geometry(synth.PARALLEL, side, 1.0, 1, side + 1, math.pi)
+        plan = api.Plan(g)
+        work = plan.workspace(api.OP_PRECOND)
+        xs = torch.empty((n_phantoms, side, side), dtype=torch.float32, device="cuda")
+        for k, mu in enumerate(pool.imap(_phantom, jobs, chunksize=max(1, chunk // procs))):
+            api.ct_precondition(plan, -1, torch.from_numpy(mu).cuda(), out=xs[k], work=work)
+            if (k + 1) % 2000 == 0:
+                print("phantoms %d / %d" % (k + 1, n_phantoms), flush=True)
+        torch.cuda.synchronize()
+    finally:
+        pool.close()
+        pool.join()
     return xs
 
 
@@ -81,14 +97,10 @@ def sample_batch(xs, batch, crop, sig_lo, sig_hi, gen):
     return noisy, clean
 
 
-def train(n_phantoms=256, steps=2000, batch=16, crop=128, lr=1e-3, sig_lo=0.02, sig_hi=2.5,
+def train(n_phantoms=20000, steps=4000, batch=16, crop=128, lr=1e-3, sig_lo=0.02, sig_hi=2.5,
           seed=0, out=DEFAULT_WEIGHTS, log_every=100, init_scale=0.5):
     t0 = time.time()
-    mus = make_phantoms(n_phantoms)
-    torch.cuda.set_device(0)
-    api.load()
-    xs = make_dataset(mus)
-    del mus
+    xs = make_dataset(n_phantoms)
     t_data = time.time() - t0
     net = api.CnnNet(master=api.CnnNet.init_master(seed, scale=init_scale))
     gen = torch.Generator().manual_seed(seed)
@@ -108,13 +120,23 @@ def train(n_phantoms=256, steps=2000, batch=16, crop=128, lr=1e-3, sig_lo=0.02, 
     if out:
         os.makedirs(os.path.dirname(out), exist_ok=True)
         net.save(out)
+        cmd = ("python -m paper_1609_04661_amd.train --phantoms %d --steps %d --batch %d --crop %d "
+               "--lr %g --sig-lo %g --sig-hi %g --seed %d" % (n_phantoms, steps, batch, crop, lr,
+                                                            sig_lo, sig_hi, seed))
+        rec = dict(command=cmd,
+                   phantoms=n_phantoms, phantom_seeds="%d + k" % TRAIN_SEED_BASE, steps=steps,
+                   batch=batch, crop=crop, lr=lr, sigma_range=[sig_lo, sig_hi], seed=seed,
+                   data_s=round(t_data, 1), train_s=round(t_train, 1),
+                   loss_history=[(k, float("%.5g" % v)) for k, v in hist])
+        with open(os.path.splitext(out)[0] + ".json", "w") as f:
+            json.dump(rec, f, indent=1)
     return dict(net=net, history=hist, data_s=t_data, train_s=t_train)
 
 
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("--phantoms", type=int, default=256)
-    ap.add_argument("--steps", type=int, default=2000)
+    ap.add_argument("--phantoms", type=int, default=20000)
+    ap.add_argument("--steps", type=int, default=4000)
     ap.add_argument("--batch", type=int, default=16)
     ap.add_argument("--crop", type=int, default=128)
     ap.add_argument("--lr", type=float, default=1e-3)

@@ -110,8 +110,11 @@ def test_batch_nlm_equals_single_slices(gpu_lib, data):
 def test_batch_slice_matches_oracle(gpu_lib, data):
     """Slice 0 (64 x 64, 30 parallel views) of the batch against the FP64
     oracle's D-GAMP-CT with the same inputs: mu within 1e-3 relative L2 and
-    tau_r within 1e-3 relative after two iterations (the FP32 NLM output and
-    its MC divergence feed tau_x, hence tau_p, tau_s and tau_r)."""
+    tau_r within 1e-3 relative after two iterations.  A regression bound, not
+    a derived one: at this slice's first iteration (tau_r ~ 1.5) NLM barely
+    moves with r, its divergence is ~1e-3, and the divergence's derived FP32
+    bound is half of that, so no useful bound on tau_r follows; the
+    full-size tests carry the derived bounds."""
     api = gpu_lib
     T = 2
     params = api.make_params(api.DEN_NLM)

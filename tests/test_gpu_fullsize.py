@@ -142,3 +142,38 @@ def test_check_status_reports_undamped_divergence(gpu_lib):
             assert status > 0 and rc == api.ERR_NUMERIC and fs == 0 and fi == int(status) - 1
         else:
             assert status == 0 and rc == 0 and fs == -1 and fi == -1
+
+
+def test_learned_denoiser_gains_over_plain(gpu_lib):
+    """The shipped CNN weights against the plain patch-based denoiser on the
+    headline inputs (same counts, probes, damping 0.15, 50 iterations): the
+    learned run ends at least 0.5 dB higher and reaches the plain run's final
+    PSNR in at most 40 of the 50 iterations."""
+    import os
+    api = gpu_lib
+    c, y, z = load_case("c2")
+    P = api.Plan(c["geom"])
+    yd = torch.as_tensor(y, dtype=torch.float32).cuda()
+    mu_true = torch.as_tensor(c["mu"], dtype=torch.float32).cuda()
+    weights = os.path.join(os.path.dirname(HERE), "paper_1609_04661_amd", "weights",
+                           "cnn_c2_x_space.safetensors")
+    net = api.CnnNet.load_file(weights)
+    runs = {"plain": (api.DEN_NLM, api.make_params(api.DEN_NLM)),
+            "learned": (api.DEN_CNN, api.make_params(api.DEN_CNN, net=net, n_pixels=P.N))}
+    curves = {}
+    mu = torch.empty((P.I, P.I), dtype=torch.float32, device="cuda")
+    for name, (kind, prm) in runs.items():
+        st = api.DgampState(P, 1.0)
+        ps = torch.empty(c["T"], dtype=torch.float64, device="cuda")
+        for t in range(c["T"]):
+            api.dgamp_iterate(P, yd, st, 1, float(z["fro2"]), c["i0"], kind, prm, probe_seed=7,
+                              eta_x=c["eta"], eta_s=c["eta"], mu_out=mu)
+            api.dg_psnr(mu, mu_true, out=ps[t:t + 1])
+        curves[name] = host(ps)
+        assert float(host(st.scal)[api.S_STATUS]) == 0.0
+    plain, learned = curves["plain"], curves["learned"]
+    reach = int(np.argmax(learned >= plain[-1])) + 1 if np.any(learned >= plain[-1]) else None
+    print("final psnr plain %.3f learned %.3f; learned reaches plain's final at iteration %s"
+          % (plain[-1], learned[-1], reach))
+    assert abs(plain[-1] - float(z["psnr"])) <= 0.1
+    assert learned[-1] >= plain[-1] + 0.5 and reach is not None and reach <= 40
