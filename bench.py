@@ -277,16 +277,18 @@ def headline(api, synth, args, mu, results):
     for _ in range(TIMED_RUNS):
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        st = run(K, events=ev.arr, log=log, mask=den_mask)
+        st = run(K, events=ev.arr, mask=den_mask)
         torch.cuda.synchronize()
         elapsed_runs.append(time.perf_counter() - t0)
         den_ms += [ev.ms(it * (api.NPHASES + 1) + den, it * (api.NPHASES + 1) + den + 1)
                    for it in range(K)]
     elapsed = statistics.median(elapsed_runs)
     status = float(st.scal[api.S_STATUS].item())
-    # untimed: the same iterations with every phase boundary marked
+    # untimed: the same iterations with every phase boundary marked and the
+    # per-iteration scalars logged (the log's copy kernel stays out of the
+    # timed runs)
     phase_ms = {name: [] for name in api.PHASES}
-    run(K, events=ev.arr)
+    run(K, events=ev.arr, log=log)
     torch.cuda.synchronize()
     for it in range(K):
         base = it * (api.NPHASES + 1)
@@ -337,7 +339,7 @@ def headline(api, synth, args, mu, results):
                                                log.view(K, api.LOG_STRIDE)[-1].cpu().numpy()])),
         "status": status,
     })
-    return dict(plan=plan, y=y, y_d=y_d, fro2=fro2, mu_d=mu_d, work=work, geom=geom)
+    return dict(plan=plan, y=y, y_d=y_d, fro2=fro2, mu_d=mu_d, work=work, geom=geom, z_d=z)
 
 
 def learned_vs_plain(api, args, h):
@@ -445,11 +447,57 @@ def ablation(api, h, T=50):
         px = px.cpu().numpy()
         with np.errstate(all="ignore"):
             mse_x = peak * peak / np.power(10.0, px / 10.0)
-            gap = 10.0 * np.log10(L[:, api.S_TAU_X] / mse_x)
+            gap = 10.0 * np.log10(L[:, api.LOG_TAU_X] / mse_x)
         ok = np.isfinite(gap[5:])
         out[name] = dict(psnr_db=psnr_mu, status=float(st.scal[api.S_STATUS].item()),
                          se_gap_db_mean=float(np.mean(gap[5:][ok])) if ok.any() else None,
                          se_gap_db_last=float(gap[-1]) if np.isfinite(gap[-1]) else None)
+        out[name]["_mse_x"] = mse_x
+        out[name]["_tau_r"] = L[:, api.LOG_TAU_R]
+    out["state_evolution"] = state_evolution(api, h, x_true, out, T)
+    for v in out.values():
+        v.pop("_mse_x", None)
+        v.pop("_tau_r", None)
+    return out
+
+
+def state_evolution(api, h, x_true, runs, T):
+    """The scalar state evolution (Sec. 4.4, eqs. SEasym / SE_matches, E_in,
+    A_in) on the headline phantom, run by the library's dgamp_state_evolution
+    with seeded standard-normal fields, beside the actual runs: the SE's
+    predicted noise level of r (xi_r = tau_r) and predicted MSE of the
+    denoiser's output E_in, against the actual run's tau_r and the actual MSE
+    of its iterate x^{t+1} (with damping the iterate mixes D(r^t) with x^t,
+    so the two MSEs differ in meaning; undamped they are the same quantity)."""
+    import numpy as np
+    import torch
+    plan, y_d, fro2 = h["plan"], h["y_d"], h["fro2"]
+    rng = np.random.default_rng(2024)
+    n = torch.as_tensor(rng.standard_normal(plan.M), dtype=torch.float32).cuda()
+    v = torch.as_tensor(rng.standard_normal(plan.N), dtype=torch.float32).cuda()
+    params = api.make_params(api.DEN_NLM, **CFG["nlm"])
+    z = h["z_d"].reshape(-1).contiguous()
+    out = {}
+    for name, eta in (("configured", CFG["eta"]), ("undamped", 1.0)):
+        L = api.dgamp_state_evolution(plan, z, x_true.reshape(-1), y_d, n, v, T, fro2, CFG["i0"],
+                                      api.DEN_NLM, params, probe_seed=CFG["probe_seed"],
+                                      eta_x=eta, eta_s=eta)
+        L = L.view(T, api.LOG_STRIDE).cpu().numpy()
+        e_in, tau_r_se = L[:, api.SE_LOG_MSE], L[:, api.LOG_TAU_R]
+        act = runs[name]
+        with np.errstate(all="ignore"):
+            gap = 10.0 * np.log10(e_in / act["_mse_x"])
+            gap_r = 10.0 * np.log10(tau_r_se / act["_tau_r"])
+        ok = np.isfinite(gap)
+        out[name] = dict(eta=eta, se_status=float(L[-1, api.LOG_STATUS]),
+                         se_mse_pred_every_5=[float("%.4g" % e) for e in e_in[4::5]],
+                         actual_mse_x_every_5=[float("%.4g" % e) for e in act["_mse_x"][4::5]],
+                         se_tau_r_every_5=[float("%.4g" % e) for e in tau_r_se[4::5]],
+                         actual_tau_r_every_5=[float("%.4g" % e) for e in act["_tau_r"][4::5]],
+                         mse_gap_db_mean=float(np.mean(gap[ok])) if ok.any() else None,
+                         mse_gap_db_last=float(gap[-1]) if np.isfinite(gap[-1]) else None,
+                         tau_r_gap_db_last=float(gap_r[-1]) if np.isfinite(gap_r[-1]) else None,
+                         actual_valid_iterations=int(ok.sum()))
     return out
 
 
