@@ -571,6 +571,104 @@ def proxtv(api, args, h, T=50):
     return out
 
 
+def paper_ops(api, synth, h, plain_psnr, T=50):
+    """The paper's own plug-in denoiser and its Fourier-slice operator.
+
+    * BM3D-D-GAMP-CT on the headline inputs (same counts, damping, probes),
+      time per iteration and PSNR beside the patch-based denoiser's run, and
+      one BM3D call with its Monte-Carlo divergence (two denoiser passes).
+    * The same method at the shape of the paper's own experiment (Sec. 6.1:
+      a 512 x 512 slice, fan beam, 102 of 1024 views over 360 degrees,
+      I0 = 1e5, about 10 iterations), on a synthetic phantom: seconds per
+      iteration beside the paper's CPU figure (context, not a target).
+    * The Fourier-slice operator pair (Sec. 2.4, eq. Radon_op) at the
+      headline geometry: time per call beside the ray-driven pair, and the
+      relative difference of the two models' projections of the phantom."""
+    import numpy as np
+    import torch
+    out = {}
+    plan, y_d, fro2, mu_d, work = h["plan"], h["y_d"], h["fro2"], h["mu_d"], h["work"]
+    I = plan.I
+    bm = api.make_params(api.DEN_BM3D, side=I)
+    mu_out = torch.empty((I, I), dtype=torch.float32, device="cuda")
+    ps = torch.empty(1, dtype=torch.float64, device="cuda")
+
+    def run(n):
+        st = api.DgampState(plan, CFG["tau_x0"])
+        api.dgamp_iterate(plan, y_d, st, n, fro2, CFG["i0"], api.DEN_BM3D, bm, mu_out=mu_out,
+                          work=work, probe_seed=CFG["probe_seed"], eta_x=CFG["eta"],
+                          eta_s=CFG["eta"])
+        return st
+    run(2)
+    s = sync_time(lambda: run(T), 3)
+    st = run(T)
+    api.dg_psnr(mu_out, mu_d, out=ps)
+    r = torch.rand((I, I), device="cuda") * 0.3
+    tau = torch.full((1,), 0.01, dtype=torch.float64, device="cuda")
+    dwork = plan.workspace(api.OP_DENOISE)
+    xo = torch.empty((I, I), dtype=torch.float32, device="cuda")
+    dv = torch.empty(1, dtype=torch.float64, device="cuda")
+    call = lambda: api.denoise(plan, api.DEN_BM3D, bm, r, tau, x_out=xo, div_out=dv, work=dwork)
+    call()
+    d_s = sync_time(call, 10)
+    out["bm3d_c2"] = dict(iterations=T, ms_per_iter=1e3 * s / T, iter_per_s=T / s,
+                          psnr_db=float(ps.item()), plain_patch_psnr_db=plain_psnr,
+                          status=float(st.scal[api.S_STATUS].item()),
+                          denoise_with_div_ms=1e3 * d_s,
+                          megapixel_per_s_per_pass=2 * I * I / d_s / 1e6)
+    # the paper's experiment shape
+    g = synth.geometry(synth.FAN, 512, 0.7, 102, 736, 2 * np.pi, dso_mm=600.0, ddo_mm=500.0)
+    P = api.Plan(g)
+    mu = synth.ellipse_phantom(512, CFG["seed"] + 7, pixel_mm=0.7, inserts=0)
+    m_d = torch.as_tensor(mu, dtype=torch.float32).cuda()
+    z = api.ct_project(P, m_d)
+    torch.cuda.synchronize()
+    y = torch.as_tensor(synth.poisson_counts(z.cpu().double().numpy(), 1e5, CFG["seed"] + 7),
+                        dtype=torch.float32).cuda()
+    f2 = float(api.dg_fro2_hutchinson(P, CFG["fro2_probes"], 99).item())
+    w2 = P.workspace(api.OP_DGAMP)
+    o2 = torch.empty((512, 512), dtype=torch.float32, device="cuda")
+    T2 = 50
+
+    def run2(n, psnr_at=()):
+        st2 = api.DgampState(P, CFG["tau_x0"])
+        curve = {}
+        done = 0
+        for t in sorted(set(psnr_at) | {n}):
+            api.dgamp_iterate(P, y, st2, t - done, f2, 1e5, api.DEN_BM3D, bm, mu_out=o2, work=w2,
+                              probe_seed=CFG["probe_seed"], eta_x=CFG["eta"], eta_s=CFG["eta"])
+            done = t
+            if t in psnr_at:
+                api.dg_psnr(o2, m_d, out=ps)
+                curve[t] = float(ps.item())
+        return st2, curve
+    run2(2)
+    s2 = sync_time(lambda: run2(T2), 3)
+    st2, curve = run2(T2, psnr_at=(10, T2))
+    out["bm3d_paper_shape"] = dict(geometry="fan 512x512 0.7 mm, 102 views over 360 deg, 736 bins, "
+                                            "D_so 600 / D_od 500 mm, I0 1e5",
+                                   iterations=T2, damping=CFG["eta"], s_per_iter=s2 / T2,
+                                   psnr_db_at={str(k): v for k, v in curve.items()},
+                                   status=float(st2.scal[api.S_STATUS].item()),
+                                   paper_cpu_s_per_iter="18-27 (8-core Xeon, MATLAB + ASTRA)")
+    # Fourier-slice operator
+    F = api.FourierOp(h["geom"])
+    zf = api.ct_project_fourier(F, mu_d)
+    zr = api.ct_project(plan, mu_d)
+    gf = api.ct_backproject_fourier(F, zf)
+    a_f = sync_time(lambda: [api.ct_project_fourier(F, mu_d, zf) for _ in range(20)], 5) / 20
+    at_f = sync_time(lambda: [api.ct_backproject_fourier(F, zf, gf) for _ in range(20)], 5) / 20
+    mu_t = mu_d.t().contiguous()
+    a_r = sync_time(lambda: [api.ct_project(plan, mu_d, mu_t, sino=zr) for _ in range(20)], 5) / 20
+    gr = torch.empty_like(gf)
+    at_r = sync_time(lambda: [api.ct_backproject(plan, zf, gr) for _ in range(20)], 5) / 20
+    torch.cuda.synchronize()
+    rel = float(torch.linalg.norm(zf - zr) / torch.linalg.norm(zr))
+    out["fourier_c2"] = dict(A_us=1e6 * a_f, At_us=1e6 * at_f, ray_A_us=1e6 * a_r,
+                             ray_At_us=1e6 * at_r, rel_diff_vs_ray_model=rel)
+    return out
+
+
 def run_batch(api, synth, slices, phantoms, den, T, reps, autotune, net=None):
     """One batch: counts from the library's projector, Hutchinson fro2 per
     slice, graph of the whole T-iteration run; returns timing and PSNRs."""
@@ -631,9 +729,10 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--only-headline", action="store_true",
                     help="skip the learned, batched and fan-beam figures")
-    ap.add_argument("--parts", default="headline,learned,batch,fan,ablation",
-                    help="comma-separated subset of headline,learned,batch,fan,ablation,proxtv "
-                         "(proxtv, the proximal-TV plug-ins with their alpha sweeps, is opt-in)")
+    ap.add_argument("--parts", default="headline,learned,batch,fan,ablation,paper_ops",
+                    help="comma-separated subset of headline,learned,batch,fan,ablation,paper_ops,"
+                         "proxtv (proxtv, the proximal-TV plug-ins with their alpha sweeps, is "
+                         "opt-in)")
     ap.add_argument("--learned-iters", type=int, default=50)
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="first copy this many MiB device-to-device 3 times (a kernel of known "
@@ -693,6 +792,9 @@ def main():
         print("proxtv", file=sys.stderr, flush=True)
         h["plain_psnr"] = res["psnr_db_after_steps"] if args.steps == 50 else None
         res["proxtv"] = proxtv(api, args, h)
+    if "paper_ops" in parts:
+        print("paper ops", file=sys.stderr, flush=True)
+        res["paper_ops"] = paper_ops(api, synth, h, res.get("psnr_db_after_steps"))
     if "batch" in parts:
         print("batch_uneven", file=sys.stderr, flush=True)
         res["batch_uneven"] = run_batch(api, synth, c3, phantoms[1:1 + len(c3)], "nlm",

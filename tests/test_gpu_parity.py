@@ -65,6 +65,16 @@ GEOMS = {
     "c2": synth.c2_geometry(),
     "ragged_parallel": synth.geometry(synth.PARALLEL, 100, 0.8, 37, 141, math.pi, angle0_rad=0.3,
                                       bin_mm=1.1),
+    # truncated detector (61 bins across a 96-pixel image): footprints run
+    # past both ends; an odd view count leaves odd view shares
+    "truncated_parallel": synth.geometry(synth.PARALLEL, 96, 1.0, 33, 61, math.pi, angle0_rad=0.1),
+    # bins of 0.4 pixel: every footprint spans 3 to 4 bins.  No view is
+    # axis-aligned: an axis-aligned ray whose offset is a pixel edge in real
+    # arithmetic (67.5 x 0.4 mm) but not in FP64 would take the half-chord
+    # edge rule on one side only (the GPU's 32.32 line position rounds onto
+    # the edge), and its chords jump there
+    "fine_parallel": synth.geometry(synth.PARALLEL, 64, 1.0, 30, 230, math.pi, angle0_rad=0.05,
+                                    bin_mm=0.4),
     "fan_small": synth.geometry(synth.FAN, 128, 0.5, 64, 200, 2 * math.pi, dso_mm=120.0,
                                 ddo_mm=100.0),
     # ragged fan: odd side, a view count that is no multiple of the
@@ -114,7 +124,8 @@ def test_backproject_matches_oracle(gpu_lib, plans, name):
     assert np.max(np.abs(out - ref)) <= 1e-4 * np.max(np.abs(ref))
 
 
-@pytest.mark.parametrize("name", ["c1", "c2", "fan_small", "ragged_fan"])
+@pytest.mark.parametrize("name", ["c1", "c2", "truncated_parallel", "fine_parallel", "fan_small",
+                                  "ragged_fan"])
 def test_gpu_adjoint_identity(gpu_lib, plans, name):
     g = GEOMS[name]
     rng = np.random.default_rng(9)
