@@ -252,6 +252,12 @@ def headline(api, synth, args, mu, results):
     # the library's autotuner picks the projector's march segmentation for
     # this geometry (untimed, before the warm-up)
     results["projector_variant"] = plan.autotune(mu_d, mu_d.t().contiguous(), reps=10)
+    # and the patch-based denoiser's tile split (8 or 4 wavefronts), on the
+    # preconditioned phantom plus noise of the run's first iterations
+    r_tune = torch.empty_like(mu_d)
+    api.ct_precondition(plan, -1, mu_d, out=r_tune)
+    r_tune += 0.1 * torch.randn_like(r_tune)
+    results["nlm_variant"] = plan.autotune_nlm(r_tune, params, reps=10)
 
     def run(n, events=None, log=None, mask=0):
         st = api.DgampState(plan, CFG["tau_x0"])

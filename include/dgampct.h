@@ -475,6 +475,25 @@ dg_status dg_plan_autotune(dg_plan* plan, const float* img, const float* img_t, 
 int32_t dg_plan_projector_variant(const dg_plan* plan);
 dg_status dg_plan_set_projector_variant(dg_plan* plan, int32_t variant);
 
+/* The non-local-means denoiser splits a 32 x 32 tile's search offsets over
+ * 8 or 4 wavefronts (variants 0, 1; default 0): a tile of 4 wavefronts
+ * needs half the LDS, so two share a compute unit, while 8 fill more
+ * compute units when an image has few tiles.  The variants add the
+ * offsets' partial sums in different groupings, so outputs agree to FP32
+ * rounding, not bit for bit.  dg_plan_autotune_nlm times both `reps` times
+ * on r (N floats) with fixed tau_r and eps, writing out (2N floats,
+ * D(r) then D(r + eps b)); it allocates a 16-byte scratch pair and
+ * synchronises the stream.  dg_batch_autotune also times them on the bound
+ * batch when its denoiser is non-local means (outputs into the batch's
+ * work buffers; the iteration state is not touched).  The setters restore
+ * a stored choice (variant outside 0..1: DG_ERR_ARG).                       */
+dg_status dg_plan_autotune_nlm(dg_plan* plan, const dg_nlm_params* params, const float* r,
+                               float* out, int32_t reps, void* stream);
+int32_t dg_plan_nlm_variant(const dg_plan* plan);
+dg_status dg_plan_set_nlm_variant(dg_plan* plan, int32_t variant);
+int32_t dg_batch_nlm_variant(const dg_batch* b);
+dg_status dg_batch_set_nlm_variant(dg_batch* b, int32_t variant);
+
 #ifdef __cplusplus
 }
 #endif

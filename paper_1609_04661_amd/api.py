@@ -43,7 +43,9 @@ EXPORTS = ("dg_plan_create", "dg_plan_destroy", "dg_workspace_bytes", "dg_channe
            "dg_psnr_workspace_bytes", "dg_psnr", "dg_tv_workspace_bytes", "dg_tvw_workspace_bytes",
            "dg_check_status", "dg_noalloc_scratch_bytes", "dgamp_iterate_noalloc",
            "dgamp_state_evolution", "dg_bm3d_workspace_bytes", "dg_fourier_create", "dg_fourier_destroy",
-           "dg_fourier_workspace_bytes", "ct_project_fourier", "ct_backproject_fourier")
+           "dg_fourier_workspace_bytes", "ct_project_fourier", "ct_backproject_fourier",
+           "dg_plan_autotune_nlm", "dg_plan_nlm_variant", "dg_plan_set_nlm_variant",
+           "dg_batch_nlm_variant", "dg_batch_set_nlm_variant")
 
 
 class DgError(RuntimeError):
@@ -149,6 +151,11 @@ def load():
         "dg_plan_projector_variant": ([_VP], i32),
         "dg_batch_set_projector_variant": ([_VP, i32], i32),
         "dg_plan_set_projector_variant": ([_VP, i32], i32),
+        "dg_plan_autotune_nlm": ([_VP, _VP, _VP, _VP, i32, _VP], i32),
+        "dg_plan_nlm_variant": ([_VP], i32),
+        "dg_plan_set_nlm_variant": ([_VP, i32], i32),
+        "dg_batch_nlm_variant": ([_VP], i32),
+        "dg_batch_set_nlm_variant": ([_VP, i32], i32),
         "dg_psnr_workspace_bytes": ([], sz),
         "dg_psnr": ([i64, _VP, _VP, _VP, _VP, _VP], i32),
         "dg_tv_workspace_bytes": ([i64], sz),
@@ -241,6 +248,25 @@ class Plan:
     @projector_variant.setter
     def projector_variant(self, v):
         _check(_lib.dg_plan_set_projector_variant(self._h, int(v)))
+
+    def autotune_nlm(self, r, params=None, reps=10):
+        """Time the non-local-means variants on `r` and keep the faster."""
+        if params is None:
+            params = make_params(DEN_NLM)
+        out = torch.empty(2 * self.N, dtype=torch.float32, device="cuda")
+        _check(_lib.dg_plan_autotune_nlm(self._h, ctypes.byref(params),
+                                         _ptr(r, torch.float32, self.N, "r"),
+                                         _ptr(out, torch.float32, 2 * self.N, "out"), int(reps),
+                                         _stream()))
+        return int(_lib.dg_plan_nlm_variant(self._h))
+
+    @property
+    def nlm_variant(self):
+        return int(_lib.dg_plan_nlm_variant(self._h))
+
+    @nlm_variant.setter
+    def nlm_variant(self, v):
+        _check(_lib.dg_plan_set_nlm_variant(self._h, int(v)))
 
     def __del__(self):
         try:
@@ -614,6 +640,14 @@ class Batch:
     @projector_variant.setter
     def projector_variant(self, v):
         _check(_lib.dg_batch_set_projector_variant(self._h, int(v)))
+
+    @property
+    def nlm_variant(self):
+        return int(_lib.dg_batch_nlm_variant(self._h))
+
+    @nlm_variant.setter
+    def nlm_variant(self, v):
+        _check(_lib.dg_batch_set_nlm_variant(self._h, int(v)))
 
     def graph(self, n_iter, tau_x0=1.0, probe_seed=0, eta_x=1.0, eta_s=1.0, onsager=True,
               channel_mode=CHANNEL_LAPLACE):

@@ -27,8 +27,9 @@ dg_status launch_project_batch(int variant, const ProjArgs* T, const int* prefix
 dg_status launch_project_variant(int variant, const ProjArgs& A, hipStream_t s);
 dg_status launch_backproject_batch(const BpArgs* T, const int* prefix, int n, int total, int mode,
                                    hipStream_t st);
-dg_status launch_nlm_batch(int P, const NlmArgs* T, const int* prefix, int n, int total,
-                           uint64_t seed, int iter, double eta_x, int t, hipStream_t st);
+dg_status launch_nlm_batch(int P, int variant, const NlmArgs* T, const int* prefix, int n,
+                           int total, uint64_t seed, int iter, double eta_x, int t,
+                           hipStream_t st);
 dg_status launch_div_finish_batch(const DivArgs* T, int n, double eta_x, int t, hipStream_t st);
 dg_status launch_div_batch(const DivArgs* T, const int* prefix, int n, int total, uint64_t seed,
                            int iter, double eta_x, int t, hipStream_t st);
@@ -106,6 +107,8 @@ struct dg_batch {
   dg_nlm_params nlm{};
   dg_cnn_params cnn{};
   int proj_variant = 1;
+  int nlm_variant = 0;
+  std::vector<NlmArgs> h_nlm;  // host copy of t_nlm (the tuner times variants on it)
   int bp_mode = 0;  // back-projector kernel: 0 all parallel beam, 1 all fan beam, 2 mixed
 };
 
@@ -362,7 +365,10 @@ extern "C" dg_status dg_batch_bind(dg_batch* b, const float* y, const double* i0
   b->xden = xden;
   b->xpert = xpert;
   b->den_kind = den_kind;
-  if (den_kind == DG_DEN_NLM) b->nlm = *np;
+  if (den_kind == DG_DEN_NLM) {
+    b->nlm = *np;
+    b->h_nlm = nlm;
+  }
   if (den_kind == DG_DEN_CNN) b->cnn = *(const dg_cnn_params*)den_params;
   b->bound = true;
   return DG_OK;
@@ -428,8 +434,8 @@ extern "C" dg_status dgamp_batch_iterate(dg_batch* b, int32_t n_iter, int32_t t0
       return rc;
     if (b->den_kind == DG_DEN_NLM) {
       // the divergence step runs inside the NLM launch
-      rc = launch_nlm_batch(b->nlm.patch_radius, b->t_nlm, b->d_pre_nlm, n, b->pre_nlm[n],
-                            probe_seed, t, eta_x, t, st);
+      rc = launch_nlm_batch(b->nlm.patch_radius, b->nlm_variant, b->t_nlm, b->d_pre_nlm, n,
+                            b->pre_nlm[n], probe_seed, t, eta_x, t, st);
     } else {
       rc = cnn_launch_denoise_batch(&b->cnn, b->r, b->scal + DG_S_EPS, DG_NSCAL, probe_seed, t,
                                     b->xden, b->xpert, n, b->uniform_I, st);
@@ -509,11 +515,74 @@ extern "C" dg_status dg_batch_autotune(dg_batch* b, int32_t reps, void* stream) 
       best_v = v;
     }
   }
+  if (rc == DG_OK && b->den_kind == DG_DEN_NLM && !b->h_nlm.empty()) {
+    // the denoiser's variants on the bound slices, without the fused
+    // divergence step (nothing of the iteration state is written) and with
+    // fixed tau_r and eps in a scratch pair
+    std::vector<NlmArgs> tn = b->h_nlm;
+    double* d = nullptr;
+    NlmArgs* dt = nullptr;
+    const double sc[2] = {1e-4, 1e-3};
+    hipError_t e;
+    if ((e = hipMalloc(&d, sizeof(sc))) != hipSuccess ||
+        (e = hipMalloc(&dt, sizeof(NlmArgs) * tn.size())) != hipSuccess) {
+      rc = hip_fail(e, "dg_batch_autotune: hipMalloc");
+    } else {
+      for (NlmArgs& a : tn) {
+        a.tau_r = d;
+        a.eps = d + 1;
+        a.eps_part = nullptr;
+        a.eps_out = nullptr;
+        a.x = nullptr;
+        a.scal = nullptr;
+        a.div_part = nullptr;
+      }
+      if ((e = hipMemcpy(d, sc, sizeof(sc), hipMemcpyHostToDevice)) != hipSuccess ||
+          (e = hipMemcpy(dt, tn.data(), sizeof(NlmArgs) * tn.size(), hipMemcpyHostToDevice)) !=
+              hipSuccess)
+        rc = hip_fail(e, "dg_batch_autotune: hipMemcpy");
+      float nbest = 1e30f;
+      int nbest_v = b->nlm_variant;
+      for (int v = 0; v < kNlmNumVariants && rc == DG_OK; ++v) {
+        rc = launch_nlm_batch(b->nlm.patch_radius, v, dt, b->d_pre_nlm, b->n, b->pre_nlm[b->n], 0, 0,
+                              0.0, 0, st);  // warm
+        if (rc != DG_OK) break;
+        (void)hipEventRecord(e0, st);
+        for (int k = 0; k < reps && rc == DG_OK; ++k)
+          rc = launch_nlm_batch(b->nlm.patch_radius, v, dt, b->d_pre_nlm, b->n, b->pre_nlm[b->n], 0,
+                                0, 0.0, 0, st);
+        (void)hipEventRecord(e1, st);
+        (void)hipEventSynchronize(e1);
+        float ms = 0.0f;
+        (void)hipEventElapsedTime(&ms, e0, e1);
+        if (ms < nbest) {
+          nbest = ms;
+          nbest_v = v;
+        }
+      }
+      if (rc == DG_OK) {
+        b->nlm_variant = nbest_v;
+        for (dg_plan* p : b->plans) p->nlm_variant = nbest_v;
+      }
+    }
+    if (dt) (void)hipFree(dt);
+    if (d) (void)hipFree(d);
+  }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   if (rc != DG_OK) return rc;
   b->proj_variant = best_v;
   for (dg_plan* p : b->plans) p->proj_variant = best_v;
+  return DG_OK;
+}
+
+extern "C" int32_t dg_batch_nlm_variant(const dg_batch* b) { return b ? b->nlm_variant : -1; }
+
+extern "C" dg_status dg_batch_set_nlm_variant(dg_batch* b, int32_t variant) {
+  DG_ARG_CHECK(b && variant >= 0 && variant < kNlmNumVariants,
+               "dg_batch_set_nlm_variant: bad argument");
+  b->nlm_variant = variant;
+  for (dg_plan* p : b->plans) p->nlm_variant = variant;
   return DG_OK;
 }
 

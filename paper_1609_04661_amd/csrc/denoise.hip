@@ -55,11 +55,11 @@ __device__ __forceinline__ int reflect_idx(int k, int I) {
 
 // Non-local means, register-blocked.  A workgroup owns a 32 x 32 output
 // tile and stages the tile plus its search and patch halos in LDS.  Its
-// kNlmWaves wavefronts split the offsets of the search window evenly, taken in
+// W wavefronts split the offsets of the search window evenly, taken in
 // row-major order (a wavefront's share may start and end inside a row: the
-// 441 offsets of S = 10 give 55 or 56 per wavefront, where whole rows
-// gave 3 rows = 63 to each of 7 wavefronts and left an eighth of the wave
-// slots idle); each thread
+// 441 offsets of S = 10 give 55 or 56 per wavefront with W = 8, where whole
+// rows gave 3 rows = 63 to each of 7 wavefronts and left an eighth of the
+// wave slots idle); each thread
 // owns a 2-wide, 8-tall block of outputs and keeps the (8 + 2P) x (2 + 2P)
 // input pixels its patches cover in registers (own).  Along a row of the
 // search window (oj = -S .. S) the shifted region slides right by one
@@ -71,12 +71,16 @@ __device__ __forceinline__ int reflect_idx(int k, int I) {
 // share the middle 2P squares, accumulated with fused multiply-adds), sums
 // those vertically with a sliding sum, and turns each sum into a weight.  The wavefronts' partial
 // sums are added in a fixed order at the end.
+// The number of wavefronts W that split a tile's offsets is a tuning
+// variant (0: W = 8, 1: W = 4): a workgroup of 4 holds half the LDS for
+// its partial sums, so two fit a compute unit where one of 8 does (the
+// register budget allows 8 wavefronts either way); the larger workgroup
+// fills more compute units when an image has few tiles.
 static constexpr int kNlmBX = 2, kNlmBY = 8;
 static_assert(kNlmBX == 2, "the row sums below are written for two outputs per row");
-static constexpr int kNlmWaves = 8;  // the (2S+1)^2 offsets split evenly, row-major
-static constexpr int kNlmThreads = 64 * kNlmWaves;
+__host__ __device__ constexpr int nlm_waves(int variant) { return variant == 1 ? 4 : 8; }
 // The search loop and the per-output normalisation of nlm_body.
-template <int P, class Emit>
+template <int P, int W, class Emit>
 __device__ __forceinline__ void nlm_search(const NlmArgs& Ar, const float* R,
                                            float (*red)[64][2 * kNlmBX * kNlmBY], int ox0, int oy0,
                                            int g, int lane, double tau_r, int ty0, int tx0,
@@ -104,7 +108,7 @@ __device__ __forceinline__ void nlm_search(const NlmArgs& Ar, const float* R,
     for (int c = 0; c < BX; ++c) wsum[a][c] = acc[a][c] = 0.0f;
   const int nside = 2 * S + 1, n2 = nside * nside;
   // this wavefront's offsets e = (oi + S) nside + (oj + S), e0 <= e < e1
-  const int e0 = g * n2 / kNlmWaves, e1 = (g + 1) * n2 / kNlmWaves;
+  const int e0 = g * n2 / W, e1 = (g + 1) * n2 / W;
   for (int row = e0 / nside; row * nside < e1; ++row) {
     const int oi = row - S;
     const int ja = max(e0 - row * nside, 0), jb = min(e1 - row * nside, nside) - 1;
@@ -174,11 +178,11 @@ __device__ __forceinline__ void nlm_search(const NlmArgs& Ar, const float* R,
       red[g][lane][2 * (a * BX + c) + 1] = acc[a][c];
     }
   __syncthreads();
-  // thread (g, lane) finalises outputs k = g, g + kNlmWaves, ... of block `lane`
-  for (int k = g; k < BX * BY; k += kNlmWaves) {
+  // thread (g, lane) finalises outputs k = g, g + W, ... of block `lane`
+  for (int k = g; k < BX * BY; k += W) {
     float ws = 0.0f, ac = 0.0f;
 #pragma unroll
-    for (int gg = 0; gg < kNlmWaves; ++gg) {
+    for (int gg = 0; gg < W; ++gg) {
       ws += red[gg][lane][2 * k];
       ac += red[gg][lane][2 * k + 1];
     }
@@ -188,10 +192,10 @@ __device__ __forceinline__ void nlm_search(const NlmArgs& Ar, const float* R,
   }
 }
 
-template <int P>
+template <int P, int W>
 __device__ void nlm_body(const NlmArgs& Ar, int bx, int by, int img, uint64_t seed, int iter,
                          double eta_x, int t, float* R, float (*red)[64][2 * kNlmBX * kNlmBY]) {
-  __shared__ double dsh[kNlmWaves + 1];
+  __shared__ double dsh[W + 1];
   constexpr int BX = kNlmBX, BY = kNlmBY;
   const float* __restrict__ r = Ar.r;
   const int I = Ar.I, S = Ar.S;
@@ -261,7 +265,7 @@ __device__ void nlm_body(const NlmArgs& Ar, int bx, int by, int img, uint64_t se
           if (gy < I && gx < I) emit(gy, gx, R[(H0 + oy0 + a) * kNlmPitch + H0 + ox0 + c]);
         }
   } else {
-    nlm_search<P>(Ar, R, red, ox0, oy0, g, lane, tau_r, ty0, tx0, emit);
+    nlm_search<P, W>(Ar, R, red, ox0, oy0, g, lane, tau_r, ty0, tx0, emit);
   }
   if (!fuse) return;
   // the workgroup's partial of b^T (D(r + eps b) - D(r)); the next launch
@@ -271,24 +275,58 @@ __device__ void nlm_body(const NlmArgs& Ar, int bx, int by, int img, uint64_t se
   if (threadIdx.x == 0) Ar.div_part[(img * g2 + by) * g2 + bx] = bs;
 }
 
-template <int P>
-__global__ void __launch_bounds__(kNlmThreads)
+template <int P, int W>
+__global__ void __launch_bounds__(64 * W)
 nlm_kernel(NlmArgs A, uint64_t seed, int iter, double eta_x, int t) {
   __shared__ float R[kNlmRegion * kNlmPitch];
-  __shared__ float red[kNlmWaves][64][2 * kNlmBX * kNlmBY];
-  nlm_body<P>(A, blockIdx.x, blockIdx.y, blockIdx.z, seed, iter, eta_x, t, R, red);
+  __shared__ float red[W][64][2 * kNlmBX * kNlmBY];
+  nlm_body<P, W>(A, blockIdx.x, blockIdx.y, blockIdx.z, seed, iter, eta_x, t, R, red);
 }
-template <int P>
-__global__ void __launch_bounds__(kNlmThreads)
+template <int P, int W>
+__global__ void __launch_bounds__(64 * W)
 nlm_batch(const NlmArgs* __restrict__ T, const int* __restrict__ prefix, int n, uint64_t seed,
           int iter, double eta_x, int t) {
   __shared__ float R[kNlmRegion * kNlmPitch];
-  __shared__ float red[kNlmWaves][64][2 * kNlmBX * kNlmBY];
+  __shared__ float red[W][64][2 * kNlmBX * kNlmBY];
   const int s = slice_of(prefix, n, blockIdx.x);
   const NlmArgs A = T[s];
   const int local = blockIdx.x - prefix[s];
   const int g = (A.I + kNlmTile - 1) / kNlmTile;
-  nlm_body<P>(A, local % g, (local / g) % g, local / (g * g), seed, iter, eta_x, t, R, red);
+  nlm_body<P, W>(A, local % g, (local / g) % g, local / (g * g), seed, iter, eta_x, t, R, red);
+}
+
+// Launch of the single-slice / batched NLM kernel for patch radius P (1, 2,
+// else 3) and tuning variant v.
+template <int W>
+static void nlm_launch_w(int P, dim3 grid, hipStream_t st, const NlmArgs& A, uint64_t seed,
+                         int iter, double eta_x, int t) {
+  if (P == 1)
+    hipLaunchKernelGGL((nlm_kernel<1, W>), grid, dim3(64 * W), 0, st, A, seed, iter, eta_x, t);
+  else if (P == 2)
+    hipLaunchKernelGGL((nlm_kernel<2, W>), grid, dim3(64 * W), 0, st, A, seed, iter, eta_x, t);
+  else
+    hipLaunchKernelGGL((nlm_kernel<3, W>), grid, dim3(64 * W), 0, st, A, seed, iter, eta_x, t);
+}
+static void nlm_launch(int v, int P, dim3 grid, hipStream_t st, const NlmArgs& A, uint64_t seed,
+                       int iter, double eta_x, int t) {
+  if (nlm_waves(v) == 4)
+    nlm_launch_w<4>(P, grid, st, A, seed, iter, eta_x, t);
+  else
+    nlm_launch_w<8>(P, grid, st, A, seed, iter, eta_x, t);
+}
+template <int W>
+static void nlm_batch_launch_w(int P, int total, hipStream_t st, const NlmArgs* T,
+                               const int* prefix, int n, uint64_t seed, int iter, double eta_x,
+                               int t) {
+  if (P == 1)
+    hipLaunchKernelGGL((nlm_batch<1, W>), dim3(total), dim3(64 * W), 0, st, T, prefix, n, seed,
+                       iter, eta_x, t);
+  else if (P == 2)
+    hipLaunchKernelGGL((nlm_batch<2, W>), dim3(total), dim3(64 * W), 0, st, T, prefix, n, seed,
+                       iter, eta_x, t);
+  else
+    hipLaunchKernelGGL((nlm_batch<3, W>), dim3(total), dim3(64 * W), 0, st, T, prefix, n, seed,
+                       iter, eta_x, t);
 }
 
 // Haar: one workgroup per B x B block (B = 2^J), dynamic LDS of B*B floats.
@@ -574,17 +612,7 @@ dg_status launch_denoiser(const dg_plan* p, int kind, const void* params, const 
       eta_x = df->eta_x;
       t = df->t;
     }
-    switch (np->patch_radius) {
-      case 1:
-        hipLaunchKernelGGL(nlm_kernel<1>, grid, dim3(kNlmThreads), 0, st, A, seed, iter, eta_x, t);
-        break;
-      case 2:
-        hipLaunchKernelGGL(nlm_kernel<2>, grid, dim3(kNlmThreads), 0, st, A, seed, iter, eta_x, t);
-        break;
-      default:
-        hipLaunchKernelGGL(nlm_kernel<3>, grid, dim3(kNlmThreads), 0, st, A, seed, iter, eta_x, t);
-        break;
-    }
+    nlm_launch(p->nlm_variant, np->patch_radius, grid, st, A, seed, iter, eta_x, t);
     DG_LAUNCH_CHECK("nlm_kernel");
     return DG_OK;
   }
@@ -632,22 +660,13 @@ unsigned int nlm_blocks(int I) {
   return (unsigned int)(g * g * 2);
 }
 
-dg_status launch_nlm_batch(int P, const NlmArgs* T, const int* prefix, int n, int total,
-                           uint64_t seed, int iter, double eta_x, int t, hipStream_t st) {
-  switch (P) {
-    case 1:
-      hipLaunchKernelGGL(nlm_batch<1>, dim3(total), dim3(kNlmThreads), 0, st, T, prefix, n, seed,
-                         iter, eta_x, t);
-      break;
-    case 2:
-      hipLaunchKernelGGL(nlm_batch<2>, dim3(total), dim3(kNlmThreads), 0, st, T, prefix, n, seed,
-                         iter, eta_x, t);
-      break;
-    default:
-      hipLaunchKernelGGL(nlm_batch<3>, dim3(total), dim3(kNlmThreads), 0, st, T, prefix, n, seed,
-                         iter, eta_x, t);
-      break;
-  }
+dg_status launch_nlm_batch(int P, int variant, const NlmArgs* T, const int* prefix, int n,
+                           int total, uint64_t seed, int iter, double eta_x, int t,
+                           hipStream_t st) {
+  if (nlm_waves(variant) == 4)
+    nlm_batch_launch_w<4>(P, total, st, T, prefix, n, seed, iter, eta_x, t);
+  else
+    nlm_batch_launch_w<8>(P, total, st, T, prefix, n, seed, iter, eta_x, t);
   DG_LAUNCH_CHECK("nlm_batch");
   return DG_OK;
 }
@@ -716,5 +735,63 @@ extern "C" dg_status denoise(const dg_plan* p, int32_t kind, const void* params,
   if (div_out)
     return launch_div(p, x_out, xpert, nullptr, w.eps, div_out, nullptr, 0, probe_seed, iter, 1.0,
                       0, w.dpart, st);
+  return DG_OK;
+}
+
+// Autotuner of the non-local-means variants on one plan: both are timed on
+// r (outputs into out, 2N floats) with fixed tau_r and eps, without the
+// divergence step, and the faster is kept.
+extern "C" dg_status dg_plan_autotune_nlm(dg_plan* p, const dg_nlm_params* np, const float* r,
+                                          float* out, int32_t reps, void* stream) {
+  DG_ARG_CHECK(p && np && r && out && reps >= 1, "dg_plan_autotune_nlm: null argument");
+  DG_ARG_CHECK(np->patch_radius >= 1 && np->patch_radius <= kMaxP && np->search_radius >= 1 &&
+                   np->search_radius <= kMaxS,
+               "dg_plan_autotune_nlm: bad NLM parameters");
+  hipStream_t st = (hipStream_t)stream;
+  double* d = nullptr;
+  const double sc[2] = {1e-4, 1e-3};
+  DG_HIP(hipMalloc(&d, sizeof(sc)));
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  hipError_t e;
+  dg_status rc = DG_OK;
+  if ((e = hipMemcpy(d, sc, sizeof(sc), hipMemcpyHostToDevice)) != hipSuccess ||
+      (e = hipEventCreate(&e0)) != hipSuccess || (e = hipEventCreate(&e1)) != hipSuccess)
+    rc = hip_fail(e, "dg_plan_autotune_nlm");
+  const dim3 grid((p->I + kNlmTile - 1) / kNlmTile, (p->I + kNlmTile - 1) / kNlmTile, 2);
+  const NlmArgs A{r,       out, out + p->N, p->I, np->search_radius, d, d + 1, (float)np->hfac,
+                  nullptr, 0,   0.0,        nullptr};
+  float best = 1e30f;
+  int best_v = p->nlm_variant;
+  for (int v = 0; v < kNlmNumVariants && rc == DG_OK; ++v) {
+    nlm_launch(v, np->patch_radius, grid, st, A, 0, 0, 0.0, 0);  // warm
+    (void)hipEventRecord(e0, st);
+    for (int k = 0; k < reps; ++k) nlm_launch(v, np->patch_radius, grid, st, A, 0, 0, 0.0, 0);
+    (void)hipEventRecord(e1, st);
+    if ((e = hipGetLastError()) != hipSuccess) {
+      rc = hip_fail(e, "dg_plan_autotune_nlm: nlm_kernel");
+      break;
+    }
+    (void)hipEventSynchronize(e1);
+    float ms = 0.0f;
+    (void)hipEventElapsedTime(&ms, e0, e1);
+    if (ms < best) {
+      best = ms;
+      best_v = v;
+    }
+  }
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  (void)hipStreamSynchronize(st);
+  (void)hipFree(d);
+  if (rc == DG_OK) p->nlm_variant = best_v;
+  return rc;
+}
+
+extern "C" int32_t dg_plan_nlm_variant(const dg_plan* p) { return p ? p->nlm_variant : -1; }
+
+extern "C" dg_status dg_plan_set_nlm_variant(dg_plan* p, int32_t variant) {
+  DG_ARG_CHECK(p && variant >= 0 && variant < kNlmNumVariants,
+               "dg_plan_set_nlm_variant: bad argument");
+  p->nlm_variant = variant;
   return DG_OK;
 }

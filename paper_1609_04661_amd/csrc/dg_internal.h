@@ -94,6 +94,7 @@ struct dg_plan {
   int fft_ok;            // I supported by the FFT kernels
   double half_diag_px;   // sqrt(2)/2 (fan candidate search)
   int proj_variant;      // index into kProjSegVariants (autotuned; default 1)
+  int nlm_variant;       // non-local means: 0 = 8 wavefronts per tile, 1 = 4 (default 0)
   float* bm3d_tab;       // device, 72: the orthonormal 8-point DCT-II matrix D[u][k]
                          // (FP64 cosines rounded to FP32) then the 8-point Kaiser window
 };
@@ -440,6 +441,7 @@ struct DivArgs {
 // projector variants (march segments per ray) the autotuner chooses from
 static constexpr int kProjSegVariants[4] = {2, 4, 8, 16};
 static constexpr int kProjNumVariants = 4;
+static constexpr int kNlmNumVariants = 2;  // non-local means: 8 or 4 wavefronts per tile
 static constexpr int kRaysPerBlock = 64;
 
 // Kernels launched by more than one file.

@@ -222,8 +222,8 @@ def test_projector_variants_match_oracle_and_autotune(gpu_lib):
 
 
 def test_batch_autotune_keeps_results(gpu_lib, data):
-    """After tuning, every slice equals its single-slice run on a plan set to
-    the tuned variant."""
+    """After tuning (projector and non-local-means variants), every slice
+    equals its single-slice run on a plan set to the tuned variants."""
     api = gpu_lib
     params = api.make_params(api.DEN_NLM)
     B, y = make_batch(api, data)
@@ -231,13 +231,17 @@ def test_batch_autotune_keeps_results(gpu_lib, data):
     B.bind(y, [d["i0"] for d in data], [d["fro2"] for d in data], api.DEN_NLM, params, mu_out)
     v = B.autotune(reps=3)
     assert v in (0, 1, 2, 3) and B.projector_variant == v
+    vn = B.nlm_variant
+    assert vn in (0, 1)
     for d in data:
         d["plan"].projector_variant = v
+        d["plan"].nlm_variant = vn
     try:
         singles = [single_run(api, d, api.DEN_NLM, params) for d in data]
     finally:
         for d in data:
             d["plan"].projector_variant = 1
+            d["plan"].nlm_variant = 0
     B.state_init(1.0)
     B.iterate(N_ITER, probe_seed=SEED, eta_x=ETA, eta_s=ETA, write_mu=True)
     check_slices_equal(api, B, data, mu_out, singles)
@@ -276,6 +280,7 @@ def test_uneven_batch_full_sizes_equal_single_slices(gpu_lib):
     B.autotune(reps=2)
     for d in data:
         d["plan"].projector_variant = B.projector_variant
+        d["plan"].nlm_variant = B.nlm_variant
     singles = [single_run(api, d, api.DEN_NLM, params, n_iter=3, eta=0.15) for d in data]
     B.state_init(1.0)
     B.iterate(3, probe_seed=SEED, eta_x=0.15, eta_s=0.15, write_mu=True)

@@ -260,6 +260,36 @@ def test_nlm_matches_oracle(gpu_lib, I, noise, tau, xspace):
     assert abs(got - div_ref) <= tol, (got, div_ref, tol)
 
 
+@pytest.mark.parametrize("I,noise,tau,xspace", [(100, 0.004, 1.6e-5, False), (512, 0.15, 0.0225, True)])
+def test_nlm_four_wavefront_variant_matches_oracle(gpu_lib, I, noise, tau, xspace):
+    """The tile split over 4 wavefronts (variant 1) under the same bounds as
+    the default split, and equal to it to FP32 rounding of the regrouped
+    partial sums; the plan's tuner keeps one of the two."""
+    g = synth.geometry(synth.PARALLEL, I, 1.0, 4, I + 1, math.pi)
+    P = gpu_lib.Plan(g)
+    base = synth.ellipse_phantom(I, 6)
+    if xspace:
+        base = precond.apply_V(base)
+    r = base + noise * np.random.default_rng(2).standard_normal((I, I))
+    r32 = r.astype(np.float32).astype(np.float64)
+    prm = gpu_lib.make_params(gpu_lib.DEN_NLM)
+    outs = []
+    for v in (0, 1):
+        P.nlm_variant = v
+        x, div = gpu_lib.denoise(P, gpu_lib.DEN_NLM, prm, cu(r32), cu([tau], torch.float64),
+                                 probe_seed=5, iteration=1)
+        outs.append((host(x), float(host(div)[0])))
+    x_ref = oden.nlm(r32, tau)
+    assert rel_l2(outs[1][0], x_ref) <= 2e-5, rel_l2(outs[1][0], x_ref)
+    assert rel_l2(outs[1][0], outs[0][0]) <= 1e-6
+    div_ref, _ = oden.mc_divergence(oden.NLM, r32, tau, {}, x_ref, 5, 1)
+    assert abs(outs[1][1] - div_ref) <= div_tol(div_ref, x_ref, r32, 2e-5)
+    v = P.autotune_nlm(cu(r32), prm, reps=3)
+    assert v in (0, 1) and P.nlm_variant == v
+    with pytest.raises(gpu_lib.DgError, match="status -1"):
+        P.nlm_variant = 2
+
+
 def test_fro2_hutchinson_matches_oracle(gpu_lib, plans):
     g = GEOMS["c1"]
     ref = ogamp.fro2_hutchinson(radon.Radon(g), 16, 2024)
