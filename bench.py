@@ -57,11 +57,16 @@ CFG = dict(i0=1e5, seed=1002, probe_seed=7, eta=0.15, tau_x0=1.0, fro2_probes=16
 # counter passes (FETCH_SIZE, WRITE_SIZE) scaled by a 256 MiB copy kernel
 # (profiles/dgamp_c2_512x512_64views_hbm_traffic.md).  Set to None whenever
 # that kernel changes until the counters are taken again.
-NLM_TRAFFIC_BYTES = 7.250e6
+NLM_TRAFFIC_BYTES = 7.261e6
 # Counters of the two operators at this workload (per launch, rocprofv3 --pmc
-# passes; profiles/radon_c2_512x512_64views_counters.md).  Set to None when
-# either kernel changes until the counters are taken again.
-A_AT_COUNTERS = None
+# passes; profiles/radon_nlm_c2_512x512_64views_counters.md).  Set to None
+# when either kernel changes until the counters are taken again.
+A_AT_COUNTERS = {
+    "A (project_kernel<4> + output channel)": {"us": 24.57, "valu_issue_frac": 0.58,
+                                               "valu_instr_per_interaction": 26.0,
+                                               "ta_busy_frac": 0.57},
+    "At (backproject_kernel<0>)": {"us": 22.44, "valu_issue_frac": 1.0,
+                                   "valu_instr_per_pixel_view": 53.7, "ta_busy_frac": 0.29}}
 # dampings tried per denoiser for the time-to-equal-PSNR comparison (above
 # 0.35 both recursions diverge on these inputs)
 DAMPING_SWEEP = (0.15, 0.25, 0.35)
@@ -257,7 +262,11 @@ def headline(api, synth, args, mu, results):
     r_tune = torch.empty_like(mu_d)
     api.ct_precondition(plan, -1, mu_d, out=r_tune)
     r_tune += 0.1 * torch.randn_like(r_tune)
-    results["nlm_variant"] = plan.autotune_nlm(r_tune, params, reps=10)
+    if args.nlm_variant == "auto":
+        results["nlm_variant"] = plan.autotune_nlm(r_tune, params, reps=10)
+    else:
+        plan.nlm_variant = int(args.nlm_variant)
+        results["nlm_variant"] = plan.nlm_variant
 
     def run(n, events=None, log=None, mask=0):
         st = api.DgampState(plan, CFG["tau_x0"])
@@ -323,7 +332,9 @@ def headline(api, synth, args, mu, results):
         "value": K / elapsed,
         "ms_per_step": 1e3 * elapsed / K,
         "timed_runs_iter_per_s": [K / e for e in elapsed_runs],
-        "roofline": {"bound": "alu", "kernel": "nlm_kernel<2>", "kernel_ms": nlm_ms,
+        "roofline": {"bound": "alu",
+                     "kernel": "nlm_kernel<2, %d>" % (4 if results["nlm_variant"] == 1 else 8),
+                     "kernel_ms": nlm_ms,
                      "achieved": achieved_tflops, "peak": FP32_VECTOR_TFLOPS,
                      "unit": "TFLOP/s", "frac": achieved_tflops / FP32_VECTOR_TFLOPS,
                      "traffic": NLM_TRAFFIC_BYTES,
@@ -740,6 +751,9 @@ def main():
                          "proxtv (proxtv, the proximal-TV plug-ins with their alpha sweeps, is "
                          "opt-in)")
     ap.add_argument("--learned-iters", type=int, default=50)
+    ap.add_argument("--nlm-variant", default="auto", choices=["auto", "0", "1"],
+                    help="the headline's NLM tile split: tuned (auto) or fixed (0: 8 wavefronts, "
+                         "1: 4), e.g. to take counters of one kernel")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="first copy this many MiB device-to-device 3 times (a kernel of known "
                          "traffic for scaling hardware byte counters)")
