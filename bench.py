@@ -731,6 +731,7 @@ def run_batch(api, synth, slices, phantoms, den, T, reps, autotune, net=None):
     return dict(slices=B.n, iterations=T, ms_per_run=1e3 * s, ms_per_batch_iter=1e3 * s / T,
                 slice_iter_per_s=B.n * T / s, pixels=int(B.totN), rays=int(B.totM),
                 megapixel_iter_per_s=B.totN * T / s / 1e6, projector_variant=variant,
+                nlm_variant=B.nlm_variant if den == "nlm" else None,
                 sides_histogram={str(v): sides.count(v) for v in sorted(set(sides))},
                 psnr_db_mean=float(np.nanmean(ps)), psnr_db_min=float(np.nanmin(ps)),
                 slices_with_status=int((status != 0).sum()))
@@ -827,7 +828,7 @@ def main():
                         autotune=True, net=net)
         fan["cnn_tflops_achieved_upper"] = (2 * cnn_flops_per_pixel() * fan["pixels"]
                                             / (fan["ms_per_batch_iter"] * 1e-3) / 1e12)
-        fan["plain_nlm"] = run_batch(api, synth, c5, p5, "nlm", C5["iters"], 1, autotune=False)
+        fan["plain_nlm"] = run_batch(api, synth, c5, p5, "nlm", C5["iters"], 1, autotune=True)
         res["fan_lowdose"] = fan
     if not args.no_cpu_baseline:
         print("cpu baseline", file=sys.stderr, flush=True)
