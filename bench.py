@@ -8,11 +8,15 @@ library's own projection) and are resident in HBM before timing starts.
 
 One step = one full D-GAMP-CT iteration (V^-1 x, A, Poisson channel, A^T,
 V^-1 g + r update, denoiser on r and r + eps b, divergence + tau_x).  The
-timed region runs `--steps` iterations from a fresh state through the C ABI,
-bracketed by torch.cuda.synchronize(); HIP events that the library records
-between the phases of every timed iteration (on the stream the kernels run
-on) give the per-phase durations used for the roofline fields.  The same
-iterations replayed from a HIP graph are timed beside it.
+timed region replays `--steps` iterations from a fresh state as one HIP
+graph (dgamp_graph_create), bracketed by torch.cuda.synchronize(); `value`
+is from the median of five replays.  The same iterations are also run with
+eager launches, five times, with HIP events that the library records around
+the denoiser of every iteration (on the stream the kernels run on): their
+average is the dominant kernel's duration in the roofline fields (a graph
+records no events), and an untimed eager rerun with every phase boundary
+marked gives the per-phase durations.  Graph and eager runs compute the same
+bits.
 
 Further figures on the same line (each its own untimed-setup, timed-run pair):
   * learned_vs_plain: the residual CNN denoiser against NLM on the headline
@@ -25,8 +29,8 @@ Further figures on the same line (each its own untimed-setup, timed-run pair):
     50 iterations of the batched learned-denoiser path in a HIP graph (and
     the NLM path beside it).
 
-Prints one JSON line.  With `--gpus N`, N > 1 exits with a message: this
-build runs on one GPU.
+Prints one JSON line.  With `--gpus N`, N > 1 exits with a message: the
+benchmark runs on one GPU only.
 """
 import argparse
 import ctypes
@@ -317,21 +321,32 @@ def headline(api, synth, args, mu, results):
     mu_hat = mu_out.cpu().double().numpy()
     psnr = float(api.dg_psnr(mu_out, mu_d).item())
 
-    # the same K iterations replayed from a graph (state reset included)
+    # timed: the same K iterations replayed from a graph (state reset
+    # included), TIMED_RUNS replays; `value` is from the median
     gst = api.DgampState(plan, CFG["tau_x0"])
     G = api.DgampGraph(plan, y_d, gst, K, fro2, CFG["i0"], api.DEN_NLM, params,
                        tau_x0=CFG["tau_x0"], mu_out=mu_out, work=work, **kw)
     G.launch()
-    graph_s = sync_time(G.launch, args.reps)
+    graph_runs = []
+    for _ in range(TIMED_RUNS):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        G.launch()
+        torch.cuda.synchronize()
+        graph_runs.append(time.perf_counter() - t0)
+    graph_s = statistics.median(graph_runs)
+    graph_psnr = float(api.dg_psnr(mu_out, mu_d).item())
 
     nlm_flops = nlm_flops_per_pixel(CFG["nlm"]["pr"], CFG["nlm"]["sr"]) * N * 2  # r, r + eps b
     achieved_tflops = nlm_flops / (nlm_ms * 1e-3) / 1e12
     a_bytes = 4.0 * (N + M)
     nnz = ray_pixel_interactions(geom)
     results.update({
-        "value": K / elapsed,
-        "ms_per_step": 1e3 * elapsed / K,
-        "timed_runs_iter_per_s": [K / e for e in elapsed_runs],
+        "value": K / graph_s,
+        "ms_per_step": 1e3 * graph_s / K,
+        "timed_runs_iter_per_s": [K / e for e in graph_runs],
+        "eager_iter_per_s": K / elapsed,
+        "eager_timed_runs_iter_per_s": [K / e for e in elapsed_runs],
         "roofline": {"bound": "alu",
                      "kernel": "nlm_kernel<2, %d>" % (4 if results["nlm_variant"] == 1 else 8),
                      "kernel_ms": nlm_ms,
@@ -351,6 +366,7 @@ def headline(api, synth, args, mu, results):
         "At_interactions_per_s": nnz / (avg["backproject"] * 1e-3),
         "A_At_counters": A_AT_COUNTERS,
         "psnr_db_after_steps": psnr,
+        "psnr_db_after_steps_graph": graph_psnr,
         "nonfinite_pixels": int((~np.isfinite(mu_hat)).sum()),
         "final_log": dict(zip(api.LOG_FIELDS, [float(v) for v in
                                                log.view(K, api.LOG_STRIDE)[-1].cpu().numpy()])),
@@ -764,8 +780,8 @@ def main():
         parts = {"headline"}
     parts.add("headline")
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path "
-              "(see DESIGN.md for how the work would shard)", file=sys.stderr)
+        print("bench.py runs on one GPU only: the library has no multi-GPU path",
+              file=sys.stderr)
         sys.exit(2)
 
     from paper_1609_04661_amd import synth

@@ -23,6 +23,6 @@ Passing" (arXiv 1609.04661), cited by section / equation / algorithm:
   cnn        FP64 forward / backward / tangent of the residual CNN denoiser
   metrics    PSNR / SSIM (Sec. 6)
 
-Parity status of each function (pinned / unpinned) is listed in the design doc
-and repeated in each module's docstring.
+Each module's docstring states the parity status (pinned / unpinned) of its
+functions and what pins them.
 """
