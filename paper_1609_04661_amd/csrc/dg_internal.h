@@ -64,16 +64,20 @@ struct ViewInfo {
   float a, b, c, hw;
   float cx, cy, inv_dg, pad;  // fan: unit vector towards iso, 1/dgamma [1/rad]
 };
-// Parallel beam: the slope terms every ray of a view shares (copies of the
-// view's RayLine fields), so the back-projector needs no per-ray record.
-// The 32.32 fixed-point values are also held as doubles (integers below
-// 2^46, so exact): the cross coordinate of bin b at major index k,
-// q0 + b dq + k m, is then two exact FMAs instead of 64-bit multiplies.
+// Parallel beam, per view, for the back-projector: a pixel centre (x, y)
+// [px] has the continuous bin coordinate u = ua x + ub y + uc, and lies
+// |u - b| dqa pixels from ray b's line along the ray's cross axis (dqa: the
+// cross-coordinate step between neighbouring bins).  The coefficients are
+// FP64 so that this distance is exact to ~1e-12 px; the chord terms are
+// those of the view's rays (RayLine).
 struct ViewRay {
-  int64_t dq_fx;  // bin b's cross coordinate is bin 0's + b dq_fx exactly
-  double m_d, q0_d, dq_d;  // m_fx, bin 0's q0_fx, dq_fx
-  float m, inv_r, pl, pad;
+  double ua, ub, uc, dqa;
+  double hwb;             // footprint half-width in bins (with a 1e-3 margin)
+  float hw, inv_r, apl;   // 0.5 + 0.5 |m|, 1/|m|, |pl|
+  int32_t flags;          // bit 0: m == 0; bit 1: hwb >= 1 (footprints over more than 2 bins)
+  int32_t pad[2];
 };
+static_assert(sizeof(ViewRay) == 64, "one scalar load per view");
 
 }  // namespace dg
 

@@ -131,13 +131,6 @@ extern "C" dg_status dg_plan_create(const dg_geom* g, dg_plan** out) {
       snapped_cos_sin(th, &c, &s);
       for (int b = 0; b < p->nb; ++b)
         rays[(size_t)k * p->nb + b] = make_ray(c, s, (b - cb) * g->bin_mm, *g);
-      // the cross coordinates of a view's bins form an arithmetic progression;
-      // store it exactly in 32.32 fixed point (bin 0's value plus b steps) so
-      // the back-projector can form them without a table
-      const double step = (std::fabs(s) >= std::fabs(c)) ? -(g->bin_mm / h) / s : (g->bin_mm / h) / c;
-      const int64_t q00 = rays[(size_t)k * p->nb].q0_fx;
-      const int64_t dq = std::llround(step * 4294967296.0);
-      for (int b = 0; b < p->nb; ++b) rays[(size_t)k * p->nb + b].q0_fx = q00 + (int64_t)b * dq;
       ViewInfo& v = views[k];
       v.a = (float)(c * h / g->bin_mm);
       v.b = (float)(s * h / g->bin_mm);
@@ -198,14 +191,31 @@ extern "C" dg_status dg_plan_create(const dg_geom* g, dg_plan** out) {
   p->twiddle = nullptr;
   p->vrays = nullptr;
   p->bm3d_tab = nullptr;
-  // parallel beam: per-view slope terms and bin progression for the back-projector
+  // parallel beam: per-view bin-coordinate map and chord terms for the
+  // back-projector
   std::vector<ViewRay> vr;
   if (g->kind == DG_GEOM_PARALLEL) {
     vr.resize((size_t)p->nv);
     for (int k = 0; k < p->nv; ++k) {
+      double c, s;
+      snapped_cos_sin(g->angle0_rad + k * g->span_rad / p->nv, &c, &s);
       const RayLine& L = rays[(size_t)k * p->nb];
-      const int64_t dq = p->nb > 1 ? rays[(size_t)k * p->nb + 1].q0_fx - L.q0_fx : 0;
-      vr[k] = ViewRay{dq, (double)L.m_fx, (double)L.q0_fx, (double)dq, L.m, L.inv_r, L.pl, 0.0f};
+      ViewRay& r = vr[k];
+      r.ua = c * h / g->bin_mm;
+      r.ub = s * h / g->bin_mm;
+      r.uc = cb;
+      // the cross axis is the row for flat rays (|sin| >= |cos|), the column
+      // otherwise; one bin moves a ray by bin / h / |sin| (resp. |cos|) there
+      r.dqa = (std::fabs(s) >= std::fabs(c)) ? (g->bin_mm / h) / std::fabs(s)
+                                             : (g->bin_mm / h) / std::fabs(c);
+      // the device forms the same half-width as __fmaf_rn(0.5f, |m|, 0.5f):
+      // 0.5 |m| is exact, so one rounding either way
+      r.hw = 0.5f * std::fabs(L.m) + 0.5f;
+      r.inv_r = L.inv_r;
+      r.apl = std::fabs(L.pl);
+      r.hwb = views[k].hw;
+      r.flags = (L.m == 0.0f ? 1 : 0) | (views[k].hw >= 1.0f ? 2 : 0);
+      r.pad[0] = r.pad[1] = 0;
     }
   }
   if ((e = hipMalloc(&p->rays, sizeof(RayLine) * rays.size())) != hipSuccess ||

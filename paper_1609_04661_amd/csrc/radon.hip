@@ -11,9 +11,11 @@
 // Back-projector: pixel-driven (fan beam: one thread per pixel; parallel
 // beam: four, each over a quarter of the views, their sums added in a fixed
 // order).  For every view it finds the few bins whose footprint covers the
-// pixel and adds weight * s for each, recomputing the weight with the very
-// same formula and operands as the projector; no atomics, so the result is
-// deterministic.
+// pixel and adds weight * s for each, with the projector's chord formula:
+// fan beam from the same ray records and fixed-point positions, parallel
+// beam from the pixel's distance to each line computed in FP64 from its bin
+// coordinate (so A and A^T are adjoint to FP32 rounding); no atomics, so the
+// result is deterministic.
 #include "dg_internal.h"
 
 namespace dg {
@@ -273,87 +275,83 @@ __device__ void backproject_body(const BpArgs& A, int bx, int by, float (*red)[k
   const float y = 0.5f * (float)(I - 1) - (float)i;
   float acc = 0.0f;
   if (MODE == 0 || (MODE == 2 && !A.fan)) {
-    const double di = (double)i, dj = (double)j;
-    // parallel beam: a view's rays share their slope terms and their cross
-    // coordinates step by dq_fx per bin, so a candidate bin costs one
-    // sinogram value.  In the parallel-only kernel kBpSplit threads share a
-    // pixel, each taking a contiguous share of the views (more wavefronts
-    // in flight to hide the gathers); their sums are added in a fixed order.
-    // The runtime-mode kernel walks the same shares in turn and adds their
-    // sums in the same order, so both kernels give identical bits.
+    // parallel beam.  A pixel whose centre has the continuous bin coordinate
+    // u (FP64, from the view's map) lies |u - b| dqa pixels from ray b's
+    // line along the cross axis; that distance, rounded once to FP32, enters
+    // the chord fraction of chord_fraction with the view's terms, so the
+    // weights are the projector's up to its 2^-32-pixel line positions and
+    // FP32 rounding.  The first candidate bin is ceil(u - hwb): a footprint
+    // shorter than 2 bins lies within it and the next (a bin past the
+    // footprint gets weight 0 from the chord formula itself); views whose
+    // bins are narrower than 1/sqrt(2) pixel finish longer footprints in a
+    // loop.  Sinogram rows are read through buffer resources sized to the
+    // row, so bins past the detector's end read 0.
+    // In the parallel-only kernel kBpSplit threads share a pixel, each taking
+    // a contiguous share of the views (more wavefronts in flight to hide the
+    // gathers); their sums are added in a fixed order.  The runtime-mode
+    // kernel walks the same shares in turn and adds their sums in the same
+    // order, so both kernels give identical bits.
     constexpr int kBpViews = kBpViewsPar;
-    // a wavefront lies in one z slice (blockDim.x is 64); saying so keeps
-    // the view tables in scalar registers
+    // a wavefront is one row of the block (blockDim.x is 64): its row index
+    // and z slice are uniform
     const int h = (MODE == 0) ? __builtin_amdgcn_readfirstlane((int)threadIdx.z) : 0;
     const int h_end = (MODE == 0) ? h + 1 : kBpSplit;
+    const double xd = (double)j - 0.5 * (double)(I - 1);
+    const double yd = 0.5 * (double)(I - 1) - (double)__builtin_amdgcn_readfirstlane(i);
+    const unsigned row_bytes = (unsigned)A.nb * 4u;
+    static_assert(kBpBinsPar == 2, "the two candidate bins are read as one 64-bit word");
     for (int hh = h; hh < h_end && inside; ++hh) {
       const int kbeg = A.nv * hh / kBpSplit, kend = A.nv * (hh + 1) / kBpSplit;
       float share = 0.0f;
-      for (int k0 = kbeg; k0 < kend; k0 += kBpViews) {
+      // sinogram rows advance with the view; a view past the share's end
+      // (odd count) reads through an empty resource and is not accumulated
+      const float* srow = A.sino + (int64_t)kbeg * A.nb;
+      for (int k0 = kbeg; k0 < kend; k0 += kBpViews, srow += kBpViews * A.nb) {
         int bb[kBpViews];
+        double ud[kBpViews];
         float sv[kBpViews][kBpBinsPar];
 #pragma unroll
         for (int g = 0; g < kBpViews; ++g) {
-          const int k = min(k0 + g, kend - 1);
-          const ViewInfo v = A.views[k];
-          const float u = __fmaf_rn(v.a, x, __fmaf_rn(v.b, y, v.c));
-          bb[g] = max((int)ceilf(u - v.hw), 0);
-          // wavefront-uniform row base, 32-bit byte offsets (bb >= 0)
-          const char* srow = (const char*)(A.sino + (int64_t)k * A.nb);
-#pragma unroll
-          for (int c = 0; c < kBpBinsPar; ++c)
-            sv[g][c] = *(const float*)(srow + (size_t)((unsigned)min(bb[g] + c, A.nb - 1) * 4u));
+          const bool live = k0 + g < kend;
+          const ViewRay& v = A.vrays[live ? k0 + g : kend - 1];
+          ud[g] = __fma_rn(v.ua, xd, __fma_rn(v.ub, yd, v.uc));
+          bb[g] = max((int)ceil(ud[g] - v.hwb), 0);
+          // both candidate bins in one 64-bit read: each dword past the row's
+          // end reads 0 on its own
+          const __amdgpu_buffer_rsrc_t srs = __builtin_amdgcn_make_buffer_rsrc(
+              (void*)(srow + g * A.nb), (short)0, (int)(live ? row_bytes : 0u), kBufferWord3);
+          const auto w2 = __builtin_amdgcn_raw_buffer_load_b64(srs, (unsigned)bb[g] * 4u, 0, 0);
+          sv[g][0] = __int_as_float((int)w2[0]);
+          sv[g][1] = __int_as_float((int)w2[1]);
         }
 #pragma unroll
         for (int g = 0; g < kBpViews; ++g) {
           if (k0 + g >= kend) continue;  // wavefront-uniform tail of the share
           const int k = k0 + g;
-          const ViewRay vr = A.vrays[k];
-          const bool steep = vr.pl < 0.0f;
-          const int p = steep ? j : i;
-          // q0 + bb dq + k m in 32.32 fixed point, formed exactly in FP64
-          // (every partial result is an integer below 2^53) and split into
-          // its words
-          const double qd = __fma_rn(vr.dq_d, (double)bb[g], __fma_rn(vr.m_d, steep ? di : dj, vr.q0_d));
-          const double qh = floor(qd * 0x1p-32);
-          int64_t q = (int64_t)(((uint64_t)(uint32_t)(int)qh << 32) |
-                                (uint64_t)(uint32_t)__fma_rn(qh, -0x1p32, qd));
+          const ViewRay& v = A.vrays[k];
           float wgt[kBpBinsPar];
-          // the axis-aligned views (m == 0) are a wavefront-uniform branch
-          if (vr.m != 0.0f) {
 #pragma unroll
-            for (int c = 0; c < kBpBinsPar; ++c) {
-              int p0;
-              float f;
-              split_fx(q, &p0, &f);
-              wgt[c] = ray_weight_pf<1>(p0, f, p, vr.m, vr.inv_r, vr.pl);
-              q += vr.dq_fx;
-            }
-          } else {
-#pragma unroll
-            for (int c = 0; c < kBpBinsPar; ++c) {
-              int p0;
-              float f;
-              split_fx(q, &p0, &f);
-              wgt[c] = ray_weight_pf<2>(p0, f, p, vr.m, vr.inv_r, vr.pl);
-              q += vr.dq_fx;
-            }
+          for (int c = 0; c < kBpBinsPar; ++c) {
+            const float d = (float)(fabs(ud[g] - (double)(bb[g] + c)) * v.dqa);
+            // the axis-aligned views (m == 0) are a wavefront-uniform branch
+            wgt[c] = (v.flags & 1) ? (d < 0.5f ? 1.0f : (d == 0.5f ? 0.5f : 0.0f))
+                                   : fminf(fmaxf(__fmul_rn(v.hw - d, v.inv_r), 0.0f), 1.0f);
           }
-          // A candidate bin past the pixel's footprint has weight 0 by the
-          // chord formula itself (its line misses the pixel), so only bins
-          // past the detector's end are masked.
+          // the view's chord fractions times its values, then times |pl|: the
+          // projector's order of operations (it scales each ray's sum)
+          float t = wgt[0] * sv[g][0];
 #pragma unroll
-          for (int c = 0; c < kBpBinsPar; ++c)
-            share = __fmaf_rn((bb[g] + c < A.nb) ? wgt[c] : 0.0f, sv[g][c], share);
-          // a footprint shorter than 2 bins covers at most 2 of them; only
-          // views with hw >= 1 (bins narrower than 1/sqrt(2) pixel) need more
-          const ViewInfo v = A.views[k];
-          if (v.hw >= 1.0f) {
-            const float u = __fmaf_rn(v.a, x, __fmaf_rn(v.b, y, v.c));
-            const int be = min((int)floorf(u + v.hw), A.nb - 1);
-            const int64_t row = (int64_t)k * A.nb;
-            for (int b = bb[g] + kBpBinsPar; b <= be; ++b)
-              share = __fmaf_rn(ray_weight(A.rays[row + b], i, j), A.sino[row + b], share);
+          for (int c = 1; c < kBpBinsPar; ++c) t = __fmaf_rn(wgt[c], sv[g][c], t);
+          share = __fmaf_rn(v.apl, t, share);
+          if (v.flags & 2) {
+            const int be = min((int)floor(ud[g] + v.hwb), A.nb - 1);
+            const float* srow = A.sino + (int64_t)k * A.nb;
+            for (int b = bb[g] + kBpBinsPar; b <= be; ++b) {
+              const float d = (float)(fabs(ud[g] - (double)b) * v.dqa);
+              const float w = (v.flags & 1) ? (d < 0.5f ? 1.0f : (d == 0.5f ? 0.5f : 0.0f))
+                                            : fminf(fmaxf(__fmul_rn(v.hw - d, v.inv_r), 0.0f), 1.0f);
+              share = __fmaf_rn(v.apl * w, srow[b], share);
+            }
           }
         }
       }
