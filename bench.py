@@ -66,11 +66,11 @@ NLM_TRAFFIC_BYTES = 7.261e6
 # passes; profiles/radon_nlm_c2_512x512_64views_counters.md).  Set to None
 # when either kernel changes until the counters are taken again.
 A_AT_COUNTERS = {
-    "A (project_kernel<4> + output channel)": {"us": 24.57, "valu_issue_frac": 0.58,
-                                               "valu_instr_per_interaction": 26.0,
-                                               "ta_busy_frac": 0.57},
-    "At (backproject_kernel<0>)": {"us": 22.44, "valu_issue_frac": 1.0,
-                                   "valu_instr_per_pixel_view": 53.7, "ta_busy_frac": 0.29}}
+    "A (project_kernel<4> + output channel)": {"us": 24.97, "valu_issue_frac": 0.55,
+                                               "valu_instr_per_interaction": 25.4,
+                                               "ta_busy_frac": 0.54},
+    "At (backproject_kernel<0>)": {"us": 11.34, "valu_issue_frac": 0.87,
+                                   "valu_instr_per_pixel_view": 23.2, "ta_busy_frac": 0.64}}
 # dampings tried per denoiser for the time-to-equal-PSNR comparison (above
 # 0.35 both recursions diverge on these inputs)
 DAMPING_SWEEP = (0.15, 0.25, 0.35)

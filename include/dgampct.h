@@ -63,7 +63,9 @@ typedef struct dg_geom {
   double pixel_mm;    /* h > 0                                            */
   double angle0_rad;
   double span_rad;
-  double bin_mm;      /* parallel detector pitch > 0                      */
+  double bin_mm;      /* parallel detector pitch > 0, with sqrt(2) h/bin_mm
+                         (1.5 I + 1) + n_bins / 2 + 8 < 65536 (bin coordinates
+                         over the image stay below 2^16)                   */
   double dso_mm;      /* fan: source to iso-centre, > I*h/sqrt(2)         */
   double ddo_mm;      /* fan: iso-centre to detector                      */
   double dgamma_rad;  /* fan: angular bin pitch, 0 = cover the image       */
@@ -73,7 +75,8 @@ typedef struct dg_plan dg_plan; /* geometry tables, FFT twiddles (device)   */
 
 /* Build the per-ray line tables, the FFT tables and the preconditioner
  * symbol for `g` on the current HIP device.  Synchronous.  The plan owns its
- * (read-only) device tables until dg_plan_destroy.                         */
+ * (read-only) device tables until dg_plan_destroy.  A geometry outside the
+ * limits stated in dg_geom returns DG_ERR_ARG with a message.              */
 dg_status dg_plan_create(const dg_geom* g, dg_plan** out);
 dg_status dg_plan_destroy(dg_plan* plan);
 

@@ -39,7 +39,7 @@ dg_status cnn_launch_denoise_batch(const void* params, const float* r, const dou
                                    int eps_stride, uint64_t seed, int iter, float* x_den,
                                    float* x_pert, int n, int I, hipStream_t st);
 unsigned int project_blocks(int64_t M);
-unsigned int backproject_blocks(int I);
+unsigned int backproject_blocks(int I, int mode);
 unsigned int red_grid(int64_t N);
 unsigned int nlm_blocks(int I);
 int prec_row_blocks(int I);
@@ -220,10 +220,13 @@ extern "C" dg_status dg_batch_create(const dg_geom* geoms, int32_t n, dg_batch**
     b->pre_rows[s + 1] = b->pre_rows[s] + prec_row_blocks(I);
     b->pre_cols[s + 1] = b->pre_cols[s] + prec_col_blocks(I);
     b->pre_proj[s + 1] = b->pre_proj[s] + (int)project_blocks(p->M);
-    b->pre_bp[s + 1] = b->pre_bp[s] + (int)backproject_blocks(I);
     b->pre_nlm[s + 1] = b->pre_nlm[s] + (int)nlm_blocks(I);
     b->pre_div[s + 1] = b->pre_div[s] + (int)red_grid(p->N);
   }
+  // the back-projector's blocks per slice depend on the kernel the whole
+  // batch runs (bp_mode)
+  for (int s = 0; s < n; ++s)
+    b->pre_bp[s + 1] = b->pre_bp[s] + (int)backproject_blocks(geoms[s].n, b->bp_mode);
   b->totN = b->img_off[n];
   b->totM = b->sino_off[n];
   b->totSpec = b->spec_off[n];

@@ -64,18 +64,25 @@ struct ViewInfo {
   float a, b, c, hw;
   float cx, cy, inv_dg, pad;  // fan: unit vector towards iso, 1/dgamma [1/rad]
 };
-// Parallel beam, per view, for the back-projector: a pixel centre (x, y)
-// [px] has the continuous bin coordinate u = ua x + ub y + uc, and lies
+// Parallel beam, per view, for the back-projector: the pixel in row i,
+// column j has the continuous bin coordinate u = P j + Q i + R, and lies
 // |u - b| dqa pixels from ray b's line along the ray's cross axis (dqa: the
-// cross-coordinate step between neighbouring bins).  The coefficients are
-// FP64 so that this distance is exact to ~1e-12 px; the chord terms are
-// those of the view's rays (RayLine).
+// cross-coordinate step between neighbouring bins).  Each of P, Q, R is split
+// into a multiple of the grain 2^-e (p1, q1, r1) and an FP32 remainder below
+// half a grain (p2, q2, r2), e chosen per view so that every partial sum of
+// q1 i + p1 j + r1 - b the kernel forms is a multiple of the grain below 2^23
+// grains: those sums are exact in FP32, and u - b = (q1 i + p1 j + r1 - b) +
+// (q2 i + p2 j + r2) has one rounding of a number of order one.  The chord
+// terms are those of the view's rays (RayLine).
 struct ViewRay {
-  double ua, ub, uc, dqa;
-  double hwb;             // footprint half-width in bins (with a 1e-3 margin)
+  float p1, q1, r1;       // grain parts of P, Q, R
+  float p2, q2, r2;       // remainders
+  float hwb;              // footprint half-width in bins, with a 1/64-bin margin
+  float dqa;
   float hw, inv_r, apl;   // 0.5 + 0.5 |m|, 1/|m|, |pl|
+  float hw_ax;            // half a pixel in bins (the step rule of axis-aligned views)
   int32_t flags;          // bit 0: m == 0; bit 1: hwb >= 1 (footprints over more than 2 bins)
-  int32_t pad[2];
+  int32_t pad[3];
 };
 static_assert(sizeof(ViewRay) == 64, "one scalar load per view");
 

@@ -99,6 +99,11 @@ extern "C" dg_status dg_plan_create(const dg_geom* g, dg_plan** out) {
                "dg_plan_create: non-finite angles");
   if (g->kind == DG_GEOM_PARALLEL) {
     DG_ARG_CHECK(g->bin_mm > 0 && std::isfinite(g->bin_mm), "dg_plan_create: bin_mm must be > 0");
+    // the back-projector picks candidate bins from FP32 bin coordinates,
+    // which needs |u| below 2^16 bins over the whole image
+    const double span = std::sqrt(2.0) * g->pixel_mm / g->bin_mm;
+    DG_ARG_CHECK(span * (1.5 * g->n + 1.0) + 0.5 * g->n_bins + 8.0 < 65536.0,
+                 "dg_plan_create: parallel bins too narrow for the image (bin coordinates reach 2^16)");
   } else {
     DG_ARG_CHECK(g->dso_mm > g->n * g->pixel_mm / std::sqrt(2.0),
                  "dg_plan_create: fan source must lie outside the image's circumscribed circle");
@@ -201,21 +206,40 @@ extern "C" dg_status dg_plan_create(const dg_geom* g, dg_plan** out) {
       snapped_cos_sin(g->angle0_rad + k * g->span_rad / p->nv, &c, &s);
       const RayLine& L = rays[(size_t)k * p->nb];
       ViewRay& r = vr[k];
-      r.ua = c * h / g->bin_mm;
-      r.ub = s * h / g->bin_mm;
-      r.uc = cb;
+      // u = ua x + ub y + cb for the centred coordinates x = j - half,
+      // y = half - i, i.e. P j + Q i + R over the pixel's indices
+      const double ua = c * h / g->bin_mm, ub = s * h / g->bin_mm;
+      const double half = 0.5 * (p->I - 1);
+      const double P = ua, Q = -ub, R = cb + (ub - ua) * half;
+      // the largest partial sum (and candidate bin) in grains stays below 2^23
+      const double bound = (std::fabs(P) + std::fabs(Q)) * (p->I - 1) + std::fabs(R) +
+                           0.5 * (std::fabs(c) + std::fabs(s)) * h / g->bin_mm + 4.0;
+      const int ge = std::min(40, (int)std::floor(std::log2(8388608.0 / bound)));
+      const double P1 = std::ldexp(std::nearbyint(std::ldexp(P, ge)), -ge);
+      const double Q1 = std::ldexp(std::nearbyint(std::ldexp(Q, ge)), -ge);
+      const double R1 = std::ldexp(std::nearbyint(std::ldexp(R, ge)), -ge);
+      r.p1 = (float)P1;
+      r.q1 = (float)Q1;
+      r.r1 = (float)R1;
+      r.p2 = (float)(P - P1);
+      r.q2 = (float)(Q - Q1);
+      r.r2 = (float)(R - R1);
       // the cross axis is the row for flat rays (|sin| >= |cos|), the column
       // otherwise; one bin moves a ray by bin / h / |sin| (resp. |cos|) there
-      r.dqa = (std::fabs(s) >= std::fabs(c)) ? (g->bin_mm / h) / std::fabs(s)
-                                             : (g->bin_mm / h) / std::fabs(c);
+      r.dqa = (float)((std::fabs(s) >= std::fabs(c)) ? (g->bin_mm / h) / std::fabs(s)
+                                                     : (g->bin_mm / h) / std::fabs(c));
       // the device forms the same half-width as __fmaf_rn(0.5f, |m|, 0.5f):
       // 0.5 |m| is exact, so one rounding either way
       r.hw = 0.5f * std::fabs(L.m) + 0.5f;
       r.inv_r = L.inv_r;
       r.apl = std::fabs(L.pl);
-      r.hwb = views[k].hw;
-      r.flags = (L.m == 0.0f ? 1 : 0) | (views[k].hw >= 1.0f ? 2 : 0);
-      r.pad[0] = r.pad[1] = 0;
+      // the candidate bins come from u rounded to FP32 (error below 2^-7
+      // bins while |u| < 2^16): a 1/64-bin margin keeps every bin of nonzero
+      // weight among them
+      r.hwb = (float)(0.5 * (std::fabs(c) + std::fabs(s)) * h / g->bin_mm + 1.0 / 64.0);
+      r.hw_ax = (float)(0.5 * h / g->bin_mm);
+      r.flags = (L.m == 0.0f ? 1 : 0) | (r.hwb >= 1.0f ? 2 : 0);
+      r.pad[0] = r.pad[1] = r.pad[2] = 0;
     }
   }
   if ((e = hipMalloc(&p->rays, sizeof(RayLine) * rays.size())) != hipSuccess ||

@@ -20,6 +20,8 @@
 
 namespace dg {
 
+// back-projector workgroups: 64 columns x kBpBlockY rows (fan and mixed
+// batches); the parallel-only kernel's shape is set below (kBpRows)
 static constexpr int kBpBlockX = 64, kBpBlockY = 4;
 
 // Block = kRaysPerBlock rays x SEGS segments: wavefront w marches segment w
@@ -250,7 +252,8 @@ __device__ __forceinline__ float ray_weight(const RayLine& L, int i, int j) {
   return ray_weight_parts(L.q0_fx, L.m_fx, L.m, L.inv_r, L.pl, i, j);
 }
 
-// bx, by: block coordinates of a (kBpBlockX x kBpBlockY) pixel block.
+// bx, by: block coordinates of a pixel block of kBpBlockX columns and
+// bp_block_rows(MODE) rows.
 // Views are taken kBpViews at a time: the footprint of the pixel in every
 // view of the group is found first and the ray records and sinogram values
 // of the first kBpBinsFan (fan) or kBpBinsPar (parallel) bins per view are
@@ -262,11 +265,25 @@ __device__ __forceinline__ float ray_weight(const RayLine& L, int i, int j) {
 // (one 32-byte ray record per bin), so a requested bin that falls outside a
 // short footprint is pure cost: it requests one bin per view and loops over
 // the rest.
-static constexpr int kBpViewsPar = 2, kBpViewsFan = 4, kBpBinsFan = 1, kBpBinsPar = 2, kBpSplit = 4;
+static constexpr int kBpViewsPar = 1, kBpViewsFan = 4, kBpBinsFan = 1, kBpBinsPar = 2, kBpSplit = 16;
+// The parallel-only kernel: a lane takes kBpRows consecutive rows of one
+// column (they share the view's terms, the column part of its bin-coordinate
+// map and the wavefront's scalar work per view), a workgroup is 64 columns x
+// kBpRows rows x kBpSplit view shares (16 wavefronts), one view per step.
+// Measured at 512^2 with 64 views: 1 row per lane 19.1 us, 2 rows 12.4, 4
+// rows 11.1-12.1 over splits of 4, 8 and 16; 8 rows leave too few
+// workgroups.  16 shares keep 4 workgroups per compute unit at 512^2 and
+// spread 384^2 evenly (11.4 us; 14.2 with 8 shares).
+static constexpr int kBpRows = 4, kBpBlockYPar = 1;
+// image rows per workgroup of the back-projector kernel of a mode
+__host__ __device__ constexpr int bp_block_rows(int mode) {
+  return mode == 0 ? kBpBlockYPar * kBpRows : kBpBlockY;
+}
 
 // MODE 0: parallel beam, 1: fan beam, 2: either (decided per slice).
 template <int MODE>
-__device__ void backproject_body(const BpArgs& A, int bx, int by, float (*red)[kBpBlockY][kBpBlockX]) {
+__device__ void backproject_body(const BpArgs& A, int bx, int by,
+                                 float (*red)[kBpRows][kBpBlockYPar][kBpBlockX]) {
   const int I = A.I;
   const int j = bx * kBpBlockX + threadIdx.x;
   const int i = by * kBpBlockY + threadIdx.y;
@@ -275,98 +292,151 @@ __device__ void backproject_body(const BpArgs& A, int bx, int by, float (*red)[k
   const float y = 0.5f * (float)(I - 1) - (float)i;
   float acc = 0.0f;
   if (MODE == 0 || (MODE == 2 && !A.fan)) {
-    // parallel beam.  A pixel whose centre has the continuous bin coordinate
-    // u (FP64, from the view's map) lies |u - b| dqa pixels from ray b's
-    // line along the cross axis; that distance, rounded once to FP32, enters
-    // the chord fraction of chord_fraction with the view's terms, so the
+    // parallel beam.  A pixel's continuous bin coordinate u comes from the
+    // view's map as an exact FP32 grain part u1 plus a small remainder su
+    // (u1 = q1 i + (p1 j + r1), su = q2 i + (p2 j + r2)); u1 - b is exact for
+    // every candidate bin b, so u - b is rounded once at a magnitude of order
+    // one.  Its distance to ray b's line along the cross axis, (u - b) dqa,
+    // enters the chord fraction of chord_fraction with the view's terms: the
     // weights are the projector's up to its 2^-32-pixel line positions and
-    // FP32 rounding.  The first candidate bin is ceil(u - hwb): a footprint
-    // shorter than 2 bins lies within it and the next (a bin past the
-    // footprint gets weight 0 from the chord formula itself); views whose
-    // bins are narrower than 1/sqrt(2) pixel finish longer footprints in a
-    // loop.  Sinogram rows are read through buffer resources sized to the
-    // row, so bins past the detector's end read 0.
-    // In the parallel-only kernel kBpSplit threads share a pixel, each taking
-    // a contiguous share of the views (more wavefronts in flight to hide the
+    // FP32 rounding.  Axis-aligned views (m == 0) give weight 1 inside the
+    // pixel's half-width, 1/2 on it: that test is made in bins, where a line
+    // through a pixel's edge is an exact tie.  The first candidate bin is
+    // ceil(u - hwb), taken from u rounded (error below 2^-7 bins while
+    // |u| < 2^16, inside hwb's 1/64-bin margin past the footprint, so no bin
+    // of nonzero weight is missed): a footprint shorter than 2 bins lies
+    // within it and the next (a bin past the footprint gets weight 0 from the
+    // chord formula itself); views whose bins are narrower than 1/sqrt(2)
+    // pixel finish longer footprints in a loop.  Sinogram rows are read
+    // through buffer resources sized to the row, so bins past the detector's
+    // end read 0.
+    // In the parallel-only kernel a lane takes kBpRows consecutive rows of
+    // one column and kBpSplit threads share a pixel, each taking a
+    // contiguous share of the views (more wavefronts in flight to hide the
     // gathers); their sums are added in a fixed order.  The runtime-mode
-    // kernel walks the same shares in turn and adds their sums in the same
-    // order, so both kernels give identical bits.
+    // kernel takes one row per thread and walks the same shares in turn with
+    // the same arithmetic per pixel and view, so both kernels give identical
+    // bits.
     constexpr int kBpViews = kBpViewsPar;
-    // a wavefront is one row of the block (blockDim.x is 64): its row index
+    constexpr int R = (MODE == 0) ? kBpRows : 1;
+    // a wavefront is one row group of the block (blockDim.x is 64): its rows
     // and z slice are uniform
     const int h = (MODE == 0) ? __builtin_amdgcn_readfirstlane((int)threadIdx.z) : 0;
     const int h_end = (MODE == 0) ? h + 1 : kBpSplit;
-    const double xd = (double)j - 0.5 * (double)(I - 1);
-    const double yd = 0.5 * (double)(I - 1) - (double)__builtin_amdgcn_readfirstlane(i);
+    const int i0 = __builtin_amdgcn_readfirstlane(
+        MODE == 0 ? (by * kBpBlockYPar + (int)threadIdx.y) * R : by * kBpBlockY + (int)threadIdx.y);
+    const bool live_px = j < I && i0 < I;
+    const float jf = (float)j;
+    float yf[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) yf[r] = (float)(i0 + r);
     const unsigned row_bytes = (unsigned)A.nb * 4u;
     static_assert(kBpBinsPar == 2, "the two candidate bins are read as one 64-bit word");
-    for (int hh = h; hh < h_end && inside; ++hh) {
+    float acc[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) acc[r] = 0.0f;
+    for (int hh = h; hh < h_end && live_px; ++hh) {
       const int kbeg = A.nv * hh / kBpSplit, kend = A.nv * (hh + 1) / kBpSplit;
-      float share = 0.0f;
+      float share[R];
+#pragma unroll
+      for (int r = 0; r < R; ++r) share[r] = 0.0f;
       // sinogram rows advance with the view; a view past the share's end
       // (odd count) reads through an empty resource and is not accumulated
       const float* srow = A.sino + (int64_t)kbeg * A.nb;
       for (int k0 = kbeg; k0 < kend; k0 += kBpViews, srow += kBpViews * A.nb) {
-        int bb[kBpViews];
-        double ud[kBpViews];
-        float sv[kBpViews][kBpBinsPar];
+        int bb[kBpViews][R];
+        float du[kBpViews][R], su[kBpViews][R];  // u1 - bb (exact), the remainder of u
+        float sv[kBpViews][R][kBpBinsPar];
 #pragma unroll
         for (int g = 0; g < kBpViews; ++g) {
           const bool live = k0 + g < kend;
           const ViewRay& v = A.vrays[live ? k0 + g : kend - 1];
-          ud[g] = __fma_rn(v.ua, xd, __fma_rn(v.ub, yd, v.uc));
-          bb[g] = max((int)ceil(ud[g] - v.hwb), 0);
-          // both candidate bins in one 64-bit read: each dword past the row's
-          // end reads 0 on its own
+          const float c1 = __fmaf_rn(v.p1, jf, v.r1);  // exact
+          const float c2 = __fmaf_rn(v.p2, jf, v.r2);
           const __amdgpu_buffer_rsrc_t srs = __builtin_amdgcn_make_buffer_rsrc(
               (void*)(srow + g * A.nb), (short)0, (int)(live ? row_bytes : 0u), kBufferWord3);
-          const auto w2 = __builtin_amdgcn_raw_buffer_load_b64(srs, (unsigned)bb[g] * 4u, 0, 0);
-          sv[g][0] = __int_as_float((int)w2[0]);
-          sv[g][1] = __int_as_float((int)w2[1]);
+#pragma unroll
+          for (int r = 0; r < R; ++r) {
+            const float u1 = __fmaf_rn(v.q1, yf[r], c1);  // exact
+            su[g][r] = __fmaf_rn(v.q2, yf[r], c2);
+            const float bf = fmaxf(ceilf((u1 - v.hwb) + su[g][r]), 0.0f);
+            du[g][r] = u1 - bf;  // exact
+            bb[g][r] = (int)bf;
+            // both candidate bins in one 64-bit read: each dword past the
+            // row's end reads 0 on its own
+            const auto w2 = __builtin_amdgcn_raw_buffer_load_b64(srs, (unsigned)bb[g][r] * 4u, 0, 0);
+            sv[g][r][0] = __int_as_float((int)w2[0]);
+            sv[g][r][1] = __int_as_float((int)w2[1]);
+          }
         }
 #pragma unroll
         for (int g = 0; g < kBpViews; ++g) {
           if (k0 + g >= kend) continue;  // wavefront-uniform tail of the share
           const int k = k0 + g;
           const ViewRay& v = A.vrays[k];
-          float wgt[kBpBinsPar];
+          if (v.flags & 1) {
+            // axis-aligned view: the step rule in bins (hw_ax = half a pixel
+            // in bins); 2^64 (hw_ax - |x|) + 1/2 clamps to 1, 1/2 or 0
 #pragma unroll
-          for (int c = 0; c < kBpBinsPar; ++c) {
-            const float d = (float)(fabs(ud[g] - (double)(bb[g] + c)) * v.dqa);
-            // the axis-aligned views (m == 0) are a wavefront-uniform branch
-            wgt[c] = (v.flags & 1) ? (d < 0.5f ? 1.0f : (d == 0.5f ? 0.5f : 0.0f))
-                                   : fminf(fmaxf(__fmul_rn(v.hw - d, v.inv_r), 0.0f), 1.0f);
+            for (int r = 0; r < R; ++r) {
+              const float x0 = du[g][r] + su[g][r];
+              const float x1 = x0 - 1.0f;
+              const float w0 = __builtin_amdgcn_fmed3f(__fmaf_rn(v.hw_ax - fabsf(x0), 0x1p64f, 0.5f), 0.0f, 1.0f);
+              const float w1 = __builtin_amdgcn_fmed3f(__fmaf_rn(v.hw_ax - fabsf(x1), 0x1p64f, 0.5f), 0.0f, 1.0f);
+              const float t = __fmaf_rn(w1, sv[g][r][1], w0 * sv[g][r][0]);
+              share[r] = __fmaf_rn(v.apl, t, share[r]);
+            }
+          } else {
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+              // signed distances [px] to the lines of the two candidates
+              const float e0 = (du[g][r] + su[g][r]) * v.dqa;
+              const float e1 = e0 - v.dqa;
+              const float w0 = fminf(fmaxf(__fmul_rn(v.hw - fabsf(e0), v.inv_r), 0.0f), 1.0f);
+              const float w1 = fminf(fmaxf(__fmul_rn(v.hw - fabsf(e1), v.inv_r), 0.0f), 1.0f);
+              // the view's chord fractions times its values, then times |pl|:
+              // the projector's order of operations (it scales each ray's sum)
+              const float t = __fmaf_rn(w1, sv[g][r][1], w0 * sv[g][r][0]);
+              share[r] = __fmaf_rn(v.apl, t, share[r]);
+            }
           }
-          // the view's chord fractions times its values, then times |pl|: the
-          // projector's order of operations (it scales each ray's sum)
-          float t = wgt[0] * sv[g][0];
-#pragma unroll
-          for (int c = 1; c < kBpBinsPar; ++c) t = __fmaf_rn(wgt[c], sv[g][c], t);
-          share = __fmaf_rn(v.apl, t, share);
           if (v.flags & 2) {
-            const int be = min((int)floor(ud[g] + v.hwb), A.nb - 1);
             const float* srow = A.sino + (int64_t)k * A.nb;
-            for (int b = bb[g] + kBpBinsPar; b <= be; ++b) {
-              const float d = (float)(fabs(ud[g] - (double)b) * v.dqa);
-              const float w = (v.flags & 1) ? (d < 0.5f ? 1.0f : (d == 0.5f ? 0.5f : 0.0f))
-                                            : fminf(fmaxf(__fmul_rn(v.hw - d, v.inv_r), 0.0f), 1.0f);
-              share = __fmaf_rn(v.apl * w, srow[b], share);
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+              const float x0 = du[g][r] + su[g][r];
+              const int be = min(bb[g][r] + (int)floorf(x0 + v.hwb), A.nb - 1);
+              for (int b = bb[g][r] + kBpBinsPar; b <= be; ++b) {
+                const float x = x0 - (float)(b - bb[g][r]);
+                const float w = (v.flags & 1)
+                    ? __builtin_amdgcn_fmed3f(__fmaf_rn(v.hw_ax - fabsf(x), 0x1p64f, 0.5f), 0.0f, 1.0f)
+                    : fminf(fmaxf(__fmul_rn(v.hw - fabsf(x * v.dqa), v.inv_r), 0.0f), 1.0f);
+                share[r] = __fmaf_rn(v.apl * w, srow[b], share[r]);
+              }
             }
           }
         }
       }
-      acc = (hh == 0) ? share : acc + share;
+#pragma unroll
+      for (int r = 0; r < R; ++r) acc[r] = (hh == 0) ? share[r] : acc[r] + share[r];
     }
     if (MODE == 0) {
-      if (h > 0) red[h - 1][threadIdx.y][threadIdx.x] = acc;
-      __syncthreads();
-      if (h == 0 && inside) {
+      if (h > 0) {
 #pragma unroll
-        for (int e = 0; e < kBpSplit - 1; ++e) acc += red[e][threadIdx.y][threadIdx.x];
-        A.img[(int64_t)i * I + j] = acc;
+        for (int r = 0; r < R; ++r) red[h - 1][r][threadIdx.y][threadIdx.x] = acc[r];
       }
-    } else if (inside) {
-      A.img[(int64_t)i * I + j] = acc;
+      __syncthreads();
+      if (h == 0 && live_px) {
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+          float a = acc[r];
+#pragma unroll
+          for (int e = 0; e < kBpSplit - 1; ++e) a += red[e][r][threadIdx.y][threadIdx.x];
+          if (i0 + r < I) A.img[(int64_t)(i0 + r) * I + j] = a;
+        }
+      }
+    } else if (live_px) {
+      A.img[(int64_t)i0 * I + j] = acc[0];
     }
     return;
   }
@@ -421,20 +491,20 @@ __device__ void backproject_body(const BpArgs& A, int bx, int by, float (*red)[k
 }
 
 // Threads per back-projector workgroup: the parallel-only kernel runs
-// kBpSplit threads per pixel (blockDim.z).
+// kBpSplit threads per pixel column (blockDim.z).
 __host__ __device__ constexpr int bp_threads(int mode) {
-  return kBpBlockX * kBpBlockY * (mode == 0 ? kBpSplit : 1);
+  return mode == 0 ? kBpBlockX * kBpBlockYPar * kBpSplit : kBpBlockX * kBpBlockY;
 }
 template <int MODE>
 __global__ void __launch_bounds__(bp_threads(MODE))
     backproject_kernel(BpArgs A) {
-  __shared__ float red[kBpSplit - 1][kBpBlockY][kBpBlockX];
+  __shared__ float red[kBpSplit - 1][kBpRows][kBpBlockYPar][kBpBlockX];
   backproject_body<MODE>(A, blockIdx.x, blockIdx.y, red);
 }
 template <int MODE>
 __global__ void __launch_bounds__(bp_threads(MODE))
     backproject_batch(const BpArgs* __restrict__ T, const int* __restrict__ prefix, int n) {
-  __shared__ float red[kBpSplit - 1][kBpBlockY][kBpBlockX];
+  __shared__ float red[kBpSplit - 1][kBpRows][kBpBlockYPar][kBpBlockX];
   const int s = slice_of(prefix, n, blockIdx.x);
   const BpArgs A = T[s];
   const int local = blockIdx.x - prefix[s];
@@ -464,8 +534,10 @@ dg_status launch_transpose(const float* in, float* out, int I, hipStream_t s) {
 }
 
 unsigned int project_blocks(int64_t M) { return (unsigned int)((M + kRaysPerBlock - 1) / kRaysPerBlock); }
-unsigned int backproject_blocks(int I) {
-  return (unsigned int)(((I + kBpBlockX - 1) / kBpBlockX) * ((I + kBpBlockY - 1) / kBpBlockY));
+// mode: as the back-projector kernels' (0 parallel-only, 1 fan, 2 either)
+unsigned int backproject_blocks(int I, int mode) {
+  const int rows = bp_block_rows(mode);
+  return (unsigned int)(((I + kBpBlockX - 1) / kBpBlockX) * ((I + rows - 1) / rows));
 }
 
 // cr applies only when A.chan_on (the fused output channel).
@@ -522,7 +594,7 @@ dg_status launch_backproject_batch(const BpArgs* T, const int* prefix, int n, in
                                    hipStream_t s) {
   const dim3 block(kBpBlockX, kBpBlockY);
   if (mode == 0)
-    hipLaunchKernelGGL(backproject_batch<0>, dim3(total), dim3(kBpBlockX, kBpBlockY, kBpSplit), 0,
+    hipLaunchKernelGGL(backproject_batch<0>, dim3(total), dim3(kBpBlockX, kBpBlockYPar, kBpSplit), 0,
                        s, T, prefix, n);
   else if (mode == 1)
     hipLaunchKernelGGL(backproject_batch<1>, dim3(total), block, 0, s, T, prefix, n);
@@ -539,14 +611,16 @@ dg_status launch_project(const dg_plan* p, const float* img, const float* img_t,
 }
 
 dg_status launch_backproject(const dg_plan* p, const float* sino, float* img, hipStream_t s) {
-  dim3 grid((p->I + kBpBlockX - 1) / kBpBlockX, (p->I + kBpBlockY - 1) / kBpBlockY);
+  const int mode = p->g.kind == DG_GEOM_FAN ? 1 : 0;
+  const int rows = bp_block_rows(mode);
+  dim3 grid((p->I + kBpBlockX - 1) / kBpBlockX, (p->I + rows - 1) / rows);
   dim3 block(kBpBlockX, kBpBlockY);
   BpArgs A{p->rays, p->views, sino, img, p->I, p->nv, p->nb, p->g.kind == DG_GEOM_FAN ? 1 : 0,
            (float)p->half_diag_px, p->vrays};
   if (A.fan)
     hipLaunchKernelGGL(backproject_kernel<1>, grid, block, 0, s, A);
   else
-    hipLaunchKernelGGL(backproject_kernel<0>, grid, dim3(kBpBlockX, kBpBlockY, kBpSplit), 0, s, A);
+    hipLaunchKernelGGL(backproject_kernel<0>, grid, dim3(kBpBlockX, kBpBlockYPar, kBpSplit), 0, s, A);
   DG_LAUNCH_CHECK("backproject_kernel");
   return DG_OK;
 }

@@ -38,12 +38,15 @@ def test_plan_create_rejects_bad_geometry():
         dict(synth.c1_geometry(), kind=7),
         dict(synth.c5_geometry(), dso_mm=100.0),
         dict(synth.c1_geometry(), span_rad=float("nan")),
+        # parallel bins so narrow that bin coordinates over the image reach 2^16
+        dict(synth.c2_geometry(), bin_mm=0.01, n_bins=64),
     ]
     for g in bad:
         c = api.Geom(**{k: g[k] for k, _ in api.Geom._fields_})
         h = ctypes.c_void_p()
         assert L.dg_plan_create(ctypes.byref(c), ctypes.byref(h)) == -1
         assert L.dg_last_error()
+    assert b"2^16" in L.dg_last_error()
     assert L.dg_plan_create(None, None) == -1
 
 
