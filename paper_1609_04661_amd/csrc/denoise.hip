@@ -80,22 +80,18 @@ static constexpr int kNlmBX = 2, kNlmBY = 8;
 static_assert(kNlmBX == 2, "the row sums below are written for two outputs per row");
 __host__ __device__ constexpr int nlm_waves(int variant) { return variant == 1 ? 4 : 8; }
 // The search loop and the per-output normalisation of nlm_body.
+// R holds the region scaled by sqrt(c1) (nlm_consts), so a patch's sum of
+// squared differences is c1 S directly; the sliding sums start at -c2, and
+// the weight 2^-max(c1 S - c2, 0) is one exp with a negated input and its
+// output clamped to [0, 1].  The weighted mean is unscaled by inv_k.
 template <int P, int W, class Emit>
 __device__ __forceinline__ void nlm_search(const NlmArgs& Ar, const float* R,
                                            float (*red)[64][2 * kNlmBX * kNlmBY], int ox0, int oy0,
-                                           int g, int lane, double tau_r, int ty0, int tx0,
-                                           Emit& emit) {
+                                           int g, int lane, float c2, float inv_k, int ty0,
+                                           int tx0, Emit& emit) {
   constexpr int BX = kNlmBX, BY = kNlmBY;
   constexpr int WX = BX + 2 * P, WY = BY + 2 * P;
   const int I = Ar.I, S = Ar.S;
-  const float hfac = Ar.hfac;
-  const float sig2 = (float)tau_r;
-  // w = exp(-max(S / n_p - 2 sigma^2, 0) / h^2) = 2^-max(c1 S - c2, 0) with
-  // c1 = log2(e) / (n_p h^2) and c2 = log2(e) 2 sigma^2 / h^2 (S the patch
-  // sum of squared differences over n_p pixels, h = hfac sigma)
-  const float l2e_h2 = 1.4426950408889634f / (hfac * hfac * sig2);
-  const float c1 = l2e_h2 / (float)((2 * P + 1) * (2 * P + 1));
-  const float c2 = l2e_h2 * 2.0f * sig2;
   float own[WY][WX];
 #pragma unroll
   for (int a = 0; a < WY; ++a)
@@ -151,16 +147,15 @@ __device__ __forceinline__ void nlm_search(const NlmArgs& Ar, const float* R,
           }
 #pragma unroll
           for (int c = 0; c < BX; ++c) {
-            float v = 0.0f;
+            float v = -c2;
 #pragma unroll
             for (int q = 0; q <= 2 * P; ++q) v += h[q][c];
 #pragma unroll
             for (int a = 0; a < BY; ++a) {
               if (a > 0) v += h[a + 2 * P][c] - h[a - 1][c];
-              // 2^-max(y, 0) = min(2^-y, 1): the clamp to [0, 1] folds into
-              // the exp instruction's output modifier
-              const float w =
-                  fminf(fmaxf(__builtin_amdgcn_exp2f(__fmaf_rn(v, -c1, c2)), 0.0f), 1.0f);
+              // v = c1 S - c2; 2^-max(v, 0) = min(2^-v, 1): the negation and
+              // the clamp to [0, 1] fold into the exp instruction's modifiers
+              const float w = fminf(fmaxf(__builtin_amdgcn_exp2f(-v), 0.0f), 1.0f);
               wsum[a][c] += w;
               acc[a][c] = __fmaf_rn(w, win[a + P][(tau + c + P) % WX], acc[a][c]);
             }
@@ -188,7 +183,7 @@ __device__ __forceinline__ void nlm_search(const NlmArgs& Ar, const float* R,
     }
     const int a = k / BX, c = k % BX;
     const int gy = ty0 + oy0 + a, gx = tx0 + ox0 + c;
-    if (gy < I && gx < I) emit(gy, gx, ac / ws);
+    if (gy < I && gx < I) emit(gy, gx, (ac / ws) * inv_k);
   }
 }
 
@@ -228,18 +223,29 @@ __device__ void nlm_body(const NlmArgs& Ar, int bx, int by, int img, uint64_t se
     eps_d = *Ar.eps;
     if (img) eps = (float)eps_d;
   }
+  // w = exp(-max(S / n_p - 2 sigma^2, 0) / h^2) = 2^-max(c1 S - c2, 0) with
+  // c1 = log2(e) / (n_p h^2) and c2 = log2(e) 2 sigma^2 / h^2 (S the patch
+  // sum of squared differences over n_p pixels, h = hfac sigma, sigma^2 =
+  // tau_r).  The region is stored scaled by k = sqrt(c1).  sigma = 0 (or a
+  // sigma^2 below FP32's range) is the identity.
+  const double tau_r = *tau_r_ptr;
+  const float sig2 = (float)tau_r;
+  const float l2e_h2 = 1.4426950408889634f / (Ar.hfac * Ar.hfac * sig2);
+  const float c1 = l2e_h2 / (float)((2 * P + 1) * (2 * P + 1));
+  const bool smooth = sig2 > 0.0f && c1 <= 3.0e38f;
+  const float kscale = smooth ? sqrtf(c1) : 1.0f;
+  const float c2 = l2e_h2 * 2.0f * sig2;
   for (int e = threadIdx.x; e < WR * WR; e += blockDim.x) {
     const int ri = e / WR, rj = e % WR;
     const int gi = reflect_idx(ty0 - H0 + ri, I), gj = reflect_idx(tx0 - H0 + rj, I);
     const int64_t gidx = (int64_t)gi * I + gj;
     float v = r[gidx];
     if (img) v = __fmaf_rn(eps, probe_sign(seed, iter, (uint64_t)gidx), v);
-    R[ri * kNlmPitch + rj] = v;
+    R[ri * kNlmPitch + rj] = v * kscale;
   }
   __syncthreads();
   const int lane = threadIdx.x & 63, g = threadIdx.x >> 6;
   const int ox0 = (lane & 15) * BX, oy0 = (lane >> 4) * BY;  // tile-relative block origin
-  const double tau_r = *tau_r_ptr;
   // an output value: stored, and with the fused divergence, x damped towards
   // D(r) (image 0) and -+ b v added to this thread's partial
   const float eta = (float)eta_x;
@@ -257,7 +263,7 @@ __device__ void nlm_body(const NlmArgs& Ar, int bx, int by, int img, uint64_t se
       }
     }
   };
-  if (!(tau_r > 0.0)) {  // sigma = 0: identity
+  if (!smooth) {  // sigma = 0: identity (the region is unscaled)
     if (g == 0)
       for (int a = 0; a < BY; ++a)
         for (int c = 0; c < BX; ++c) {
@@ -265,7 +271,7 @@ __device__ void nlm_body(const NlmArgs& Ar, int bx, int by, int img, uint64_t se
           if (gy < I && gx < I) emit(gy, gx, R[(H0 + oy0 + a) * kNlmPitch + H0 + ox0 + c]);
         }
   } else {
-    nlm_search<P, W>(Ar, R, red, ox0, oy0, g, lane, tau_r, ty0, tx0, emit);
+    nlm_search<P, W>(Ar, R, red, ox0, oy0, g, lane, c2, 1.0f / kscale, ty0, tx0, emit);
   }
   if (!fuse) return;
   // the workgroup's partial of b^T (D(r + eps b) - D(r)); the next launch

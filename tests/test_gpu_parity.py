@@ -75,6 +75,12 @@ GEOMS = {
     # the edge), and its chords jump there
     "fine_parallel": synth.geometry(synth.PARALLEL, 64, 1.0, 30, 230, math.pi, angle0_rad=0.05,
                                     bin_mm=0.4),
+    # a side that is no multiple of the back-projector's 4 rows per lane or
+    # 64 columns per wavefront
+    "odd_side_parallel": synth.geometry(synth.PARALLEL, 75, 1.0, 19, 109, math.pi, angle0_rad=0.2),
+    # fewer views than the back-projector's 16 view shares (some are empty);
+    # view 0 is axis-aligned with every pixel centre on a bin edge
+    "few_views_parallel": synth.geometry(synth.PARALLEL, 72, 1.0, 7, 103, math.pi),
     "fan_small": synth.geometry(synth.FAN, 128, 0.5, 64, 200, 2 * math.pi, dso_mm=120.0,
                                 ddo_mm=100.0),
     # ragged fan: odd side, a view count that is no multiple of the
@@ -124,7 +130,8 @@ def test_backproject_matches_oracle(gpu_lib, plans, name):
     assert np.max(np.abs(out - ref)) <= 1e-4 * np.max(np.abs(ref))
 
 
-@pytest.mark.parametrize("name", ["c1", "c2", "truncated_parallel", "fine_parallel", "fan_small",
+@pytest.mark.parametrize("name", ["c1", "c2", "truncated_parallel", "fine_parallel",
+                                  "odd_side_parallel", "few_views_parallel", "fan_small",
                                   "ragged_fan"])
 def test_gpu_adjoint_identity(gpu_lib, plans, name):
     g = GEOMS[name]
@@ -149,6 +156,22 @@ def test_projector_edge_rays_half_weight(gpu_lib):
         ref = radon.Radon(g).project(e)
         assert np.array_equal(out, ref.astype(np.float32).astype(np.float64)), (i, j)
         assert sorted(set(np.round(out[out > 0], 12))) == [0.5]
+
+
+def test_backprojector_edge_rays_half_weight(gpu_lib):
+    """A^T of a single edge ray (0 and 90 degrees, even grid, odd bin count):
+    the two pixel columns (rows) beside the line get half its value, exactly
+    as the oracle's transpose, every other pixel 0."""
+    g = synth.geometry(synth.PARALLEL, 16, 1.0, 2, 23, math.pi)
+    P = gpu_lib.Plan(g)
+    R = radon.Radon(g)
+    for k, b in [(0, 11), (1, 4), (0, 19), (1, 3)]:
+        s = np.zeros((2, 23))
+        s[k, b] = 1.0
+        out = host(gpu_lib.ct_backproject(P, cu(s)))
+        ref = R.backproject(s)
+        assert np.array_equal(out, ref.astype(np.float32).astype(np.float64)), (k, b)
+        assert sorted(set(np.round(out[out > 0], 12))) == [0.5], (k, b)
 
 
 @pytest.mark.parametrize("I", [8, 12, 64, 96, 256, 384, 512, 768, 1024])
