@@ -337,7 +337,7 @@ extern "C" dg_status dg_batch_bind(dg_batch* b, const float* y, const double* i0
     // the channel finish runs in the slice's first row workgroup of V^-1 g
     rf_g[k] = RowsFwdArgs{g + io, sp, p->twiddle, I, 1, chan[k], DivFinish{}};
     bp[k] = BpArgs{p->rays, p->views, s + so, g + io, I, p->nv, p->nb,
-                   p->g.kind == DG_GEOM_FAN ? 1 : 0, (float)p->half_diag_px, p->vrays};
+                   p->g.kind == DG_GEOM_FAN ? 1 : 0, (float)p->half_diag_px, p->vrays, p->frays};
     // NLM also finishes the Monte-Carlo step and performs the divergence step
     if (den_kind == DG_DEN_NLM)
       nlm[k] = NlmArgs{r + io,           xden + io, xpert + io,       I,

@@ -55,11 +55,28 @@ struct RayLine {
   float pl, m, inv_r, q0;
 };
 
+// Fan beam, per ray, for the back-projector: the ray's cross coordinate at
+// major index k is q(k) = q0 + m k (pixel-index units, as RayLine), with
+// q0 = c1 + c2 and m = m1 + m2 split into multiples of a per-ray grain 2^-e
+// (c1, m1) and FP32 remainders below half a grain (c2, m2), e chosen so that
+// (c1 - p) + m1 k is exact in FP32 for every pixel index p and k of the
+// image; q(k) - p is then rounded once, at a magnitude of order one for the
+// pixels the ray meets.  The chord fraction is clamp((hw - |q(k) - p|) inv_r
+// + off): hw, inv_r as RayLine's (off = 0); an axis-aligned ray has hw = 1/2,
+// inv_r = 2^64 and off = 1/2, which gives its step rule (1 inside, 1/2 on
+// the edge, 0 outside) in the same expression.  pl: RayLine's pl (its sign
+// marks a steep ray).
+struct FanRay {
+  float c1, m1, c2, m2;
+  float hw, inv_r, off, pl;
+};
+static_assert(sizeof(FanRay) == 32, "two 16-byte loads per ray");
+
 // Per-view data for the pixel-driven back-projector's candidate search.
 //  parallel: bin coordinate of a pixel centre (x, y) [px] is
 //            u = a*x + b*y + c; candidates are within +-hw of u.
-//  fan:      a, b = source position (px); c = central bin; hw unused
-//            (computed per pixel from the source distance).
+//  fan:      a, b = source position (px); c = central bin; hw = margin in
+//            bins added to the per-pixel footprint bound; pad = 1.001 / dgamma.
 struct ViewInfo {
   float a, b, c, hw;
   float cx, cy, inv_dg, pad;  // fan: unit vector towards iso, 1/dgamma [1/rad]
@@ -101,6 +118,7 @@ struct dg_plan {
   dg::RayLine* rays;     // device, M
   dg::ViewInfo* views;   // device, nv
   dg::ViewRay* vrays;    // device, nv (parallel beam only, else null)
+  dg::FanRay* frays;     // device, M (fan beam only, else null)
   float2* twiddle;       // device, I: exp(-2 pi i t / I)
   int fft_ok;            // I supported by the FFT kernels
   double half_diag_px;   // sqrt(2)/2 (fan candidate search)
@@ -248,6 +266,7 @@ struct BpArgs {
   int I, nv, nb, fan;
   float half_diag;
   const ViewRay* vrays;  // parallel beam: per-view slope terms
+  const FanRay* frays;   // fan beam: per-ray lines for the back-projector
 };
 // Output channel argument block (per slice).  Standalone: zp = p, s_out,
 // tau_p_ptr, tau_s_out.  Fused: zp = z, s_io = s (in: s_prev, out: s), scal.

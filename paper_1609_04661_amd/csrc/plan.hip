@@ -44,11 +44,14 @@ static double fan_dgamma(const dg_geom& g) {
   return 2.0 * std::asin(R / g.dso_mm) / g.n_bins;
 }
 
-static RayLine make_ray(double c, double s, double off_mm, const dg_geom& g) {
+// The line of a ray with direction (c, s) and signed offset off_mm from the
+// iso-centre: cross coordinate q0 + m k at major index k (pixel-index units)
+// and chord step pl (its sign marks a steep ray).
+static void ray_params(double c, double s, double off_mm, const dg_geom& g, double* q0_out,
+                       double* m_out, double* pl_out) {
   const double h = g.pixel_mm;
   const double off = off_mm / h;  // pixel units
   const double half = 0.5 * (g.n - 1);
-  RayLine L;
   double m, q0, pl;
   if (std::fabs(s) >= std::fabs(c)) {  // flat: march over columns, cross = row
     m = c / s;
@@ -59,6 +62,15 @@ static RayLine make_ray(double c, double s, double off_mm, const dg_geom& g) {
     q0 = off / c + half * (1.0 - m);
     pl = -h / std::fabs(c);
   }
+  *q0_out = q0;
+  *m_out = m;
+  *pl_out = pl;
+}
+
+static RayLine make_ray(double c, double s, double off_mm, const dg_geom& g) {
+  RayLine L;
+  double m, q0, pl;
+  ray_params(c, s, off_mm, g, &q0, &m, &pl);
   const double two32 = 4294967296.0;
   L.q0_fx = std::llround(q0 * two32);
   L.m_fx = std::llround(m * two32);
@@ -67,6 +79,36 @@ static RayLine make_ray(double c, double s, double off_mm, const dg_geom& g) {
   L.pl = (float)pl;
   L.inv_r = (L.m == 0.0f) ? INFINITY : (float)(1.0 / std::fabs((double)L.m));
   return L;
+}
+
+// The back-projector's record of a fan ray (FanRay): the line split into
+// grain parts and FP32 remainders, and the chord terms of its RayLine L.
+static FanRay make_fan_ray(double c, double s, double off_mm, const dg_geom& g, const RayLine& L) {
+  double m, q0, pl;
+  ray_params(c, s, off_mm, g, &q0, &m, &pl);
+  // largest |(c1 - p) + m1 k| over the image's pixel indices, with slack
+  const double bound = std::fabs(q0) + std::fabs(m) * (g.n - 1) + g.n + 4.0;
+  const int ge = std::min(40, (int)std::floor(std::log2(8388608.0 / bound)));
+  const double c1 = std::ldexp(std::nearbyint(std::ldexp(q0, ge)), -ge);
+  const double m1 = std::ldexp(std::nearbyint(std::ldexp(m, ge)), -ge);
+  FanRay F;
+  F.c1 = (float)c1;
+  F.m1 = (float)m1;
+  F.c2 = (float)(q0 - c1);
+  F.m2 = (float)(m - m1);
+  if (L.m == 0.0f) {
+    F.hw = 0.5f;
+    F.inv_r = 18446744073709551616.0f;  // 2^64
+    F.off = 0.5f;
+  } else {
+    // the device's own half-width, __fmaf_rn(0.5f, |m|, 0.5f): 0.5 |m| is
+    // exact, so one rounding either way
+    F.hw = 0.5f * std::fabs(L.m) + 0.5f;
+    F.inv_r = L.inv_r;
+    F.off = 0.0f;
+  }
+  F.pl = L.pl;
+  return F;
 }
 
 static bool fft_size_ok(int I) {
@@ -128,6 +170,8 @@ extern "C" dg_status dg_plan_create(const dg_geom* g, dg_plan** out) {
 
   std::vector<RayLine> rays((size_t)p->M);
   std::vector<ViewInfo> views((size_t)p->nv);
+  // fan beam: the back-projector's per-ray records
+  std::vector<FanRay> fr(g->kind == DG_GEOM_FAN ? (size_t)p->M : 0);
   const double h = g->pixel_mm;
   const double cb = 0.5 * (g->n_bins - 1);
   if (g->kind == DG_GEOM_PARALLEL) {
@@ -150,17 +194,21 @@ extern "C" dg_status dg_plan_create(const dg_geom* g, dg_plan** out) {
       for (int b = 0; b < p->nb; ++b) {
         double gam = (b - cb) * dg_, c, s;
         snapped_cos_sin(beta + gam + 0.5 * M_PI, &c, &s);
-        rays[(size_t)k * p->nb + b] = make_ray(c, s, -g->dso_mm * std::sin(gam), *g);
+        const double off_mm = -g->dso_mm * std::sin(gam);
+        rays[(size_t)k * p->nb + b] = make_ray(c, s, off_mm, *g);
+        fr[(size_t)k * p->nb + b] = make_fan_ray(c, s, off_mm, *g, rays[(size_t)k * p->nb + b]);
       }
       ViewInfo& v = views[k];
       v.a = (float)(g->dso_mm * std::cos(beta) / h);
       v.b = (float)(g->dso_mm * std::sin(beta) / h);
       v.c = (float)cb;
-      v.hw = 0.0f;
+      // the device's fan angle is within 2e-6 rad of atan; its footprint
+      // bound is widened by 0.1 % and this many bins
+      v.hw = (float)(4e-6 / dg_ + 1e-3);
       v.cx = (float)(-std::cos(beta));
       v.cy = (float)(-std::sin(beta));
       v.inv_dg = (float)(1.0 / dg_);
-      v.pad = 0.0f;
+      v.pad = (float)(1.001 / dg_);
     }
   }
   std::vector<float2> tw((size_t)p->I);
@@ -195,6 +243,7 @@ extern "C" dg_status dg_plan_create(const dg_geom* g, dg_plan** out) {
   p->views = nullptr;
   p->twiddle = nullptr;
   p->vrays = nullptr;
+  p->frays = nullptr;
   p->bm3d_tab = nullptr;
   // parallel beam: per-view bin-coordinate map and chord terms for the
   // back-projector
@@ -246,7 +295,8 @@ extern "C" dg_status dg_plan_create(const dg_geom* g, dg_plan** out) {
       (e = hipMalloc(&p->views, sizeof(ViewInfo) * views.size())) != hipSuccess ||
       (e = hipMalloc(&p->twiddle, sizeof(float2) * tw.size())) != hipSuccess ||
       (e = hipMalloc(&p->bm3d_tab, sizeof(float) * bt.size())) != hipSuccess ||
-      (!vr.empty() && (e = hipMalloc(&p->vrays, sizeof(ViewRay) * vr.size())) != hipSuccess)) {
+      (!vr.empty() && (e = hipMalloc(&p->vrays, sizeof(ViewRay) * vr.size())) != hipSuccess) ||
+      (!fr.empty() && (e = hipMalloc(&p->frays, sizeof(FanRay) * fr.size())) != hipSuccess)) {
     dg_plan_destroy(p);
     hip_fail(e, "dg_plan_create: hipMalloc");
     return DG_ERR_NOMEM;
@@ -260,6 +310,8 @@ extern "C" dg_status dg_plan_create(const dg_geom* g, dg_plan** out) {
       (e = hipMemcpy(p->bm3d_tab, bt.data(), sizeof(float) * bt.size(), hipMemcpyHostToDevice)) !=
           hipSuccess ||
       (!vr.empty() && (e = hipMemcpy(p->vrays, vr.data(), sizeof(ViewRay) * vr.size(),
+                                     hipMemcpyHostToDevice)) != hipSuccess) ||
+      (!fr.empty() && (e = hipMemcpy(p->frays, fr.data(), sizeof(FanRay) * fr.size(),
                                      hipMemcpyHostToDevice)) != hipSuccess)) {
     dg_plan_destroy(p);
     return hip_fail(e, "dg_plan_create: hipMemcpy");
@@ -275,6 +327,7 @@ extern "C" dg_status dg_plan_destroy(dg_plan* p) {
   if (p->bm3d_tab) (void)hipFree(p->bm3d_tab);
   if (p->twiddle) (void)hipFree(p->twiddle);
   if (p->vrays) (void)hipFree(p->vrays);
+  if (p->frays) (void)hipFree(p->frays);
   delete p;
   return DG_OK;
 }

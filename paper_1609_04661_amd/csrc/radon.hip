@@ -252,6 +252,37 @@ __device__ __forceinline__ float ray_weight(const RayLine& L, int i, int j) {
   return ray_weight_parts(L.q0_fx, L.m_fx, L.m, L.inv_r, L.pl, i, j);
 }
 
+// Fan angle atan(t) of t = cr / along (along > 0): an odd polynomial in t
+// on [0, 1], fitted to atan by weighted least squares on Chebyshev nodes
+// (Lawson's reweighting towards the minimax fit; largest error 1.7e-6 rad in
+// FP32), and atan(t) = pi/2 - atan(1/t) above 1.  Within 2e-6 rad of atan;
+// the candidate bins it selects are widened by more than that.
+__device__ __forceinline__ float fan_angle(float cr, float along) {
+  const float t = cr * __builtin_amdgcn_rcpf(along);
+  const float a = fabsf(t);
+  const bool inv = a > 1.0f;
+  const float r = inv ? __builtin_amdgcn_rcpf(a) : a;
+  const float s = r * r;
+  float q = -0.01171912718564272f;
+  q = __fmaf_rn(q, s, 0.052647341042757034f);
+  q = __fmaf_rn(q, s, -0.1164264902472496f);
+  q = __fmaf_rn(q, s, 0.19354039430618286f);
+  q = __fmaf_rn(q, s, -0.33262282609939575f);
+  q = __fmaf_rn(q, s, 0.9999772310256958f);
+  const float p = q * r;
+  return copysignf(inv ? 1.5707963267948966f - p : p, t);
+}
+
+// A fan ray's chord weight at pixel (row i, column j) from its FanRay
+// record: the cross coordinate's distance q(k) - p from exact grain sums
+// plus one rounding, then the chord fraction and |pl|.
+__device__ __forceinline__ float fan_weight(const FanRay& L, float fi, float fj) {
+  const bool steep = L.pl < 0.0f;
+  const float k = steep ? fi : fj, p = steep ? fj : fi;
+  const float d = __fmaf_rn(L.m1, k, L.c1 - p) + __fmaf_rn(L.m2, k, L.c2);
+  return fabsf(L.pl) * fminf(fmaxf(__fmaf_rn(L.hw - fabsf(d), L.inv_r, L.off), 0.0f), 1.0f);
+}
+
 // bx, by: block coordinates of a pixel block of kBpBlockX columns and
 // bp_block_rows(MODE) rows.
 // Views are taken kBpViews at a time: the footprint of the pixel in every
@@ -443,9 +474,10 @@ __device__ void backproject_body(const BpArgs& A, int bx, int by,
   if (!inside) return;
   if (MODE == 0) return;
   constexpr int kBpViews = kBpViewsFan;
+  const float fi = (float)i, fj = (float)j;
   for (int k0 = 0; k0 < A.nv; k0 += kBpViews) {
     int bb[kBpViews], be[kBpViews];
-    RayLine L[kBpViews][kBpBinsFan];
+    FanRay L[kBpViews][kBpBinsFan];
     float sv[kBpViews][kBpBinsFan];
 #pragma unroll
     for (int g = 0; g < kBpViews; ++g) {
@@ -455,12 +487,15 @@ __device__ void backproject_body(const BpArgs& A, int bx, int by,
       if (k < A.nv) {
         const ViewInfo v = A.views[k];
         const float dx = x - v.a, dy = y - v.b;
-        const float along = v.cx * dx + v.cy * dy;
-        const float cr = v.cx * dy - v.cy * dx;
-        const float dist = sqrtf(dx * dx + dy * dy);
-        const float gam = atan2f(cr, along);
-        const float u = __fmaf_rn(gam, v.inv_dg, v.c);
-        const float hw = asinf(fminf(A.half_diag / dist, 1.0f)) * v.inv_dg * 1.001f + 1e-3f;
+        const float along = __fmaf_rn(v.cx, dx, v.cy * dy);
+        const float cr = __fmaf_rn(v.cx, dy, -(v.cy * dx));
+        const float u = __fmaf_rn(fan_angle(cr, along), v.inv_dg, v.c);
+        // the pixel's angular half-width seen from the source is at most
+        // asin(xs), xs = half diagonal / distance, and asin(xs) <=
+        // tan(asin(xs)) = xs / sqrt(1 - xs^2)
+        const float xs = A.half_diag * __builtin_amdgcn_rsqf(__fmaf_rn(dx, dx, dy * dy));
+        const float tn = xs * __builtin_amdgcn_rsqf(fmaxf(__fmaf_rn(-xs, xs, 1.0f), 1e-6f));
+        const float hw = __fmaf_rn(tn, v.pad, v.hw);
         bb[g] = max((int)ceilf(u - hw), 0);
         be[g] = min((int)floorf(u + hw), A.nb - 1);
       }
@@ -469,7 +504,7 @@ __device__ void backproject_body(const BpArgs& A, int bx, int by,
 #pragma unroll
       for (int c = 0; c < kBpBinsFan; ++c) {
         const int b = min(max(bb[g] + c, 0), A.nb - 1);
-        L[g][c] = A.rays[row + b];
+        L[g][c] = A.frays[row + b];
         sv[g][c] = A.sino[row + b];
       }
     }
@@ -477,13 +512,13 @@ __device__ void backproject_body(const BpArgs& A, int bx, int by,
     for (int g = 0; g < kBpViews; ++g) {
 #pragma unroll
       for (int c = 0; c < kBpBinsFan; ++c) {
-        const float wgt = (bb[g] + c <= be[g]) ? ray_weight(L[g][c], i, j) : 0.0f;
+        const float wgt = (bb[g] + c <= be[g]) ? fan_weight(L[g][c], fi, fj) : 0.0f;
         acc = __fmaf_rn(wgt, sv[g][c], acc);
       }
       if (be[g] - bb[g] + 1 > kBpBinsFan) {
         const int64_t row = (int64_t)(k0 + g) * A.nb;
         for (int b = bb[g] + kBpBinsFan; b <= be[g]; ++b)
-          acc = __fmaf_rn(ray_weight(A.rays[row + b], i, j), A.sino[row + b], acc);
+          acc = __fmaf_rn(fan_weight(A.frays[row + b], fi, fj), A.sino[row + b], acc);
       }
     }
   }
@@ -616,7 +651,7 @@ dg_status launch_backproject(const dg_plan* p, const float* sino, float* img, hi
   dim3 grid((p->I + kBpBlockX - 1) / kBpBlockX, (p->I + rows - 1) / rows);
   dim3 block(kBpBlockX, kBpBlockY);
   BpArgs A{p->rays, p->views, sino, img, p->I, p->nv, p->nb, p->g.kind == DG_GEOM_FAN ? 1 : 0,
-           (float)p->half_diag_px, p->vrays};
+           (float)p->half_diag_px, p->vrays, p->frays};
   if (A.fan)
     hipLaunchKernelGGL(backproject_kernel<1>, grid, block, 0, s, A);
   else
