@@ -426,8 +426,9 @@ dg_status dg_psnr(int64_t n, const float* est, const float* ref, double* out, vo
  * All buffers are device memory owned by the caller.                        */
 typedef struct dg_batch dg_batch;
 
-/* Build one plan per geometry (n in 1..4096, every image side supported by
- * the preconditioner FFT, else DG_ERR_UNSUPPORTED).                         */
+/* Build one plan per distinct geometry (n in 1..4096, every image side
+ * supported by the preconditioner FFT, else DG_ERR_UNSUPPORTED); slices
+ * with equal dg_geom fields share a plan and its device tables.            */
 dg_status dg_batch_create(const dg_geom* geoms, int32_t n, dg_batch** out);
 dg_status dg_batch_destroy(dg_batch* b);
 /* Host arrays of n+1 entries: element offsets of every slice's image and

@@ -168,9 +168,23 @@ extern "C" dg_status dg_batch_destroy(dg_batch* b) {
                  b->d_pre_bp,   b->d_pre_nlm,  b->d_pre_div};
   for (int* p : pres)
     if (p) (void)hipFree(p);
-  for (dg_plan* p : b->plans) dg_plan_destroy(p);
+  // slices with one geometry share a plan: destroy each plan once
+  for (size_t k = 0; k < b->plans.size(); ++k) {
+    bool first = true;
+    for (size_t e = 0; e < k && first; ++e) first = b->plans[e] != b->plans[k];
+    if (first) dg_plan_destroy(b->plans[k]);
+  }
   delete b;
   return DG_OK;
+}
+
+// Two acquisitions with the same parameters (the plan's tables depend on
+// nothing else).
+static bool same_geometry(const dg_geom& a, const dg_geom& b) {
+  return a.kind == b.kind && a.n == b.n && a.n_views == b.n_views && a.n_bins == b.n_bins &&
+         a.pixel_mm == b.pixel_mm && a.angle0_rad == b.angle0_rad && a.span_rad == b.span_rad &&
+         a.bin_mm == b.bin_mm && a.dso_mm == b.dso_mm && a.ddo_mm == b.ddo_mm &&
+         a.dgamma_rad == b.dgamma_rad;
 }
 
 extern "C" dg_status dg_batch_create(const dg_geom* geoms, int32_t n, dg_batch** out) {
@@ -195,11 +209,18 @@ extern "C" dg_status dg_batch_create(const dg_geom* geoms, int32_t n, dg_batch**
   b->spec_off.assign(n + 1, 0);
   b->uniform_I = geoms[0].n;
   for (int s = 0; s < n; ++s) {
+    // a slice whose geometry an earlier slice has uses that slice's plan, so
+    // the kernels read one copy of its ray and view tables (C5's 16 slices
+    // share one 4 MB fan-ray table instead of gathering from 16)
     dg_plan* p = nullptr;
-    dg_status rc = dg_plan_create(&geoms[s], &p);
-    if (rc != DG_OK) {
-      dg_batch_destroy(b);
-      return rc;
+    for (int e = 0; e < s && !p; ++e)
+      if (same_geometry(geoms[e], geoms[s])) p = b->plans[e];
+    if (!p) {
+      dg_status rc = dg_plan_create(&geoms[s], &p);
+      if (rc != DG_OK) {
+        dg_batch_destroy(b);
+        return rc;
+      }
     }
     b->plans.push_back(p);
     if (!p->fft_ok) {
