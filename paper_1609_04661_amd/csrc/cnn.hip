@@ -402,11 +402,14 @@ static constexpr int kDualT = 16, kDualH = kDualT + 2;
 static constexpr int kDualRows = kDualT / kMidWaves;                // 2
 static constexpr int kDualChunks = kDualH * kDualH * 8;            // per image
 static constexpr int kDualRounds = (2 * kDualChunks + kMidThreads - 1) / kMidThreads;
+static constexpr int kDualEarly = 6;
 
 __host__ __device__ inline int dual_tiles(int n, int H, int W) {
   return n * ((H + kDualT - 1) / kDualT) * ((W + kDualT - 1) / kDualT);
 }
 
+// Rounds Q0 <= q < Q1 of a tile's halo loads into hr.
+template <int Q0 = 0, int Q1 = kDualRounds>
 __device__ __forceinline__ void dual_fetch(const bf16* __restrict__ in0, const bf16* __restrict__ in1,
                                            int tile, int tiles_x, int tiles_y, int H, int W,
                                            bf16x8 (&hr)[kDualRounds]) {
@@ -416,7 +419,7 @@ __device__ __forceinline__ void dual_fetch(const bf16* __restrict__ in0, const b
   const int64_t off = ((int64_t)img * H * W + (int64_t)y0 * W + x0) * kC;
   const bool interior = y0 >= 0 && x0 >= 0 && y0 + kDualH <= H && x0 + kDualH <= W;
 #pragma unroll
-  for (int q = 0; q < kDualRounds; ++q) {
+  for (int q = Q0; q < Q1; ++q) {
     const int e = q * kMidThreads + threadIdx.x;
     const int which = e >= kDualChunks;
     const int e2 = e - which * kDualChunks;
@@ -477,6 +480,10 @@ cnn_mid_dual_kernel(const bf16* __restrict__ in, const bf16* __restrict__ int_,
     const int y0 = (trem / tiles_x) * kDualT, x0 = (trem % tiles_x) * kDualT;
     const int64_t ibase = (int64_t)img * H * W;
     const int next = tile + gridDim.x;
+    // the first kDualEarly rounds of the next tile's halo loads are issued
+    // now and stay in flight while this tile's MFMAs run (all of them would
+    // not fit the register budget beside the accumulators)
+    if (next < ntiles) dual_fetch<0, kDualEarly>(in, int_, next, tiles_x, tiles_y, H, W, hr);
     floatx4 acc[2][kDualRows][4];
 #pragma unroll
     for (int m = 0; m < 2; ++m)
@@ -532,7 +539,7 @@ cnn_mid_dual_kernel(const bf16* __restrict__ in, const bf16* __restrict__ int_,
       }
     }
     if (next < ntiles) {
-      dual_fetch(in, int_, next, tiles_x, tiles_y, H, W, hr);
+      dual_fetch<kDualEarly, kDualRounds>(in, int_, next, tiles_x, tiles_y, H, W, hr);
       __syncthreads();  // every wavefront is done reading this tile's halos
       dual_store(sX, hr);
       __syncthreads();
