@@ -702,6 +702,40 @@ def paper_ops(api, synth, h, plain_psnr, T=50):
     return out
 
 
+def operators(api, synth):
+    """A and A^T on their own, per configured geometry: microseconds per call
+    (median of 5 timings of 20 back-to-back calls after a warm-up, device
+    inputs resident, projector segmentation tuned per plan) and ray-pixel
+    interactions per second (ray_pixel_interactions)."""
+    import torch
+    geoms = {
+        "C1 64^2 parallel, 30 views x 91": synth.c1_geometry(),
+        "C2 512^2 parallel, 64 views x 729": synth.c2_geometry(),
+        "C3 384^2 parallel, 96 views x 545": synth.geometry(synth.PARALLEL, 384, 1.0, 96, 545,
+                                                             math.pi),
+        "C5 1024^2 fan, 128 views x 1024": synth.c5_geometry(),
+    }
+    out = {}
+    gen = torch.Generator(device="cuda").manual_seed(7)
+    for name, g in geoms.items():
+        P = api.Plan(g)
+        mu = torch.rand((g["n"], g["n"]), device="cuda", generator=gen)
+        mu_t = mu.t().contiguous()
+        z = torch.rand((g["n_views"], g["n_bins"]), device="cuda", generator=gen)
+        P.autotune(mu, mu_t, reps=10)
+        zo = torch.empty_like(z)
+        go = torch.empty_like(mu)
+        for _ in range(3):
+            api.ct_project(P, mu, mu_t, sino=zo)
+            api.ct_backproject(P, z, go)
+        a = sync_time(lambda: [api.ct_project(P, mu, mu_t, sino=zo) for _ in range(20)], 5) / 20
+        at = sync_time(lambda: [api.ct_backproject(P, z, go) for _ in range(20)], 5) / 20
+        nnz = ray_pixel_interactions(g)
+        out[name] = dict(A_us=1e6 * a, At_us=1e6 * at, interactions=nnz,
+                         A_interactions_per_s=nnz / a, At_interactions_per_s=nnz / at)
+    return out
+
+
 def run_batch(api, synth, slices, phantoms, den, T, reps, autotune, net=None):
     """One batch: counts from the library's projector, Hutchinson fro2 per
     slice, graph of the whole T-iteration run; returns timing and PSNRs."""
@@ -763,10 +797,10 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--only-headline", action="store_true",
                     help="skip the learned, batched and fan-beam figures")
-    ap.add_argument("--parts", default="headline,learned,batch,fan,ablation,paper_ops",
+    ap.add_argument("--parts", default="headline,learned,batch,fan,ablation,paper_ops,operators",
                     help="comma-separated subset of headline,learned,batch,fan,ablation,paper_ops,"
-                         "proxtv (proxtv, the proximal-TV plug-ins with their alpha sweeps, is "
-                         "opt-in)")
+                         "operators,proxtv (proxtv, the proximal-TV plug-ins with their alpha "
+                         "sweeps, is opt-in)")
     ap.add_argument("--learned-iters", type=int, default=50)
     ap.add_argument("--nlm-variant", default="auto", choices=["auto", "0", "1"],
                     help="the headline's NLM tile split: tuned (auto) or fixed (0: 8 wavefronts, "
@@ -832,6 +866,9 @@ def main():
     if "paper_ops" in parts:
         print("paper ops", file=sys.stderr, flush=True)
         res["paper_ops"] = paper_ops(api, synth, h, res.get("psnr_db_after_steps"))
+    if "operators" in parts:
+        print("operators", file=sys.stderr, flush=True)
+        res["operators"] = operators(api, synth)
     if "batch" in parts:
         print("batch_uneven", file=sys.stderr, flush=True)
         res["batch_uneven"] = run_batch(api, synth, c3, phantoms[1:1 + len(c3)], "nlm",
