@@ -88,6 +88,11 @@ GEOMS = {
     # footprints span several of them
     "ragged_fan": synth.geometry(synth.FAN, 77, 0.9, 29, 311, 1.3 * math.pi, angle0_rad=0.7,
                                  dso_mm=90.0, ddo_mm=80.0),
+    # a source 4.7 pixels outside the image's circumscribed circle: fan
+    # angles up to 65 degrees (tan > 1, the back-projector's reduced angle
+    # branch) and footprints of up to 18 bins
+    "wide_fan": synth.geometry(synth.FAN, 64, 1.0, 24, 160, 2 * math.pi, dso_mm=50.0,
+                               ddo_mm=40.0),
     "c5": synth.c5_geometry(),
 }
 
@@ -132,7 +137,7 @@ def test_backproject_matches_oracle(gpu_lib, plans, name):
 
 @pytest.mark.parametrize("name", ["c1", "c2", "truncated_parallel", "fine_parallel",
                                   "odd_side_parallel", "few_views_parallel", "fan_small",
-                                  "ragged_fan"])
+                                  "ragged_fan", "wide_fan"])
 def test_gpu_adjoint_identity(gpu_lib, plans, name):
     g = GEOMS[name]
     rng = np.random.default_rng(9)
