@@ -1,5 +1,6 @@
-// Plan creation: per-ray line tables, per-view candidate-search data and FFT
-// twiddles, all derived in FP64 on the host and stored in FP32 on the device.
+// Plan creation: per-ray line tables (32.32 fixed point for the projector;
+// FP32 grain parts and remainders for the fan-beam back-projector), per-view
+// candidate-search data and FFT twiddles, all derived in FP64 on the host.
 // Error plumbing of the C ABI lives here too.
 #include <cmath>
 #include <cstdio>

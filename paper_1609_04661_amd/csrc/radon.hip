@@ -9,13 +9,14 @@
 // of the image when one is supplied, which makes their reads consecutive too.
 //
 // Back-projector: pixel-driven (fan beam: one thread per pixel; parallel
-// beam: four, each over a quarter of the views, their sums added in a fixed
-// order).  For every view it finds the few bins whose footprint covers the
-// pixel and adds weight * s for each, with the projector's chord formula:
-// fan beam from the same ray records and fixed-point positions, parallel
-// beam from the pixel's distance to each line computed in FP64 from its bin
-// coordinate (so A and A^T are adjoint to FP32 rounding); no atomics, so the
-// result is deterministic.
+// beam: a lane takes four rows of one column and sixteen lanes share a
+// column's views, their sums added in a fixed order).  For every view it
+// finds the few bins whose footprint covers the pixel and adds weight * s
+// for each, with the projector's chord formula evaluated at the pixel's
+// distance to each line: parallel beam from the view's bin-coordinate map,
+// fan beam from per-ray line records, both split into exact FP32 grain sums
+// plus one rounding (so A and A^T are adjoint to FP32 rounding); no atomics,
+// so the result is deterministic.
 #include "dg_internal.h"
 
 namespace dg {
