@@ -80,8 +80,15 @@ __global__ void __launch_bounds__(256) bm3d_zero(Bm3dArgs A, int nimg) {
 
 // ---------------------------------------------------------------- matching
 
+// candidates per work item of the matching: a lane takes kRun consecutive
+// candidates of one row and slides a kRun + kB - 1 column window of the
+// region along each block row
+static constexpr int kRun = 5;
+
 __global__ void __launch_bounds__(64) bm3d_match(Bm3dArgs A) {
-  __shared__ float reg[kReg * kReg];
+  // the region, padded so that a run's window may read past the last column
+  // (those values feed only candidates past the row's end, which are dropped)
+  __shared__ float reg[kReg * kReg + kRun + kB];
   __shared__ uint64_t keys[(2 * kNs + 1) * (2 * kNs + 1)];
   const int img = blockIdx.y;
   const float* r = bm3d_in(A, img);
@@ -95,18 +102,43 @@ __global__ void __launch_bounds__(64) bm3d_match(Bm3dArgs A) {
   const float thr = (float)(kTauMatch * *A.tau_r);
   const int ny = yb - ya + 1, nx = xb - xa + 1, nc = ny * nx;
   const int oy = yr - ya, ox = xr - xa;
-  for (int c = lane; c < nc; c += 64) {
-    const int cy = c / nx, cx = c % nx;
-    float acc = 0.0f;
-    for (int u = 0; u < kB; ++u)
-      for (int v = 0; v < kB; ++v) {
-        const float t = __fsub_rn(reg[(oy + u) * kReg + ox + v], reg[(cy + u) * kReg + cx + v]);
-        acc = __fadd_rn(acc, __fmul_rn(t, t));
-      }
-    const float d = __fmul_rn(acc, 1.0f / 64.0f);
-    const bool self = (cy == oy && cx == ox);
-    const uint32_t pos = (uint32_t)((ya + cy) * I + xa + cx);
-    keys[c] = (d <= thr && !self) ? (((uint64_t)__float_as_uint(d) << 32) | pos) : ~0ull;
+  // the reference block in registers (the same 64 values in every lane)
+  float rv[kB2];
+#pragma unroll
+  for (int u = 0; u < kB; ++u)
+#pragma unroll
+    for (int v = 0; v < kB; ++v) rv[u * kB + v] = reg[(oy + u) * kReg + ox + v];
+  // each candidate's sum runs over u, then v, each product rounded then
+  // added: the same order and roundings as one candidate at a time
+  const int runs = (nx + kRun - 1) / kRun;
+  for (int it = lane; it < ny * runs; it += 64) {
+    const int cy = it / runs, cx0 = (it - cy * runs) * kRun;
+    float acc[kRun];
+#pragma unroll
+    for (int k = 0; k < kRun; ++k) acc[k] = 0.0f;
+#pragma unroll
+    for (int u = 0; u < kB; ++u) {
+      float w[kRun + kB - 1];
+      const float* rowp = reg + (cy + u) * kReg + cx0;
+#pragma unroll
+      for (int e = 0; e < kRun + kB - 1; ++e) w[e] = rowp[e];
+#pragma unroll
+      for (int v = 0; v < kB; ++v)
+#pragma unroll
+        for (int k = 0; k < kRun; ++k) {
+          const float t = __fsub_rn(rv[u * kB + v], w[k + v]);
+          acc[k] = __fadd_rn(acc[k], __fmul_rn(t, t));
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < kRun; ++k) {
+      const int cx = cx0 + k;
+      if (cx >= nx) break;
+      const float d = __fmul_rn(acc[k], 1.0f / 64.0f);
+      const bool self = (cy == oy && cx == ox);
+      const uint32_t pos = (uint32_t)((ya + cy) * I + xa + cx);
+      keys[cy * nx + cx] = (d <= thr && !self) ? (((uint64_t)__float_as_uint(d) << 32) | pos) : ~0ull;
+    }
   }
   __syncthreads();
   int* g = A.grp + ((int64_t)img * A.na * A.na + q) * kN2;
