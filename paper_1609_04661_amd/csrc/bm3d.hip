@@ -89,7 +89,6 @@ __global__ void __launch_bounds__(64) bm3d_match(Bm3dArgs A) {
   // the region, padded so that a run's window may read past the last column
   // (those values feed only candidates past the row's end, which are dropped)
   __shared__ float reg[kReg * kReg + kRun + kB];
-  __shared__ uint64_t keys[(2 * kNs + 1) * (2 * kNs + 1)];
   const int img = blockIdx.y;
   const float* r = bm3d_in(A, img);
   const int I = A.I, q = blockIdx.x, lane = threadIdx.x;
@@ -97,7 +96,9 @@ __global__ void __launch_bounds__(64) bm3d_match(Bm3dArgs A) {
   const int ya = max(0, yr - kNs), yb = min(I - kB, yr + kNs);  // candidate rows
   const int xa = max(0, xr - kNs), xb = min(I - kB, xr + kNs);
   const int ry = yb - ya + kB, rx = xb - xa + kB;              // region extent <= 46
-  for (int e = lane; e < ry * rx; e += 64) reg[(e / rx) * kReg + e % rx] = r[(int64_t)(ya + e / rx) * I + xa + e % rx];
+  // the region row by row (rx <= 46 < 64: one column per lane)
+  for (int y = 0; y < ry; ++y)
+    if (lane < rx) reg[y * kReg + lane] = r[(int64_t)(ya + y) * I + xa + lane];
   __syncthreads();
   const float thr = (float)(kTauMatch * *A.tau_r);
   const int ny = yb - ya + 1, nx = xb - xa + 1, nc = ny * nx;
@@ -111,7 +112,16 @@ __global__ void __launch_bounds__(64) bm3d_match(Bm3dArgs A) {
   // each candidate's sum runs over u, then v, each product rounded then
   // added: the same order and roundings as one candidate at a time
   const int runs = (nx + kRun - 1) / kRun;
-  for (int it = lane; it < ny * runs; it += 64) {
+  // this lane's keys (its work items it = lane + 64 j) and their minimum
+  constexpr int kItems = ((2 * kNs + 1) * ((2 * kNs + 1 + kRun - 1) / kRun) + 63) / 64;
+  uint64_t lk[kItems][kRun];
+  uint64_t lmin = ~0ull;
+#pragma unroll
+  for (int j = 0; j < kItems; ++j) {
+#pragma unroll
+    for (int k = 0; k < kRun; ++k) lk[j][k] = ~0ull;
+    const int it = lane + 64 * j;
+    if (it >= ny * runs) continue;
     const int cy = it / runs, cx0 = (it - cy * runs) * kRun;
     float acc[kRun];
 #pragma unroll
@@ -137,26 +147,39 @@ __global__ void __launch_bounds__(64) bm3d_match(Bm3dArgs A) {
       const float d = __fmul_rn(acc[k], 1.0f / 64.0f);
       const bool self = (cy == oy && cx == ox);
       const uint32_t pos = (uint32_t)((ya + cy) * I + xa + cx);
-      keys[cy * nx + cx] = (d <= thr && !self) ? (((uint64_t)__float_as_uint(d) << 32) | pos) : ~0ull;
+      const uint64_t key = (d <= thr && !self) ? (((uint64_t)__float_as_uint(d) << 32) | pos) : ~0ull;
+      lk[j][k] = key;
+      lmin = key < lmin ? key : lmin;
     }
   }
-  __syncthreads();
+  // the kN2 - 1 smallest keys in ascending order.  Keys are unique (the
+  // position is in the low word), so a lane whose minimum is taken finds
+  // its next one as the smallest of its own keys above the one taken; the
+  // other lanes keep theirs.  Each round: a wavefront minimum over the 64
+  // lane minima, and one lane's rescan of its ~25 keys.
   int* g = A.grp + ((int64_t)img * A.na * A.na + q) * kN2;
   int cnt = 1;
   if (lane == 0) g[0] = yr * I + xr;
   for (int k = 1; k < kN2; ++k) {
-    uint64_t best = ~0ull;
-    for (int c = lane; c < nc; c += 64) best = keys[c] < best ? keys[c] : best;
+    uint64_t best = lmin;
     for (int o = 32; o > 0; o >>= 1) {
       const uint64_t other = __shfl_xor(best, o, 64);
       best = other < best ? other : best;
     }
     if (best == ~0ull) break;  // wavefront-uniform
     if (lane == 0) g[k] = (int)(uint32_t)best;
-    for (int c = lane; c < nc; c += 64)
-      if (keys[c] == best) keys[c] = ~0ull;
     ++cnt;
-    __syncthreads();
+    if (lmin == best) {
+      uint64_t next = ~0ull;
+#pragma unroll
+      for (int j = 0; j < kItems; ++j)
+#pragma unroll
+        for (int k = 0; k < kRun; ++k) {
+          const uint64_t key = lk[j][k];
+          next = (key > best && key < next) ? key : next;
+        }
+      lmin = next;
+    }
   }
   int p2 = 1;
   while (2 * p2 <= cnt) p2 *= 2;
