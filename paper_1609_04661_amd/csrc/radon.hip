@@ -130,40 +130,70 @@ __device__ void project_body(const ProjArgs& A, int blk, float (*part)[kRaysPerB
     const unsigned skb = (unsigned)sk * 4u, spb = (unsigned)sp * 4u;
     uint32_t qlo = (uint32_t)(uint64_t)q, qhi = (uint32_t)((uint64_t)q >> 32);
     const uint32_t mlo = (uint32_t)(uint64_t)L.m_fx, mhi = (uint32_t)((uint64_t)L.m_fx >> 32);
-    for (int k = ka; k <= kb; k += kMarch) {
-      float v[2 * kMarch], w[2 * kMarch];
-#pragma unroll
-      for (int u = 0; u < kMarch; ++u) {
-        const int kk = k + u;
-        // q in 32.32 fixed point as two words; advancing it is one add with
-        // carry, and floor(q), q - floor(q) are its words (split_fx)
-        const int p0 = (int)qhi;
-        const float f = (float)qlo * 2.3283064365386962890625e-10f;  // 2^-32
-        const uint32_t nlo = qlo + mlo;
-        qhi += mhi + (nlo < qlo ? 1u : 0u);
-        qlo = nlo;
-        // chord_fraction's general branch, written out so both candidates of
-        // all steps are formed before any load is consumed
-        float g0 = fminf(fmaxf(__fmul_rn(hw - f, L.inv_r), 0.0f), 1.0f);
-        const float d1 = 1.0f - f;
-        float g1 = fminf(fmaxf(__fmul_rn(hw - d1, L.inv_r), 0.0f), 1.0f);
-        if (axis) {
-          g0 = wc0;
-          g1 = wc1;
-        }
-        w[2 * u] = g0;
-        w[2 * u + 1] = g1;
-        const bool live = kk <= kb;
-        // 24-bit multiplies (full rate): kk < I and p0 + 1 lies in [0, I]
-        // whenever an offset is used, and both strides are at most 4 I bytes
-        const unsigned o1 = boff + __umul24((unsigned)kk, skb) + __umul24((unsigned)(p0 + 1), spb);
-        const unsigned off0 = (live && (unsigned)p0 < (unsigned)I) ? o1 - spb : 0xffffffffu;
-        const unsigned off1 = (live && (unsigned)(p0 + 1) < (unsigned)I) ? o1 : 0xffffffffu;
-        v[2 * u] = __int_as_float(__builtin_amdgcn_raw_buffer_load_b32(img, off0, 0, 0));
-        v[2 * u + 1] = __int_as_float(__builtin_amdgcn_raw_buffer_load_b32(img, off1, 0, 0));
+    // one step: both candidates' weights (chord_fraction's general branch,
+    // written out so that the candidates of all steps of a group are formed
+    // before any load is consumed) and the 24-bit offset of the second
+    // (full-rate multiplies: kk < I and p0 + 1 lies in [0, I] whenever an
+    // offset is used, and both strides are at most 4 I bytes)
+    auto step = [&](int kk, int& p0, float& g0, float& g1, unsigned& o1) {
+      p0 = (int)qhi;
+      const float f = (float)qlo * 2.3283064365386962890625e-10f;  // 2^-32
+      const uint32_t nlo = qlo + mlo;
+      qhi += mhi + (nlo < qlo ? 1u : 0u);
+      qlo = nlo;
+      g0 = fminf(fmaxf(__fmul_rn(hw - f, L.inv_r), 0.0f), 1.0f);
+      const float d1 = 1.0f - f;
+      g1 = fminf(fmaxf(__fmul_rn(hw - d1, L.inv_r), 0.0f), 1.0f);
+      if (axis) {
+        g0 = wc0;
+        g1 = wc1;
       }
+      o1 = boff + __umul24((unsigned)kk, skb) + __umul24((unsigned)(p0 + 1), spb);
+    };
+    if (use_t) {
+      // every ray reads a buffer laid out with its major index as the row
+      // (spb = 4), so its two candidates are adjacent words: one 64-bit
+      // read per step.  At the image's edge the read moves onto the valid
+      // candidate and the other value is 0 (the word beside it belongs to
+      // a neighbouring row); a step with neither candidate inside reads
+      // past the buffer (0).
+      for (int k = ka; k <= kb; k += kMarch) {
+        float v[2 * kMarch], w[2 * kMarch];
 #pragma unroll
-      for (int e = 0; e < 2 * kMarch; ++e) acc = __fmaf_rn(w[e], v[e], acc);
+        for (int u = 0; u < kMarch; ++u) {
+          const int kk = k + u;
+          int p0;
+          unsigned o1;
+          step(kk, p0, w[2 * u], w[2 * u + 1], o1);
+          const bool live = kk <= kb;
+          const bool in0 = (unsigned)p0 < (unsigned)I, in1 = (unsigned)(p0 + 1) < (unsigned)I;
+          const unsigned off = (live && (in0 || in1)) ? (in0 ? o1 - 4u : o1) : 0xfffffff0u;
+          const auto w2 = __builtin_amdgcn_raw_buffer_load_b64(img, off, 0, 0);
+          const float a = __int_as_float((int)w2[0]), b = __int_as_float((int)w2[1]);
+          v[2 * u] = in0 ? a : 0.0f;
+          v[2 * u + 1] = in0 ? (in1 ? b : 0.0f) : a;
+        }
+#pragma unroll
+        for (int e = 0; e < 2 * kMarch; ++e) acc = __fmaf_rn(w[e], v[e], acc);
+      }
+    } else {
+      for (int k = ka; k <= kb; k += kMarch) {
+        float v[2 * kMarch], w[2 * kMarch];
+#pragma unroll
+        for (int u = 0; u < kMarch; ++u) {
+          const int kk = k + u;
+          int p0;
+          unsigned o1;
+          step(kk, p0, w[2 * u], w[2 * u + 1], o1);
+          const bool live = kk <= kb;
+          const unsigned off0 = (live && (unsigned)p0 < (unsigned)I) ? o1 - spb : 0xffffffffu;
+          const unsigned off1 = (live && (unsigned)(p0 + 1) < (unsigned)I) ? o1 : 0xffffffffu;
+          v[2 * u] = __int_as_float(__builtin_amdgcn_raw_buffer_load_b32(img, off0, 0, 0));
+          v[2 * u + 1] = __int_as_float(__builtin_amdgcn_raw_buffer_load_b32(img, off1, 0, 0));
+        }
+#pragma unroll
+        for (int e = 0; e < 2 * kMarch; ++e) acc = __fmaf_rn(w[e], v[e], acc);
+      }
     }
   }
   part[seg][lane] = acc;
