@@ -153,10 +153,11 @@ __device__ void project_body(const ProjArgs& A, int blk, float (*part)[kRaysPerB
     if (use_t) {
       // every ray reads a buffer laid out with its major index as the row
       // (spb = 4), so its two candidates are adjacent words: one 64-bit
-      // read per step.  At the image's edge the read moves onto the valid
-      // candidate and the other value is 0 (the word beside it belongs to
-      // a neighbouring row); a step with neither candidate inside reads
-      // past the buffer (0).
+      // read per step.  Each read stays inside row kk: with p0 = -1 it
+      // takes words 0 and 1, with p0 = I - 1 words I - 2 and I - 1 (the
+      // word after the last one can lie past the image's allocation), and
+      // the candidate outside the image gets 0.  A step with neither
+      // candidate inside reads past the resource (0).
       for (int k = ka; k <= kb; k += kMarch) {
         float v[2 * kMarch], w[2 * kMarch];
 #pragma unroll
@@ -167,11 +168,12 @@ __device__ void project_body(const ProjArgs& A, int blk, float (*part)[kRaysPerB
           step(kk, p0, w[2 * u], w[2 * u + 1], o1);
           const bool live = kk <= kb;
           const bool in0 = (unsigned)p0 < (unsigned)I, in1 = (unsigned)(p0 + 1) < (unsigned)I;
-          const unsigned off = (live && (in0 || in1)) ? (in0 ? o1 - 4u : o1) : 0xfffffff0u;
+          const unsigned off =
+              (live && (in0 || in1)) ? (in1 ? (in0 ? o1 - 4u : o1) : o1 - 8u) : 0xfffffff0u;
           const auto w2 = __builtin_amdgcn_raw_buffer_load_b64(img, off, 0, 0);
           const float a = __int_as_float((int)w2[0]), b = __int_as_float((int)w2[1]);
-          v[2 * u] = in0 ? a : 0.0f;
-          v[2 * u + 1] = in0 ? (in1 ? b : 0.0f) : a;
+          v[2 * u] = in0 ? (in1 ? a : b) : 0.0f;
+          v[2 * u + 1] = in1 ? (in0 ? b : a) : 0.0f;
         }
 #pragma unroll
         for (int e = 0; e < 2 * kMarch; ++e) acc = __fmaf_rn(w[e], v[e], acc);
