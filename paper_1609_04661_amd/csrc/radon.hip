@@ -153,27 +153,48 @@ __device__ void project_body(const ProjArgs& A, int blk, float (*part)[kRaysPerB
     if (use_t) {
       // every ray reads a buffer laid out with its major index as the row
       // (spb = 4), so its two candidates are adjacent words: one 64-bit
-      // read per step.  Each read stays inside row kk: with p0 = -1 it
-      // takes words 0 and 1, with p0 = I - 1 words I - 2 and I - 1 (the
-      // word after the last one can lie past the image's allocation), and
-      // the candidate outside the image gets 0.  A step with neither
-      // candidate inside reads past the resource (0).
-      for (int k = ka; k <= kb; k += kMarch) {
+      // read per step, of words c and c + 1 of row kk with c = p0 clamped
+      // to [0, I - 2], which never leaves the row (the word after the last
+      // one can lie past the image's allocation).  Each word takes the
+      // chord rule at its own distance from the line, f + (p0 - c) and
+      // f + (p0 - c - 1): for c = p0 these are the two candidates' f and
+      // 1 - f, at the row's ends one word is the in-image candidate (its
+      // distance formed exactly) and the other lies a pixel or more from
+      // the line (weight 0).  Axis-aligned rays take the same expression
+      // with 1/|m| = 2^64 and 1/2 added, which gives their step rule (1
+      // inside, 1/2 at distance 1/2, 0 beyond).  A step with no candidate
+      // inside reads past the resource (0).
+      const float ir = axis ? 0x1p64f : L.inv_r;
+      const float oc = axis ? 0.5f : 0.0f;
+      const int cmax = I - 2;
+      // the march bounds are the same in every lane (a wavefront's union
+      // range and its segment): in scalar registers, a step's row offset
+      // kk * 4 I is scalar work
+      const int kau = __builtin_amdgcn_readfirstlane(ka);
+      const int kbu = __builtin_amdgcn_readfirstlane(kb);
+      uint64_t qq = (uint64_t)q;
+      const uint64_t mq = (uint64_t)L.m_fx;
+      for (int k = kau; k <= kbu; k += kMarch) {
         float v[2 * kMarch], w[2 * kMarch];
 #pragma unroll
         for (int u = 0; u < kMarch; ++u) {
           const int kk = k + u;
-          int p0;
-          unsigned o1;
-          step(kk, p0, w[2 * u], w[2 * u + 1], o1);
-          const bool live = kk <= kb;
-          const bool in0 = (unsigned)p0 < (unsigned)I, in1 = (unsigned)(p0 + 1) < (unsigned)I;
-          const unsigned off =
-              (live && (in0 || in1)) ? (in1 ? (in0 ? o1 - 4u : o1) : o1 - 8u) : 0xfffffff0u;
+          const int p0 = (int)(uint32_t)(qq >> 32);
+          const float f = (float)(uint32_t)qq * 2.3283064365386962890625e-10f;  // 2^-32
+          qq += mq;
+          // an empty statement that keeps the compiler from replacing this
+          // one running sum by a separate 64-bit sum per unrolled step
+          asm volatile("" : "+v"(qq));
+          const int c = min(max(p0, 0), cmax);
+          const float fd = (float)(p0 - c);
+          const float xa = f + fd, xb = f + (fd - 1.0f);
+          w[2 * u] = fminf(fmaxf(__fmaf_rn(hw - fabsf(xa), ir, oc), 0.0f), 1.0f);
+          w[2 * u + 1] = fminf(fmaxf(__fmaf_rn(hw - fabsf(xb), ir, oc), 0.0f), 1.0f);
+          const bool ok = kk <= kbu && (unsigned)p0 + 1u <= (unsigned)I;
+          const unsigned off = ok ? boff + (unsigned)kk * skb + ((unsigned)c << 2) : 0xfffffff0u;
           const auto w2 = __builtin_amdgcn_raw_buffer_load_b64(img, off, 0, 0);
-          const float a = __int_as_float((int)w2[0]), b = __int_as_float((int)w2[1]);
-          v[2 * u] = in0 ? (in1 ? a : b) : 0.0f;
-          v[2 * u + 1] = in1 ? (in0 ? b : a) : 0.0f;
+          v[2 * u] = __int_as_float((int)w2[0]);
+          v[2 * u + 1] = __int_as_float((int)w2[1]);
         }
 #pragma unroll
         for (int e = 0; e < 2 * kMarch; ++e) acc = __fmaf_rn(w[e], v[e], acc);
