@@ -66,7 +66,9 @@ NLM_TRAFFIC_BYTES = 7.253e6
 # passes; profiles/radon_nlm_c2_512x512_64views_counters.md).  Set to None
 # when either kernel changes until the counters are taken again.
 A_AT_COUNTERS = {
-    "A (project_kernel<8> + output channel)": None,
+    "A (project_kernel<8> + output channel)": {"us": 16.56, "valu_issue_frac": 0.70,
+                                               "valu_instr_per_interaction": 21.8,
+                                               "ta_busy_frac": 0.52},
     "At (backproject_kernel<0>)": {"us": 11.34, "valu_issue_frac": 0.87,
                                    "valu_instr_per_pixel_view": 23.2, "ta_busy_frac": 0.64}}
 # dampings tried per denoiser for the time-to-equal-PSNR comparison (above
