@@ -125,6 +125,31 @@ def test_project_matches_oracle(gpu_lib, plans, name):
 
 
 @pytest.mark.parametrize("name", list(GEOMS))
+def test_projector_transposed_copy_is_bit_identical(gpu_lib, plans, name):
+    """Given the transposed copy, every ray reads both candidates of a step as
+    one 64-bit word, clamped into its row at the image's ends, and each word
+    is weighted at its own distance from the line.  Without the copy it
+    makes two 32-bit reads.  The weights and the summation order are the
+    same, so the sinograms agree bit for bit wherever the copy lies: below
+    or above the image in one buffer, or in an allocation of its own (the
+    word after the lower buffer's last row is never read)."""
+    g = GEOMS[name]
+    P = plans[name]
+    I = g["n"]
+    img = cu(image_for(name, g, seed=23))
+    ref = host(gpu_lib.ct_project(P, img))
+    both = torch.empty(2 * I * I, dtype=torch.float32, device="cuda")
+    for t_below in (True, False):
+        lo, hi = both[:I * I], both[I * I:]
+        t_buf, m_buf = (lo, hi) if t_below else (hi, lo)
+        t_buf.copy_(img.t().contiguous().reshape(-1))
+        m_buf.copy_(img.reshape(-1))
+        out = host(gpu_lib.ct_project(P, m_buf.view(I, I), t_buf.view(I, I)))
+        assert np.array_equal(out, ref), (name, t_below)
+    assert np.array_equal(host(gpu_lib.ct_project(P, img, img.t().contiguous())), ref)
+
+
+@pytest.mark.parametrize("name", list(GEOMS))
 def test_backproject_matches_oracle(gpu_lib, plans, name):
     g = GEOMS[name]
     R = radon.Radon(g)
