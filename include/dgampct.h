@@ -97,9 +97,10 @@ const char* dg_last_error(void);
  * exactly on a pixel edge gives half of its length to each neighbour.
  * img: I*I floats; sino: n_views*n_bins floats (mm * 1/mm = dimensionless).
  * img_t: optional transposed copy of img (img_t[j*I+i] = img[i*I+j]) that
- * makes the reads of near-horizontal rays coalesced; NULL = derive it
- * internally (needs no workspace: a transposed copy is not made, the slower
- * strided read path is used).                                               */
+ * makes the reads of near-horizontal rays coalesced.  NULL: no copy is made
+ * and those rays read img with a stride of I floats, several times slower
+ * (512^2, 64 views: about 88 us against 16 us).  The sinogram is the same
+ * bit for bit either way, wherever img_t lies in memory.                    */
 dg_status ct_project(const dg_plan* plan, const float* img, const float* img_t,
                      float* sino, void* stream);
 
