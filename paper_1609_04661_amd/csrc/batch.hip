@@ -113,7 +113,9 @@ struct dg_batch {
 };
 
 static size_t batch_work_layout(const dg_batch* b, void* base, char** parts) {
-  // parts: spec, mu, mu_t, z, g, r, xden, xpert, dpart, fpart, npart (NLM
+  // parts: spec, mu and mu^T (each slice's pair side by side, so that the
+  // projector's buffer resource spans the two at any batch size), unused,
+  // z, g, r, xden, xpert, dpart, fpart, npart (NLM
   // divergence partials, per-slice offsets pre_nlm), ppart (the projector's
   // fused-channel partials, offsets pre_proj)
   char* c = (char*)base;
@@ -126,8 +128,8 @@ static size_t batch_work_layout(const dg_batch* b, void* base, char** parts) {
   const size_t nb = sizeof(float) * (size_t)b->totN, mb = sizeof(float) * (size_t)b->totM;
   char* tmp[12];
   tmp[0] = take(sizeof(float2) * (size_t)b->totSpec);
-  tmp[1] = take(nb);
-  tmp[2] = take(nb);
+  tmp[1] = take(2 * nb);
+  tmp[2] = nullptr;
   tmp[3] = take(mb);
   tmp[4] = take(nb);
   tmp[5] = take(nb);
@@ -303,8 +305,8 @@ extern "C" dg_status dg_batch_bind(dg_batch* b, const float* y, const double* i0
   char* parts[12];
   batch_work_layout(b, work, parts);
   float2* spec = (float2*)parts[0];
+  // slice k's mu at 2 img_off[k], its transpose right after it
   float* mu = (float*)parts[1];
-  float* mu_t = (float*)parts[2];
   float* z = (float*)parts[3];
   float* g = (float*)parts[4];
   float* r = (float*)parts[5];
@@ -342,10 +344,12 @@ extern "C" dg_status dg_batch_bind(dg_batch* b, const float* y, const double* i0
                               ? DivFinish{np_k, nb_k, (double)p->N, sc + DG_S_EPS, sc}
                               : DivFinish{}};
     cols[k] = ColsArgs{sp, p->twiddle, I, 1};
-    ri_mu[k] = RowsInvArgs{sp, p->twiddle, I, PREC_PLAIN, mu + io, mu_t + io, nullptr, nullptr,
+    float* mu_k = mu + 2 * io;
+    float* mu_t_k = mu_k + p->N;
+    ri_mu[k] = RowsInvArgs{sp, p->twiddle, I, PREC_PLAIN, mu_k, mu_t_k, nullptr, nullptr,
                            nullptr};
     ri_r[k] = RowsInvArgs{sp, p->twiddle, I, PREC_UPDATE_R, r + io, nullptr, x + io, sc, fp};
-    ri_out[k] = RowsInvArgs{sp, p->twiddle, I, PREC_PLAIN, mu_out ? mu_out + io : mu + io, nullptr,
+    ri_out[k] = RowsInvArgs{sp, p->twiddle, I, PREC_PLAIN, mu_out ? mu_out + io : mu_k, nullptr,
                             nullptr, nullptr, nullptr};
     eps[k] = EpsArgs{fp, prec_row_blocks(I), eps_rel, sc + DG_S_EPS};
     // the output channel runs in the projector's epilogue (projc); proj is
@@ -353,8 +357,8 @@ extern "C" dg_status dg_batch_bind(dg_batch* b, const float* y, const double* i0
     chan[k] = ChanArgs{p->M,    nullptr,  y + so,       s + so,       nullptr,
                        nullptr, sc,       nullptr,      i0[k],        fro2[k],
                        (double)p->N, ppart + b->pre_proj[k], b->pre_proj[k + 1] - b->pre_proj[k]};
-    proj[k] = ProjArgs{p->rays, mu + io, mu_t + io, z + so, I, p->M, 0, ChanArgs{}};
-    projc[k] = ProjArgs{p->rays, mu + io, mu_t + io, z + so, I, p->M, 1, chan[k]};
+    proj[k] = ProjArgs{p->rays, mu_k, mu_t_k, z + so, I, p->M, 0, ChanArgs{}};
+    projc[k] = ProjArgs{p->rays, mu_k, mu_t_k, z + so, I, p->M, 1, chan[k]};
     // the channel finish runs in the slice's first row workgroup of V^-1 g
     rf_g[k] = RowsFwdArgs{g + io, sp, p->twiddle, I, 1, chan[k], DivFinish{}};
     bp[k] = BpArgs{p->rays, p->views, s + so, g + io, I, p->nv, p->nb,
