@@ -6,7 +6,9 @@
 // q(k) = q0 + m k, candidates floor(q) and floor(q) + 1).  Threads of a
 // wavefront hold consecutive bins of one view, so for steep rays they read
 // consecutive columns of one image row.  Flat rays read the transposed copy
-// of the image when one is supplied, which makes their reads consecutive too.
+// of the image when one is supplied, which makes their reads consecutive too;
+// with it, every step reads its two candidates as one 64-bit word of its row
+// and weights each word at its own distance from the line (project_body).
 //
 // Back-projector: pixel-driven (fan beam: one thread per pixel; parallel
 // beam: a lane takes four rows of one column and sixteen lanes share a
