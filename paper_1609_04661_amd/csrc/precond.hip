@@ -255,12 +255,18 @@ __device__ void rows_inv_body(const RowsInvArgs& A, int blk, FftShared& S) {
   }
   if (A.out_t) {
     __syncthreads();
-    for (int idx = threadIdx.x; idx < I * kRowsPerBlock; idx += blockDim.x) {
-      const int t = idx / kRowsPerBlock, c = idx % kRowsPerBlock;
-      const int row = blk * kRowsPerBlock + c;
+    // the transposed copy, four rows per 16-byte store: rows 4q .. 4q + 3 of
+    // this block are wavefronts 2q and 2q + 1's row pairs.  Every supported
+    // side is a multiple of 4, so a group of four rows lies wholly inside the
+    // image or wholly past it, and each store is 16-byte aligned.
+    static_assert(kRowsPerBlock == 8, "two groups of four rows per block");
+    for (int idx = threadIdx.x; idx < I * 2; idx += blockDim.x) {
+      const int t = idx >> 1, q = idx & 1;
+      const int row = blk * kRowsPerBlock + 4 * q;
       if (row < I) {
-        const float2 v = S.buf[c >> 1][1][t];
-        A.out_t[(int64_t)t * I + row] = (c & 1) ? v.y : v.x;
+        const float2 a = S.buf[2 * q][1][t], b = S.buf[2 * q + 1][1][t];
+        *reinterpret_cast<float4*>(A.out_t + (int64_t)t * I + row) =
+            make_float4(a.x, a.y, b.x, b.y);
       }
     }
   }
