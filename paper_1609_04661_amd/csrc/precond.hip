@@ -91,10 +91,16 @@ __device__ void rows_fwd_body(const RowsFwdArgs& A, int blk, FftShared& S, int f
     }
   }
   __syncthreads();
-  for (int idx = threadIdx.x; idx < half * kRowsPerBlock; idx += blockDim.x) {
-    const int k = idx / kRowsPerBlock, c = idx % kRowsPerBlock;
-    const int row = blk * kRowsPerBlock + c;
-    if (row < I) A.spec[(int64_t)k * I + row] = S.buf[c >> 1][1][(c & 1) * half + k];
+  // the spectrum block, one 16-byte store per row pair: rows 2w and 2w + 1
+  // are wavefront w's pair (I is even, and every slice's spectrum and row
+  // offset keeps the store 16-byte aligned)
+  for (int idx = threadIdx.x; idx < half * (kRowsPerBlock / 2); idx += blockDim.x) {
+    const int k = idx >> 2, w = idx & 3;
+    const int row = blk * kRowsPerBlock + 2 * w;
+    if (row < I) {
+      const float2 lo = S.buf[w][1][k], hi = S.buf[w][1][half + k];
+      *reinterpret_cast<float4*>(A.spec + (int64_t)k * I + row) = make_float4(lo.x, lo.y, hi.x, hi.y);
+    }
   }
 }
 
@@ -177,15 +183,17 @@ __device__ void rows_inv_body(const RowsInvArgs& A, int blk, FftShared& S) {
   const bool reg = I == 512 || I == 256;
   // every global load of the workgroup (its spectrum block and, for the r
   // update, its rows of x) is issued before the twiddles are staged
-  constexpr int kSpecPer = (kMaxFft / 2 + 1) * kRowsPerBlock / kFftThreads + 1;
-  float2 sv[kSpecPer];
+  // one 16-byte load per row pair (rows 2w, 2w + 1 of column k)
+  constexpr int kSpecPer = (kMaxFft / 2 + 1) * (kRowsPerBlock / 2) / kFftThreads + 1;
+  float4 sv[kSpecPer];
 #pragma unroll
   for (int q = 0; q < kSpecPer; ++q) {
     const int idx = threadIdx.x + kFftThreads * q;
-    const int k = idx / kRowsPerBlock, c = idx % kRowsPerBlock;
-    const int row = blk * kRowsPerBlock + c;
-    sv[q] = make_float2(0.0f, 0.0f);
-    if (idx < half * kRowsPerBlock && row < I) sv[q] = A.spec[(int64_t)k * I + row];
+    const int k = idx >> 2, w = idx & 3;
+    const int row = blk * kRowsPerBlock + 2 * w;
+    sv[q] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+    if (idx < half * (kRowsPerBlock / 2) && row < I)
+      sv[q] = *reinterpret_cast<const float4*>(A.spec + (int64_t)k * I + row);
   }
   float xa[kPerLane], xb[kPerLane];
   if (upd && live) {
@@ -202,8 +210,11 @@ __device__ void rows_inv_body(const RowsInvArgs& A, int blk, FftShared& S) {
 #pragma unroll
   for (int q = 0; q < kSpecPer; ++q) {
     const int idx = threadIdx.x + kFftThreads * q;
-    const int k = idx / kRowsPerBlock, c = idx % kRowsPerBlock;
-    if (idx < half * kRowsPerBlock) S.buf[c >> 1][1][(c & 1) * half + k] = sv[q];
+    const int k = idx >> 2, w = idx & 3;
+    if (idx < half * (kRowsPerBlock / 2)) {
+      S.buf[w][1][k] = make_float2(sv[q].x, sv[q].y);
+      S.buf[w][1][half + k] = make_float2(sv[q].z, sv[q].w);
+    }
   }
   __syncthreads();
   float2* a = S.buf[w][0];
