@@ -38,6 +38,7 @@ dg_status tvw_launch_denoise(const dg_plan* p, const void* params, const float* 
 static constexpr int kMaxP = 3, kMaxS = 10;
 static constexpr int kNlmTile = 32;
 static constexpr int kNlmRegion = kNlmTile + 2 * (kMaxS + kMaxP);  // 58
+static_assert(kNlmRegion <= 64, "the staging loop gives each region column a lane");
 static constexpr int kNlmPitch = kNlmRegion + 1;
 static constexpr int kRedBlock = 256;
 static constexpr int kRedMaxBlocks = 1024;
@@ -235,16 +236,20 @@ __device__ void nlm_body(const NlmArgs& Ar, int bx, int by, int img, uint64_t se
   const bool smooth = sig2 > 0.0f && c1 <= 3.0e38f;
   const float kscale = smooth ? sqrtf(c1) : 1.0f;
   const float c2 = l2e_h2 * 2.0f * sig2;
-  for (int e = threadIdx.x; e < WR * WR; e += blockDim.x) {
-    const int ri = e / WR, rj = e % WR;
-    const int gi = reflect_idx(ty0 - H0 + ri, I), gj = reflect_idx(tx0 - H0 + rj, I);
-    const int64_t gidx = (int64_t)gi * I + gj;
-    float v = r[gidx];
-    if (img) v = __fmaf_rn(eps, probe_sign(seed, iter, (uint64_t)gidx), v);
-    R[ri * kNlmPitch + rj] = v * kscale;
+  const int lane = threadIdx.x & 63, g = threadIdx.x >> 6;
+  // the region, a row per wavefront and a column per lane (WR <= 58 < 64):
+  // each lane reflects its column once, each wavefront its row once per row
+  if (lane < WR) {
+    const int gj = reflect_idx(tx0 - H0 + lane, I);
+    for (int ri = g; ri < WR; ri += W) {
+      const int gi = reflect_idx(ty0 - H0 + ri, I);
+      const int64_t gidx = (int64_t)gi * I + gj;
+      float v = r[gidx];
+      if (img) v = __fmaf_rn(eps, probe_sign(seed, iter, (uint64_t)gidx), v);
+      R[ri * kNlmPitch + lane] = v * kscale;
+    }
   }
   __syncthreads();
-  const int lane = threadIdx.x & 63, g = threadIdx.x >> 6;
   const int ox0 = (lane & 15) * BX, oy0 = (lane >> 4) * BY;  // tile-relative block origin
   // an output value: stored, and with the fused divergence, x damped towards
   // D(r) (image 0) and -+ b v added to this thread's partial
