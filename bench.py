@@ -61,7 +61,7 @@ CFG = dict(i0=1e5, seed=1002, probe_seed=7, eta=0.15, tau_x0=1.0, fro2_probes=16
 # counter passes (FETCH_SIZE, WRITE_SIZE) scaled by a 256 MiB copy kernel
 # (profiles/dgamp_c2_512x512_64views_hbm_traffic.md).  Set to None whenever
 # that kernel changes until the counters are taken again.
-NLM_TRAFFIC_BYTES = 7.253e6
+NLM_TRAFFIC_BYTES = 7.250e6
 # Counters of the two operators at this workload (per launch, rocprofv3 --pmc
 # passes; profiles/radon_nlm_c2_512x512_64views_counters.md).  Set to None
 # when either kernel changes until the counters are taken again.
